@@ -1,0 +1,220 @@
+/*
+ * hdivsp.h - C ABI of the MI355X library for the transformed H(div)
+ * saddle-point system and its block-preconditioned MINRES solver.
+ *
+ * Method: Pazner, Kolev, Vassilevski, "Matrix-free GPU-accelerated
+ * saddle-point solvers for high-order problems in H(div)".
+ *
+ *   A = [ M   D^T ]      M  : RT_p mass matrix weighted by c_mass per element
+ *       [ D   -C  ]      D  : +-1 sub-element incidence (interpolation-
+ *                             histopolation basis, Section 2.1)
+ *                        C  : block diagonal, C_e = kappa_e W_e^{-1}, W_e the
+ *                             element L2 mass matrix
+ *   grad-div (eq. transformed-system):          c_mass = beta, kappa = 1/alpha
+ *   Darcy    (eq. transformed-system-darcy,
+ *             piecewise-constant gamma):         c_mass = 1/eps, kappa = gamma
+ *
+ *   B^{-1} = diag( (tau diag(M))^{-1}, one AMG V-cycle on
+ *                  S~ = C~ + D diag(M)^{-1} D^T )      (eq. approx-schur,
+ *                  eq. approx-schur-entries, Prop. 5)
+ *
+ * Mesh: structured nx x ny x nz hexahedra with arbitrary (trilinear) vertex
+ * positions.  Vertices: host array [(nx+1)(ny+1)(nz+1)][3], x fastest.
+ * Element e = ex + nx (ey + ny ez).
+ *
+ * Vector layout (length n_u + n_q, one right-hand side):
+ *   [0, n_u)   RT dofs, one per sub-element face of the refined grid,
+ *              direction-major (x-normal faces, then y, then z), each block
+ *              lexicographic over the refined face grid, first index fastest;
+ *              orientation +axis.
+ *   [n_u, n)   L2 dofs, element-major: e, then (a, b, c), a fastest.
+ * Multi-RHS buffers (nrhs > 1) are RHS-major: nrhs consecutive vectors.
+ *
+ * Essential flux dofs (faces on the box sides selected by ess_sides) have
+ * identity rows and columns: apply() ignores their input values in every
+ * other row and copies the input to their output.
+ *
+ * Conventions
+ *   - Device pointers are caller-owned, allocated on the context's device,
+ *     of the precision named by `prec` (HD_F64: double, HD_F32: float).
+ *   - Host pointers passed to setup calls are copied before return.
+ *   - All work is enqueued on the context stream; calls that return data to
+ *     the host (sizes, info, hierarchy queries) synchronise that stream.
+ *   - Return value: 0 on success, < 0 on error (see HD_ERR_*), > 0 warning.
+ *     The message of the last non-zero status is kept in the context.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef HDIVSP_H
+#define HDIVSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hd_ctx hd_ctx;
+
+enum {
+    HD_OK = 0,
+    HD_ERR_ARG = -1,        /* invalid argument or size */
+    HD_ERR_MESH = -2,       /* non-positive Jacobian determinant */
+    HD_ERR_HIP = -3,        /* HIP runtime error */
+    HD_ERR_OOM = -4,        /* device allocation failed */
+    HD_ERR_AMG = -5,        /* AMG setup failed */
+    HD_ERR_BREAKDOWN = -6,  /* MINRES: preconditioner not positive definite */
+    HD_ERR_NONFINITE = -7,  /* non-finite value in input or iteration */
+    HD_ERR_STATE = -8,      /* call order violated (e.g. solve before setup) */
+    HD_NOT_CONVERGED = 1,   /* max iterations reached, info filled */
+    HD_FALLBACK_USED = 2
+};
+
+enum { HD_GRADDIV = 0, HD_DARCY = 1 };
+enum { HD_F64 = 0, HD_F32 = 1 };
+
+/* ess_sides bits */
+enum { HD_SIDE_XMIN = 1, HD_SIDE_XMAX = 2, HD_SIDE_YMIN = 4, HD_SIDE_YMAX = 8,
+       HD_SIDE_ZMIN = 16, HD_SIDE_ZMAX = 32, HD_SIDE_ALL = 63 };
+
+/* MINRES modes */
+enum {
+    HD_MODE_PLAIN64 = 0,   /* everything in FP64 */
+    HD_MODE_MIXED = 1,     /* FP64 residual refinement around FP32 MINRES
+                              (FP32 vectors, operator and preconditioner;
+                              FP64 dot products, recurrences and coarse solve) */
+    HD_MODE_PREC32 = 2     /* FP64 MINRES with the FP32 preconditioner */
+};
+
+typedef struct hd_precond_params {
+    double tau;          /* (1,1)-block scaling (remark after Prop. 3); default 1 */
+    double theta;        /* AMG strength threshold; default 0.25 */
+    int max_coarse;      /* AMG coarsest size; default 1024 */
+    int max_levels;      /* default 25 */
+    double omega;        /* prolongator smoothing weight; default 2/3 */
+} hd_precond_params;
+
+typedef struct hd_solve_params {
+    double tol;          /* relative tolerance (see mode); default 1e-8 */
+    int max_it;          /* max MINRES iterations (inner, per refinement); default 10000 */
+    int mode;            /* HD_MODE_* */
+    int use_x0;          /* 1: x holds the initial guess; 0: start from zero */
+    double inner_tol;    /* HD_MODE_MIXED: inner FP32 tolerance; default 1e-5 */
+    int max_outer;       /* HD_MODE_MIXED: max refinement steps; default 20 */
+    int check_every;     /* iterations between host polls of the flag; default 8 */
+} hd_solve_params;
+
+typedef struct hd_solve_info {
+    int status;          /* 0 converged, HD_NOT_CONVERGED, HD_ERR_BREAKDOWN */
+    int iterations;      /* total operator applications (all precisions) */
+    int outer;           /* refinement steps (HD_MODE_MIXED), else 1 */
+    double eta_rel;      /* last |eta| / |eta_0| of the (last) MINRES */
+    double true_rel_res; /* ||b - A x||_2 / ||b||_2 in FP64 */
+    double time_s;       /* wall time of the solve on the device stream */
+} hd_solve_info;
+
+/* Context bound to `device` and to `stream` (a hipStream_t, may be NULL for
+ * the default stream).  Section 3 (solver overview). */
+int hd_create(hd_ctx** out, int device, void* stream);
+int hd_destroy(hd_ctx* ctx);
+const char* hd_last_error(const hd_ctx* ctx);
+
+/* Structured mesh and RT order p (1 <= p <= 8).  Computes the geometric
+ * factors at the (p+1)^3 Gauss-Legendre points of every element
+ * (w J^T J / det J and w / det J; partial assembly, Section 3) and rejects
+ * det J <= 0 at quadrature points and vertices with HD_ERR_MESH. */
+int hd_setup_mesh(hd_ctx* ctx, int nx, int ny, int nz, int p, const double* vertices);
+
+/* Coefficients per element (host arrays of length nx*ny*nz, copied).
+ * problem = HD_GRADDIV: c_mass = beta > 0, c_22 = alpha > 0 (required).
+ * problem = HD_DARCY:   c_mass = 1/eps > 0, c_22 = gamma >= 0 or NULL (0).
+ * ess_sides: bit mask of box sides whose RT dofs are essential. */
+int hd_setup_coeffs(hd_ctx* ctx, int problem, const double* c_mass, const double* c_22,
+                    uint32_t ess_sides);
+
+/* Global sizes n_u (RT) and n_q (L2). */
+int hd_sizes(const hd_ctx* ctx, int64_t* n_u, int64_t* n_q);
+
+/* y = A x (eq. transformed-saddle-point, Section 3).  x != y, device
+ * pointers of length nrhs*(n_u+n_q).  Essential convention as above.
+ * Matrix-free: M by sum factorisation at the quadrature points, D and D^T
+ * by the +-1 sub-element incidence, C by a per-element preconditioned CG in
+ * the Gauss-Legendre basis (Section 2.5, Section 3.1). */
+int hd_apply_block_op(hd_ctx* ctx, int prec, int nrhs, const void* x, void* y);
+
+/* y_q = C x_q = kappa_e W_e^{-1} x_q per element (the (2,2) block without
+ * its sign), for L2 vectors of length n_q.  For HD_DARCY with gamma = 0 use
+ * hd_apply_l2_mass_inverse.  Section 2.5. */
+int hd_apply_mass_inverse(hd_ctx* ctx, int prec, int nrhs, const void* x, void* y);
+
+/* y_q = W^{-1} x_q (unweighted), e.g. to form W^{-1} g^ for Darcy
+ * right-hand sides or p = W^{-1} p~ in post-processing (Section 3). */
+int hd_apply_l2_mass_inverse(hd_ctx* ctx, int prec, const void* x, void* y);
+
+/* b <- lifted right-hand side for essential values u_bc (device, length
+ * n_u, only essential entries read): b_f -= (A_full [u_bc;0])_f on free rows,
+ * b_e = u_bc on essential rows.  FP64. */
+int hd_lift_essential(hd_ctx* ctx, const double* u_bc, double* b);
+
+/* Diagonal M~ = diag(M), the approximate Schur complement S~ in CSR form
+ * (eq. approx-schur-entries, assembled row by row; 1 on essential
+ * dofs of M~) and the AMG hierarchy on S~.  params may be NULL (defaults). */
+int hd_build_precond(hd_ctx* ctx, const hd_precond_params* params);
+
+/* z = B^{-1} r.  Device pointers of length nrhs*(n_u+n_q). */
+int hd_apply_precond(hd_ctx* ctx, int prec, int nrhs, const void* r, void* z);
+
+/* Block-preconditioned MINRES on A x = b.  b, x: FP64 device pointers of
+ * length nrhs*(n_u+n_q).  info: host array of nrhs entries (may be NULL).
+ * Returns 0 when every right-hand side converged, HD_NOT_CONVERGED or an
+ * error code otherwise. */
+int hd_minres_solve(hd_ctx* ctx, const hd_solve_params* params, int nrhs,
+                    const double* b, double* x, hd_solve_info* info);
+
+/* ---- inspection (parity checks) ---------------------------------------- */
+
+/* Copy diag(M) (n_u) and diag(W) (unweighted, n_q) into device buffers. */
+int hd_get_diagonals(hd_ctx* ctx, double* m_diag, double* w_diag);
+
+/* S~ in CSR: query nnz with rowptr == NULL, then pass host buffers of n_q+1,
+ * nnz, nnz entries. */
+int hd_get_schur(hd_ctx* ctx, int64_t* nnz, int32_t* rowptr, int32_t* col, double* val);
+
+/* Number of AMG levels and the size/nnz of level `level` (A), and, when the
+ * buffers are non-NULL, its CSR arrays (host).  For level < nlevels-1 the
+ * prolongator P (rows of level, cols of level+1) is returned by
+ * hd_get_amg_prolongator. */
+int hd_get_amg_nlevels(hd_ctx* ctx, int* nlevels);
+int hd_get_amg_level(hd_ctx* ctx, int level, int64_t* n, int64_t* nnz,
+                     int32_t* rowptr, int32_t* col, double* val);
+int hd_get_amg_prolongator(hd_ctx* ctx, int level, int64_t* nrows, int64_t* ncols, int64_t* nnz,
+                           int32_t* rowptr, int32_t* col, double* val);
+
+/* Average device duration (ms) of the block-apply kernel over the calls since
+ * the last reset, measured with events on the context stream (reset = 1
+ * clears the accumulators). */
+int hd_apply_timing(hd_ctx* ctx, int reset, double* avg_ms, int64_t* count);
+
+/* ---- host-only entry (no device needed) -------------------------------- */
+
+/* Build the aggregation AMG hierarchy of a host CSR matrix with the
+ * library's host code and return level sizes; the hierarchy is kept in a
+ * host handle for hd_host_amg_level / hd_host_amg_free.  For checks on
+ * machines without a GPU. */
+typedef struct hd_host_amg hd_host_amg;
+int hd_host_amg_build(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                      const hd_precond_params* params, int singular, hd_host_amg** out);
+int hd_host_amg_nlevels(const hd_host_amg* h);
+int hd_host_amg_level(const hd_host_amg* h, int level, int64_t* n, int64_t* nnz,
+                      int32_t* rowptr, int32_t* col, double* val);
+int hd_host_amg_prolongator(const hd_host_amg* h, int level, int64_t* nrows, int64_t* ncols,
+                            int64_t* nnz, int32_t* rowptr, int32_t* col, double* val);
+int hd_host_amg_free(hd_host_amg* h);
+
+/* 1D tables of degree p as computed by the library (host, no device):
+ * Gauss-Lobatto points (p+1), Gauss-Legendre points and weights (p+1). */
+int hd_host_tables(int p, double* gll, double* gl_x, double* gl_w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -248,3 +248,45 @@ class Problem:
         out = b - A @ ub
         out[:nu][self.ess] = u_bc[self.ess]
         return out
+
+
+def apply_element_rows(mesh, problem, c_mass, c_22, ess_sides, x, elems):
+    """Rows of y = A x owned by the listed elements, computed from those
+    elements' matrices only (for sampled checks on meshes too large to
+    assemble).  Returns (q_rows, y_q, u_rows, y_u): all L2 rows of the
+    elements, and the RT rows that lie strictly inside them."""
+    from .element import element_matrices
+    elems = np.asarray(elems)
+    p = mesh.p
+    nl = p ** 3
+    V = mesh.element_vertices(elems)
+    em = element_matrices(p, V, np.asarray(c_mass)[elems])
+    if problem == GRADDIV:
+        kap = 1.0 / np.asarray(c_22)[elems]
+    else:
+        kap = np.zeros(len(elems)) if c_22 is None else np.asarray(c_22)[elems]
+    l2g = mesh.rt_local_to_global(elems)
+    ess = mesh.essential_mask(ess_sides)
+    nu = mesh.n_u
+    from .element import reference_divergence
+    D = reference_divergence(p)
+    q_rows, y_q, u_rows, y_u = [], [], [], []
+    # RT dofs strictly interior to an element: normal index not 0 or p
+    from .element import rt_shapes
+    interior = []
+    for comp, shp in enumerate(rt_shapes(p)):
+        kk, jj, ii = np.meshgrid(np.arange(shp[2]), np.arange(shp[1]), np.arange(shp[0]), indexing='ij')
+        t = [ii, jj, kk][comp].ravel()
+        interior.append((t > 0) & (t < p))
+    interior = np.concatenate(interior)
+    for n, e in enumerate(elems):
+        xu = x[l2g[n]].copy()
+        xu[ess[l2g[n]]] = 0.0
+        xq = x[nu + e * nl: nu + (e + 1) * nl]
+        yu = em['M'][n] @ xu + D.T @ xq
+        yq = D @ xu - kap[n] * np.linalg.solve(em['W'][n], xq)
+        q_rows.append(nu + e * nl + np.arange(nl))
+        y_q.append(yq)
+        u_rows.append(l2g[n][interior])
+        y_u.append(yu[interior])
+    return (np.concatenate(q_rows), np.concatenate(y_q), np.concatenate(u_rows), np.concatenate(y_u))

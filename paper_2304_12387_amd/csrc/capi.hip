@@ -1,0 +1,422 @@
+// extern "C" entry points of libhdivsp (declared in include/hdivsp.h).
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "hd_internal.hpp"
+
+namespace hd {
+
+int set_err(hd_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+}  // namespace hd
+
+using namespace hd;
+
+namespace {
+
+void free_mesh(hd_ctx* c) {
+    dfree(c->d_pa);
+    dfree(c->d_pa32);
+    c->d_pa = nullptr;
+    c->d_pa32 = nullptr;
+    c->have_mesh = false;
+}
+
+void free_coeffs(hd_ctx* c) {
+    dfree(c->d_cm);
+    dfree(c->d_kap);
+    dfree(c->d_cm32);
+    dfree(c->d_kap32);
+    c->d_cm = c->d_kap = nullptr;
+    c->d_cm32 = c->d_kap32 = nullptr;
+    c->have_coeffs = false;
+}
+
+void free_prec(hd_ctx* c) {
+    free_levels(c);
+    dfree(c->S.rp);
+    dfree(c->S.ci);
+    dfree(c->S.v);
+    dfree(c->S.v32);
+    c->S = DevCSR();
+    dfree(c->d_mdiag);
+    dfree(c->d_wdiag);
+    dfree(c->d_mdinv);
+    dfree(c->d_mdinv32);
+    c->d_mdiag = c->d_wdiag = c->d_mdinv = nullptr;
+    c->d_mdinv32 = nullptr;
+    c->host_amg = HostAMG();
+    c->have_prec = false;
+}
+
+int use_device(hd_ctx* c) {
+    HD_HIP(c, hipSetDevice(c->device));
+    return HD_OK;
+}
+
+__global__ void f64_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+int upload_f64_f32(hd_ctx* c, const double* host, int64_t n, double*& d64, float*& d32) {
+    d64 = dalloc<double>(n);
+    d32 = dalloc<float>(n);
+    if (!d64 || !d32) return set_err(c, HD_ERR_OOM, "coefficient storage");
+    HD_HIP(c, hipMemcpyAsync(d64, host, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(f64_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, d64, d32, n);
+    HD_HIP(c, hipGetLastError());
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    return HD_OK;
+}
+
+hd_precond_params default_precond() {
+    hd_precond_params p;
+    p.tau = 1.0;
+    p.theta = 0.25;
+    p.max_coarse = 1024;
+    p.max_levels = 25;
+    p.omega = 2.0 / 3.0;
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hd_create(hd_ctx** out, int device, void* stream) {
+    if (!out) return HD_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HD_ERR_HIP;
+    hd_ctx* c = new (std::nothrow) hd_ctx;
+    if (!c) return HD_ERR_OOM;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return HD_ERR_HIP;
+    }
+    c->d_scal = dalloc<double>(16);
+    c->d_flag = dalloc<int>(4);
+    if (!c->d_scal || !c->d_flag || hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return HD_ERR_HIP;
+    }
+    (void)hipMemset(c->d_scal, 0, 16 * sizeof(double));
+    *out = c;
+    return HD_OK;
+}
+
+int hd_destroy(hd_ctx* c) {
+    if (!c) return HD_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_prec(c);
+    free_coeffs(c);
+    free_mesh(c);
+    dfree(c->d_tab64);
+    dfree(c->d_tab32);
+    dfree(c->d_partial);
+    dfree(c->d_scal);
+    dfree(c->d_flag);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+    return HD_OK;
+}
+
+const char* hd_last_error(const hd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int hd_setup_mesh(hd_ctx* c, int nx, int ny, int nz, int p, const double* vertices) {
+    if (!c) return HD_ERR_ARG;
+    if (nx < 1 || ny < 1 || nz < 1 || !vertices) return set_err(c, HD_ERR_ARG, "bad mesh sizes");
+    if (p < 1 || p > 6) return set_err(c, HD_ERR_ARG, "p must be in [1, 6]");
+    int rc = use_device(c);
+    if (rc) return rc;
+    free_prec(c);
+    free_mesh(c);
+    const int64_t nv = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+    for (int64_t i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(vertices[i])) return set_err(c, HD_ERR_NONFINITE, "non-finite vertex coordinate");
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->p = p;
+    c->ne = (int64_t)nx * ny * nz;
+    c->nface[0] = (int64_t)(nx * p + 1) * (ny * p) * (nz * p);
+    c->nface[1] = (int64_t)(nx * p) * (ny * p + 1) * (nz * p);
+    c->nface[2] = (int64_t)(nx * p) * (ny * p) * (nz * p + 1);
+    c->n_u = c->nface[0] + c->nface[1] + c->nface[2];
+    c->n_q = c->ne * p * p * p;
+    if (c->n_u + c->n_q > (int64_t)INT32_MAX) return set_err(c, HD_ERR_ARG, "problem too large for 32-bit indices");
+    Tables<double> t64;
+    Tables<float> t32;
+    build_tables(p, t64, t32);
+    if (!c->d_tab64) c->d_tab64 = dalloc<Tables<double>>(1);
+    if (!c->d_tab32) c->d_tab32 = dalloc<Tables<float>>(1);
+    if (!c->d_tab64 || !c->d_tab32) return set_err(c, HD_ERR_OOM, "tables");
+    HD_HIP(c, hipMemcpyAsync(c->d_tab64, &t64, sizeof(t64), hipMemcpyHostToDevice, c->stream));
+    HD_HIP(c, hipMemcpyAsync(c->d_tab32, &t32, sizeof(t32), hipMemcpyHostToDevice, c->stream));
+    const int64_t q3 = (int64_t)(p + 1) * (p + 1) * (p + 1);
+    c->d_pa = dalloc<double>(c->ne * NPA * q3);
+    c->d_pa32 = dalloc<float>(c->ne * NPA * q3);
+    double* dv = dalloc<double>(3 * nv);
+    if (!c->d_pa || !c->d_pa32 || !dv) {
+        dfree(dv);
+        return set_err(c, HD_ERR_OOM, "geometric factors");
+    }
+    HD_HIP(c, hipMemcpyAsync(dv, vertices, sizeof(double) * 3 * nv, hipMemcpyHostToDevice, c->stream));
+    HD_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+    rc = launch_geometry(c, dv, c->d_flag);
+    int bad = 0;
+    if (!rc) {
+        HD_HIP(c, hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HD_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    dfree(dv);
+    if (rc) return rc;
+    if (bad) {
+        free_mesh(c);
+        return set_err(c, HD_ERR_MESH, "Jacobian determinant <= 0 in some element");
+    }
+    rc = launch_ensure_partial(c, c->ne);
+    if (rc) return rc;
+    c->have_mesh = true;
+    c->have_coeffs = false;
+    return HD_OK;
+}
+
+int hd_setup_coeffs(hd_ctx* c, int problem, const double* c_mass, const double* c_22, uint32_t ess_sides) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_mesh) return set_err(c, HD_ERR_STATE, "hd_setup_mesh first");
+    if (problem != HD_GRADDIV && problem != HD_DARCY) return set_err(c, HD_ERR_ARG, "unknown problem");
+    if (!c_mass) return set_err(c, HD_ERR_ARG, "c_mass required");
+    if (problem == HD_GRADDIV && !c_22) return set_err(c, HD_ERR_ARG, "grad-div needs alpha (c_22)");
+    if (ess_sides > 63) return set_err(c, HD_ERR_ARG, "ess_sides must be a 6-bit mask");
+    int rc = use_device(c);
+    if (rc) return rc;
+    const int64_t ne = c->ne;
+    std::vector<double> kap(ne, 0.0);
+    for (int64_t e = 0; e < ne; ++e) {
+        if (!std::isfinite(c_mass[e]) || (c_22 && !std::isfinite(c_22[e])))
+            return set_err(c, HD_ERR_NONFINITE, "non-finite coefficient");
+        if (!(c_mass[e] > 0)) return set_err(c, HD_ERR_ARG, "c_mass must be positive");
+        if (problem == HD_GRADDIV) {
+            if (!(c_22[e] > 0)) return set_err(c, HD_ERR_ARG, "alpha must be positive");
+            kap[e] = 1.0 / c_22[e];
+        } else if (c_22) {
+            if (c_22[e] < 0) return set_err(c, HD_ERR_ARG, "gamma must be non-negative");
+            kap[e] = c_22[e];
+        }
+    }
+    free_prec(c);
+    free_coeffs(c);
+    c->problem = problem;
+    c->ess = ess_sides;
+    c->kappa_zero = true;
+    for (double k : kap)
+        if (k != 0.0) c->kappa_zero = false;
+    if ((rc = upload_f64_f32(c, c_mass, ne, c->d_cm, c->d_cm32))) return rc;
+    if ((rc = upload_f64_f32(c, kap.data(), ne, c->d_kap, c->d_kap32))) return rc;
+    c->have_coeffs = true;
+    return HD_OK;
+}
+
+int hd_sizes(const hd_ctx* c, int64_t* n_u, int64_t* n_q) {
+    if (!c || !c->have_mesh) return HD_ERR_STATE;
+    if (n_u) *n_u = c->n_u;
+    if (n_q) *n_q = c->n_q;
+    return HD_OK;
+}
+
+int hd_apply_block_op(hd_ctx* c, int prec, int nrhs, const void* x, void* y) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
+    if (nrhs != 1) return set_err(c, HD_ERR_ARG, "nrhs must be 1 in this version");
+    if (prec != HD_F64 && prec != HD_F32) return set_err(c, HD_ERR_ARG, "prec");
+    if (!x || !y || x == y) return set_err(c, HD_ERR_ARG, "x, y must be distinct device pointers");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_apply(c, prec, x, y, nullptr, nullptr, ESS_IDENTITY, nullptr);
+}
+
+int hd_apply_mass_inverse(hd_ctx* c, int prec, int nrhs, const void* x, void* y) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
+    if (nrhs != 1) return set_err(c, HD_ERR_ARG, "nrhs must be 1 in this version");
+    if (!x || !y) return set_err(c, HD_ERR_ARG, "null pointer");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_mass_inverse(c, prec, x, y, true);
+}
+
+int hd_apply_l2_mass_inverse(hd_ctx* c, int prec, const void* x, void* y) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_mesh || !c->d_kap) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
+    if (!x || !y) return set_err(c, HD_ERR_ARG, "null pointer");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_mass_inverse(c, prec, x, y, false);
+}
+
+int hd_lift_essential(hd_ctx* c, const double* u_bc, double* b) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
+    if (!u_bc || !b) return set_err(c, HD_ERR_ARG, "null pointer");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_lift(c, u_bc, b);
+}
+
+int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
+    hd_precond_params prm = params ? *params : default_precond();
+    if (!(prm.tau > 0) || !(prm.theta >= 0) || prm.max_coarse < 1 || prm.max_levels < 1 || !(prm.omega > 0))
+        return set_err(c, HD_ERR_ARG, "bad preconditioner parameters");
+    int rc = use_device(c);
+    if (rc) return rc;
+    free_prec(c);
+    c->tau = prm.tau;
+    c->d_mdiag = dalloc<double>(c->n_u);
+    c->d_mdinv = dalloc<double>(c->n_u);
+    c->d_mdinv32 = dalloc<float>(c->n_u);
+    c->d_wdiag = dalloc<double>(c->n_q);
+    if (!c->d_mdiag || !c->d_mdinv || !c->d_mdinv32 || !c->d_wdiag) return set_err(c, HD_ERR_OOM, "diagonals");
+    if ((rc = launch_diagonals(c))) return rc;
+    if ((rc = launch_schur(c))) return rc;
+    // S~ to the host for the AMG setup
+    HostCSR S;
+    S.nrows = S.ncols = c->n_q;
+    S.rp.resize(c->n_q + 1);
+    S.ci.resize(c->S.nnz);
+    S.v.resize(c->S.nnz);
+    HD_HIP(c, hipMemcpyAsync(S.rp.data(), c->S.rp, sizeof(int32_t) * (c->n_q + 1), hipMemcpyDeviceToHost, c->stream));
+    HD_HIP(c, hipMemcpyAsync(S.ci.data(), c->S.ci, sizeof(int32_t) * c->S.nnz, hipMemcpyDeviceToHost, c->stream));
+    HD_HIP(c, hipMemcpyAsync(S.v.data(), c->S.v, sizeof(double) * c->S.nnz, hipMemcpyDeviceToHost, c->stream));
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    // S~ is singular when C~ = 0 and every boundary face is essential
+    c->singular = c->kappa_zero && c->ess == HD_SIDE_ALL;
+    std::string err;
+    rc = build_amg_host(S, prm, c->singular, c->host_amg, err);
+    if (rc) return set_err(c, rc, err);
+    if ((rc = upload_amg(c))) return rc;
+    c->have_prec = true;
+    return HD_OK;
+}
+
+int hd_apply_precond(hd_ctx* c, int prec, int nrhs, const void* r, void* z) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
+    if (nrhs != 1) return set_err(c, HD_ERR_ARG, "nrhs must be 1 in this version");
+    if (!r || !z || r == z) return set_err(c, HD_ERR_ARG, "r, z must be distinct device pointers");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_precond(c, prec, r, z, nullptr, nullptr, nullptr);
+}
+
+int hd_minres_solve(hd_ctx* c, const hd_solve_params* params, int nrhs, const double* b, double* x,
+                    hd_solve_info* info) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
+    if (nrhs != 1) return set_err(c, HD_ERR_ARG, "nrhs must be 1 in this version");
+    if (!b || !x || b == x) return set_err(c, HD_ERR_ARG, "b, x must be distinct device pointers");
+    hd_solve_params prm;
+    if (params) prm = *params;
+    else {
+        prm.tol = 1e-8;
+        prm.max_it = 10000;
+        prm.mode = HD_MODE_PLAIN64;
+        prm.use_x0 = 0;
+        prm.inner_tol = 1e-5;
+        prm.max_outer = 20;
+        prm.check_every = 8;
+    }
+    if (!(prm.tol > 0) || prm.max_it < 1) return set_err(c, HD_ERR_ARG, "bad solve parameters");
+    if (prm.mode == HD_MODE_MIXED && (!(prm.inner_tol > 0) || prm.max_outer < 1))
+        return set_err(c, HD_ERR_ARG, "bad refinement parameters");
+    int rc = use_device(c);
+    if (rc) return rc;
+    hd_solve_info inf;
+    rc = minres_solve(c, prm, b, x, inf);
+    if (info) info[0] = inf;
+    if (rc == HD_NOT_CONVERGED) c->err = "MINRES did not reach the tolerance";
+    return rc;
+}
+
+int hd_get_diagonals(hd_ctx* c, double* m_diag, double* w_diag) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
+    if (m_diag)
+        HD_HIP(c, hipMemcpyAsync(m_diag, c->d_mdiag, sizeof(double) * c->n_u, hipMemcpyDeviceToDevice, c->stream));
+    if (w_diag)
+        HD_HIP(c, hipMemcpyAsync(w_diag, c->d_wdiag, sizeof(double) * c->n_q, hipMemcpyDeviceToDevice, c->stream));
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    return HD_OK;
+}
+
+int hd_get_schur(hd_ctx* c, int64_t* nnz, int32_t* rowptr, int32_t* col, double* val) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
+    if (nnz) *nnz = c->S.nnz;
+    if (!rowptr) return HD_OK;
+    HD_HIP(c, hipMemcpyAsync(rowptr, c->S.rp, sizeof(int32_t) * (c->n_q + 1), hipMemcpyDeviceToHost, c->stream));
+    if (col) HD_HIP(c, hipMemcpyAsync(col, c->S.ci, sizeof(int32_t) * c->S.nnz, hipMemcpyDeviceToHost, c->stream));
+    if (val) HD_HIP(c, hipMemcpyAsync(val, c->S.v, sizeof(double) * c->S.nnz, hipMemcpyDeviceToHost, c->stream));
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    return HD_OK;
+}
+
+int hd_get_amg_nlevels(hd_ctx* c, int* nlevels) {
+    if (!c || !nlevels) return HD_ERR_ARG;
+    if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
+    *nlevels = (int)c->host_amg.A.size();
+    return HD_OK;
+}
+
+int hd_get_amg_level(hd_ctx* c, int level, int64_t* n, int64_t* nnz, int32_t* rowptr, int32_t* col, double* val) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
+    if (level < 0 || level >= (int)c->host_amg.A.size()) return set_err(c, HD_ERR_ARG, "level");
+    const HostCSR& A = c->host_amg.A[level];
+    if (n) *n = A.nrows;
+    if (nnz) *nnz = A.nnz();
+    if (rowptr) std::memcpy(rowptr, A.rp.data(), sizeof(int32_t) * (A.nrows + 1));
+    if (col) std::memcpy(col, A.ci.data(), sizeof(int32_t) * A.nnz());
+    if (val) std::memcpy(val, A.v.data(), sizeof(double) * A.nnz());
+    return HD_OK;
+}
+
+int hd_get_amg_prolongator(hd_ctx* c, int level, int64_t* nrows, int64_t* ncols, int64_t* nnz, int32_t* rowptr,
+                           int32_t* col, double* val) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
+    if (level < 0 || level >= (int)c->host_amg.P.size()) return set_err(c, HD_ERR_ARG, "level");
+    const HostCSR& P = c->host_amg.P[level];
+    if (nrows) *nrows = P.nrows;
+    if (ncols) *ncols = P.ncols;
+    if (nnz) *nnz = P.nnz();
+    if (rowptr) std::memcpy(rowptr, P.rp.data(), sizeof(int32_t) * (P.nrows + 1));
+    if (col) std::memcpy(col, P.ci.data(), sizeof(int32_t) * P.nnz());
+    if (val) std::memcpy(val, P.v.data(), sizeof(double) * P.nnz());
+    return HD_OK;
+}
+
+int hd_apply_timing(hd_ctx* c, int reset, double* avg_ms, int64_t* count) {
+    if (!c) return HD_ERR_ARG;
+    if (avg_ms) *avg_ms = c->apply_count ? c->apply_ms_sum / (double)c->apply_count : 0.0;
+    if (count) *count = c->apply_count;
+    if (reset) {
+        c->apply_ms_sum = 0.0;
+        c->apply_count = 0;
+    }
+    c->time_apply = true;
+    return HD_OK;
+}
+
+}  // extern "C"

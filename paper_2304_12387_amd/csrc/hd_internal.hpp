@@ -1,0 +1,194 @@
+// Internal declarations of the hdivsp library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hdivsp.h"
+
+#define HD_MAXP 8
+#define HD_MAXQ (HD_MAXP + 1)
+
+namespace hd {
+
+// 1D tables of degree p with q = p + 1 Gauss-Legendre quadrature points.
+//   L[a][i]  = l_i(x_a)       interpolation at the Gauss-Lobatto nodes (i <= p)
+//   H[a][j]  = h_j(x_a)       histopolation on the Gauss-Lobatto sub-intervals
+//   Bg[a][m] = L^g_m(x_a)     Lagrange basis at the p Gauss-Legendre nodes
+//   L2, H2, Bg2               squares (diagonal assembly by sum factorisation)
+//   Tinv                      inverse of Tm[m][j] = h_j(g_m) (IH -> GL nodal)
+//   wq, xq                    quadrature weights and points on [0, 1]
+template <typename T>
+struct Tables {
+    T L[HD_MAXQ][HD_MAXQ];
+    T H[HD_MAXQ][HD_MAXP];
+    T Bg[HD_MAXQ][HD_MAXP];
+    T L2[HD_MAXQ][HD_MAXQ];
+    T H2[HD_MAXQ][HD_MAXP];
+    T Bg2[HD_MAXQ][HD_MAXP];
+    T Tinv[HD_MAXP][HD_MAXP];
+    T wq[HD_MAXQ];
+    T xq[HD_MAXQ];
+};
+
+void gauss_legendre01(int n, double* x, double* w);
+void gauss_lobatto01(int p, double* xi);
+void build_tables(int p, Tables<double>& t64, Tables<float>& t32);
+
+// Number of geometric factors stored per quadrature point: the 6 entries of
+// the symmetric w J^T J / det J and w / det J.
+constexpr int NPA = 7;
+
+// Host-side CSR (AMG setup works on the host).
+struct HostCSR {
+    int64_t nrows = 0, ncols = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v;
+    int64_t nnz() const { return (int64_t)ci.size(); }
+};
+
+struct HostAMG {
+    std::vector<HostCSR> A;   // level matrices
+    std::vector<HostCSR> P;   // prolongators level l -> l+1 (rows of l)
+    std::vector<double> coarse_inv;   // dense, row-major
+    bool singular = false;
+};
+
+int build_amg_host(const HostCSR& S, const hd_precond_params& prm, bool singular, HostAMG& out,
+                   std::string& err);
+
+// Structured-mesh geometry passed to kernels: element counts and the offsets
+// of the x-, y- and z-normal RT dof blocks.
+struct Geo {
+    int nx, ny, nz;
+    int64_t off[3];
+};
+
+// Device CSR with FP64 and FP32 values.
+struct DevCSR {
+    int64_t nrows = 0, ncols = 0, nnz = 0;
+    int32_t* rp = nullptr;
+    int32_t* ci = nullptr;
+    double* v = nullptr;
+    float* v32 = nullptr;
+};
+
+struct DevLevel {
+    DevCSR A, P, R;           // R = P^T
+    double* dinv = nullptr;   // 1 / sum_j |a_ij|
+    float* dinv32 = nullptr;
+    // work vectors (FP64 and FP32)
+    double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr;
+    float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr, *z32 = nullptr;
+};
+
+}  // namespace hd
+
+struct hd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // mesh
+    bool have_mesh = false;
+    int nx = 0, ny = 0, nz = 0, p = 0;
+    int64_t ne = 0, n_u = 0, n_q = 0, nface[3] = {0, 0, 0};
+    double* d_pa = nullptr;   // [ne][NPA][q^3]
+    float* d_pa32 = nullptr;
+    hd::Tables<double>* d_tab64 = nullptr;
+    hd::Tables<float>* d_tab32 = nullptr;
+
+    // coefficients
+    bool have_coeffs = false;
+    int problem = 0;
+    uint32_t ess = 0;
+    double* d_cm = nullptr;      // c_mass per element
+    double* d_kap = nullptr;     // kappa per element
+    float* d_cm32 = nullptr;
+    float* d_kap32 = nullptr;
+    bool kappa_zero = true;
+
+    // preconditioner
+    bool have_prec = false;
+    double tau = 1.0;
+    double* d_mdiag = nullptr;   // diag(M), 1 on essential dofs
+    double* d_wdiag = nullptr;   // diag(W) unweighted
+    double* d_mdinv = nullptr;   // 1 / (tau diag(M)), 1 on essential dofs
+    float* d_mdinv32 = nullptr;
+    hd::DevCSR S;                // S~
+    std::vector<hd::DevLevel> lev;
+    int64_t n_coarse = 0;
+    double* d_cinv = nullptr;
+    float* d_cinv32 = nullptr;
+    bool singular = false;
+    hd::HostAMG host_amg;        // kept for inspection
+
+    // scratch
+    double* d_partial = nullptr;     // per-block partial sums (>= ne and >= reduce grid)
+    int64_t partial_cap = 0;
+    double* d_scal = nullptr;        // small device scalar block
+    int* d_flag = nullptr;
+
+    // timing of the block apply
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double apply_ms_sum = 0.0;
+    int64_t apply_count = 0;
+    bool time_apply = false;
+};
+
+namespace hd {
+
+// error helpers
+int set_err(hd_ctx* c, int code, const std::string& msg);
+#define HD_HIP(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return hd::set_err((ctx), HD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+inline T* dalloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) return nullptr;
+    return (T*)p;
+}
+inline void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+// kernels and launchers (setup.hip)
+int launch_geometry(hd_ctx* c, const double* d_vert, int* d_bad);
+int launch_diagonals(hd_ctx* c);
+int launch_schur(hd_ctx* c);
+int launch_ensure_partial(hd_ctx* c, int64_t n);
+
+// apply.hip
+enum { ESS_NONE = 0, ESS_IDENTITY = 1 };
+int launch_apply(hd_ctx* c, int prec, const void* x, void* y, const double* in_scale, double* dot_partial,
+                 int ess_mode, const int* done);
+int launch_mass_inverse(hd_ctx* c, int prec, const void* x, void* y, bool weighted);
+int launch_lift(hd_ctx* c, const double* ubc, double* b);
+
+// precond.hip
+int upload_amg(hd_ctx* c);
+int launch_precond(hd_ctx* c, int prec, const void* r, void* z, double* dot_partial_u, double* dot_partial_q,
+                   const int* done);
+int launch_diag_prec(hd_ctx* c, int prec, const void* r, void* z, double* part);
+int launch_schur_prec(hd_ctx* c, int prec, const void* b, void* z, double* part, const int* done);
+int precond_partials(const hd_ctx* c);
+void free_levels(hd_ctx* c);
+Geo geo_of(const hd_ctx* c);
+int scan_counts(hd_ctx* c, const int32_t* cnt, int64_t n, int32_t* rp, int64_t* total_host);
+
+// minres.hip
+int minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, double* x, hd_solve_info& info);
+
+// reductions (setup.hip)
+int reduce_sum_partials(hd_ctx* c, const double* partial, int64_t n, double* out_dev);
+
+}  // namespace hd

@@ -1,0 +1,306 @@
+"""Thin ctypes binding of libhdivsp (include/hdivsp.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device buffers are torch tensors on the context's device; the context is
+bound to torch's current HIP stream unless another stream is given.  If the
+library is missing or cannot be loaded this module raises, it never falls
+back to another implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libhdivsp.so')
+
+HD_OK = 0
+HD_ERR_ARG, HD_ERR_MESH, HD_ERR_HIP, HD_ERR_OOM, HD_ERR_AMG = -1, -2, -3, -4, -5
+HD_ERR_BREAKDOWN, HD_ERR_NONFINITE, HD_ERR_STATE = -6, -7, -8
+HD_NOT_CONVERGED, HD_FALLBACK_USED = 1, 2
+HD_GRADDIV, HD_DARCY = 0, 1
+HD_F64, HD_F32 = 0, 1
+HD_MODE_PLAIN64, HD_MODE_MIXED, HD_MODE_PREC32 = 0, 1, 2
+HD_SIDE_ALL = 63
+
+EXPORTED = [
+    'hd_create', 'hd_destroy', 'hd_last_error', 'hd_setup_mesh', 'hd_setup_coeffs', 'hd_sizes',
+    'hd_apply_block_op', 'hd_apply_mass_inverse', 'hd_apply_l2_mass_inverse', 'hd_lift_essential',
+    'hd_build_precond', 'hd_apply_precond', 'hd_minres_solve', 'hd_get_diagonals', 'hd_get_schur',
+    'hd_get_amg_nlevels', 'hd_get_amg_level', 'hd_get_amg_prolongator', 'hd_apply_timing',
+    'hd_host_amg_build', 'hd_host_amg_nlevels', 'hd_host_amg_level', 'hd_host_amg_prolongator',
+    'hd_host_amg_free', 'hd_host_tables',
+]
+
+
+class HdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f'hdivsp error {code}: {msg}')
+        self.code = code
+
+
+class PrecondParams(ctypes.Structure):
+    _fields_ = [('tau', ctypes.c_double), ('theta', ctypes.c_double), ('max_coarse', ctypes.c_int),
+                ('max_levels', ctypes.c_int), ('omega', ctypes.c_double)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [('tol', ctypes.c_double), ('max_it', ctypes.c_int), ('mode', ctypes.c_int),
+                ('use_x0', ctypes.c_int), ('inner_tol', ctypes.c_double), ('max_outer', ctypes.c_int),
+                ('check_every', ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [('status', ctypes.c_int), ('iterations', ctypes.c_int), ('outer', ctypes.c_int),
+                ('eta_rel', ctypes.c_double), ('true_rel_res', ctypes.c_double), ('time_s', ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libhdivsp.so (torch is imported first so that the library binds
+    to the HIP runtime torch already loaded)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f'{LIB_PATH} is missing: build it with `python -m paper_2304_12387_amd.build`')
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    I64 = ctypes.c_int64
+    D = ctypes.c_double
+    pI64 = ctypes.POINTER(I64)
+    sigs = {
+        'hd_create': (I, [ctypes.POINTER(P), I, P]),
+        'hd_destroy': (I, [P]),
+        'hd_last_error': (ctypes.c_char_p, [P]),
+        'hd_setup_mesh': (I, [P, I, I, I, I, P]),
+        'hd_setup_coeffs': (I, [P, I, P, P, ctypes.c_uint32]),
+        'hd_sizes': (I, [P, pI64, pI64]),
+        'hd_apply_block_op': (I, [P, I, I, P, P]),
+        'hd_apply_mass_inverse': (I, [P, I, I, P, P]),
+        'hd_apply_l2_mass_inverse': (I, [P, I, P, P]),
+        'hd_lift_essential': (I, [P, P, P]),
+        'hd_build_precond': (I, [P, ctypes.POINTER(PrecondParams)]),
+        'hd_apply_precond': (I, [P, I, I, P, P]),
+        'hd_minres_solve': (I, [P, ctypes.POINTER(SolveParams), I, P, P, ctypes.POINTER(SolveInfo)]),
+        'hd_get_diagonals': (I, [P, P, P]),
+        'hd_get_schur': (I, [P, pI64, P, P, P]),
+        'hd_get_amg_nlevels': (I, [P, ctypes.POINTER(I)]),
+        'hd_get_amg_level': (I, [P, I, pI64, pI64, P, P, P]),
+        'hd_get_amg_prolongator': (I, [P, I, pI64, pI64, pI64, P, P, P]),
+        'hd_apply_timing': (I, [P, I, ctypes.POINTER(D), pI64]),
+        'hd_host_amg_build': (I, [I64, P, P, P, ctypes.POINTER(PrecondParams), I, ctypes.POINTER(P)]),
+        'hd_host_amg_nlevels': (I, [P]),
+        'hd_host_amg_level': (I, [P, I, pI64, pI64, P, P, P]),
+        'hd_host_amg_prolongator': (I, [P, I, pI64, pI64, pI64, P, P, P]),
+        'hd_host_amg_free': (I, [P]),
+        'hd_host_tables': (I, [I, P, P, P]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    """Device pointer of a torch tensor or host pointer of a numpy array."""
+    if a is None:
+        return None
+    if hasattr(a, 'data_ptr'):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def precond_params(tau=1.0, theta=0.25, max_coarse=1024, max_levels=25, omega=2.0 / 3.0):
+    return PrecondParams(tau, theta, max_coarse, max_levels, omega)
+
+
+def solve_params(tol=1e-8, max_it=10000, mode=HD_MODE_PLAIN64, use_x0=0, inner_tol=1e-5, max_outer=20,
+                 check_every=8):
+    return SolveParams(tol, max_it, mode, use_x0, inner_tol, max_outer, check_every)
+
+
+class Context:
+    """An hd_ctx bound to one device and one HIP stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        self.device = torch.device('cuda', device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.hd_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise HdError(rc, 'hd_create failed')
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.hd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != 0 and rc not in allow:
+            raise HdError(rc, self.lib.hd_last_error(self.h).decode())
+        return rc
+
+    # ---- setup ------------------------------------------------------------
+    def setup_mesh(self, nx, ny, nz, p, vertices):
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        return self._check(self.lib.hd_setup_mesh(self.h, nx, ny, nz, p, _ptr(v)))
+
+    def setup_coeffs(self, problem, c_mass, c_22=None, ess_sides=0):
+        cm = np.ascontiguousarray(c_mass, dtype=np.float64)
+        c2 = None if c_22 is None else np.ascontiguousarray(c_22, dtype=np.float64)
+        return self._check(self.lib.hd_setup_coeffs(self.h, problem, _ptr(cm), _ptr(c2), ess_sides))
+
+    def sizes(self):
+        nu, nq = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.hd_sizes(self.h, ctypes.byref(nu), ctypes.byref(nq)))
+        return nu.value, nq.value
+
+    # ---- operator ---------------------------------------------------------
+    def apply_block_op(self, x, y, prec=HD_F64, nrhs=1):
+        return self._check(self.lib.hd_apply_block_op(self.h, prec, nrhs, _ptr(x), _ptr(y)))
+
+    def apply_mass_inverse(self, x, y, prec=HD_F64, nrhs=1):
+        return self._check(self.lib.hd_apply_mass_inverse(self.h, prec, nrhs, _ptr(x), _ptr(y)))
+
+    def apply_l2_mass_inverse(self, x, y, prec=HD_F64):
+        return self._check(self.lib.hd_apply_l2_mass_inverse(self.h, prec, _ptr(x), _ptr(y)))
+
+    def lift_essential(self, u_bc, b):
+        return self._check(self.lib.hd_lift_essential(self.h, _ptr(u_bc), _ptr(b)))
+
+    # ---- preconditioner and solver -----------------------------------------
+    def build_precond(self, params=None):
+        pp = ctypes.byref(params) if params is not None else None
+        return self._check(self.lib.hd_build_precond(self.h, pp))
+
+    def apply_precond(self, r, z, prec=HD_F64, nrhs=1):
+        return self._check(self.lib.hd_apply_precond(self.h, prec, nrhs, _ptr(r), _ptr(z)))
+
+    def minres_solve(self, b, x, params=None, nrhs=1):
+        info = SolveInfo()
+        pp = ctypes.byref(params) if params is not None else None
+        rc = self.lib.hd_minres_solve(self.h, pp, nrhs, _ptr(b), _ptr(x), ctypes.byref(info))
+        self._check(rc, allow=(HD_NOT_CONVERGED,))
+        return info.as_dict()
+
+    # ---- inspection ---------------------------------------------------------
+    def get_diagonals(self):
+        torch = self.torch
+        nu, nq = self.sizes()
+        m = torch.empty(nu, dtype=torch.float64, device=self.device)
+        w = torch.empty(nq, dtype=torch.float64, device=self.device)
+        self._check(self.lib.hd_get_diagonals(self.h, _ptr(m), _ptr(w)))
+        return m, w
+
+    def get_schur(self):
+        nnz = ctypes.c_int64()
+        self._check(self.lib.hd_get_schur(self.h, ctypes.byref(nnz), None, None, None))
+        _, nq = self.sizes()
+        rp = np.empty(nq + 1, np.int32)
+        ci = np.empty(nnz.value, np.int32)
+        v = np.empty(nnz.value, np.float64)
+        self._check(self.lib.hd_get_schur(self.h, ctypes.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v)))
+        return rp, ci, v
+
+    def amg_nlevels(self):
+        n = ctypes.c_int()
+        self._check(self.lib.hd_get_amg_nlevels(self.h, ctypes.byref(n)))
+        return n.value
+
+    def get_amg_level(self, level):
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.hd_get_amg_level(self.h, level, ctypes.byref(n), ctypes.byref(nnz), None, None, None))
+        rp = np.empty(n.value + 1, np.int32)
+        ci = np.empty(nnz.value, np.int32)
+        v = np.empty(nnz.value, np.float64)
+        self._check(self.lib.hd_get_amg_level(self.h, level, ctypes.byref(n), ctypes.byref(nnz), _ptr(rp), _ptr(ci),
+                                              _ptr(v)))
+        return rp, ci, v
+
+    def get_amg_prolongator(self, level):
+        nr, nc, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.hd_get_amg_prolongator(self.h, level, ctypes.byref(nr), ctypes.byref(nc),
+                                                    ctypes.byref(nnz), None, None, None))
+        rp = np.empty(nr.value + 1, np.int32)
+        ci = np.empty(nnz.value, np.int32)
+        v = np.empty(nnz.value, np.float64)
+        self._check(self.lib.hd_get_amg_prolongator(self.h, level, ctypes.byref(nr), ctypes.byref(nc),
+                                                    ctypes.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v)))
+        return (nr.value, nc.value), rp, ci, v
+
+    def apply_timing(self, reset=False):
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.hd_apply_timing(self.h, 1 if reset else 0, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+
+# ---- host-only helpers (no device needed) -----------------------------------
+
+def host_tables(p):
+    lib = load()
+    gll = np.empty(p + 1)
+    x = np.empty(p + 1)
+    w = np.empty(p + 1)
+    rc = lib.hd_host_tables(p, _ptr(gll), _ptr(x), _ptr(w))
+    if rc:
+        raise HdError(rc, 'hd_host_tables')
+    return gll, x, w
+
+
+def host_amg(rowptr, col, val, singular=False, params=None):
+    """Build the library's AMG hierarchy on the host from a CSR matrix.
+    Returns (levels, prolongators) as lists of (shape, rowptr, col, val)."""
+    lib = load()
+    rp = np.ascontiguousarray(rowptr, np.int32)
+    ci = np.ascontiguousarray(col, np.int32)
+    v = np.ascontiguousarray(val, np.float64)
+    n = len(rp) - 1
+    h = ctypes.c_void_p()
+    pp = ctypes.byref(params) if params is not None else None
+    rc = lib.hd_host_amg_build(n, _ptr(rp), _ptr(ci), _ptr(v), pp, 1 if singular else 0, ctypes.byref(h))
+    if rc:
+        raise HdError(rc, 'hd_host_amg_build')
+    try:
+        levels, prolongs = [], []
+        for l in range(lib.hd_host_amg_nlevels(h)):
+            nn, nnz = ctypes.c_int64(), ctypes.c_int64()
+            lib.hd_host_amg_level(h, l, ctypes.byref(nn), ctypes.byref(nnz), None, None, None)
+            a = np.empty(nn.value + 1, np.int32)
+            b = np.empty(nnz.value, np.int32)
+            c = np.empty(nnz.value, np.float64)
+            lib.hd_host_amg_level(h, l, ctypes.byref(nn), ctypes.byref(nnz), _ptr(a), _ptr(b), _ptr(c))
+            levels.append(((nn.value, nn.value), a, b, c))
+        for l in range(len(levels) - 1):
+            nr, nc, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+            lib.hd_host_amg_prolongator(h, l, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(nnz), None, None, None)
+            a = np.empty(nr.value + 1, np.int32)
+            b = np.empty(nnz.value, np.int32)
+            c = np.empty(nnz.value, np.float64)
+            lib.hd_host_amg_prolongator(h, l, ctypes.byref(nr), ctypes.byref(nc), ctypes.byref(nnz), _ptr(a), _ptr(b),
+                                        _ptr(c))
+            prolongs.append(((nr.value, nc.value), a, b, c))
+        return levels, prolongs
+    finally:
+        lib.hd_host_amg_free(h)

@@ -1,0 +1,161 @@
+"""GPU parity of the preconditioner (AMG hierarchy, V-cycle) and of the
+MINRES solver against the oracle."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from gpu_helpers import gpu_context, make_case, oracle_problem, rel, to_dev, torch_cuda
+from oracle import assemble, manufactured, minres, precond
+from paper_2304_12387_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+PCASES = [
+    # (nx, ny, nz, p, problem, ess, gamma)
+    (4, 3, 3, 2, 0, 0, False),
+    (3, 3, 3, 3, 1, 0, True),
+    (4, 3, 3, 2, 1, 63, False),
+    (3, 4, 2, 2, 1, 0, False),
+]
+
+
+def _id(c):
+    return 'n%dx%dx%d_p%d_pb%d_ess%d%s' % (c[0], c[1], c[2], c[3], c[4], c[5], '_gamma' if c[6] else '')
+
+
+def _params(h, max_coarse):
+    return h.precond_params(max_coarse=max_coarse)
+
+
+@pytest.mark.parametrize("c", PCASES, ids=[_id(c) for c in PCASES])
+def test_amg_hierarchy_and_precond_apply(c):
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    print('case', _id(c), flush=True)
+    case = make_case(*c[:4], problem=c[4], ess=c[5], gamma=c[6])
+    prob = oracle_problem(case)
+    ctx = gpu_context(case, precond=True, params=_params(hdivsp, 40))
+    P = precond.BlockPreconditioner(prob, amg_kwargs=dict(max_coarse=40))
+    L = ctx.amg_nlevels()
+    assert L == P.amg.nlevels and L >= 2
+    for l in range(L):
+        rp, ci, v = ctx.get_amg_level(l)
+        A = sp.csr_matrix((v, ci, rp), shape=P.amg.A[l].shape)
+        assert abs((A - P.amg.A[l]).toarray()).max() <= 1e-12 * abs(P.amg.A[l]).max()
+    n = prob.mesh.n
+    r = np.random.default_rng(3).uniform(-1, 1, n)
+    if P.singular:
+        r[prob.mesh.n_u:] -= r[prob.mesh.n_u:].mean()
+    zr = P(r)
+    rd = to_dev(r)
+    zd = torch.empty_like(rd)
+    ctx.apply_precond(rd, zd)
+    torch.cuda.synchronize()
+    assert rel(zd.cpu().numpy(), zr) <= 1e-12
+    z32 = torch.empty_like(rd.float())
+    ctx.apply_precond(rd.float(), z32, prec=1)
+    torch.cuda.synchronize()
+    assert rel(z32.double().cpu().numpy(), zr) <= 1e-5
+    ctx.close()
+
+
+SCASES = [
+    (3, 3, 3, 2, 0, 0, False),
+    (3, 3, 2, 3, 0, 0, False),
+    (4, 3, 3, 2, 1, 0, True),
+    (3, 3, 3, 2, 0, 63, False),
+]
+
+
+@pytest.mark.parametrize("c", SCASES, ids=[_id(c) for c in SCASES])
+def test_minres_matches_oracle_and_direct_solve(c):
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    print('case', _id(c), flush=True)
+    case = make_case(*c[:4], problem=c[4], ess=c[5], gamma=c[6])
+    prob = oracle_problem(case)
+    ctx = gpu_context(case, precond=True, params=_params(hdivsp, 40))
+    b = inputs.graddiv_rhs(prob.mesh.n_u, prob.mesh.n_q, seed=5)
+    b[:prob.mesh.n_u][prob.ess] = 0.0
+    P = precond.BlockPreconditioner(prob, amg_kwargs=dict(max_coarse=40))
+    tol = 1e-12
+    xo, ito, _ = minres.minres(prob.apply, P, b, tol=tol)
+    bd = to_dev(b)
+    xd = torch.zeros_like(bd)
+    info = ctx.minres_solve(bd, xd, hdivsp.solve_params(tol=tol, max_it=2000))
+    x = xd.cpu().numpy()
+    print('iterations gpu', info['iterations'], 'oracle', ito, flush=True)
+    assert info['status'] == 0
+    assert abs(info['iterations'] - ito) <= 2
+    xdir = spla.spsolve(prob.block_matrix().tocsc(), b)
+    assert rel(x, xdir) <= 1e-8
+    assert info['true_rel_res'] <= 1e-9
+    ctx.close()
+
+
+def test_darcy_cube_4_manufactured():
+    """Darcy 4^3 Cartesian, p = 2, manufactured p = sin sin sin, MINRES to
+    1e-10: same iterations as the oracle (within 2), the solution of the
+    direct solve within 1e-8, and the same discretisation errors."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    cfg = inputs.darcy_cube_4()
+    m = assemble.Mesh(4, 4, 4, 2, cfg['vertices'])
+    prob = assemble.Problem(m, cfg['problem'], cfg['c_mass'], cfg['c_22'], cfg['ess_sides'])
+    b = manufactured.darcy_rhs(prob)
+    P = precond.BlockPreconditioner(prob)
+    xo, ito, _ = minres.minres(prob.apply, P, b, tol=cfg['tol'])
+    ctx = gpu_context(cfg, precond=True)
+    bd = to_dev(b)
+    xd = torch.zeros_like(bd)
+    info = ctx.minres_solve(bd, xd, hdivsp.solve_params(tol=cfg['tol']))
+    x = xd.cpu().numpy()
+    print('iterations gpu', info['iterations'], 'oracle', ito, flush=True)
+    assert info['status'] == 0 and abs(info['iterations'] - ito) <= 2
+    xdir = spla.spsolve(prob.block_matrix().tocsc(), b)
+    assert rel(x, xdir) <= 1e-8
+    e_gpu = manufactured.darcy_errors(prob, x)
+    e_dir = manufactured.darcy_errors(prob, xdir)
+    for k in e_gpu:
+        assert abs(e_gpu[k] - e_dir[k]) <= 1e-6 * e_dir[k]
+    ctx.close()
+
+
+def test_mixed_precision_refinement():
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    case = make_case(4, 4, 3, 3, problem=0)
+    prob = oracle_problem(case)
+    ctx = gpu_context(case, precond=True, params=_params(hdivsp, 40))
+    b = inputs.graddiv_rhs(prob.mesh.n_u, prob.mesh.n_q, seed=9)
+    bd = to_dev(b)
+    x64 = torch.zeros_like(bd)
+    i64 = ctx.minres_solve(bd, x64, hdivsp.solve_params(tol=1e-8))
+    xm = torch.zeros_like(bd)
+    im = ctx.minres_solve(bd, xm, hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_MIXED, inner_tol=1e-5))
+    print('plain', i64, 'mixed', im, flush=True)
+    assert i64['status'] == 0 and im['status'] == 0
+    assert im['true_rel_res'] <= 1e-8 and im['outer'] >= 1
+    A = prob.block_matrix()
+    xmn = xm.cpu().numpy()
+    assert np.linalg.norm(b - A @ xmn) <= 1e-8 * np.linalg.norm(b) * 1.0001
+    xdir = spla.spsolve(A.tocsc(), b)
+    assert rel(xmn, xdir) <= 1e-5
+    ctx.close()
+
+
+def test_lift_essential_matches_oracle():
+    torch = torch_cuda()
+    case = make_case(3, 3, 2, 2, problem=1, ess=63)
+    prob = oracle_problem(case)
+    ctx = gpu_context(case)
+    rng = np.random.default_rng(4)
+    ubc = rng.uniform(-1, 1, prob.mesh.n_u)
+    b = rng.uniform(-1, 1, prob.mesh.n)
+    ref = prob.lift_essential(b, ubc)
+    bd = to_dev(b)
+    ctx.lift_essential(to_dev(ubc), bd)
+    torch.cuda.synchronize()
+    assert rel(bd.cpu().numpy(), ref) <= 1e-12
+    ctx.close()
