@@ -103,7 +103,7 @@ def main():
     y32 = torch.empty_like(x32)
     b = torch.from_numpy(inputs.graddiv_rhs(nu, nq, 22)).to(dev)
     sol = torch.zeros_like(b)
-    p_plain = hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_PLAIN64)
+    p_plain = hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_PLAIN64, stop_true=1)
     p_mixed = hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_MIXED, inner_tol=1e-5)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)

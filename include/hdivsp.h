@@ -94,13 +94,19 @@ typedef struct hd_precond_params {
 } hd_precond_params;
 
 typedef struct hd_solve_params {
-    double tol;          /* relative tolerance (see mode); default 1e-8 */
+    double tol;          /* relative tolerance (see mode and stop_true); default 1e-8.
+                            HD_MODE_MIXED always stops on the true FP64 residual */
     int max_it;          /* max MINRES iterations (inner, per refinement); default 10000 */
     int mode;            /* HD_MODE_* */
     int use_x0;          /* 1: x holds the initial guess; 0: start from zero */
     double inner_tol;    /* HD_MODE_MIXED: inner FP32 tolerance; default 1e-5 */
     int max_outer;       /* HD_MODE_MIXED: max refinement steps; default 20 */
     int check_every;     /* iterations between host polls of the flag; default 8 */
+    int stop_true;       /* HD_MODE_PLAIN64: 0 stops when |eta| <= tol |eta_0| (the
+                            preconditioned residual norm carried by the
+                            recurrence); 1 also requires the true FP64
+                            ||b - A x||_2 <= tol ||b||_2, tightening the
+                            threshold and continuing the same recurrence */
 } hd_solve_params;
 
 typedef struct hd_solve_info {

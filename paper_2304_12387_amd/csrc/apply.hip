@@ -18,7 +18,7 @@
 // in LDS.  Element-interior RT dofs are written with plain stores; dofs on a
 // face shared with a neighbour element receive exactly two atomic additions
 // onto a zero-initialised value, which is order-independent (a + b = b + a).
-#include "kernels_common.hpp"
+#include "pencil.hpp"
 
 #include <type_traits>
 
@@ -26,260 +26,347 @@ namespace hd {
 
 namespace {
 
-constexpr int TEAM = 64;
-
-// Load the tables of degree P compactly into LDS.
-template <int P, typename T>
-__device__ void load_tables(const Tables<T>* __restrict__ tab, T* sL, T* sH, T* sBg, T* sBg2, T* sTi, int tid) {
-    constexpr int Q = P + 1;
-    for (int i = tid; i < Q * (P + 1); i += TEAM) sL[i] = tab->L[i / (P + 1)][i % (P + 1)];
-    for (int i = tid; i < Q * P; i += TEAM) {
-        sH[i] = tab->H[i / P][i % P];
-        sBg[i] = tab->Bg[i / P][i % P];
-        sBg2[i] = tab->Bg2[i / P][i % P];
-    }
-    for (int i = tid; i < P * P; i += TEAM) sTi[i] = tab->Tinv[i / P][i % P];
-}
-
-// y = M u for one component on the element: interpolate to the quadrature
-// points (3 stages), the caller applies G, then transpose back (3 stages).
-template <int P, typename T, int C>
-__device__ void interp_to_quad(const T* u, T* U, T* b1, T* b2, const T* sL, const T* sH, int tid) {
-    constexpr int Q = P + 1;
-    constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
-    const T* B0 = C == 0 ? sL : sH;
-    const T* B1 = C == 1 ? sL : sH;
-    const T* B2 = C == 2 ? sL : sH;
-    constexpr int L0 = C == 0 ? P + 1 : P, L1 = C == 1 ? P + 1 : P, L2 = C == 2 ? P + 1 : P;
-    contract<T, N0, N1, N2, 0, Q, false, L0>(u, b1, B0, tid, TEAM);
-    team_sync();
-    contract<T, Q, N1, N2, 1, Q, false, L1>(b1, b2, B1, tid, TEAM);
-    team_sync();
-    contract<T, Q, Q, N2, 2, Q, false, L2>(b2, U, B2, tid, TEAM);
-}
-
-template <int P, typename T, int C>
-__device__ void quad_to_dofs(const T* U, T* y, T* b1, T* b2, const T* sL, const T* sH, int tid) {
-    constexpr int Q = P + 1;
-    constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
-    const T* B0 = C == 0 ? sL : sH;
-    const T* B1 = C == 1 ? sL : sH;
-    const T* B2 = C == 2 ? sL : sH;
-    constexpr int L0 = C == 0 ? P + 1 : P, L1 = C == 1 ? P + 1 : P, L2 = C == 2 ? P + 1 : P;
-    contract<T, Q, Q, Q, 2, N2, true, L2>(U, b1, B2, tid, TEAM);
-    team_sync();
-    contract<T, Q, Q, N2, 1, N1, true, L1>(b1, b2, B1, tid, TEAM);
-    team_sync();
-    contract<T, Q, N1, N2, 0, N0, true, L0>(b2, y, B0, tid, TEAM);
-}
-
-// Solve W_e x = rhs (unweighted element L2 mass, IH basis) in place in
-// `sol`, given the quadrature weights gw = w/detJ at the Q^3 points (LDS).
-// Returns nothing; `sol` receives the solution in the IH basis.
-template <int P, typename T>
-__device__ void local_cg(const T* rhs, T* sol, const T* gw, T* r, T* z, T* pv, T* dW, T* b1, T* b2, T* b3,
-                         const T* sBg, const T* sBg2, const T* sTi, int tid, T tol, int maxit) {
-    constexpr int Q = P + 1;
-    constexpr int NL = P * P * P;
-    constexpr int PER = (NL + TEAM - 1) / TEAM;
-    // r = T^{-T} rhs  (Bm(o=m, k=j) = Ti[j][m])
-    contract<T, P, P, P, 0, P, true, P>(rhs, b1, sTi, tid, TEAM);
-    team_sync();
-    contract<T, P, P, P, 1, P, true, P>(b1, b2, sTi, tid, TEAM);
-    team_sync();
-    contract<T, P, P, P, 2, P, true, P>(b2, r, sTi, tid, TEAM);
-    // Jacobi diagonal of the Gauss-Legendre mass: (Bg^2)^T (x) (Bg^2)^T (x) (Bg^2)^T gw
-    contract<T, Q, Q, Q, 0, P, true, P>(gw, b3, sBg2, tid, TEAM);
-    team_sync();
-    contract<T, P, Q, Q, 1, P, true, P>(b3, b1, sBg2, tid, TEAM);
-    team_sync();
-    contract<T, P, P, Q, 2, P, true, P>(b1, dW, sBg2, tid, TEAM);
-    team_sync();
-    // x = 0, z = r / d, p = z
-    T rz = 0, rr0 = 0;
-    for (int l = tid; l < NL; l += TEAM) {
-        T zz = r[l] / dW[l];
-        z[l] = zz;
-        pv[l] = zz;
-        sol[l] = 0;
-        rz += r[l] * zz;
-    }
-    rz = wave_sum(rz);
-    rr0 = rz;
-    (void)PER;
-    if (rr0 == T(0)) {
-        team_sync();
-    } else {
-        for (int it = 0; it < maxit; ++it) {
-            team_sync();
-            // Ap = Bg^T diag(gw) Bg p
-            contract<T, P, P, P, 0, Q, false, P>(pv, b1, sBg, tid, TEAM);
-            team_sync();
-            contract<T, Q, P, P, 1, Q, false, P>(b1, b2, sBg, tid, TEAM);
-            team_sync();
-            contract<T, Q, Q, P, 2, Q, false, P>(b2, b3, sBg, tid, TEAM);
-            team_sync();
-            for (int qd = tid; qd < Q * Q * Q; qd += TEAM) b3[qd] *= gw[qd];
-            team_sync();
-            contract<T, Q, Q, Q, 2, P, true, P>(b3, b1, sBg, tid, TEAM);
-            team_sync();
-            contract<T, Q, Q, P, 1, P, true, P>(b1, b2, sBg, tid, TEAM);
-            team_sync();
-            contract<T, Q, P, P, 0, P, true, P>(b2, b1, sBg, tid, TEAM);   // b1 = A p
-            team_sync();
-            T pAp = 0;
-            for (int l = tid; l < NL; l += TEAM) pAp += pv[l] * b1[l];
-            pAp = wave_sum(pAp);
-            const T alpha = rz / pAp;
-            T rz_new = 0;
-            for (int l = tid; l < NL; l += TEAM) {
-                sol[l] += alpha * pv[l];
-                T rl = r[l] - alpha * b1[l];
-                r[l] = rl;
-                T zl = rl / dW[l];
-                z[l] = zl;
-                rz_new += rl * zl;
-            }
-            rz_new = wave_sum(rz_new);
-            if (rz_new <= tol * tol * rr0) break;
-            const T beta = rz_new / rz;
-            rz = rz_new;
-            for (int l = tid; l < NL; l += TEAM) pv[l] = z[l] + beta * pv[l];
-        }
-        team_sync();
-    }
-    // sol <- T^{-1} sol  (Bm(o=j, k=m) = Ti[j][m])
-    contract<T, P, P, P, 0, P, false, P>(sol, b1, sTi, tid, TEAM);
-    team_sync();
-    contract<T, P, P, P, 1, P, false, P>(b1, b2, sTi, tid, TEAM);
-    team_sync();
-    contract<T, P, P, P, 2, P, false, P>(b2, sol, sTi, tid, TEAM);
-    team_sync();
-}
-
 template <typename T>
 struct CGParams {
     T tol;
     int maxit;
 };
 
+// Lanes per element: the largest pencil count of any stage is (p+1)^2; a
+// wavefront holds 64 / W elements.
+template <int P>
+struct Slot {
+    static constexpr int Q = P + 1;
+    static constexpr int W = Q * Q <= 16 ? 16 : (Q * Q <= 32 ? 32 : 64);
+    static constexpr int EPW = 64 / W;
+};
+
 template <int P, typename T>
-__global__ __launch_bounds__(TEAM) void block_apply_kernel(
-    Geo g, const T* __restrict__ pa, const Tables<T>* __restrict__ tab, const T* __restrict__ cm,
-    const T* __restrict__ kap, uint32_t ess, int ess_mode, int64_t n_u, const T* __restrict__ x,
-    T* __restrict__ y, const double* __restrict__ in_scale, double* __restrict__ dot_partial,
-    const int* __restrict__ done, CGParams<T> cgp, int with_c) {
-    if (done && *done) return;
-    using D = Dim<P>;
-    constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC, NRT = D::NRT;
-    __shared__ T sL[Q * (P + 1)], sH[Q * P], sBg[Q * P], sBg2[Q * P], sTi[P * P];
-    __shared__ T su[NRT], sq[NL], syu[NRT], syq[NL];
-    __shared__ T sU[3 * Q3], b1[Q3], b2[Q3], b3[Q3], gw[Q3];
-    __shared__ T cr[NL], cz[NL], cp[NL], cd[NL], csol[NL];
-    const int tid = threadIdx.x;
-    const int64_t e = blockIdx.x;
-    const int ex = (int)(e % g.nx), ey = (int)((e / g.nx) % g.ny), ez = (int)(e / ((int64_t)g.nx * g.ny));
-    load_tables<P, T>(tab, sL, sH, sBg, sBg2, sTi, tid);
-    const T s_in = in_scale ? (T)(*in_scale) : T(1);
-    const T cM = cm[e];
-    const T kE = kap[e];
-    // gather u (essential dofs read as zero), q~
-    for (int l = tid; l < NRT; l += TEAM) {
-        int c = l / NC, ll = l % NC, i, j, k, onf, bs;
-        local_ijk<P>(c, ll, i, j, k);
-        int64_t gidx = rt_global<P>(g, c, ex, ey, ez, i, j, k, onf, bs);
-        bool is_ess = ess_mode == ESS_IDENTITY && bs >= 0 && (ess >> (2 * c + bs)) & 1u;
-        su[l] = is_ess ? T(0) : s_in * x[gidx];
-    }
-    for (int l = tid; l < NL; l += TEAM) sq[l] = s_in * x[n_u + e * NL + l];
-    const T* pe = pa + (size_t)e * NPA * Q3;
-    for (int qd = tid; qd < Q3; qd += TEAM) gw[qd] = pe[6 * Q3 + qd];
-    team_sync();
+struct ElemLDS {
+    T su[Dim<P>::NRT];   // gathered RT coefficients (scaled, essential dofs zeroed)
+    T sq[Dim<P>::NL];    // gathered L2 coefficients
+    T syq[Dim<P>::NL];   // L2 output
+    T A1[Dim<P>::Q3];    // stage buffers
+    T A2[Dim<P>::Q3];
+};
 
-    // ---- M u: interpolate the three components to the quadrature points
-    interp_to_quad<P, T, 0>(su, sU, b1, b2, sL, sH, tid);
-    team_sync();
-    interp_to_quad<P, T, 1>(su + NC, sU + Q3, b1, b2, sL, sH, tid);
-    team_sync();
-    interp_to_quad<P, T, 2>(su + 2 * NC, sU + 2 * Q3, b1, b2, sL, sH, tid);
-    team_sync();
-    for (int qd = tid; qd < Q3; qd += TEAM) {
-        const T g00 = pe[0 * Q3 + qd], g01 = pe[1 * Q3 + qd], g02 = pe[2 * Q3 + qd];
-        const T g11 = pe[3 * Q3 + qd], g12 = pe[4 * Q3 + qd], g22 = pe[5 * Q3 + qd];
-        const T a = sU[qd], b = sU[Q3 + qd], c = sU[2 * Q3 + qd];
-        sU[qd] = cM * (g00 * a + g01 * b + g02 * c);
-        sU[Q3 + qd] = cM * (g01 * a + g11 * b + g12 * c);
-        sU[2 * Q3 + qd] = cM * (g02 * a + g12 * b + g22 * c);
+// ---------------------------------------------------------------------------
+// Local preconditioned CG for W_e x = rhs (Section 2.5): runs in the
+// Gauss-Legendre nodal basis; vectors live in x-pencil registers of the slot
+// (lane t < P^2 holds the x-line (., j, k), t = j + P k).  The right-hand
+// side enters as sq (IH basis) in LDS; the IH-basis solution times -kappa is
+// added into syq.  gw: w / det J at the quadrature points held as z-pencils
+// (lane t < Q^2 holds (a, b, .), t = a + Q b).  Every slot iterates until its
+// own residual meets the tolerance; the wavefront loops while any slot has
+// not converged.
+// ---------------------------------------------------------------------------
+template <int P, typename T>
+__device__ void local_cg(ElemLDS<P, T>& L, const TabK<P, T>& tb, const T (&gw)[P + 1], int t, bool active, T kE,
+                         const CGParams<T>& cgp) {
+    constexpr int Q = P + 1;
+    constexpr int W = Slot<P>::W;
+    const T* Ti = &tb.Ti[0][0];
+    const T* Bg = &tb.Bg[0][0];
+    const T* Bg2 = &tb.Bg2[0][0];
+    T r[P], z[P], pv[P], x[P], dW[P], Ap[P];
+    // rhs in the GL nodal basis: T^{-T} sq, contracted z, y, then x
+    stage_lds<T, P, P, P, 2, P, P, true>(L.sq, L.A1, Ti, t);
+    __syncthreads();
+    stage_lds<T, P, P, P, 1, P, P, true>(L.A1, L.A2, Ti, t);
+    __syncthreads();
+    if (t < P * P) {
+        T in[P];
+        pencil_load<T, P, P, P, 0>(L.A2, t, in);
+        pencil_mul<T, P, P, P, true>(in, r, Ti);
     }
-    team_sync();
-    quad_to_dofs<P, T, 0>(sU, syu, b1, b2, sL, sH, tid);
-    team_sync();
-    quad_to_dofs<P, T, 1>(sU + Q3, syu + NC, b1, b2, sL, sH, tid);
-    team_sync();
-    quad_to_dofs<P, T, 2>(sU + 2 * Q3, syu + 2 * NC, b1, b2, sL, sH, tid);
-    team_sync();
-
-    // ---- D^T q~ into y_u and D u into y_q
-    for (int l = tid; l < NRT; l += TEAM) {
-        int c = l / NC, ll = l % NC, i, j, k;
-        local_ijk<P>(c, ll, i, j, k);
-        int t = c == 0 ? i : (c == 1 ? j : k);
-        int a = i, b = j, cc = k;
-        T add = 0;
-        // volume below the face (index t-1 along c) sees it as its upper face: +1
-        if (t >= 1) {
-            if (c == 0) a = i - 1; else if (c == 1) b = j - 1; else cc = k - 1;
-            add += sq[a + P * (b + P * cc)];
-            a = i; b = j; cc = k;
+    __syncthreads();
+    // Jacobi diagonal of the GL mass: (Bg^2)^T applied to gw in z, y, x
+    if (t < Q * Q) {
+        T o[P];
+        pencil_mul<T, Q, P, P, true>(gw, o, Bg2);
+        pencil_store<T, Q, Q, Q, 2, P>(L.A1, t, o);
+    }
+    __syncthreads();
+    stage_lds<T, Q, Q, P, 1, P, P, true>(L.A1, L.A2, Bg2, t);
+    __syncthreads();
+    T rz = 0;
+    if (t < P * P) {
+        T in[Q];
+        pencil_load<T, Q, P, P, 0>(L.A2, t, in);
+        pencil_mul<T, Q, P, P, true>(in, dW, Bg2);
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+            z[s] = r[s] / dW[s];
+            pv[s] = z[s];
+            x[s] = 0;
+            rz += r[s] * z[s];
         }
-        if (t <= P - 1) add -= sq[a + P * (b + P * cc)];
-        syu[l] += add;
+    } else {
+#pragma unroll
+        for (int s = 0; s < P; ++s) r[s] = z[s] = pv[s] = x[s] = dW[s] = T(0);
     }
-    for (int l = tid; l < NL; l += TEAM) {
-        int a = l % P, b = (l / P) % P, c = l / (P * P);
-        // x-face (i, b, c) has local index i + (P+1)(b + P c)
-        T v = su[(a + 1) + (P + 1) * (b + P * c)] - su[a + (P + 1) * (b + P * c)];
-        // y-face (a, j, c): a + P (j + (P+1) c)
-        v += su[NC + a + P * ((b + 1) + (P + 1) * c)] - su[NC + a + P * (b + (P + 1) * c)];
-        // z-face (a, b, k): a + P (b + P k)
-        v += su[2 * NC + a + P * (b + P * (c + 1))] - su[2 * NC + a + P * (b + P * c)];
-        syq[l] = v;
+    rz = slot_sum<T, W>(rz);
+    const T rr0 = rz;
+    bool done = !active || !(rr0 > T(0));
+    for (int it = 0; it < cgp.maxit; ++it) {
+        if (__all(done)) break;
+        __syncthreads();
+        // Ap = Bg^T diag(gw) Bg p : x (regs) -> y (LDS) -> z (regs), scale,
+        // z^T (regs) -> y^T (LDS) -> x^T (regs)
+        if (t < P * P) {
+            T o[Q];
+            pencil_mul<T, P, Q, P, false>(pv, o, Bg);
+            pencil_store<T, P, P, P, 0, Q>(L.A1, t, o);
+        }
+        __syncthreads();
+        stage_lds<T, Q, P, P, 1, Q, P, false>(L.A1, L.A2, Bg, t);
+        __syncthreads();
+        if (t < Q * Q) {
+            T in[P], w[Q], o[P];
+            pencil_load<T, Q, Q, P, 2>(L.A2, t, in);
+            pencil_mul<T, P, Q, P, false>(in, w, Bg);
+#pragma unroll
+            for (int c = 0; c < Q; ++c) w[c] *= gw[c];
+            pencil_mul<T, Q, P, P, true>(w, o, Bg);
+            pencil_store<T, Q, Q, Q, 2, P>(L.A1, t, o);
+        }
+        __syncthreads();
+        stage_lds<T, Q, Q, P, 1, P, P, true>(L.A1, L.A2, Bg, t);
+        __syncthreads();
+        T pAp = 0;
+        if (t < P * P) {
+            T in[Q];
+            pencil_load<T, Q, P, P, 0>(L.A2, t, in);
+            pencil_mul<T, Q, P, P, true>(in, Ap, Bg);
+#pragma unroll
+            for (int s = 0; s < P; ++s) pAp += pv[s] * Ap[s];
+        }
+        pAp = slot_sum<T, W>(pAp);
+        T rzn = 0;
+        const T alpha = rz / pAp;
+        if (!done && t < P * P) {
+#pragma unroll
+            for (int s = 0; s < P; ++s) {
+                x[s] += alpha * pv[s];
+                r[s] -= alpha * Ap[s];
+                z[s] = r[s] / dW[s];
+                rzn += r[s] * z[s];
+            }
+        }
+        rzn = slot_sum<T, W>(rzn);
+        if (!done) {
+            if (rzn <= cgp.tol * cgp.tol * rr0) {
+                done = true;
+            } else {
+                const T beta = rzn / rz;
+                rz = rzn;
+#pragma unroll
+                for (int s = 0; s < P; ++s) pv[s] = z[s] + beta * pv[s];
+            }
+        }
     }
-    team_sync();
+    __syncthreads();
+    // IH-basis solution T^{-1} x: x (regs) -> y (LDS) -> z, syq -= kappa * sol
+    if (t < P * P) {
+        T o[P];
+        pencil_mul<T, P, P, P, false>(x, o, Ti);
+        pencil_store<T, P, P, P, 0, P>(L.A1, t, o);
+    }
+    __syncthreads();
+    stage_lds<T, P, P, P, 1, P, P, false>(L.A1, L.A2, Ti, t);
+    __syncthreads();
+    if (t < P * P && active) {
+        T in[P], o[P];
+        pencil_load<T, P, P, P, 2>(L.A2, t, in);
+        pencil_mul<T, P, P, P, false>(in, o, Ti);
+        using G = PencilGeom<P, P, P, 2>;
+        const int b = G::base(t);
+#pragma unroll
+        for (int s = 0; s < P; ++s) L.syq[b + s * G::STRIDE] -= kE * o[s];
+    }
+    __syncthreads();
+}
 
-    // ---- -kappa_e W_e^{-1} q~
-    if (with_c && kE != T(0)) {
-        local_cg<P, T>(sq, csol, gw, cr, cz, cp, cd, b1, b2, b3, sBg, sBg2, sTi, tid, cgp.tol, cgp.maxit);
-        for (int l = tid; l < NL; l += TEAM) syq[l] -= kE * csol[l];
-        team_sync();
+// Forward sum factorisation of RT component C (shape N0,N1,N2) to the
+// quadrature points: x and y through LDS, z into registers (z-pencil of the
+// quadrature point column (a, b, .) for lane t = a + Q b).
+template <int P, typename T, int C>
+__device__ __forceinline__ void rt_to_quad(ElemLDS<P, T>& L, const TabK<P, T>& tb, int t, T (&U)[P + 1]) {
+    constexpr int Q = P + 1, NC = Dim<P>::NC;
+    constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
+    const T* B0 = C == 0 ? &tb.L[0][0] : &tb.H[0][0];
+    const T* B1 = C == 1 ? &tb.L[0][0] : &tb.H[0][0];
+    const T* B2 = C == 2 ? &tb.L[0][0] : &tb.H[0][0];
+    stage_lds<T, N0, N1, N2, 0, Q, N0, false>(L.su + C * NC, L.A1, B0, t);
+    __syncthreads();
+    stage_lds<T, Q, N1, N2, 1, Q, N1, false>(L.A1, L.A2, B1, t);
+    __syncthreads();
+    if (t < Q * Q) {
+        T in[N2];
+        pencil_load<T, Q, Q, N2, 2>(L.A2, t, in);
+        pencil_mul<T, N2, Q, N2, false>(in, U, B2);
     }
+    __syncthreads();
+}
 
-    // ---- scatter, and the local contribution to <y, x_scaled>
+// Transpose of rt_to_quad for component C: from z-pencil registers V to
+// x-pencil registers y (lane t = j + N1 k holds (., j, k), N0 values).
+template <int P, typename T, int C>
+__device__ __forceinline__ void quad_to_rt(ElemLDS<P, T>& L, const TabK<P, T>& tb, int t, const T (&V)[P + 1],
+                                           T (&y)[P + 1]) {
+    constexpr int Q = P + 1;
+    constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
+    const T* B0 = C == 0 ? &tb.L[0][0] : &tb.H[0][0];
+    const T* B1 = C == 1 ? &tb.L[0][0] : &tb.H[0][0];
+    const T* B2 = C == 2 ? &tb.L[0][0] : &tb.H[0][0];
+    if (t < Q * Q) {
+        T o[N2];
+        pencil_mul<T, Q, N2, N2, true>(V, o, B2);
+        pencil_store<T, Q, Q, Q, 2, N2>(L.A2, t, o);
+    }
+    __syncthreads();
+    stage_lds<T, Q, Q, N2, 1, N1, N1, true>(L.A2, L.A1, B1, t);
+    __syncthreads();
+    if (t < N1 * N2) {
+        T in[Q], o[N0];
+        pencil_load<T, Q, N1, N2, 0>(L.A1, t, in);
+        pencil_mul<T, Q, N0, N0, true>(in, o, B0);
+#pragma unroll
+        for (int s = 0; s < N0; ++s) y[s] = o[s];
+    }
+    __syncthreads();
+}
+
+// D^T q~ added to the x-pencil of component C, then scatter to y and the
+// local contribution to <y, x_scaled>.
+template <int P, typename T, int C>
+__device__ __forceinline__ double finish_rt(ElemLDS<P, T>& L, const Geo& g, int ex, int ey, int ez, int t,
+                                            T (&yv)[P + 1], uint32_t ess, int ess_mode, T s_in,
+                                            const T* __restrict__ x, T* __restrict__ y) {
+    constexpr int NC = Dim<P>::NC;
+    constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
     double dot = 0.0;
-    for (int l = tid; l < NRT; l += TEAM) {
-        int c = l / NC, ll = l % NC, i, j, k, onf, bs;
-        local_ijk<P>(c, ll, i, j, k);
-        int64_t gidx = rt_global<P>(g, c, ex, ey, ez, i, j, k, onf, bs);
-        bool is_ess = ess_mode == ESS_IDENTITY && bs >= 0 && (ess >> (2 * c + bs)) & 1u;
+    if (t >= N1 * N2) return dot;
+    const int j = t % N1, k = t / N1;
+#pragma unroll
+    for (int i = 0; i < N0; ++i) {
+        const int tn = C == 0 ? i : (C == 1 ? j : k);   // index along the normal
+        int a = i, b = j, c = k;
+        T add = 0;
+        if (tn >= 1) {
+            if (C == 0) a = i - 1; else if (C == 1) b = j - 1; else c = k - 1;
+            add += L.sq[a + P * (b + P * c)];
+        }
+        if (tn <= P - 1) add -= L.sq[i + P * (j + P * k)];
+        int onf, bs;
+        const int64_t gidx = rt_global<P>(g, C, ex, ey, ez, i, j, k, onf, bs);
+        const bool is_ess = ess_mode == ESS_IDENTITY && bs >= 0 && ((ess >> (2 * C + bs)) & 1u);
+        const int l = C * NC + i + N0 * (j + N1 * k);
         if (is_ess) {
-            T xv = s_in * x[gidx];
+            const T xv = s_in * x[gidx];
             y[gidx] = xv;
             dot += (double)xv * (double)xv;
         } else {
-            T v = syu[l];
+            const T v = yv[i] + add;
             if (!onf || bs >= 0) y[gidx] = v;
             else atomicAdd(&y[gidx], v);
-            dot += (double)v * (double)su[l];
+            dot += (double)v * (double)L.su[l];
         }
     }
-    for (int l = tid; l < NL; l += TEAM) {
-        T v = syq[l];
-        y[n_u + e * NL + l] = v;
-        dot += (double)v * (double)sq[l];
+    return dot;
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(64) void block_apply_kernel(
+    Geo g, const T* __restrict__ pa, TabK<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
+    int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ x, T* __restrict__ y,
+    const double* __restrict__ in_scale, double* __restrict__ dot_partial, const int* __restrict__ done,
+    CGParams<T> cgp, int with_c) {
+    if (done && *done) return;
+    using D = Dim<P>;
+    using S = Slot<P>;
+    constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC, NRT = D::NRT, W = S::W;
+    __shared__ ElemLDS<P, T> sm[S::EPW];
+    const int lane = threadIdx.x;
+    const int slot = lane / W, t = lane % W;
+    const int64_t e = (int64_t)blockIdx.x * S::EPW + slot;
+    const bool valid = e < ne;
+    const int64_t ee = valid ? e : ne - 1;   // clamp for address arithmetic only
+    ElemLDS<P, T>& L = sm[slot];
+    const int ex = (int)(ee % g.nx), ey = (int)((ee / g.nx) % g.ny), ez = (int)(ee / ((int64_t)g.nx * g.ny));
+    const T s_in = in_scale ? (T)(*in_scale) : T(1);
+    const T cM = cm[ee];
+    const T kE = kap[ee];
+    // gather u (essential dofs read as zero) and q~
+    if (valid) {
+        for (int l = t; l < NRT; l += W) {
+            const int c = l / NC, ll = l % NC;
+            int i, j, k, onf, bs;
+            local_ijk<P>(c, ll, i, j, k);
+            const int64_t gidx = rt_global<P>(g, c, ex, ey, ez, i, j, k, onf, bs);
+            const bool is_ess = ess_mode == ESS_IDENTITY && bs >= 0 && ((ess >> (2 * c + bs)) & 1u);
+            L.su[l] = is_ess ? T(0) : s_in * x[gidx];
+        }
+        for (int l = t; l < NL; l += W) L.sq[l] = s_in * x[n_u + ee * NL + l];
+    }
+    __syncthreads();
+    // D u (element-local, +1 upper face, -1 lower face)
+    if (valid) {
+        for (int l = t; l < NL; l += W) {
+            const int a = l % P, b = (l / P) % P, c = l / (P * P);
+            T v = L.su[(a + 1) + (P + 1) * (b + P * c)] - L.su[a + (P + 1) * (b + P * c)];
+            v += L.su[NC + a + P * ((b + 1) + (P + 1) * c)] - L.su[NC + a + P * (b + (P + 1) * c)];
+            v += L.su[2 * NC + a + P * (b + P * (c + 1))] - L.su[2 * NC + a + P * (b + P * c)];
+            L.syq[l] = v;
+        }
+    }
+    // M u: the three components to the quadrature points
+    T U0[Q], U1[Q], U2[Q];
+    rt_to_quad<P, T, 0>(L, tb, t, U0);
+    rt_to_quad<P, T, 1>(L, tb, t, U1);
+    rt_to_quad<P, T, 2>(L, tb, t, U2);
+    // geometric factors (c_mass w J^T J / det J) at the quadrature column (a, b, .)
+    T gw[Q];
+    const T* pe = pa + (size_t)ee * NPA * Q3;
+    if (t < Q * Q) {
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const int qd = t + Q * Q * c;
+            const T g00 = pe[0 * Q3 + qd], g01 = pe[1 * Q3 + qd], g02 = pe[2 * Q3 + qd];
+            const T g11 = pe[3 * Q3 + qd], g12 = pe[4 * Q3 + qd], g22 = pe[5 * Q3 + qd];
+            gw[c] = pe[6 * Q3 + qd];
+            const T a0 = U0[c], a1 = U1[c], a2 = U2[c];
+            U0[c] = cM * (g00 * a0 + g01 * a1 + g02 * a2);
+            U1[c] = cM * (g01 * a0 + g11 * a1 + g12 * a2);
+            U2[c] = cM * (g02 * a0 + g12 * a1 + g22 * a2);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < Q; ++c) gw[c] = T(1);
+    }
+    double dot = 0.0;
+    {
+        T yv[Q];
+        quad_to_rt<P, T, 0>(L, tb, t, U0, yv);
+        if (valid) dot += finish_rt<P, T, 0>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y);
+        quad_to_rt<P, T, 1>(L, tb, t, U1, yv);
+        if (valid) dot += finish_rt<P, T, 1>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y);
+        quad_to_rt<P, T, 2>(L, tb, t, U2, yv);
+        if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y);
+    }
+    // -kappa_e W_e^{-1} q~
+    if (with_c) local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
+    __syncthreads();
+    if (valid) {
+        for (int l = t; l < NL; l += W) {
+            const T v = L.syq[l];
+            y[n_u + ee * NL + l] = v;
+            dot += (double)v * (double)L.sq[l];
+        }
     }
     if (dot_partial) {
-        dot = wave_sum(dot);
-        if (tid == 0) dot_partial[e] = dot;
+        dot = slot_sum<double, 64>(dot);
+        if (lane == 0) dot_partial[blockIdx.x] = dot;
     }
 }
 
@@ -311,28 +398,45 @@ __global__ void zero_shared_faces(Geo g, int P, T* __restrict__ y, int64_t n_x, 
     }
 }
 
-// y_q = (weighted ? kappa_e : 1) W_e^{-1} x_q, one wavefront per element.
+// y_q = (weighted ? kappa_e : 1) W_e^{-1} x_q (same local CG).
 template <int P, typename T>
-__global__ __launch_bounds__(TEAM) void mass_inverse_kernel(const T* __restrict__ pa, const Tables<T>* __restrict__ tab,
-                                                            const T* __restrict__ kap, int weighted,
-                                                            const T* __restrict__ x, T* __restrict__ y,
-                                                            CGParams<T> cgp) {
+__global__ __launch_bounds__(64) void mass_inverse_kernel(const T* __restrict__ pa, TabK<P, T> tb,
+                                                          const T* __restrict__ kap, int weighted, int64_t ne,
+                                                          const T* __restrict__ x, T* __restrict__ y,
+                                                          CGParams<T> cgp) {
     using D = Dim<P>;
-    constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL;
-    __shared__ T sL[Q * (P + 1)], sH[Q * P], sBg[Q * P], sBg2[Q * P], sTi[P * P];
-    __shared__ T sq[NL], b1[Q3], b2[Q3], b3[Q3], gw[Q3];
-    __shared__ T cr[NL], cz[NL], cp[NL], cd[NL], csol[NL];
-    const int tid = threadIdx.x;
-    const int64_t e = blockIdx.x;
-    load_tables<P, T>(tab, sL, sH, sBg, sBg2, sTi, tid);
-    const T* pe = pa + (size_t)e * NPA * Q3;
-    for (int qd = tid; qd < Q3; qd += TEAM) gw[qd] = pe[6 * Q3 + qd];
-    for (int l = tid; l < NL; l += TEAM) sq[l] = x[e * NL + l];
-    team_sync();
-    local_cg<P, T>(sq, csol, gw, cr, cz, cp, cd, b1, b2, b3, sBg, sBg2, sTi, tid, cgp.tol, cgp.maxit);
-    const T s = weighted ? kap[e] : T(1);
-    for (int l = tid; l < NL; l += TEAM) y[e * NL + l] = s * csol[l];
+    using S = Slot<P>;
+    constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, W = S::W;
+    __shared__ ElemLDS<P, T> sm[S::EPW];
+    const int lane = threadIdx.x;
+    const int slot = lane / W, t = lane % W;
+    const int64_t e = (int64_t)blockIdx.x * S::EPW + slot;
+    const bool valid = e < ne;
+    const int64_t ee = valid ? e : ne - 1;
+    ElemLDS<P, T>& L = sm[slot];
+    if (valid)
+        for (int l = t; l < NL; l += W) {
+            L.sq[l] = x[ee * NL + l];
+            L.syq[l] = T(0);
+        }
+    T gw[Q];
+    const T* pe = pa + (size_t)ee * NPA * Q3;
+#pragma unroll
+    for (int c = 0; c < Q; ++c) gw[c] = t < Q * Q ? pe[6 * Q3 + t + Q * Q * c] : T(1);
+    __syncthreads();
+    // syq = -(1) * W^{-1} sq  -> negate on output
+    local_cg<P, T>(L, tb, gw, t, valid, T(1), cgp);
+    const T s = weighted ? kap[ee] : T(1);
+    if (valid)
+        for (int l = t; l < NL; l += W) y[ee * NL + l] = -s * L.syq[l];
 }
+
+template <typename T>
+const Tables<T>& host_tables(const hd_ctx* c);
+template <>
+const Tables<double>& host_tables<double>(const hd_ctx* c) { return c->tab64_host; }
+template <>
+const Tables<float>& host_tables<float>(const hd_ctx* c) { return c->tab32_host; }
 
 template <typename T>
 CGParams<T> cg_params();
@@ -355,21 +459,23 @@ void launch_apply_p(hd_ctx* c, const T* x, T* y, const double* in_scale, double*
                            y, nsx, nsy, nsz);
     }
     const T* pa = std::is_same<T, double>::value ? (const T*)c->d_pa : (const T*)c->d_pa32;
-    const Tables<T>* tab = std::is_same<T, double>::value ? (const Tables<T>*)c->d_tab64 : (const Tables<T>*)c->d_tab32;
     const T* cm = std::is_same<T, double>::value ? (const T*)c->d_cm : (const T*)c->d_cm32;
     const T* kap = std::is_same<T, double>::value ? (const T*)c->d_kap : (const T*)c->d_kap32;
-    hipLaunchKernelGGL((block_apply_kernel<P, T>), dim3((unsigned)c->ne), dim3(TEAM), 0, c->stream, g, pa, tab, cm,
-                       kap, c->ess, ess_mode, c->n_u, x, y, in_scale, dot_partial, done, cg_params<T>(),
+    const TabK<P, T> tb = make_tabk<P, T>(host_tables<T>(c));
+    const unsigned nb = (unsigned)((c->ne + Slot<P>::EPW - 1) / Slot<P>::EPW);
+    hipLaunchKernelGGL((block_apply_kernel<P, T>), dim3(nb), dim3(64), 0, c->stream, g, pa, tb, cm, kap, c->ess,
+                       ess_mode, c->ne, c->n_u, x, y, in_scale, dot_partial, done, cg_params<T>(),
                        c->kappa_zero ? 0 : 1);
 }
 
 template <int P, typename T>
 void launch_minv_p(hd_ctx* c, const T* x, T* y, bool weighted) {
     const T* pa = std::is_same<T, double>::value ? (const T*)c->d_pa : (const T*)c->d_pa32;
-    const Tables<T>* tab = std::is_same<T, double>::value ? (const Tables<T>*)c->d_tab64 : (const Tables<T>*)c->d_tab32;
     const T* kap = std::is_same<T, double>::value ? (const T*)c->d_kap : (const T*)c->d_kap32;
-    hipLaunchKernelGGL((mass_inverse_kernel<P, T>), dim3((unsigned)c->ne), dim3(TEAM), 0, c->stream, pa, tab, kap,
-                       weighted ? 1 : 0, x, y, cg_params<T>());
+    const TabK<P, T> tb = make_tabk<P, T>(host_tables<T>(c));
+    const unsigned nb = (unsigned)((c->ne + Slot<P>::EPW - 1) / Slot<P>::EPW);
+    hipLaunchKernelGGL((mass_inverse_kernel<P, T>), dim3(nb), dim3(64), 0, c->stream, pa, tb, kap, weighted ? 1 : 0,
+                       c->ne, x, y, cg_params<T>());
 }
 
 template <typename T>
@@ -414,6 +520,19 @@ __global__ void lift_finish_kernel(Geo g, int P, uint32_t ess, int64_t n_u, int6
 }
 
 }  // namespace
+
+int64_t apply_partial_count(const hd_ctx* c) {
+    int epw = 1;
+    switch (c->p) {
+        case 1: epw = Slot<1>::EPW; break;
+        case 2: epw = Slot<2>::EPW; break;
+        case 3: epw = Slot<3>::EPW; break;
+        case 4: epw = Slot<4>::EPW; break;
+        case 5: epw = Slot<5>::EPW; break;
+        case 6: epw = Slot<6>::EPW; break;
+    }
+    return (c->ne + epw - 1) / epw;
+}
 
 int launch_lift(hd_ctx* c, const double* ubc, double* b) {
     const int64_t N = c->n_u + c->n_q;

@@ -154,8 +154,8 @@ int hd_setup_mesh(hd_ctx* c, int nx, int ny, int nz, int p, const double* vertic
     c->n_u = c->nface[0] + c->nface[1] + c->nface[2];
     c->n_q = c->ne * p * p * p;
     if (c->n_u + c->n_q > (int64_t)INT32_MAX) return set_err(c, HD_ERR_ARG, "problem too large for 32-bit indices");
-    Tables<double> t64;
-    Tables<float> t32;
+    Tables<double>& t64 = c->tab64_host;
+    Tables<float>& t32 = c->tab32_host;
     build_tables(p, t64, t32);
     if (!c->d_tab64) c->d_tab64 = dalloc<Tables<double>>(1);
     if (!c->d_tab32) c->d_tab32 = dalloc<Tables<float>>(1);
@@ -336,6 +336,7 @@ int hd_minres_solve(hd_ctx* c, const hd_solve_params* params, int nrhs, const do
         prm.inner_tol = 1e-5;
         prm.max_outer = 20;
         prm.check_every = 8;
+        prm.stop_true = 0;
     }
     if (!(prm.tol > 0) || prm.max_it < 1) return set_err(c, HD_ERR_ARG, "bad solve parameters");
     if (prm.mode == HD_MODE_MIXED && (!(prm.inner_tol > 0) || prm.max_outer < 1))

@@ -100,6 +100,8 @@ struct hd_ctx {
     float* d_pa32 = nullptr;
     hd::Tables<double>* d_tab64 = nullptr;
     hd::Tables<float>* d_tab32 = nullptr;
+    hd::Tables<double> tab64_host;
+    hd::Tables<float> tab32_host;
 
     // coefficients
     bool have_coeffs = false;
@@ -173,6 +175,7 @@ int launch_apply(hd_ctx* c, int prec, const void* x, void* y, const double* in_s
                  int ess_mode, const int* done);
 int launch_mass_inverse(hd_ctx* c, int prec, const void* x, void* y, bool weighted);
 int launch_lift(hd_ctx* c, const double* ubc, double* b);
+int64_t apply_partial_count(const hd_ctx* c);
 
 // precond.hip
 int upload_amg(hd_ctx* c);
@@ -180,7 +183,7 @@ int launch_precond(hd_ctx* c, int prec, const void* r, void* z, double* dot_part
                    const int* done);
 int launch_diag_prec(hd_ctx* c, int prec, const void* r, void* z, double* part);
 int launch_schur_prec(hd_ctx* c, int prec, const void* b, void* z, double* part, const int* done);
-int precond_partials(const hd_ctx* c);
+int64_t schur_partial_count(const hd_ctx* c);
 void free_levels(hd_ctx* c);
 Geo geo_of(const hd_ctx* c);
 int scan_counts(hd_ctx* c, const int32_t* cnt, int64_t n, int32_t* rp, int64_t* total_host);

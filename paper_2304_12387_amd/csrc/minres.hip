@@ -23,6 +23,7 @@
 // scalars, FP64 coarse solve).
 #include "kernels_common.hpp"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <type_traits>
@@ -249,6 +250,7 @@ struct Work {
     int prec = HD_F64;
     void *v = nullptr, *vo = nullptr, *z = nullptr, *zn = nullptr, *w = nullptr, *wo = nullptr, *q = nullptr;
     double *pd = nullptr, *pu = nullptr, *pq = nullptr;
+    int64_t nq_part = 0;
     MinresState* st = nullptr;
     MinresState* st_host = nullptr;
 };
@@ -279,7 +281,8 @@ int alloc_work(hd_ctx* c, Work& w, int prec) {
     }
     w.pd = dalloc<double>(c->ne);
     w.pu = dalloc<double>(nblk(w.N));
-    w.pq = dalloc<double>(nblk(c->n_q));
+    w.nq_part = schur_partial_count(c);
+    w.pq = dalloc<double>(std::max<int64_t>(w.nq_part, nblk(w.N)));
     w.st = dalloc<MinresState>(1);
     if (!w.pd || !w.pu || !w.pq || !w.st) return set_err(c, HD_ERR_OOM, "MINRES partials");
     if (hipHostMalloc((void**)&w.st_host, sizeof(MinresState)) != hipSuccess)
@@ -287,11 +290,22 @@ int alloc_work(hd_ctx* c, Work& w, int prec) {
     return HD_OK;
 }
 
+int true_residual(hd_ctx* c, Work& wk64, const double* b, const double* x, double* r, double& rel,
+                  double* rnorm_dev);
+
+// tighten the stop threshold and resume a converged recurrence
+__global__ void k_retarget(MinresState* st, double tol) {
+    if (st->status == 0) {
+        st->tol = tol;
+        st->stop = 0;
+    }
+}
+
 // Preconditioned MINRES in precision T on A x = b (b of precision B, x of
 // precision T, x0 = 0 unless use_x0).  Returns iterations and status.
 template <typename T, typename B>
 int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, int maxit, int check_every,
-                int& iters, int& status, double& eta_rel) {
+                int& iters, int& status, double& eta_rel, double true_tol = 0.0) {
     const int prec = std::is_same<T, double>::value ? HD_F64 : HD_F32;
     const int64_t N = wk.N, nu = c->n_u, nq = c->n_q;
     T* v = (T*)wk.v;
@@ -316,19 +330,19 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
     // the diag kernel covers n_u rows; its partial count is nblk(n_u) <= nblk(N)
     if ((rc = launch_schur_prec(c, prec, v + nu, z + nu, wk.pq, nullptr))) return rc;
     hipLaunchKernelGGL(k_start, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)nblk(nu), wk.pq,
-                       (int64_t)nblk(nq), tol);
+                       wk.nq_part, tol);
     HD_HIP(c, hipGetLastError());
     const int* stop = &wk.st->stop;
-    int it_launched = 0;
+    int it_launched = 0, retargets = 0;
     for (;;) {
         for (int k = 0; k < check_every && it_launched < maxit; ++k, ++it_launched) {
             if ((rc = launch_apply(c, prec, z, q, &wk.st->inv_gamma, wk.pd, ESS_IDENTITY, stop))) return rc;
-            hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pd, c->ne);
+            hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pd, apply_partial_count(c));
             hipLaunchKernelGGL(k_vupd<T>, dim3(nblk(N)), dim3(BS), 0, c->stream, N, nu, q, v, vo, mdinv, zn, wk.st,
                                wk.pu);
             if ((rc = launch_schur_prec(c, prec, vo + nu, zn + nu, wk.pq, stop))) return rc;
             hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)nblk(N), wk.pq,
-                               (int64_t)nblk(nq), maxit);
+                               wk.nq_part, maxit);
             hipLaunchKernelGGL((k_wupd<T, T>), dim3(nblk(N)), dim3(BS), 0, c->stream, N, z, wo, w, x, wk.st);
             std::swap(v, vo);
             std::swap(z, zn);
@@ -337,6 +351,33 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
         HD_HIP(c, hipGetLastError());
         HD_HIP(c, hipMemcpyAsync(wk.st_host, wk.st, sizeof(MinresState), hipMemcpyDeviceToHost, c->stream));
         HD_HIP(c, hipStreamSynchronize(c->stream));
+        // iterations launched after the stop flag was raised were no-ops on
+        // the device; every executed iteration swapped each buffer pair once,
+        // so the parity of the executed count fixes the live arrangement
+        {
+            const bool odd = wk.st_host->iter % 2 != 0;
+            v = (T*)(odd ? wk.vo : wk.v);
+            vo = (T*)(odd ? wk.v : wk.vo);
+            z = (T*)(odd ? wk.zn : wk.z);
+            zn = (T*)(odd ? wk.z : wk.zn);
+            w = (T*)(odd ? wk.wo : wk.w);
+            wo = (T*)(odd ? wk.w : wk.wo);
+        }
+        if (wk.st_host->stop && wk.st_host->status == 0 && true_tol > 0.0 && retargets < 8) {
+            // the recurrence stops on the preconditioned residual norm; when the
+            // caller asks for a true FP64 residual, check it and, if it is not
+            // yet met, continue the same recurrence with a tighter threshold
+            if constexpr (std::is_same<T, double>::value && std::is_same<B, double>::value) {
+                double rel = 0.0;
+                if ((rc = true_residual(c, wk, b, x, nullptr, rel, nullptr))) return rc;
+                if (rel > true_tol) {
+                    const double nt = wk.st_host->tol * (true_tol / rel) * 0.7;
+                    hipLaunchKernelGGL(k_retarget, dim3(1), dim3(1), 0, c->stream, wk.st, nt);
+                    ++retargets;
+                    if (it_launched < maxit) continue;
+                }
+            }
+        }
         if (wk.st_host->stop || it_launched >= maxit) break;
     }
     const MinresState& s = *wk.st_host;
@@ -374,12 +415,6 @@ int minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, double*
     auto t0 = std::chrono::steady_clock::now();
     Work w64;
     int rc = alloc_work(c, w64, HD_F64);
-    // residual partials need nblk(N) entries in pq as well
-    if (!rc) {
-        dfree(w64.pq);
-        w64.pq = dalloc<double>(nblk(w64.N));
-        if (!w64.pq) rc = set_err(c, HD_ERR_OOM, "MINRES partials");
-    }
     if (rc) {
         free_work(w64);
         return rc;
@@ -389,7 +424,8 @@ int minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, double*
     if (prm.mode == HD_MODE_PLAIN64) {
         int it = 0;
         double er = 0;
-        rc = minres_core<double, double>(c, w64, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, it, status, er);
+        rc = minres_core<double, double>(c, w64, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, it, status, er,
+                                         prm.stop_true ? prm.tol : 0.0);
         info.iterations = it;
         info.outer = 1;
         info.eta_rel = er;

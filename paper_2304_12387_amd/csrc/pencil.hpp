@@ -1,0 +1,108 @@
+// Register-pencil tensor contractions for the element kernels.
+//
+// An element tensor of shape (N0, N1, N2) (N0 fastest) is processed by a team
+// of lanes; for a contraction along one direction each active lane owns one
+// 1D line ("pencil") of the tensor along that direction, reads it into
+// registers, multiplies it by a small dense 1D matrix whose entries are
+// uniform across the wavefront (kernel arguments, held in scalar registers)
+// and writes the resulting pencil.  LDS is used only to change the pencil
+// direction between stages, so the multiply-adds read no LDS at all.
+#pragma once
+
+#include "kernels_common.hpp"
+
+namespace hd {
+
+// 1D tables of degree P passed by value (kernel-argument constant buffer).
+template <int P, typename T>
+struct TabK {
+    static constexpr int Q = P + 1;
+    T L[Q][P + 1];     // l_i(x_a)
+    T H[Q][P];         // h_j(x_a)
+    T Bg[Q][P];        // Gauss-Legendre nodal basis at x_a
+    T Bg2[Q][P];       // Bg^2
+    T Ti[P][P];        // inverse change of basis IH -> GL nodal
+};
+
+template <int P, typename T>
+TabK<P, T> make_tabk(const Tables<T>& t) {
+    TabK<P, T> k;
+    for (int a = 0; a <= P; ++a) {
+        for (int i = 0; i <= P; ++i) k.L[a][i] = t.L[a][i];
+        for (int j = 0; j < P; ++j) {
+            k.H[a][j] = t.H[a][j];
+            k.Bg[a][j] = t.Bg[a][j];
+            k.Bg2[a][j] = t.Bg2[a][j];
+        }
+    }
+    for (int r = 0; r < P; ++r)
+        for (int c = 0; c < P; ++c) k.Ti[r][c] = t.Tinv[r][c];
+    return k;
+}
+
+// Pencil index helpers for a (N0, N1, N2) array, contraction along DIM.
+template <int N0, int N1, int N2, int DIM>
+struct PencilGeom {
+    static constexpr int K = DIM == 0 ? N0 : (DIM == 1 ? N1 : N2);
+    static constexpr int NP = N0 * N1 * N2 / K;
+    static constexpr int STRIDE = DIM == 0 ? 1 : (DIM == 1 ? N0 : N0 * N1);
+    // base offset of pencil t in an array with this shape
+    __device__ static __forceinline__ int base(int t) {
+        if (DIM == 0) return N0 * t;                    // t = j + N1 k
+        if (DIM == 1) return (t % N0) + N0 * N1 * (t / N0);   // t = i + N0 k
+        return t;                                       // t = i + N0 j
+    }
+};
+
+// out-pencil = B * in-pencil, B(o, s) = TR ? Bm[s][o] : Bm[o][s].
+template <typename T, int K, int M, int LDB, bool TR>
+__device__ __forceinline__ void pencil_mul(const T (&in)[K], T (&out)[M], const T* Bm) {
+#pragma unroll
+    for (int o = 0; o < M; ++o) {
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) s += (TR ? Bm[k * LDB + o] : Bm[o * LDB + k]) * in[k];
+        out[o] = s;
+    }
+}
+
+// Read pencil t of `src` (shape N0,N1,N2, along DIM) into registers.
+template <typename T, int N0, int N1, int N2, int DIM>
+__device__ __forceinline__ void pencil_load(const T* src, int t, T (&v)[PencilGeom<N0, N1, N2, DIM>::K]) {
+    using G = PencilGeom<N0, N1, N2, DIM>;
+    const int b = G::base(t);
+#pragma unroll
+    for (int s = 0; s < G::K; ++s) v[s] = src[b + s * G::STRIDE];
+}
+
+// Write pencil t (length M along DIM) into `dst` of shape (N0,N1,N2) with
+// extent M along DIM.
+template <typename T, int N0, int N1, int N2, int DIM, int M>
+__device__ __forceinline__ void pencil_store(T* dst, int t, const T (&v)[M]) {
+    constexpr int O0 = DIM == 0 ? M : N0, O1 = DIM == 1 ? M : N1, O2 = DIM == 2 ? M : N2;
+    using G = PencilGeom<O0, O1, O2, DIM>;
+    const int b = G::base(t);
+#pragma unroll
+    for (int s = 0; s < M; ++s) dst[b + s * G::STRIDE] = v[s];
+}
+
+// Full LDS -> LDS stage: contract `src` (N0,N1,N2) along DIM to extent M.
+template <typename T, int N0, int N1, int N2, int DIM, int M, int LDB, bool TR>
+__device__ __forceinline__ void stage_lds(const T* src, T* dst, const T* Bm, int t) {
+    using G = PencilGeom<N0, N1, N2, DIM>;
+    if (t < G::NP) {
+        T in[G::K], out[M];
+        pencil_load<T, N0, N1, N2, DIM>(src, t, in);
+        pencil_mul<T, G::K, M, LDB, TR>(in, out, Bm);
+        pencil_store<T, N0, N1, N2, DIM, M>(dst, t, out);
+    }
+}
+
+template <typename T, int W>
+__device__ __forceinline__ T slot_sum(T v) {
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+    return v;
+}
+
+}  // namespace hd

@@ -24,63 +24,87 @@ constexpr int BS = 256;
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
 
-template <typename T>
-__global__ void vc_pre_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                              const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
-                              T* __restrict__ x, T* __restrict__ r, const int* __restrict__ done) {
-    if (done && *done) return;
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Sub-wave CSR row products: a group of G lanes (G a power of two <= 64)
+// handles one row; the group sum is formed with cross-lane shuffles.
+template <int G, typename T, typename F>
+__device__ __forceinline__ T group_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                       const T* __restrict__ av, int64_t row, int lane, F&& xval) {
     T s = 0;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int32_t j = ci[k];
-        s += av[k] * (dinv[j] * b[j]);
-    }
-    x[i] = dinv[i] * b[i];
-    r[i] = b[i] - s;
+    const int32_t e = rp[row + 1];
+    for (int32_t k = rp[row] + lane; k < e; k += G) s += av[k] * xval(ci[k]);
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+    return s;
 }
 
-// y_i = sum_k M_ik x_k  (restriction with R = P^T) or y_i += ... (prolongation)
-template <typename T, bool ADD>
-__global__ void vc_spmv_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                               const T* __restrict__ mv, const T* __restrict__ x, T* __restrict__ y,
-                               const int* __restrict__ done) {
-    if (done && *done) return;
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    T s = 0;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) s += mv[k] * x[ci[k]];
-    if (ADD) y[i] += s;
-    else y[i] = s;
-}
-
-// z = x + dinv (b - A x); optional partial sums of z (for the mean) or of
-// z * b (the preconditioned norm), one per block
-template <typename T>
-__global__ void vc_post_kernel(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                               const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
-                               const T* __restrict__ x, T* __restrict__ z, double* __restrict__ part, int part_kind,
-                               const int* __restrict__ done) {
-    if (done && *done) return;
+// block-wide sum of one value per row (lane 0 of each group contributes)
+__device__ __forceinline__ void block_partial(double v, double* __restrict__ part) {
     __shared__ double s[BS];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    double contrib = 0.0;
-    if (i < n) {
-        T acc = 0;
-        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) acc += av[k] * x[ci[k]];
-        const T zi = x[i] + dinv[i] * (b[i] - acc);
-        z[i] = zi;
-        contrib = part_kind == 1 ? (double)zi : (double)zi * (double)b[i];
-    }
-    if (part) {
-        s[threadIdx.x] = contrib;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
         __syncthreads();
-        for (int off = BS / 2; off > 0; off >>= 1) {
-            if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[blockIdx.x] = s[0];
     }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// x = dinv b;  r = b - A (dinv b)
+template <int G, typename T>
+__global__ __launch_bounds__(BS) void vc_pre_kernel(int64_t n, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ci, const T* __restrict__ av,
+                                                    const T* __restrict__ dinv, const T* __restrict__ b,
+                                                    T* __restrict__ x, T* __restrict__ r, const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t row = (blockIdx.x * (int64_t)BS + threadIdx.x) / G;
+    const int lane = threadIdx.x % G;
+    if (row >= n) return;
+    const T s = group_row<G, T>(rp, ci, av, row, lane, [&](int32_t j) { return dinv[j] * b[j]; });
+    if (lane == 0) {
+        x[row] = dinv[row] * b[row];
+        r[row] = b[row] - s;
+    }
+}
+
+// y = M x (restriction with R = P^T) or y += M x (prolongation)
+template <int G, typename T, bool ADD>
+__global__ __launch_bounds__(BS) void vc_spmv_kernel(int64_t n, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const T* __restrict__ mv,
+                                                     const T* __restrict__ x, T* __restrict__ y,
+                                                     const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t row = (blockIdx.x * (int64_t)BS + threadIdx.x) / G;
+    const int lane = threadIdx.x % G;
+    if (row >= n) return;
+    const T s = group_row<G, T>(rp, ci, mv, row, lane, [&](int32_t j) { return x[j]; });
+    if (lane == 0) {
+        if (ADD) y[row] += s;
+        else y[row] = s;
+    }
+}
+
+// z = x + dinv (b - A x); optional per-block partial sums of z (kind 1, for
+// the mean) or of z * b (kind 2, the preconditioned norm)
+template <int G, typename T>
+__global__ __launch_bounds__(BS) void vc_post_kernel(int64_t n, const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const T* __restrict__ av,
+                                                     const T* __restrict__ dinv, const T* __restrict__ b,
+                                                     const T* __restrict__ x, T* __restrict__ z,
+                                                     double* __restrict__ part, int part_kind,
+                                                     const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t row = (blockIdx.x * (int64_t)BS + threadIdx.x) / G;
+    const int lane = threadIdx.x % G;
+    double contrib = 0.0;
+    if (row < n) {
+        const T acc = group_row<G, T>(rp, ci, av, row, lane, [&](int32_t j) { return x[j]; });
+        if (lane == 0) {
+            const T zi = x[row] + dinv[row] * (b[row] - acc);
+            z[row] = zi;
+            contrib = part_kind == 1 ? (double)zi : (double)zi * (double)b[row];
+        }
+    }
+    if (part) block_partial(contrib, part);
 }
 
 // z -= mean (mean = sum / n from a device scalar), partial sums of z * b
@@ -156,6 +180,25 @@ T* pickw(double* d, float* f) {
     else return f;
 }
 
+// lanes per row for a CSR matrix: a power of two near its mean row length
+inline int group_of(const DevCSR& m) {
+    const double avg = m.nrows ? (double)m.nnz / (double)m.nrows : 1.0;
+    int g = 4;
+    while (g < 64 && g < avg) g *= 2;
+    return g;
+}
+
+inline unsigned gblk(int64_t rows, int g) { return (unsigned)((rows * g + BS - 1) / BS); }
+
+#define HD_GROUP_DISPATCH(g, KERNEL, ...)                                  \
+    switch (g) {                                                           \
+        case 4: KERNEL(4, __VA_ARGS__); break;                             \
+        case 8: KERNEL(8, __VA_ARGS__); break;                             \
+        case 16: KERNEL(16, __VA_ARGS__); break;                           \
+        case 32: KERNEL(32, __VA_ARGS__); break;                           \
+        default: KERNEL(64, __VA_ARGS__); break;                           \
+    }
+
 template <typename T>
 int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const int* done) {
     const int L = (int)c->lev.size();
@@ -173,16 +216,21 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
     DevLevel& nx = c->lev[l + 1];
     T* bc = pickw<T>(nx.b, nx.b32);
     T* zc = pickw<T>(nx.z, nx.z32);
-    hipLaunchKernelGGL(vc_pre_kernel<T>, dim3(nblk(n)), dim3(BS), 0, c->stream, n, lv.A.rp, lv.A.ci, av, dinv, b, x,
-                       r, done);
-    hipLaunchKernelGGL((vc_spmv_kernel<T, false>), dim3(nblk(lv.R.nrows)), dim3(BS), 0, c->stream, lv.R.nrows,
-                       lv.R.rp, lv.R.ci, pick<T>(lv.R.v, lv.R.v32), r, bc, done);
+    const int gA = group_of(lv.A), gR = group_of(lv.R), gP = group_of(lv.P);
+#define PRE(G, ...) hipLaunchKernelGGL((vc_pre_kernel<G, T>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
+#define RES(G, ...) hipLaunchKernelGGL((vc_spmv_kernel<G, T, false>), dim3(gblk(lv.R.nrows, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
+#define PRO(G, ...) hipLaunchKernelGGL((vc_spmv_kernel<G, T, true>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
+#define POST(G, ...) hipLaunchKernelGGL((vc_post_kernel<G, T>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
+    HD_GROUP_DISPATCH(gA, PRE, n, lv.A.rp, lv.A.ci, av, dinv, b, x, r, done)
+    HD_GROUP_DISPATCH(gR, RES, lv.R.nrows, lv.R.rp, lv.R.ci, pick<T>(lv.R.v, lv.R.v32), (const T*)r, bc, done)
     int rc = cycle<T>(c, l + 1, bc, zc, nullptr, 0, done);
     if (rc) return rc;
-    hipLaunchKernelGGL((vc_spmv_kernel<T, true>), dim3(nblk(n)), dim3(BS), 0, c->stream, n, lv.P.rp, lv.P.ci,
-                       pick<T>(lv.P.v, lv.P.v32), zc, x, done);
-    hipLaunchKernelGGL(vc_post_kernel<T>, dim3(nblk(n)), dim3(BS), 0, c->stream, n, lv.A.rp, lv.A.ci, av, dinv, b, x,
-                       z, part, part_kind, done);
+    HD_GROUP_DISPATCH(gP, PRO, n, lv.P.rp, lv.P.ci, pick<T>(lv.P.v, lv.P.v32), (const T*)zc, x, done)
+    HD_GROUP_DISPATCH(gA, POST, n, lv.A.rp, lv.A.ci, av, dinv, b, (const T*)x, z, part, part_kind, done)
+#undef PRE
+#undef RES
+#undef PRO
+#undef POST
     return HD_OK;
 }
 
@@ -201,8 +249,15 @@ __global__ void sum_partial_kernel(int64_t n, const T* __restrict__ a, const T* 
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
+// Number of per-block partial sums the level-0 post-smoothing writes.
+int64_t post_partials(const hd_ctx* c) {
+    if (c->lev.size() <= 1) return nblk(c->n_q);
+    return gblk(c->n_q, group_of(c->lev[0].A));
+}
+
 // z = S^{-1} b on the L2 dofs; `part` (optional) receives per-block partial
-// sums of z * b after the constant has been removed (singular case).
+// sums of z * b (after the constant has been removed in the singular case);
+// their number is schur_partial_count().
 template <typename T>
 int schur_apply(hd_ctx* c, const T* b, T* z, double* part, const int* done) {
     const int64_t n = c->n_q;
@@ -214,7 +269,8 @@ int schur_apply(hd_ctx* c, const T* b, T* z, double* part, const int* done) {
             hipLaunchKernelGGL(sum_partial_kernel<T>, dim3(nblk(n)), dim3(BS), 0, c->stream, n, z, b, part, done);
         return HD_OK;
     }
-    int rc = launch_ensure_partial(c, (int64_t)nblk(n));
+    const int64_t np = post_partials(c);
+    int rc = launch_ensure_partial(c, np);
     if (rc) return rc;
     double* zs = c->d_partial;
     rc = cycle<T>(c, 0, b, z, one_level ? nullptr : zs, 1, done);
@@ -222,7 +278,7 @@ int schur_apply(hd_ctx* c, const T* b, T* z, double* part, const int* done) {
     if (one_level)
         hipLaunchKernelGGL(sum_partial_kernel<T>, dim3(nblk(n)), dim3(BS), 0, c->stream, n, z, (const T*)nullptr, zs,
                            done);
-    rc = reduce_sum_partials(c, zs, nblk(n), c->d_scal + 6);
+    rc = reduce_sum_partials(c, zs, np, c->d_scal + 6);
     if (rc) return rc;
     hipLaunchKernelGGL(vc_sub_mean_kernel<T>, dim3(nblk(n)), dim3(BS), 0, c->stream, n, c->d_scal + 6, b, z, part,
                        done);
@@ -251,7 +307,10 @@ int launch_schur_prec(hd_ctx* c, int prec, const void* b, void* z, double* part,
     return HD_OK;
 }
 
-int precond_partials(const hd_ctx* c) { return (int)nblk(c->n_q > c->n_u ? c->n_q : c->n_u); }
+int64_t schur_partial_count(const hd_ctx* c) {
+    if (c->singular || c->lev.size() <= 1) return nblk(c->n_q);
+    return post_partials(c);
+}
 
 int launch_precond(hd_ctx* c, int prec, const void* r, void* z, double* dot_partial_u, double* dot_partial_q,
                    const int* done) {

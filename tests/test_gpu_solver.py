@@ -137,6 +137,12 @@ def test_mixed_precision_refinement():
     print('plain', i64, 'mixed', im, flush=True)
     assert i64['status'] == 0 and im['status'] == 0
     assert im['true_rel_res'] <= 1e-8 and im['outer'] >= 1
+    # plain FP64 with the true-residual stop: continues the recurrence until
+    # ||b - A x|| <= tol ||b|| and needs at least the iterations of the eta stop
+    xt = torch.zeros_like(bd)
+    it_ = ctx.minres_solve(bd, xt, hdivsp.solve_params(tol=1e-8, stop_true=1))
+    assert it_['status'] == 0 and it_['true_rel_res'] <= 1e-8
+    assert it_['iterations'] >= i64['iterations']
     A = prob.block_matrix()
     xmn = xm.cpu().numpy()
     assert np.linalg.norm(b - A @ xmn) <= 1e-8 * np.linalg.norm(b) * 1.0001
