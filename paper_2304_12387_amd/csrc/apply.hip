@@ -13,11 +13,14 @@
 // Gauss-Legendre mass matrix, formed on the fly by squared-basis sum
 // factorisation.
 //
-// Launch: one 64-lane workgroup (one wavefront) per element.  The element's
-// RT and L2 coefficients, its quadrature-point values and the 1D tables live
-// in LDS.  Element-interior RT dofs are written with plain stores; dofs on a
-// face shared with a neighbour element receive exactly two atomic additions
-// onto a zero-initialised value, which is order-independent (a + b = b + a).
+// Launch: one 64-lane wavefront per workgroup, holding 64 / W elements (W
+// lanes per element, W >= (p+1)^2).  Each lane owns register pencils; LDS
+// only re-orients pencils between contraction directions.  RT dofs are
+// shared only by the two elements across a face, and face neighbours always
+// differ in the parity of ex + ey + ez, so the operator runs as two launches
+// (two colours): the first stores every dof it touches, the second stores
+// its own dofs and adds its contribution to the faces it shares with the
+// first.  No atomics, no zero fill, and a fixed summation order.
 #include "pencil.hpp"
 
 #include <type_traits>
@@ -42,6 +45,17 @@ struct Slot {
 };
 
 template <int P, typename T>
+using tkp = const __attribute__((address_space(4))) TabK<P, T>*;
+
+// A fresh view of the table pointer for each stage (see stage_tab).
+template <int P, typename T>
+__device__ __forceinline__ tkp<P, T> tfence(tkp<P, T> p) {
+    uint64_t v = (uint64_t)p;
+    asm volatile("" : "+s"(v));
+    return (tkp<P, T>)v;
+}
+
+template <int P, typename T>
 struct ElemLDS {
     T su[Dim<P>::NRT];   // gathered RT coefficients (scaled, essential dofs zeroed)
     T sq[Dim<P>::NL];    // gathered L2 coefficients
@@ -61,13 +75,13 @@ struct ElemLDS {
 // not converged.
 // ---------------------------------------------------------------------------
 template <int P, typename T>
-__device__ void local_cg(ElemLDS<P, T>& L, const TabK<P, T>& tb, const T (&gw)[P + 1], int t, bool active, T kE,
+__device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], int t, bool active, T kE,
                          const CGParams<T>& cgp) {
     constexpr int Q = P + 1;
     constexpr int W = Slot<P>::W;
-    const T* Ti = &tb.Ti[0][0];
-    const T* Bg = &tb.Bg[0][0];
-    const T* Bg2 = &tb.Bg2[0][0];
+#define Ti (&tfence<P, T>(tk)->Ti[0][0])
+#define Bg (&tfence<P, T>(tk)->Bg[0][0])
+#define Bg2 (&tfence<P, T>(tk)->Bg2[0][0])
     T r[P], z[P], pv[P], x[P], dW[P], Ap[P];
     // rhs in the GL nodal basis: T^{-T} sq, contracted z, y, then x
     stage_lds<T, P, P, P, 2, P, P, true>(L.sq, L.A1, Ti, t);
@@ -96,7 +110,8 @@ __device__ void local_cg(ElemLDS<P, T>& L, const TabK<P, T>& tb, const T (&gw)[P
         pencil_mul<T, Q, P, P, true>(in, dW, Bg2);
 #pragma unroll
         for (int s = 0; s < P; ++s) {
-            z[s] = r[s] / dW[s];
+            dW[s] = T(1) / dW[s];   // keep the reciprocal of the Jacobi diagonal
+            z[s] = r[s] * dW[s];
             pv[s] = z[s];
             x[s] = 0;
             rz += r[s] * z[s];
@@ -149,7 +164,7 @@ __device__ void local_cg(ElemLDS<P, T>& L, const TabK<P, T>& tb, const T (&gw)[P
             for (int s = 0; s < P; ++s) {
                 x[s] += alpha * pv[s];
                 r[s] -= alpha * Ap[s];
-                z[s] = r[s] / dW[s];
+                z[s] = r[s] * dW[s];
                 rzn += r[s] * z[s];
             }
         }
@@ -185,18 +200,21 @@ __device__ void local_cg(ElemLDS<P, T>& L, const TabK<P, T>& tb, const T (&gw)[P
         for (int s = 0; s < P; ++s) L.syq[b + s * G::STRIDE] -= kE * o[s];
     }
     __syncthreads();
+#undef Ti
+#undef Bg
+#undef Bg2
 }
 
 // Forward sum factorisation of RT component C (shape N0,N1,N2) to the
 // quadrature points: x and y through LDS, z into registers (z-pencil of the
 // quadrature point column (a, b, .) for lane t = a + Q b).
 template <int P, typename T, int C>
-__device__ __forceinline__ void rt_to_quad(ElemLDS<P, T>& L, const TabK<P, T>& tb, int t, T (&U)[P + 1]) {
+__device__ __forceinline__ void rt_to_quad(ElemLDS<P, T>& L, tkp<P, T> tk, int t, T (&U)[P + 1]) {
     constexpr int Q = P + 1, NC = Dim<P>::NC;
     constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
-    const T* B0 = C == 0 ? &tb.L[0][0] : &tb.H[0][0];
-    const T* B1 = C == 1 ? &tb.L[0][0] : &tb.H[0][0];
-    const T* B2 = C == 2 ? &tb.L[0][0] : &tb.H[0][0];
+#define B0 (C == 0 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
+#define B1 (C == 1 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
+#define B2 (C == 2 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
     stage_lds<T, N0, N1, N2, 0, Q, N0, false>(L.su + C * NC, L.A1, B0, t);
     __syncthreads();
     stage_lds<T, Q, N1, N2, 1, Q, N1, false>(L.A1, L.A2, B1, t);
@@ -207,18 +225,21 @@ __device__ __forceinline__ void rt_to_quad(ElemLDS<P, T>& L, const TabK<P, T>& t
         pencil_mul<T, N2, Q, N2, false>(in, U, B2);
     }
     __syncthreads();
+#undef B0
+#undef B1
+#undef B2
 }
 
 // Transpose of rt_to_quad for component C: from z-pencil registers V to
 // x-pencil registers y (lane t = j + N1 k holds (., j, k), N0 values).
 template <int P, typename T, int C>
-__device__ __forceinline__ void quad_to_rt(ElemLDS<P, T>& L, const TabK<P, T>& tb, int t, const T (&V)[P + 1],
+__device__ __forceinline__ void quad_to_rt(ElemLDS<P, T>& L, tkp<P, T> tk, int t, const T (&V)[P + 1],
                                            T (&y)[P + 1]) {
     constexpr int Q = P + 1;
     constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
-    const T* B0 = C == 0 ? &tb.L[0][0] : &tb.H[0][0];
-    const T* B1 = C == 1 ? &tb.L[0][0] : &tb.H[0][0];
-    const T* B2 = C == 2 ? &tb.L[0][0] : &tb.H[0][0];
+#define B0 (C == 0 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
+#define B1 (C == 1 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
+#define B2 (C == 2 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
     if (t < Q * Q) {
         T o[N2];
         pencil_mul<T, Q, N2, N2, true>(V, o, B2);
@@ -235,6 +256,73 @@ __device__ __forceinline__ void quad_to_rt(ElemLDS<P, T>& L, const TabK<P, T>& t
         for (int s = 0; s < N0; ++s) y[s] = o[s];
     }
     __syncthreads();
+#undef B0
+#undef B1
+#undef B2
+}
+
+// Global position of the x-line (., j, k) of RT component C in element
+// (ex, ey, ez): index of its first dof, whether the whole line lies on an
+// element face normal to y or z (C = 1, 2), and its domain-boundary side.
+struct RtLine {
+    int64_t base;      // global index of local i = 0
+    int tan_face;      // C = 1 (j in {0,P}) or C = 2 (k in {0,P}): the line lies on an element face
+    int tan_bnd;       // ... and that face is on the domain boundary: side 0 / 1, else -1
+};
+
+template <int P, int C>
+__device__ __forceinline__ RtLine rt_line(const Geo& g, int ex, int ey, int ez, int j, int k) {
+    const int64_t d0 = (int64_t)g.nx * P + (C == 0), d1 = (int64_t)g.ny * P + (C == 1);
+    const int64_t gj = (int64_t)ey * P + j, gk = (int64_t)ez * P + k;
+    RtLine r;
+    r.base = g.off[C] + (int64_t)ex * P + d0 * (gj + d1 * gk);
+    r.tan_face = 0;
+    r.tan_bnd = -1;
+    if (C == 1) {
+        r.tan_face = j == 0 || j == P;
+        r.tan_bnd = gj == 0 ? 0 : (gj == (int64_t)g.ny * P ? 1 : -1);
+    } else if (C == 2) {
+        r.tan_face = k == 0 || k == P;
+        r.tan_bnd = gk == 0 ? 0 : (gk == (int64_t)g.nz * P ? 1 : -1);
+    }
+    return r;
+}
+
+// Classify dof i of an x-line of component C: on an element face, and on
+// which domain-boundary side (-1: interior).
+template <int P, int C>
+__device__ __forceinline__ void rt_line_dof(const Geo& g, int ex, const RtLine& r, int i, int& onf, int& bs) {
+    if (C == 0) {
+        onf = i == 0 || i == P;
+        const int gi = ex * P + i;
+        bs = gi == 0 ? 0 : (gi == g.nx * P ? 1 : -1);
+    } else {
+        onf = r.tan_face;
+        bs = r.tan_bnd;
+    }
+}
+
+// Gather the RT coefficients of component C line by line into LDS.
+template <int P, typename T, int C>
+__device__ __forceinline__ void gather_rt(ElemLDS<P, T>& L, const Geo& g, int ex, int ey, int ez, int t, uint32_t ess,
+                                          int ess_mode, T s_in, const T* __restrict__ x) {
+    constexpr int NC = Dim<P>::NC;
+    constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
+    constexpr int W = Slot<P>::W;
+    for (int tt = t; tt < N1 * N2; tt += W) {
+        const int j = tt % N1, k = tt / N1;
+        const RtLine r = rt_line<P, C>(g, ex, ey, ez, j, k);
+        T v[N0];
+#pragma unroll
+        for (int i = 0; i < N0; ++i) v[i] = x[r.base + i];
+#pragma unroll
+        for (int i = 0; i < N0; ++i) {
+            int onf, bs;
+            rt_line_dof<P, C>(g, ex, r, i, onf, bs);
+            const bool is_ess = ess_mode == ESS_IDENTITY && bs >= 0 && ((ess >> (2 * C + bs)) & 1u);
+            L.su[C * NC + N0 * tt + i] = is_ess ? T(0) : s_in * v[i];
+        }
+    }
 }
 
 // D^T q~ added to the x-pencil of component C, then scatter to y and the
@@ -242,12 +330,13 @@ __device__ __forceinline__ void quad_to_rt(ElemLDS<P, T>& L, const TabK<P, T>& t
 template <int P, typename T, int C>
 __device__ __forceinline__ double finish_rt(ElemLDS<P, T>& L, const Geo& g, int ex, int ey, int ez, int t,
                                             T (&yv)[P + 1], uint32_t ess, int ess_mode, T s_in,
-                                            const T* __restrict__ x, T* __restrict__ y) {
+                                            const T* __restrict__ x, T* __restrict__ y, int colour) {
     constexpr int NC = Dim<P>::NC;
     constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
     double dot = 0.0;
     if (t >= N1 * N2) return dot;
     const int j = t % N1, k = t / N1;
+    const RtLine r = rt_line<P, C>(g, ex, ey, ez, j, k);
 #pragma unroll
     for (int i = 0; i < N0; ++i) {
         const int tn = C == 0 ? i : (C == 1 ? j : k);   // index along the normal
@@ -259,17 +348,20 @@ __device__ __forceinline__ double finish_rt(ElemLDS<P, T>& L, const Geo& g, int 
         }
         if (tn <= P - 1) add -= L.sq[i + P * (j + P * k)];
         int onf, bs;
-        const int64_t gidx = rt_global<P>(g, C, ex, ey, ez, i, j, k, onf, bs);
+        rt_line_dof<P, C>(g, ex, r, i, onf, bs);
+        const int64_t gidx = r.base + i;
         const bool is_ess = ess_mode == ESS_IDENTITY && bs >= 0 && ((ess >> (2 * C + bs)) & 1u);
-        const int l = C * NC + i + N0 * (j + N1 * k);
+        const int l = C * NC + i + N0 * t;
         if (is_ess) {
             const T xv = s_in * x[gidx];
             y[gidx] = xv;
             dot += (double)xv * (double)xv;
         } else {
             const T v = yv[i] + add;
-            if (!onf || bs >= 0) y[gidx] = v;
-            else atomicAdd(&y[gidx], v);
+            // faces shared with a neighbour: the first colour stores, the
+            // second adds (face neighbours always have opposite colours)
+            if (colour == 1 && onf && bs < 0) y[gidx] = y[gidx] + v;
+            else y[gidx] = v;
             dot += (double)v * (double)L.su[l];
         }
     }
@@ -278,10 +370,10 @@ __device__ __forceinline__ double finish_rt(ElemLDS<P, T>& L, const Geo& g, int 
 
 template <int P, typename T>
 __global__ __launch_bounds__(64) void block_apply_kernel(
-    Geo g, const T* __restrict__ pa, TabK<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
+    Geo g, const T* __restrict__ pa, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
     int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ x, T* __restrict__ y,
     const double* __restrict__ in_scale, double* __restrict__ dot_partial, const int* __restrict__ done,
-    CGParams<T> cgp, int with_c) {
+    CGParams<T> cgp, int with_c, int colour, int64_t part_offset) {
     if (done && *done) return;
     using D = Dim<P>;
     using S = Slot<P>;
@@ -289,24 +381,35 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     __shared__ ElemLDS<P, T> sm[S::EPW];
     const int lane = threadIdx.x;
     const int slot = lane / W, t = lane % W;
-    const int64_t e = (int64_t)blockIdx.x * S::EPW + slot;
-    const bool valid = e < ne;
-    const int64_t ee = valid ? e : ne - 1;   // clamp for address arithmetic only
+    // elements of one colour ((ex + ey + ez) mod 2 == colour), half-row by half-row
+    const int hx = (g.nx + 1) / 2;
+    const int64_t idx = (int64_t)blockIdx.x * S::EPW + slot;
+    const int64_t row = idx / hx;
+    const int m = (int)(idx % hx);
+    const int ey0 = (int)(row % g.ny), ez0 = (int)(row / g.ny);
+    const int ex0 = 2 * m + ((colour + ey0 + ez0) & 1);
+    const bool valid = row < (int64_t)g.ny * g.nz && ex0 < g.nx;
+    const int ex = valid ? ex0 : 0, ey = valid ? ey0 : 0, ez = valid ? ez0 : 0;
+    const int64_t ee = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);   // clamped for address arithmetic
     ElemLDS<P, T>& L = sm[slot];
-    const int ex = (int)(ee % g.nx), ey = (int)((ee / g.nx) % g.ny), ez = (int)(ee / ((int64_t)g.nx * g.ny));
     const T s_in = in_scale ? (T)(*in_scale) : T(1);
     const T cM = cm[ee];
     const T kE = kap[ee];
+    // issue the loads of this lane's geometric factors first so that they are
+    // in flight during the gather and the forward sum factorisation
+    T G[NPA][Q];
+    {
+        const T* pe = pa + (size_t)ee * NPA * Q3 + (t < Q * Q ? t : 0);
+#pragma unroll
+        for (int m = 0; m < NPA; ++m)
+#pragma unroll
+            for (int c = 0; c < Q; ++c) G[m][c] = pe[m * Q3 + Q * Q * c];
+    }
     // gather u (essential dofs read as zero) and q~
     if (valid) {
-        for (int l = t; l < NRT; l += W) {
-            const int c = l / NC, ll = l % NC;
-            int i, j, k, onf, bs;
-            local_ijk<P>(c, ll, i, j, k);
-            const int64_t gidx = rt_global<P>(g, c, ex, ey, ez, i, j, k, onf, bs);
-            const bool is_ess = ess_mode == ESS_IDENTITY && bs >= 0 && ((ess >> (2 * c + bs)) & 1u);
-            L.su[l] = is_ess ? T(0) : s_in * x[gidx];
-        }
+        gather_rt<P, T, 0>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
+        gather_rt<P, T, 1>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
+        gather_rt<P, T, 2>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
         for (int l = t; l < NL; l += W) L.sq[l] = s_in * x[n_u + ee * NL + l];
     }
     __syncthreads();
@@ -327,18 +430,14 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     rt_to_quad<P, T, 2>(L, tb, t, U2);
     // geometric factors (c_mass w J^T J / det J) at the quadrature column (a, b, .)
     T gw[Q];
-    const T* pe = pa + (size_t)ee * NPA * Q3;
     if (t < Q * Q) {
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
-            const int qd = t + Q * Q * c;
-            const T g00 = pe[0 * Q3 + qd], g01 = pe[1 * Q3 + qd], g02 = pe[2 * Q3 + qd];
-            const T g11 = pe[3 * Q3 + qd], g12 = pe[4 * Q3 + qd], g22 = pe[5 * Q3 + qd];
-            gw[c] = pe[6 * Q3 + qd];
             const T a0 = U0[c], a1 = U1[c], a2 = U2[c];
-            U0[c] = cM * (g00 * a0 + g01 * a1 + g02 * a2);
-            U1[c] = cM * (g01 * a0 + g11 * a1 + g12 * a2);
-            U2[c] = cM * (g02 * a0 + g12 * a1 + g22 * a2);
+            U0[c] = cM * (G[0][c] * a0 + G[1][c] * a1 + G[2][c] * a2);
+            U1[c] = cM * (G[1][c] * a0 + G[3][c] * a1 + G[4][c] * a2);
+            U2[c] = cM * (G[2][c] * a0 + G[4][c] * a1 + G[5][c] * a2);
+            gw[c] = G[6][c];
         }
     } else {
 #pragma unroll
@@ -348,11 +447,11 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     {
         T yv[Q];
         quad_to_rt<P, T, 0>(L, tb, t, U0, yv);
-        if (valid) dot += finish_rt<P, T, 0>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y);
+        if (valid) dot += finish_rt<P, T, 0>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
         quad_to_rt<P, T, 1>(L, tb, t, U1, yv);
-        if (valid) dot += finish_rt<P, T, 1>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y);
+        if (valid) dot += finish_rt<P, T, 1>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
         quad_to_rt<P, T, 2>(L, tb, t, U2, yv);
-        if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y);
+        if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
     }
     // -kappa_e W_e^{-1} q~
     if (with_c) local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
@@ -366,41 +465,13 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     }
     if (dot_partial) {
         dot = slot_sum<double, 64>(dot);
-        if (lane == 0) dot_partial[blockIdx.x] = dot;
-    }
-}
-
-// Zero the RT dofs on faces shared by two elements (the only ones updated
-// with atomics).  One thread per shared face dof.
-template <typename T>
-__global__ void zero_shared_faces(Geo g, int P, T* __restrict__ y, int64_t n_x, int64_t n_y, int64_t n_z) {
-    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t nxp = (int64_t)g.nx * P, nyp = (int64_t)g.ny * P, nzp = (int64_t)g.nz * P;
-    if (t < n_x) {
-        // planes f = 1..nx-1 at gi = f P; (gj, gk) over nyp x nzp
-        int64_t f = t / (nyp * nzp) + 1, r = t % (nyp * nzp);
-        int64_t gj = r % nyp, gk = r / nyp;
-        y[g.off[0] + f * P + (nxp + 1) * (gj + nyp * gk)] = T(0);
-        return;
-    }
-    t -= n_x;
-    if (t < n_y) {
-        int64_t f = t / (nxp * nzp) + 1, r = t % (nxp * nzp);
-        int64_t gi = r % nxp, gk = r / nxp;
-        y[g.off[1] + gi + nxp * (f * P + (nyp + 1) * gk)] = T(0);
-        return;
-    }
-    t -= n_y;
-    if (t < n_z) {
-        int64_t f = t / (nxp * nyp) + 1, r = t % (nxp * nyp);
-        int64_t gi = r % nxp, gj = r / nxp;
-        y[g.off[2] + gi + nxp * (gj + nyp * (f * P))] = T(0);
+        if (lane == 0) dot_partial[part_offset + blockIdx.x] = dot;
     }
 }
 
 // y_q = (weighted ? kappa_e : 1) W_e^{-1} x_q (same local CG).
 template <int P, typename T>
-__global__ __launch_bounds__(64) void mass_inverse_kernel(const T* __restrict__ pa, TabK<P, T> tb,
+__global__ __launch_bounds__(64) void mass_inverse_kernel(const T* __restrict__ pa, tkp<P, T> tb,
                                                           const T* __restrict__ kap, int weighted, int64_t ne,
                                                           const T* __restrict__ x, T* __restrict__ y,
                                                           CGParams<T> cgp) {
@@ -431,6 +502,12 @@ __global__ __launch_bounds__(64) void mass_inverse_kernel(const T* __restrict__ 
         for (int l = t; l < NL; l += W) y[ee * NL + l] = -s * L.syq[l];
 }
 
+// blocks per colour: half-rows of ceil(nx / 2) elements, EPW elements per block
+inline unsigned apply_blocks_per_colour(int nx, int ny, int nz, int epw) {
+    const int64_t slots = (int64_t)((nx + 1) / 2) * ny * nz;
+    return (unsigned)((slots + epw - 1) / epw);
+}
+
 template <typename T>
 const Tables<T>& host_tables(const hd_ctx* c);
 template <>
@@ -449,30 +526,22 @@ template <int P, typename T>
 void launch_apply_p(hd_ctx* c, const T* x, T* y, const double* in_scale, double* dot_partial, int ess_mode,
                     const int* done) {
     Geo g = geo_of(c);
-    const int64_t nsx = (int64_t)(c->nx - 1) * c->ny * P * c->nz * P;
-    const int64_t nsy = (int64_t)(c->ny - 1) * c->nx * P * c->nz * P;
-    const int64_t nsz = (int64_t)(c->nz - 1) * c->nx * P * c->ny * P;
-    const int64_t ns = nsx + nsy + nsz;
-    if (ns > 0) {
-        const int bs = 256;
-        hipLaunchKernelGGL(zero_shared_faces<T>, dim3((unsigned)((ns + bs - 1) / bs)), dim3(bs), 0, c->stream, g, P,
-                           y, nsx, nsy, nsz);
-    }
     const T* pa = std::is_same<T, double>::value ? (const T*)c->d_pa : (const T*)c->d_pa32;
     const T* cm = std::is_same<T, double>::value ? (const T*)c->d_cm : (const T*)c->d_cm32;
     const T* kap = std::is_same<T, double>::value ? (const T*)c->d_kap : (const T*)c->d_kap32;
-    const TabK<P, T> tb = make_tabk<P, T>(host_tables<T>(c));
-    const unsigned nb = (unsigned)((c->ne + Slot<P>::EPW - 1) / Slot<P>::EPW);
-    hipLaunchKernelGGL((block_apply_kernel<P, T>), dim3(nb), dim3(64), 0, c->stream, g, pa, tb, cm, kap, c->ess,
-                       ess_mode, c->ne, c->n_u, x, y, in_scale, dot_partial, done, cg_params<T>(),
-                       c->kappa_zero ? 0 : 1);
+    const tkp<P, T> tb = (tkp<P, T>)(std::is_same<T, double>::value ? c->d_tabk64 : c->d_tabk32);
+    const unsigned nb = apply_blocks_per_colour(c->nx, c->ny, c->nz, Slot<P>::EPW);
+    for (int colour = 0; colour < 2; ++colour)
+        hipLaunchKernelGGL((block_apply_kernel<P, T>), dim3(nb), dim3(64), 0, c->stream, g, pa, tb, cm, kap, c->ess,
+                           ess_mode, c->ne, c->n_u, x, y, in_scale, dot_partial, done, cg_params<T>(),
+                           c->kappa_zero ? 0 : 1, colour, (int64_t)colour * nb);
 }
 
 template <int P, typename T>
 void launch_minv_p(hd_ctx* c, const T* x, T* y, bool weighted) {
     const T* pa = std::is_same<T, double>::value ? (const T*)c->d_pa : (const T*)c->d_pa32;
     const T* kap = std::is_same<T, double>::value ? (const T*)c->d_kap : (const T*)c->d_kap32;
-    const TabK<P, T> tb = make_tabk<P, T>(host_tables<T>(c));
+    const tkp<P, T> tb = (tkp<P, T>)(std::is_same<T, double>::value ? c->d_tabk64 : c->d_tabk32);
     const unsigned nb = (unsigned)((c->ne + Slot<P>::EPW - 1) / Slot<P>::EPW);
     hipLaunchKernelGGL((mass_inverse_kernel<P, T>), dim3(nb), dim3(64), 0, c->stream, pa, tb, kap, weighted ? 1 : 0,
                        c->ne, x, y, cg_params<T>());
@@ -521,6 +590,33 @@ __global__ void lift_finish_kernel(Geo g, int P, uint32_t ess, int64_t n_u, int6
 
 }  // namespace
 
+template <int P>
+int upload_tabk_p(hd_ctx* c) {
+    const TabK<P, double> t64 = make_tabk<P, double>(c->tab64_host);
+    const TabK<P, float> t32 = make_tabk<P, float>(c->tab32_host);
+    dfree(c->d_tabk64);
+    dfree(c->d_tabk32);
+    c->d_tabk64 = dalloc<TabK<P, double>>(1);
+    c->d_tabk32 = dalloc<TabK<P, float>>(1);
+    if (!c->d_tabk64 || !c->d_tabk32) return set_err(c, HD_ERR_OOM, "kernel tables");
+    HD_HIP(c, hipMemcpyAsync(c->d_tabk64, &t64, sizeof(t64), hipMemcpyHostToDevice, c->stream));
+    HD_HIP(c, hipMemcpyAsync(c->d_tabk32, &t32, sizeof(t32), hipMemcpyHostToDevice, c->stream));
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    return HD_OK;
+}
+
+int upload_kernel_tables(hd_ctx* c) {
+    switch (c->p) {
+        case 1: return upload_tabk_p<1>(c);
+        case 2: return upload_tabk_p<2>(c);
+        case 3: return upload_tabk_p<3>(c);
+        case 4: return upload_tabk_p<4>(c);
+        case 5: return upload_tabk_p<5>(c);
+        case 6: return upload_tabk_p<6>(c);
+    }
+    return set_err(c, HD_ERR_ARG, "p out of range");
+}
+
 int64_t apply_partial_count(const hd_ctx* c) {
     int epw = 1;
     switch (c->p) {
@@ -531,7 +627,7 @@ int64_t apply_partial_count(const hd_ctx* c) {
         case 5: epw = Slot<5>::EPW; break;
         case 6: epw = Slot<6>::EPW; break;
     }
-    return (c->ne + epw - 1) / epw;
+    return 2 * (int64_t)apply_blocks_per_colour(c->nx, c->ny, c->nz, epw);
 }
 
 int launch_lift(hd_ctx* c, const double* ubc, double* b) {

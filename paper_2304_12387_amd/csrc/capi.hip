@@ -121,6 +121,8 @@ int hd_destroy(hd_ctx* c) {
     free_mesh(c);
     dfree(c->d_tab64);
     dfree(c->d_tab32);
+    dfree(c->d_tabk64);
+    dfree(c->d_tabk32);
     dfree(c->d_partial);
     dfree(c->d_scal);
     dfree(c->d_flag);
@@ -162,6 +164,7 @@ int hd_setup_mesh(hd_ctx* c, int nx, int ny, int nz, int p, const double* vertic
     if (!c->d_tab64 || !c->d_tab32) return set_err(c, HD_ERR_OOM, "tables");
     HD_HIP(c, hipMemcpyAsync(c->d_tab64, &t64, sizeof(t64), hipMemcpyHostToDevice, c->stream));
     HD_HIP(c, hipMemcpyAsync(c->d_tab32, &t32, sizeof(t32), hipMemcpyHostToDevice, c->stream));
+    if ((rc = upload_kernel_tables(c))) return rc;
     const int64_t q3 = (int64_t)(p + 1) * (p + 1) * (p + 1);
     c->d_pa = dalloc<double>(c->ne * NPA * q3);
     c->d_pa32 = dalloc<float>(c->ne * NPA * q3);

@@ -100,6 +100,8 @@ struct hd_ctx {
     float* d_pa32 = nullptr;
     hd::Tables<double>* d_tab64 = nullptr;
     hd::Tables<float>* d_tab32 = nullptr;
+    void* d_tabk64 = nullptr;       // compact per-degree tables for the element kernels
+    void* d_tabk32 = nullptr;
     hd::Tables<double> tab64_host;
     hd::Tables<float> tab32_host;
 
@@ -176,6 +178,7 @@ int launch_apply(hd_ctx* c, int prec, const void* x, void* y, const double* in_s
 int launch_mass_inverse(hd_ctx* c, int prec, const void* x, void* y, bool weighted);
 int launch_lift(hd_ctx* c, const double* ubc, double* b);
 int64_t apply_partial_count(const hd_ctx* c);
+int upload_kernel_tables(hd_ctx* c);
 
 // precond.hip
 int upload_amg(hd_ctx* c);

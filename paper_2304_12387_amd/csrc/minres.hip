@@ -279,7 +279,7 @@ int alloc_work(hd_ctx* c, Work& w, int prec) {
     for (void** p : vs) {
         if (hipMalloc(p, es * w.N) != hipSuccess) return set_err(c, HD_ERR_OOM, "MINRES vectors");
     }
-    w.pd = dalloc<double>(c->ne);
+    w.pd = dalloc<double>(std::max<int64_t>(c->ne, apply_partial_count(c)));
     w.pu = dalloc<double>(nblk(w.N));
     w.nq_part = schur_partial_count(c);
     w.pq = dalloc<double>(std::max<int64_t>(w.nq_part, nblk(w.N)));

@@ -40,6 +40,22 @@ TabK<P, T> make_tabk(const Tables<T>& t) {
     return k;
 }
 
+// Tables live in device memory in the constant address space, so that loads
+// with wavefront-uniform addresses become scalar loads.  `stage_tab` hides
+// the table pointer from loop-invariant code motion: each stage re-reads its
+// 1D matrix (a few scalar-cache hits) instead of the compiler hoisting every
+// table into scalar registers up front, which would exceed the scalar
+// register file and spill into vector-register lanes.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> stage_tab(cptr<T> p) {
+    uint64_t v = (uint64_t)p;
+    asm volatile("" : "+s"(v));
+    return (cptr<T>)v;
+}
+
 // Pencil index helpers for a (N0, N1, N2) array, contraction along DIM.
 template <int N0, int N1, int N2, int DIM>
 struct PencilGeom {
@@ -55,8 +71,8 @@ struct PencilGeom {
 };
 
 // out-pencil = B * in-pencil, B(o, s) = TR ? Bm[s][o] : Bm[o][s].
-template <typename T, int K, int M, int LDB, bool TR>
-__device__ __forceinline__ void pencil_mul(const T (&in)[K], T (&out)[M], const T* Bm) {
+template <typename T, int K, int M, int LDB, bool TR, typename BP>
+__device__ __forceinline__ void pencil_mul(const T (&in)[K], T (&out)[M], BP Bm) {
 #pragma unroll
     for (int o = 0; o < M; ++o) {
         T s = 0;
@@ -87,8 +103,8 @@ __device__ __forceinline__ void pencil_store(T* dst, int t, const T (&v)[M]) {
 }
 
 // Full LDS -> LDS stage: contract `src` (N0,N1,N2) along DIM to extent M.
-template <typename T, int N0, int N1, int N2, int DIM, int M, int LDB, bool TR>
-__device__ __forceinline__ void stage_lds(const T* src, T* dst, const T* Bm, int t) {
+template <typename T, int N0, int N1, int N2, int DIM, int M, int LDB, bool TR, typename BP>
+__device__ __forceinline__ void stage_lds(const T* src, T* dst, BP Bm, int t) {
     using G = PencilGeom<N0, N1, N2, DIM>;
     if (t < G::NP) {
         T in[G::K], out[M];
