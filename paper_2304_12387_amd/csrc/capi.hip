@@ -47,8 +47,12 @@ void free_prec(hd_ctx* c) {
     dfree(c->d_wdiag);
     dfree(c->d_mdinv);
     dfree(c->d_mdinv32);
-    c->d_mdiag = c->d_wdiag = c->d_mdinv = nullptr;
-    c->d_mdinv32 = nullptr;
+    dfree(c->d_wface);
+    dfree(c->d_wface32);
+    dfree(c->d_sdiag);
+    dfree(c->d_sdiag32);
+    c->d_mdiag = c->d_wdiag = c->d_mdinv = c->d_wface = c->d_sdiag = nullptr;
+    c->d_mdinv32 = c->d_wface32 = c->d_sdiag32 = nullptr;
     c->host_amg = HostAMG();
     c->have_prec = false;
 }
@@ -290,7 +294,13 @@ int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
     c->d_mdinv = dalloc<double>(c->n_u);
     c->d_mdinv32 = dalloc<float>(c->n_u);
     c->d_wdiag = dalloc<double>(c->n_q);
-    if (!c->d_mdiag || !c->d_mdinv || !c->d_mdinv32 || !c->d_wdiag) return set_err(c, HD_ERR_OOM, "diagonals");
+    c->d_wface = dalloc<double>(c->n_u);
+    c->d_wface32 = dalloc<float>(c->n_u);
+    c->d_sdiag = dalloc<double>(c->n_q);
+    c->d_sdiag32 = dalloc<float>(c->n_q);
+    if (!c->d_mdiag || !c->d_mdinv || !c->d_mdinv32 || !c->d_wdiag || !c->d_wface || !c->d_wface32 || !c->d_sdiag ||
+        !c->d_sdiag32)
+        return set_err(c, HD_ERR_OOM, "diagonals");
     if ((rc = launch_diagonals(c))) return rc;
     if ((rc = launch_schur(c))) return rc;
     // S~ to the host for the AMG setup

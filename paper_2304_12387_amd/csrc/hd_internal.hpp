@@ -122,6 +122,10 @@ struct hd_ctx {
     double* d_wdiag = nullptr;   // diag(W) unweighted
     double* d_mdinv = nullptr;   // 1 / (tau diag(M)), 1 on essential dofs
     float* d_mdinv32 = nullptr;
+    double* d_wface = nullptr;   // 1 / M~_kk on free interior faces, 0 elsewhere (n_u)
+    float* d_wface32 = nullptr;
+    double* d_sdiag = nullptr;   // diagonal of S~ (n_q)
+    float* d_sdiag32 = nullptr;
     hd::DevCSR S;                // S~
     std::vector<hd::DevLevel> lev;
     int64_t n_coarse = 0;

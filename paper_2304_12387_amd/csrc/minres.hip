@@ -34,6 +34,9 @@ namespace {
 
 constexpr int BS = 256;
 inline unsigned nblk(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
+// kernels emitting per-block partial sums use at most RED_BLOCKS blocks
+constexpr unsigned RED_BLOCKS = 1024;
+inline unsigned red_grid(int64_t n) { return nblk(n) < RED_BLOCKS ? nblk(n) : RED_BLOCKS; }
 
 struct MinresState {
     double gamma, gamma_old, delta;
@@ -150,16 +153,15 @@ __global__ void k_vupd(int64_t N, int64_t nu, const T* __restrict__ q, const T* 
                        double* __restrict__ part) {
     if (st->stop) return;
     __shared__ double s[BS];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const T cv1 = (T)st->cv1, cv2 = (T)st->cv2;
     double contrib = 0.0;
-    if (i < N) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
         const T vn = q[i] - cv1 * v[i] - cv2 * vo[i];
         vo[i] = vn;
         if (i < nu) {
             const T zi = mdinv[i] * vn;
             z[i] = zi;
-            contrib = (double)zi * (double)vn;
+            contrib += (double)zi * (double)vn;
         }
     }
     s[threadIdx.x] = contrib;
@@ -206,13 +208,12 @@ __global__ void k_zero(int64_t N, T* __restrict__ x) {
 __global__ void k_residual(int64_t N, const double* __restrict__ b, const double* __restrict__ q,
                            double* __restrict__ r, double* __restrict__ pr, double* __restrict__ pb) {
     __shared__ double s[BS];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double rr = 0.0, bb = 0.0;
-    if (i < N) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
         const double ri = b[i] - q[i];
         if (r) r[i] = ri;
-        rr = ri * ri;
-        bb = b[i] * b[i];
+        rr += ri * ri;
+        bb += b[i] * b[i];
     }
     s[threadIdx.x] = rr;
     __syncthreads();
@@ -329,7 +330,7 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
     if ((rc = launch_diag_prec(c, prec, v, z, wk.pu))) return rc;
     // the diag kernel covers n_u rows; its partial count is nblk(n_u) <= nblk(N)
     if ((rc = launch_schur_prec(c, prec, v + nu, z + nu, wk.pq, nullptr))) return rc;
-    hipLaunchKernelGGL(k_start, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)nblk(nu), wk.pq,
+    hipLaunchKernelGGL(k_start, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)red_grid(nu), wk.pq,
                        wk.nq_part, tol);
     HD_HIP(c, hipGetLastError());
     const int* stop = &wk.st->stop;
@@ -338,11 +339,11 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
         for (int k = 0; k < check_every && it_launched < maxit; ++k, ++it_launched) {
             if ((rc = launch_apply(c, prec, z, q, &wk.st->inv_gamma, wk.pd, ESS_IDENTITY, stop))) return rc;
             hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pd, apply_partial_count(c));
-            hipLaunchKernelGGL(k_vupd<T>, dim3(nblk(N)), dim3(BS), 0, c->stream, N, nu, q, v, vo, mdinv, zn, wk.st,
-                               wk.pu);
+            hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N)), dim3(BS), 0, c->stream, N, nu, q, v, vo, mdinv, zn,
+                               wk.st, wk.pu);
             if ((rc = launch_schur_prec(c, prec, vo + nu, zn + nu, wk.pq, stop))) return rc;
-            hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)nblk(N), wk.pq,
-                               wk.nq_part, maxit);
+            hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)red_grid(N),
+                               wk.pq, wk.nq_part, maxit);
             hipLaunchKernelGGL((k_wupd<T, T>), dim3(nblk(N)), dim3(BS), 0, c->stream, N, z, wo, w, x, wk.st);
             std::swap(v, vo);
             std::swap(z, zn);
@@ -394,11 +395,10 @@ int true_residual(hd_ctx* c, Work& wk64, const double* b, const double* x, doubl
     const int64_t N = c->n_u + c->n_q;
     int rc;
     if ((rc = launch_apply(c, HD_F64, x, wk64.q, nullptr, nullptr, ESS_IDENTITY, nullptr))) return rc;
-    hipLaunchKernelGGL(k_residual, dim3(nblk(N)), dim3(BS), 0, c->stream, N, b, (const double*)wk64.q, r, wk64.pu,
-                       wk64.pq);
-    // the pq buffer holds nblk(n_q) entries; use pu (nblk(N)) for r and the tail of pd for b
-    if ((rc = reduce_sum_partials(c, wk64.pu, nblk(N), c->d_scal + 0))) return rc;
-    if ((rc = reduce_sum_partials(c, wk64.pq, nblk(N), c->d_scal + 1))) return rc;
+    hipLaunchKernelGGL(k_residual, dim3(red_grid(N)), dim3(BS), 0, c->stream, N, b, (const double*)wk64.q, r,
+                       wk64.pu, wk64.pq);
+    if ((rc = reduce_sum_partials(c, wk64.pu, red_grid(N), c->d_scal + 0))) return rc;
+    if ((rc = reduce_sum_partials(c, wk64.pq, red_grid(N), c->d_scal + 1))) return rc;
     hipLaunchKernelGGL(k_sqrt, dim3(1), dim3(64), 0, c->stream, c->d_scal, 2);
     double h[2];
     HD_HIP(c, hipMemcpyAsync(h, c->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));

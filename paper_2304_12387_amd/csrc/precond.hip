@@ -24,6 +24,97 @@ constexpr int BS = 256;
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
 
+// Kernels that emit per-block partial sums use at most RED_BLOCKS blocks with
+// a grid-stride loop, so that the one-block final reductions stay short.
+constexpr unsigned RED_BLOCKS = 1024;
+inline unsigned red_grid(int64_t n) { return nblk(n) < RED_BLOCKS ? nblk(n) : RED_BLOCKS; }
+
+// ---------------------------------------------------------------------------
+// Level 0 of the hierarchy is S~ itself, the 7-point sub-volume operator of
+// eq. (approx-schur-entries): S~ x = diag(S~) x - sum over the free interior
+// faces k of w_k x_{neighbour(k)}, w_k = 1/M~_kk.  It is applied matrix-free
+// from diag(S~) and the face weights, walking the structured neighbours.
+// ---------------------------------------------------------------------------
+template <int P, typename F>
+__device__ __forceinline__ void for_each_coupling(const Geo& g, int64_t i, F&& f) {
+    constexpr int NL = P * P * P;
+    const int64_t e = i / NL;
+    const int l = (int)(i % NL);
+    const int a = l % P, b = (l / P) % P, c = l / (P * P);
+    const int ex = (int)(e % g.nx), ey = (int)((e / g.nx) % g.ny), ez = (int)(e / ((int64_t)g.nx * g.ny));
+    const int64_t nxp = (int64_t)g.nx * P, nyp = (int64_t)g.ny * P;
+    const int64_t gx = (int64_t)ex * P + a, gy = (int64_t)ey * P + b, gz = (int64_t)ez * P + c;
+    const int64_t eNL = NL, rowNL = (int64_t)g.nx * NL, planeNL = (int64_t)g.nx * g.ny * NL;
+    // x-normal faces
+    {
+        const int64_t k = g.off[0] + gx + (nxp + 1) * (gy + nyp * gz);
+        if (a > 0) f(k, i - 1);
+        else if (ex > 0) f(k, i - eNL + (P - 1));
+        if (a < P - 1) f(k + 1, i + 1);
+        else if (ex < g.nx - 1) f(k + 1, i + eNL - (P - 1));
+    }
+    // y-normal faces
+    {
+        const int64_t k = g.off[1] + gx + nxp * (gy + (nyp + 1) * gz);
+        if (b > 0) f(k, i - P);
+        else if (ey > 0) f(k, i - rowNL + (P - 1) * P);
+        if (b < P - 1) f(k + nxp, i + P);
+        else if (ey < g.ny - 1) f(k + nxp, i + rowNL - (P - 1) * P);
+    }
+    // z-normal faces
+    {
+        const int64_t k = g.off[2] + gx + nxp * (gy + nyp * gz);
+        if (c > 0) f(k, i - P * P);
+        else if (ez > 0) f(k, i - planeNL + (P - 1) * P * P);
+        if (c < P - 1) f(k + nxp * nyp, i + P * P);
+        else if (ez < g.nz - 1) f(k + nxp * nyp, i + planeNL - (P - 1) * P * P);
+    }
+}
+
+// x = dinv b;  r = b - S~ (dinv b)
+template <int P, typename T>
+__global__ __launch_bounds__(BS) void s0_pre_kernel(Geo g, int64_t n, const T* __restrict__ sdiag,
+                                                    const T* __restrict__ wf, const T* __restrict__ dinv,
+                                                    const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r,
+                                                    const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+    if (i >= n) return;
+    T off = 0;
+    for_each_coupling<P>(g, i, [&](int64_t k, int64_t j) { off += wf[k] * (dinv[j] * b[j]); });
+    const T xi = dinv[i] * b[i];
+    x[i] = xi;
+    r[i] = b[i] - (sdiag[i] * xi - off);
+}
+
+// z = x + dinv (b - S~ x), per-block partials of z (kind 1) or z b (kind 2)
+template <int P, typename T>
+__global__ __launch_bounds__(BS) void s0_post_kernel(Geo g, int64_t n, const T* __restrict__ sdiag,
+                                                     const T* __restrict__ wf, const T* __restrict__ dinv,
+                                                     const T* __restrict__ b, const T* __restrict__ x,
+                                                     T* __restrict__ z, double* __restrict__ part, int part_kind,
+                                                     const int* __restrict__ done) {
+    if (done && *done) return;
+    double contrib = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        T off = 0;
+        for_each_coupling<P>(g, i, [&](int64_t k, int64_t j) { off += wf[k] * x[j]; });
+        const T zi = x[i] + dinv[i] * (b[i] - (sdiag[i] * x[i] - off));
+        z[i] = zi;
+        contrib += part_kind == 1 ? (double)zi : (double)zi * (double)b[i];
+    }
+    if (part) {
+        __shared__ double s[BS];
+        s[threadIdx.x] = contrib;
+        __syncthreads();
+        for (int off = BS / 2; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+    }
+}
+
 // Sub-wave CSR row products: a group of G lanes (G a power of two <= 64)
 // handles one row; the group sum is formed with cross-lane shuffles.
 template <int G, typename T, typename F>
@@ -113,13 +204,12 @@ __global__ void vc_sub_mean_kernel(int64_t n, const double* __restrict__ sum, co
                                    T* __restrict__ z, double* __restrict__ part, const int* __restrict__ done) {
     if (done && *done) return;
     __shared__ double s[BS];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const double mean = *sum / (double)n;
     double contrib = 0.0;
-    if (i < n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
         const T zi = (T)((double)z[i] - mean);
         z[i] = zi;
-        contrib = (double)zi * (double)b[i];
+        contrib += (double)zi * (double)b[i];
     }
     if (part) {
         s[threadIdx.x] = contrib;
@@ -151,12 +241,11 @@ template <typename T>
 __global__ void diag_prec_kernel(int64_t n, const T* __restrict__ mdinv, const T* __restrict__ r, T* __restrict__ z,
                                  double* __restrict__ part) {
     __shared__ double s[BS];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double contrib = 0.0;
-    if (i < n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
         const T zi = mdinv[i] * r[i];
         z[i] = zi;
-        contrib = (double)zi * (double)r[i];
+        contrib += (double)zi * (double)r[i];
     }
     if (part) {
         s[threadIdx.x] = contrib;
@@ -184,7 +273,7 @@ T* pickw(double* d, float* f) {
 inline int group_of(const DevCSR& m) {
     const double avg = m.nrows ? (double)m.nnz / (double)m.nrows : 1.0;
     int g = 4;
-    while (g < 64 && g < avg) g *= 2;
+    while (g < 64 && 1.5 * g < avg) g *= 2;
     return g;
 }
 
@@ -221,12 +310,44 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
 #define RES(G, ...) hipLaunchKernelGGL((vc_spmv_kernel<G, T, false>), dim3(gblk(lv.R.nrows, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
 #define PRO(G, ...) hipLaunchKernelGGL((vc_spmv_kernel<G, T, true>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
 #define POST(G, ...) hipLaunchKernelGGL((vc_post_kernel<G, T>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
-    HD_GROUP_DISPATCH(gA, PRE, n, lv.A.rp, lv.A.ci, av, dinv, b, x, r, done)
+    if (l == 0) {
+        const T* sd = pick<T>(c->d_sdiag, c->d_sdiag32);
+        const T* wf = pick<T>(c->d_wface, c->d_wface32);
+        const Geo g = geo_of(c);
+#define S0PRE(PP) hipLaunchKernelGGL((s0_pre_kernel<PP, T>), dim3(nblk(n)), dim3(BS), 0, c->stream, g, n, sd, wf, dinv, b, x, r, done)
+        switch (c->p) {
+            case 1: S0PRE(1); break;
+            case 2: S0PRE(2); break;
+            case 3: S0PRE(3); break;
+            case 4: S0PRE(4); break;
+            case 5: S0PRE(5); break;
+            default: S0PRE(6); break;
+        }
+#undef S0PRE
+    } else {
+        HD_GROUP_DISPATCH(gA, PRE, n, lv.A.rp, lv.A.ci, av, dinv, b, x, r, done)
+    }
     HD_GROUP_DISPATCH(gR, RES, lv.R.nrows, lv.R.rp, lv.R.ci, pick<T>(lv.R.v, lv.R.v32), (const T*)r, bc, done)
     int rc = cycle<T>(c, l + 1, bc, zc, nullptr, 0, done);
     if (rc) return rc;
     HD_GROUP_DISPATCH(gP, PRO, n, lv.P.rp, lv.P.ci, pick<T>(lv.P.v, lv.P.v32), (const T*)zc, x, done)
-    HD_GROUP_DISPATCH(gA, POST, n, lv.A.rp, lv.A.ci, av, dinv, b, (const T*)x, z, part, part_kind, done)
+    if (l == 0) {
+        const T* sd = pick<T>(c->d_sdiag, c->d_sdiag32);
+        const T* wf = pick<T>(c->d_wface, c->d_wface32);
+        const Geo g = geo_of(c);
+#define S0POST(PP) hipLaunchKernelGGL((s0_post_kernel<PP, T>), dim3(part ? red_grid(n) : nblk(n)), dim3(BS), 0, c->stream, g, n, sd, wf, dinv, b, (const T*)x, z, part, part_kind, done)
+        switch (c->p) {
+            case 1: S0POST(1); break;
+            case 2: S0POST(2); break;
+            case 3: S0POST(3); break;
+            case 4: S0POST(4); break;
+            case 5: S0POST(5); break;
+            default: S0POST(6); break;
+        }
+#undef S0POST
+    } else {
+        HD_GROUP_DISPATCH(gA, POST, n, lv.A.rp, lv.A.ci, av, dinv, b, (const T*)x, z, part, part_kind, done)
+    }
 #undef PRE
 #undef RES
 #undef PRO
@@ -239,8 +360,10 @@ __global__ void sum_partial_kernel(int64_t n, const T* __restrict__ a, const T* 
                                    double* __restrict__ part, const int* __restrict__ done) {
     if (done && *done) return;
     __shared__ double s[BS];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    s[threadIdx.x] = i < n ? (b ? (double)a[i] * (double)b[i] : (double)a[i]) : 0.0;
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        acc += b ? (double)a[i] * (double)b[i] : (double)a[i];
+    s[threadIdx.x] = acc;
     __syncthreads();
     for (int off = BS / 2; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
@@ -249,11 +372,8 @@ __global__ void sum_partial_kernel(int64_t n, const T* __restrict__ a, const T* 
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-// Number of per-block partial sums the level-0 post-smoothing writes.
-int64_t post_partials(const hd_ctx* c) {
-    if (c->lev.size() <= 1) return nblk(c->n_q);
-    return gblk(c->n_q, group_of(c->lev[0].A));
-}
+// Number of per-block partial sums of every kernel that reduces over the L2 dofs.
+int64_t post_partials(const hd_ctx* c) { return red_grid(c->n_q); }
 
 // z = S^{-1} b on the L2 dofs; `part` (optional) receives per-block partial
 // sums of z * b (after the constant has been removed in the singular case);
@@ -266,7 +386,7 @@ int schur_apply(hd_ctx* c, const T* b, T* z, double* part, const int* done) {
         int rc = cycle<T>(c, 0, b, z, one_level ? nullptr : part, 2, done);
         if (rc) return rc;
         if (one_level && part)
-            hipLaunchKernelGGL(sum_partial_kernel<T>, dim3(nblk(n)), dim3(BS), 0, c->stream, n, z, b, part, done);
+            hipLaunchKernelGGL(sum_partial_kernel<T>, dim3(red_grid(n)), dim3(BS), 0, c->stream, n, z, b, part, done);
         return HD_OK;
     }
     const int64_t np = post_partials(c);
@@ -276,12 +396,12 @@ int schur_apply(hd_ctx* c, const T* b, T* z, double* part, const int* done) {
     rc = cycle<T>(c, 0, b, z, one_level ? nullptr : zs, 1, done);
     if (rc) return rc;
     if (one_level)
-        hipLaunchKernelGGL(sum_partial_kernel<T>, dim3(nblk(n)), dim3(BS), 0, c->stream, n, z, (const T*)nullptr, zs,
-                           done);
+        hipLaunchKernelGGL(sum_partial_kernel<T>, dim3(red_grid(n)), dim3(BS), 0, c->stream, n, z, (const T*)nullptr,
+                           zs, done);
     rc = reduce_sum_partials(c, zs, np, c->d_scal + 6);
     if (rc) return rc;
-    hipLaunchKernelGGL(vc_sub_mean_kernel<T>, dim3(nblk(n)), dim3(BS), 0, c->stream, n, c->d_scal + 6, b, z, part,
-                       done);
+    hipLaunchKernelGGL(vc_sub_mean_kernel<T>, dim3(red_grid(n)), dim3(BS), 0, c->stream, n, c->d_scal + 6, b, z,
+                       part, done);
     return HD_OK;
 }
 
@@ -290,10 +410,10 @@ int schur_apply(hd_ctx* c, const T* b, T* z, double* part, const int* done) {
 int launch_diag_prec(hd_ctx* c, int prec, const void* r, void* z, double* part) {
     const int64_t n = c->n_u;
     if (prec == HD_F64)
-        hipLaunchKernelGGL(diag_prec_kernel<double>, dim3(nblk(n)), dim3(BS), 0, c->stream, n, c->d_mdinv,
+        hipLaunchKernelGGL(diag_prec_kernel<double>, dim3(red_grid(n)), dim3(BS), 0, c->stream, n, c->d_mdinv,
                            (const double*)r, (double*)z, part);
     else
-        hipLaunchKernelGGL(diag_prec_kernel<float>, dim3(nblk(n)), dim3(BS), 0, c->stream, n, c->d_mdinv32,
+        hipLaunchKernelGGL(diag_prec_kernel<float>, dim3(red_grid(n)), dim3(BS), 0, c->stream, n, c->d_mdinv32,
                            (const float*)r, (float*)z, part);
     HD_HIP(c, hipGetLastError());
     return HD_OK;
@@ -307,10 +427,7 @@ int launch_schur_prec(hd_ctx* c, int prec, const void* b, void* z, double* part,
     return HD_OK;
 }
 
-int64_t schur_partial_count(const hd_ctx* c) {
-    if (c->singular || c->lev.size() <= 1) return nblk(c->n_q);
-    return post_partials(c);
-}
+int64_t schur_partial_count(const hd_ctx* c) { return red_grid(c->n_q); }
 
 int launch_precond(hd_ctx* c, int prec, const void* r, void* z, double* dot_partial_u, double* dot_partial_q,
                    const int* done) {

@@ -161,19 +161,32 @@ __global__ void fill_kernel(T* __restrict__ y, T v, int64_t n) {
     if (i < n) y[i] = v;
 }
 
-// essential dofs of diag(M) -> 1; inverse of tau diag(M) in FP64 and FP32
+// essential dofs of diag(M) -> 1; inverse of tau diag(M) in FP64 and FP32;
+// coupling weight 1/M~_kk of every free face shared by two sub-volumes (0 on
+// essential and domain-boundary faces), the off-diagonal magnitude of S~
 __global__ void mdiag_finish_kernel(Geo g, int P, uint32_t ess, double tau, double* __restrict__ mdiag,
-                                    double* __restrict__ mdinv, float* __restrict__ mdinv32, int64_t n_u) {
+                                    double* __restrict__ mdinv, float* __restrict__ mdinv32,
+                                    double* __restrict__ wface, float* __restrict__ wface32, int64_t n_u) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= n_u) return;
+    const int c = t >= g.off[2] ? 2 : (t >= g.off[1] ? 1 : 0);
+    const int64_t r = t - g.off[c];
+    const int64_t d0 = (int64_t)g.nx * P + (c == 0), d1 = (int64_t)g.ny * P + (c == 1);
+    const int64_t coord = c == 0 ? r % d0 : (c == 1 ? (r / d0) % d1 : r / (d0 * d1));
+    const int64_t nal = c == 0 ? (int64_t)g.nx * P : (c == 1 ? (int64_t)g.ny * P : (int64_t)g.nz * P);
+    const bool boundary = coord == 0 || coord == nal;
     if (rt_is_essential(g, P, ess, t)) {
         mdiag[t] = 1.0;
         mdinv[t] = 1.0;
         mdinv32[t] = 1.0f;
+        wface[t] = 0.0;
+        wface32[t] = 0.0f;
     } else {
         const double m = mdiag[t];
         mdinv[t] = 1.0 / (tau * m);
         mdinv32[t] = (float)(1.0 / (tau * m));
+        wface[t] = boundary ? 0.0 : 1.0 / m;
+        wface32[t] = boundary ? 0.0f : (float)(1.0 / m);
     }
 }
 
@@ -257,7 +270,7 @@ __global__ void schur_count_kernel(Geo g, int P, uint32_t ess, int64_t nq, const
 __global__ void schur_fill_kernel(Geo g, int P, uint32_t ess, int64_t nq, const double* __restrict__ mdiag,
                                   const double* __restrict__ wdiag, const double* __restrict__ kap,
                                   const int32_t* __restrict__ rp, int32_t* __restrict__ ci, double* __restrict__ v,
-                                  float* __restrict__ v32) {
+                                  float* __restrict__ v32, double* __restrict__ sdiag, float* __restrict__ sdiag32) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nq) return;
     RowEnt ent[7];
@@ -267,6 +280,10 @@ __global__ void schur_fill_kernel(Geo g, int P, uint32_t ess, int64_t nq, const 
         ci[o + k] = ent[k].col;
         v[o + k] = ent[k].val;
         v32[o + k] = (float)ent[k].val;
+        if (ent[k].col == (int32_t)i) {
+            sdiag[i] = ent[k].val;
+            sdiag32[i] = (float)ent[k].val;
+        }
     }
 }
 
@@ -403,7 +420,7 @@ int launch_diagonals(hd_ctx* c) {
         default: return set_err(c, HD_ERR_ARG, "p out of range");
     }
     hipLaunchKernelGGL(mdiag_finish_kernel, dim3((unsigned)((c->n_u + bs - 1) / bs)), dim3(bs), 0, c->stream, g,
-                       c->p, c->ess, c->tau, c->d_mdiag, c->d_mdinv, c->d_mdinv32, c->n_u);
+                       c->p, c->ess, c->tau, c->d_mdiag, c->d_mdinv, c->d_mdinv32, c->d_wface, c->d_wface32, c->n_u);
     HD_HIP(c, hipGetLastError());
     return HD_OK;
 }
@@ -451,7 +468,7 @@ int launch_schur(hd_ctx* c) {
     S.v32 = dalloc<float>(nnz);
     if (!S.ci || !S.v || !S.v32) return set_err(c, HD_ERR_OOM, "S~ storage");
     hipLaunchKernelGGL(schur_fill_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, c->stream, g, c->p,
-                       c->ess, n, c->d_mdiag, c->d_wdiag, c->d_kap, S.rp, S.ci, S.v, S.v32);
+                       c->ess, n, c->d_mdiag, c->d_wdiag, c->d_kap, S.rp, S.ci, S.v, S.v32, c->d_sdiag, c->d_sdiag32);
     HD_HIP(c, hipGetLastError());
     return HD_OK;
 }
