@@ -148,7 +148,7 @@ int hd_sizes(const hd_ctx* ctx, int64_t* n_u, int64_t* n_q);
 int hd_apply_block_op(hd_ctx* ctx, int prec, int nrhs, const void* x, void* y);
 
 /* y_q = C x_q = kappa_e W_e^{-1} x_q per element (the (2,2) block without
- * its sign), for L2 vectors of length n_q.  For HD_DARCY with gamma = 0 use
+ * its sign), for nrhs L2 vectors of length n_q stored one after the other.  For HD_DARCY with gamma = 0 use
  * hd_apply_l2_mass_inverse.  Section 2.5. */
 int hd_apply_mass_inverse(hd_ctx* ctx, int prec, int nrhs, const void* x, void* y);
 

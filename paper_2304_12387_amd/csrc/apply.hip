@@ -368,16 +368,28 @@ __device__ __forceinline__ double finish_rt(ElemLDS<P, T>& L, const Geo& g, int 
     return dot;
 }
 
+// Per-right-hand-side arguments of the apply: nrhs vectors stored one after
+// the other (stride ldv); optional per-RHS input scale and skip flag (strided
+// views into caller state) and per-RHS partial sums of <A x, x>.
+struct RhsArgs {
+    int nrhs;
+    int64_t ldv;
+    const double* scale;
+    int scale_stride;
+    const int* done;
+    int done_stride;
+    double* partial;
+    int64_t part_stride;
+};
+
 template <int P, typename T>
 __global__ __launch_bounds__(64) void block_apply_kernel(
     Geo g, const T* __restrict__ pa, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
-    int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ x, T* __restrict__ y,
-    const double* __restrict__ in_scale, double* __restrict__ dot_partial, const int* __restrict__ done,
+    int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
     CGParams<T> cgp, int with_c, int colour, int64_t part_offset) {
-    if (done && *done) return;
     using D = Dim<P>;
     using S = Slot<P>;
-    constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC, NRT = D::NRT, W = S::W;
+    constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC, W = S::W;
     __shared__ ElemLDS<P, T> sm[S::EPW];
     const int lane = threadIdx.x;
     const int slot = lane / W, t = lane % W;
@@ -392,11 +404,11 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     const int ex = valid ? ex0 : 0, ey = valid ? ey0 : 0, ez = valid ? ez0 : 0;
     const int64_t ee = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);   // clamped for address arithmetic
     ElemLDS<P, T>& L = sm[slot];
-    const T s_in = in_scale ? (T)(*in_scale) : T(1);
     const T cM = cm[ee];
     const T kE = kap[ee];
-    // issue the loads of this lane's geometric factors first so that they are
-    // in flight during the gather and the forward sum factorisation
+    // the lane's geometric factors are loaded once and serve every right-hand
+    // side; they are issued first so that they are in flight during the
+    // gather and the forward sum factorisation
     T G[NPA][Q];
     {
         const T* pe = pa + (size_t)ee * NPA * Q3 + (t < Q * Q ? t : 0);
@@ -405,67 +417,74 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
 #pragma unroll
             for (int c = 0; c < Q; ++c) G[m][c] = pe[m * Q3 + Q * Q * c];
     }
-    // gather u (essential dofs read as zero) and q~
-    if (valid) {
-        gather_rt<P, T, 0>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
-        gather_rt<P, T, 1>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
-        gather_rt<P, T, 2>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
-        for (int l = t; l < NL; l += W) L.sq[l] = s_in * x[n_u + ee * NL + l];
-    }
-    __syncthreads();
-    // D u (element-local, +1 upper face, -1 lower face)
-    if (valid) {
-        for (int l = t; l < NL; l += W) {
-            const int a = l % P, b = (l / P) % P, c = l / (P * P);
-            T v = L.su[(a + 1) + (P + 1) * (b + P * c)] - L.su[a + (P + 1) * (b + P * c)];
-            v += L.su[NC + a + P * ((b + 1) + (P + 1) * c)] - L.su[NC + a + P * (b + (P + 1) * c)];
-            v += L.su[2 * NC + a + P * (b + P * (c + 1))] - L.su[2 * NC + a + P * (b + P * c)];
-            L.syq[l] = v;
+    for (int r = 0; r < ra.nrhs; ++r) {
+        if (ra.done && ra.done[(int64_t)r * ra.done_stride]) continue;
+        const T* __restrict__ x = xall + r * ra.ldv;
+        T* __restrict__ y = yall + r * ra.ldv;
+        const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
+        __syncthreads();
+        // gather u (essential dofs read as zero) and q~
+        if (valid) {
+            gather_rt<P, T, 0>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
+            gather_rt<P, T, 1>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
+            gather_rt<P, T, 2>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
+            for (int l = t; l < NL; l += W) L.sq[l] = s_in * x[n_u + ee * NL + l];
         }
-    }
-    // M u: the three components to the quadrature points
-    T U0[Q], U1[Q], U2[Q];
-    rt_to_quad<P, T, 0>(L, tb, t, U0);
-    rt_to_quad<P, T, 1>(L, tb, t, U1);
-    rt_to_quad<P, T, 2>(L, tb, t, U2);
-    // geometric factors (c_mass w J^T J / det J) at the quadrature column (a, b, .)
-    T gw[Q];
-    if (t < Q * Q) {
+        __syncthreads();
+        // D u (element-local, +1 upper face, -1 lower face)
+        if (valid) {
+            for (int l = t; l < NL; l += W) {
+                const int a = l % P, b = (l / P) % P, c = l / (P * P);
+                T v = L.su[(a + 1) + (P + 1) * (b + P * c)] - L.su[a + (P + 1) * (b + P * c)];
+                v += L.su[NC + a + P * ((b + 1) + (P + 1) * c)] - L.su[NC + a + P * (b + (P + 1) * c)];
+                v += L.su[2 * NC + a + P * (b + P * (c + 1))] - L.su[2 * NC + a + P * (b + P * c)];
+                L.syq[l] = v;
+            }
+        }
+        // M u: the three components to the quadrature points
+        T U0[Q], U1[Q], U2[Q];
+        rt_to_quad<P, T, 0>(L, tb, t, U0);
+        rt_to_quad<P, T, 1>(L, tb, t, U1);
+        rt_to_quad<P, T, 2>(L, tb, t, U2);
+        // c_mass w J^T J / det J at the quadrature column (a, b, .)
+        T gw[Q];
+        if (t < Q * Q) {
 #pragma unroll
-        for (int c = 0; c < Q; ++c) {
-            const T a0 = U0[c], a1 = U1[c], a2 = U2[c];
-            U0[c] = cM * (G[0][c] * a0 + G[1][c] * a1 + G[2][c] * a2);
-            U1[c] = cM * (G[1][c] * a0 + G[3][c] * a1 + G[4][c] * a2);
-            U2[c] = cM * (G[2][c] * a0 + G[4][c] * a1 + G[5][c] * a2);
-            gw[c] = G[6][c];
-        }
-    } else {
+            for (int c = 0; c < Q; ++c) {
+                const T a0 = U0[c], a1 = U1[c], a2 = U2[c];
+                U0[c] = cM * (G[0][c] * a0 + G[1][c] * a1 + G[2][c] * a2);
+                U1[c] = cM * (G[1][c] * a0 + G[3][c] * a1 + G[4][c] * a2);
+                U2[c] = cM * (G[2][c] * a0 + G[4][c] * a1 + G[5][c] * a2);
+                gw[c] = G[6][c];
+            }
+        } else {
 #pragma unroll
-        for (int c = 0; c < Q; ++c) gw[c] = T(1);
-    }
-    double dot = 0.0;
-    {
-        T yv[Q];
-        quad_to_rt<P, T, 0>(L, tb, t, U0, yv);
-        if (valid) dot += finish_rt<P, T, 0>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
-        quad_to_rt<P, T, 1>(L, tb, t, U1, yv);
-        if (valid) dot += finish_rt<P, T, 1>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
-        quad_to_rt<P, T, 2>(L, tb, t, U2, yv);
-        if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
-    }
-    // -kappa_e W_e^{-1} q~
-    if (with_c) local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
-    __syncthreads();
-    if (valid) {
-        for (int l = t; l < NL; l += W) {
-            const T v = L.syq[l];
-            y[n_u + ee * NL + l] = v;
-            dot += (double)v * (double)L.sq[l];
+            for (int c = 0; c < Q; ++c) gw[c] = T(1);
         }
-    }
-    if (dot_partial) {
-        dot = slot_sum<double, 64>(dot);
-        if (lane == 0) dot_partial[part_offset + blockIdx.x] = dot;
+        double dot = 0.0;
+        {
+            T yv[Q];
+            quad_to_rt<P, T, 0>(L, tb, t, U0, yv);
+            if (valid) dot += finish_rt<P, T, 0>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
+            quad_to_rt<P, T, 1>(L, tb, t, U1, yv);
+            if (valid) dot += finish_rt<P, T, 1>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
+            quad_to_rt<P, T, 2>(L, tb, t, U2, yv);
+            if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
+        }
+        // -kappa_e W_e^{-1} q~
+        if (with_c) local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
+        __syncthreads();
+        if (valid) {
+            for (int l = t; l < NL; l += W) {
+                const T v = L.syq[l];
+                y[n_u + ee * NL + l] = v;
+                dot += (double)v * (double)L.sq[l];
+            }
+        }
+        if (ra.partial) {
+            dot = slot_sum<double, 64>(dot);
+            if (lane == 0) ra.partial[r * ra.part_stride + part_offset + blockIdx.x] = dot;
+        }
     }
 }
 
@@ -523,8 +542,7 @@ template <>
 CGParams<float> cg_params<float>() { return {1e-6f, 32}; }
 
 template <int P, typename T>
-void launch_apply_p(hd_ctx* c, const T* x, T* y, const double* in_scale, double* dot_partial, int ess_mode,
-                    const int* done) {
+void launch_apply_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int ess_mode) {
     Geo g = geo_of(c);
     const T* pa = std::is_same<T, double>::value ? (const T*)c->d_pa : (const T*)c->d_pa32;
     const T* cm = std::is_same<T, double>::value ? (const T*)c->d_cm : (const T*)c->d_cm32;
@@ -533,8 +551,8 @@ void launch_apply_p(hd_ctx* c, const T* x, T* y, const double* in_scale, double*
     const unsigned nb = apply_blocks_per_colour(c->nx, c->ny, c->nz, Slot<P>::EPW);
     for (int colour = 0; colour < 2; ++colour)
         hipLaunchKernelGGL((block_apply_kernel<P, T>), dim3(nb), dim3(64), 0, c->stream, g, pa, tb, cm, kap, c->ess,
-                           ess_mode, c->ne, c->n_u, x, y, in_scale, dot_partial, done, cg_params<T>(),
-                           c->kappa_zero ? 0 : 1, colour, (int64_t)colour * nb);
+                           ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), c->kappa_zero ? 0 : 1, colour,
+                           (int64_t)colour * nb);
 }
 
 template <int P, typename T>
@@ -548,14 +566,14 @@ void launch_minv_p(hd_ctx* c, const T* x, T* y, bool weighted) {
 }
 
 template <typename T>
-void dispatch_apply(hd_ctx* c, const T* x, T* y, const double* s, double* dp, int em, const int* done) {
+void dispatch_apply(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int em) {
     switch (c->p) {
-        case 1: launch_apply_p<1, T>(c, x, y, s, dp, em, done); break;
-        case 2: launch_apply_p<2, T>(c, x, y, s, dp, em, done); break;
-        case 3: launch_apply_p<3, T>(c, x, y, s, dp, em, done); break;
-        case 4: launch_apply_p<4, T>(c, x, y, s, dp, em, done); break;
-        case 5: launch_apply_p<5, T>(c, x, y, s, dp, em, done); break;
-        case 6: launch_apply_p<6, T>(c, x, y, s, dp, em, done); break;
+        case 1: launch_apply_p<1, T>(c, x, y, ra, em); break;
+        case 2: launch_apply_p<2, T>(c, x, y, ra, em); break;
+        case 3: launch_apply_p<3, T>(c, x, y, ra, em); break;
+        case 4: launch_apply_p<4, T>(c, x, y, ra, em); break;
+        case 5: launch_apply_p<5, T>(c, x, y, ra, em); break;
+        case 6: launch_apply_p<6, T>(c, x, y, ra, em); break;
     }
 }
 
@@ -642,7 +660,8 @@ int launch_lift(hd_ctx* c, const double* ubc, double* b) {
     Geo g = geo_of(c);
     const unsigned nb = (unsigned)((N + 255) / 256);
     hipLaunchKernelGGL(lift_prepare_kernel, dim3(nb), dim3(256), 0, c->stream, g, c->p, c->ess, c->n_u, N, ubc, t);
-    dispatch_apply<double>(c, t, y, nullptr, nullptr, ESS_NONE, nullptr);
+    RhsArgs ra = {1, N, nullptr, 0, nullptr, 0, nullptr, 0};
+    dispatch_apply<double>(c, t, y, ra, ESS_NONE);
     hipLaunchKernelGGL(lift_finish_kernel, dim3(nb), dim3(256), 0, c->stream, g, c->p, c->ess, c->n_u, N, ubc, y, b);
     hipError_t e = hipStreamSynchronize(c->stream);
     dfree(t);
@@ -651,13 +670,14 @@ int launch_lift(hd_ctx* c, const double* ubc, double* b) {
     return HD_OK;
 }
 
-int launch_apply(hd_ctx* c, int prec, const void* x, void* y, const double* in_scale, double* dot_partial,
-                 int ess_mode, const int* done) {
+int launch_apply(hd_ctx* c, int prec, int nrhs, const void* x, void* y, const double* in_scale, int scale_stride,
+                 double* dot_partial, int64_t part_stride, int ess_mode, const int* done, int done_stride) {
     if (c->time_apply) HD_HIP(c, hipEventRecord(c->ev0, c->stream));
+    const RhsArgs ra = {nrhs, c->n_u + c->n_q, in_scale, scale_stride, done, done_stride, dot_partial, part_stride};
     if (prec == HD_F64)
-        dispatch_apply<double>(c, (const double*)x, (double*)y, in_scale, dot_partial, ess_mode, done);
+        dispatch_apply<double>(c, (const double*)x, (double*)y, ra, ess_mode);
     else
-        dispatch_apply<float>(c, (const float*)x, (float*)y, in_scale, dot_partial, ess_mode, done);
+        dispatch_apply<float>(c, (const float*)x, (float*)y, ra, ess_mode);
     HD_HIP(c, hipGetLastError());
     if (c->time_apply) {
         HD_HIP(c, hipEventRecord(c->ev1, c->stream));

@@ -244,22 +244,28 @@ int hd_sizes(const hd_ctx* c, int64_t* n_u, int64_t* n_q) {
 int hd_apply_block_op(hd_ctx* c, int prec, int nrhs, const void* x, void* y) {
     if (!c) return HD_ERR_ARG;
     if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
-    if (nrhs != 1) return set_err(c, HD_ERR_ARG, "nrhs must be 1 in this version");
+    if (nrhs < 1) return set_err(c, HD_ERR_ARG, "nrhs must be >= 1");
     if (prec != HD_F64 && prec != HD_F32) return set_err(c, HD_ERR_ARG, "prec");
     if (!x || !y || x == y) return set_err(c, HD_ERR_ARG, "x, y must be distinct device pointers");
     int rc = use_device(c);
     if (rc) return rc;
-    return launch_apply(c, prec, x, y, nullptr, nullptr, ESS_IDENTITY, nullptr);
+    return launch_apply(c, prec, nrhs, x, y, nullptr, 0, nullptr, 0, ESS_IDENTITY, nullptr, 0);
 }
 
 int hd_apply_mass_inverse(hd_ctx* c, int prec, int nrhs, const void* x, void* y) {
     if (!c) return HD_ERR_ARG;
     if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
-    if (nrhs != 1) return set_err(c, HD_ERR_ARG, "nrhs must be 1 in this version");
+    if (nrhs < 1) return set_err(c, HD_ERR_ARG, "nrhs must be >= 1");
+    if (prec != HD_F64 && prec != HD_F32) return set_err(c, HD_ERR_ARG, "prec");
     if (!x || !y) return set_err(c, HD_ERR_ARG, "null pointer");
     int rc = use_device(c);
     if (rc) return rc;
-    return launch_mass_inverse(c, prec, x, y, true);
+    const size_t es = prec == HD_F64 ? sizeof(double) : sizeof(float);
+    for (int r = 0; r < nrhs; ++r) {
+        const size_t off = es * (size_t)c->n_q * r;
+        if ((rc = launch_mass_inverse(c, prec, (const char*)x + off, (char*)y + off, true))) return rc;
+    }
+    return HD_OK;
 }
 
 int hd_apply_l2_mass_inverse(hd_ctx* c, int prec, const void* x, void* y) {
@@ -326,18 +332,24 @@ int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
 int hd_apply_precond(hd_ctx* c, int prec, int nrhs, const void* r, void* z) {
     if (!c) return HD_ERR_ARG;
     if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
-    if (nrhs != 1) return set_err(c, HD_ERR_ARG, "nrhs must be 1 in this version");
+    if (nrhs < 1) return set_err(c, HD_ERR_ARG, "nrhs must be >= 1");
+    if (prec != HD_F64 && prec != HD_F32) return set_err(c, HD_ERR_ARG, "prec");
     if (!r || !z || r == z) return set_err(c, HD_ERR_ARG, "r, z must be distinct device pointers");
     int rc = use_device(c);
     if (rc) return rc;
-    return launch_precond(c, prec, r, z, nullptr, nullptr, nullptr);
+    const size_t es = prec == HD_F64 ? sizeof(double) : sizeof(float);
+    for (int k = 0; k < nrhs; ++k) {
+        const size_t off = es * (size_t)(c->n_u + c->n_q) * k;
+        if ((rc = launch_precond(c, prec, (const char*)r + off, (char*)z + off, nullptr, nullptr, nullptr))) return rc;
+    }
+    return HD_OK;
 }
 
 int hd_minres_solve(hd_ctx* c, const hd_solve_params* params, int nrhs, const double* b, double* x,
                     hd_solve_info* info) {
     if (!c) return HD_ERR_ARG;
     if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
-    if (nrhs != 1) return set_err(c, HD_ERR_ARG, "nrhs must be 1 in this version");
+    if (nrhs < 1) return set_err(c, HD_ERR_ARG, "nrhs must be >= 1");
     if (!b || !x || b == x) return set_err(c, HD_ERR_ARG, "b, x must be distinct device pointers");
     hd_solve_params prm;
     if (params) prm = *params;
@@ -356,9 +368,7 @@ int hd_minres_solve(hd_ctx* c, const hd_solve_params* params, int nrhs, const do
         return set_err(c, HD_ERR_ARG, "bad refinement parameters");
     int rc = use_device(c);
     if (rc) return rc;
-    hd_solve_info inf;
-    rc = minres_solve(c, prm, b, x, inf);
-    if (info) info[0] = inf;
+    rc = minres_solve(c, prm, nrhs, b, x, info);
     if (rc == HD_NOT_CONVERGED) c->err = "MINRES did not reach the tolerance";
     return rc;
 }

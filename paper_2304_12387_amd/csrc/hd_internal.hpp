@@ -177,8 +177,11 @@ int launch_ensure_partial(hd_ctx* c, int64_t n);
 
 // apply.hip
 enum { ESS_NONE = 0, ESS_IDENTITY = 1 };
-int launch_apply(hd_ctx* c, int prec, const void* x, void* y, const double* in_scale, double* dot_partial,
-                 int ess_mode, const int* done);
+// y = A x for nrhs vectors (stride n_u + n_q).  in_scale[r * scale_stride]
+// scales the input of RHS r, done[r * done_stride] != 0 skips it, and the
+// per-block partial sums of <A x, x> of RHS r start at dot_partial + r * part_stride.
+int launch_apply(hd_ctx* c, int prec, int nrhs, const void* x, void* y, const double* in_scale, int scale_stride,
+                 double* dot_partial, int64_t part_stride, int ess_mode, const int* done, int done_stride);
 int launch_mass_inverse(hd_ctx* c, int prec, const void* x, void* y, bool weighted);
 int launch_lift(hd_ctx* c, const double* ubc, double* b);
 int64_t apply_partial_count(const hd_ctx* c);
@@ -196,7 +199,8 @@ Geo geo_of(const hd_ctx* c);
 int scan_counts(hd_ctx* c, const int32_t* cnt, int64_t n, int32_t* rp, int64_t* total_host);
 
 // minres.hip
-int minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, double* x, hd_solve_info& info);
+// nrhs right-hand sides stored one after the other; info: nrhs entries
+int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* b, double* x, hd_solve_info* info);
 
 // reductions (setup.hip)
 int reduce_sum_partials(hd_ctx* c, const double* partial, int64_t n, double* out_dev);

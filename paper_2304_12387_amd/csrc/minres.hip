@@ -5,11 +5,14 @@
 // B^{-1}-norm of the residual and the iteration stops when
 // |eta| <= tol |eta_0|.
 //
-// The Lanczos/Givens scalars live on the device in FP64 and are updated by a
-// one-block kernel per iteration, so no host round trip is needed between
-// iterations; the host polls the stop flag every few iterations.  Inner
-// products are two-stage deterministic reductions in FP64 (per-block
-// partials, then one block in fixed order).  Per iteration:
+// Several right-hand sides are solved together: vectors are stored one after
+// the other, every right-hand side has its own FP64 recurrence state on the
+// device (one reduction block per right-hand side) and its own stop flag,
+// and the kernels of one iteration serve all of them (the block apply loads
+// each element's geometric factors once for all right-hand sides).  No host
+// round trip is needed between iterations; the host polls the flags every
+// few iterations.  Inner products are two-stage deterministic reductions in
+// FP64.  Per iteration:
 //   1. q = A (z_j / gamma_j)          block apply, fused partials of <q, z_j/gamma_j>
 //   2. delta = sum of partials
 //   3. v_{j+1} = q - (delta/gamma_j) v_j - (gamma_j/gamma_{j-1}) v_{j-1}
@@ -27,6 +30,7 @@
 #include <chrono>
 #include <cmath>
 #include <type_traits>
+#include <vector>
 
 namespace hd {
 
@@ -48,6 +52,9 @@ struct MinresState {
     double tol;
     int iter, stop, skipped, status;
 };
+constexpr int ST_STRIDE_D = sizeof(MinresState) / sizeof(double);
+constexpr int ST_STRIDE_I = sizeof(MinresState) / sizeof(int);
+static_assert(sizeof(MinresState) % sizeof(double) == 0, "state layout");
 
 __device__ double block_sum(double v) {
     __shared__ double s[1024];
@@ -57,78 +64,92 @@ __device__ double block_sum(double v) {
         if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
         __syncthreads();
     }
-    return s[0];
+    const double r = s[0];
+    __syncthreads();
+    return r;
 }
 
-__global__ void k_delta(MinresState* st, const double* __restrict__ part, int64_t n) {
-    if (st->stop) return;
+// one block per right-hand side r: delta = sum of its apply partials
+__global__ void k_delta(MinresState* st, const double* __restrict__ part, int64_t n, int64_t stride) {
+    MinresState* S = st + blockIdx.x;
+    if (S->stop) return;
+    const double* p = part + blockIdx.x * stride;
     double acc = 0.0;
-    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) acc += part[k];
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) acc += p[k];
     const double d = block_sum(acc);
     if (threadIdx.x == 0) {
-        st->delta = d;
-        st->cv1 = d / st->gamma;
-        st->cv2 = st->gamma / st->gamma_old;
+        S->delta = d;
+        S->cv1 = d / S->gamma;
+        S->cv2 = S->gamma / S->gamma_old;
     }
 }
 
-__global__ void k_givens(MinresState* st, const double* __restrict__ pu, int64_t nu, const double* __restrict__ pq,
-                         int64_t nq, int maxit) {
-    if (st->stop) {
-        if (threadIdx.x == 0) st->skipped = 1;
+__global__ void k_givens(MinresState* st, const double* __restrict__ pu, int64_t nu, int64_t su,
+                         const double* __restrict__ pq, int64_t nq, int64_t sq, int maxit) {
+    MinresState* S = st + blockIdx.x;
+    if (S->stop) {
+        if (threadIdx.x == 0) S->skipped = 1;
         return;
     }
+    const double* a = pu + blockIdx.x * su;
+    const double* b = pq + blockIdx.x * sq;
     double acc = 0.0;
-    for (int64_t k = threadIdx.x; k < nu; k += blockDim.x) acc += pu[k];
+    for (int64_t k = threadIdx.x; k < nu; k += blockDim.x) acc += a[k];
     double acc2 = 0.0;
-    for (int64_t k = threadIdx.x; k < nq; k += blockDim.x) acc2 += pq[k];
-    const double g2 = block_sum(acc) + block_sum(acc2);
+    for (int64_t k = threadIdx.x; k < nq; k += blockDim.x) acc2 += b[k];
+    const double s1 = block_sum(acc);
+    const double s2 = block_sum(acc2);
     if (threadIdx.x != 0) return;
-    st->skipped = 0;
+    const double g2 = s1 + s2;
+    S->skipped = 0;
     if (!(g2 >= 0.0) || !isfinite(g2)) {
-        st->status = isfinite(g2) ? HD_ERR_BREAKDOWN : HD_ERR_NONFINITE;
-        st->stop = 1;
-        st->skipped = 1;
+        S->status = isfinite(g2) ? HD_ERR_BREAKDOWN : HD_ERR_NONFINITE;
+        S->stop = 1;
+        S->skipped = 1;
         return;
     }
-    const double gamma = st->gamma, delta = st->delta;
+    const double gamma = S->gamma, delta = S->delta;
     const double gnew = sqrt(g2);
-    const double a0 = st->c * delta - st->c_old * st->s * gamma;
+    const double a0 = S->c * delta - S->c_old * S->s * gamma;
     const double a1 = sqrt(a0 * a0 + gnew * gnew);
-    const double a2 = st->s * delta + st->c_old * st->c * gamma;
-    const double a3 = st->s_old * gamma;
+    const double a2 = S->s * delta + S->c_old * S->c * gamma;
+    const double a3 = S->s_old * gamma;
     const double cn = a0 / a1, sn = gnew / a1;
-    st->a1inv = 1.0 / a1;
-    st->a2 = a2;
-    st->a3 = a3;
-    st->zscale = 1.0 / gamma;
-    st->xcoef = cn * st->eta;
-    st->eta = -sn * st->eta;
-    st->gamma_old = gamma;
-    st->gamma = gnew;
-    st->inv_gamma = gnew > 0.0 ? 1.0 / gnew : 0.0;
-    st->c_old = st->c;
-    st->c = cn;
-    st->s_old = st->s;
-    st->s = sn;
-    st->iter += 1;
-    if (fabs(st->eta) <= st->tol * st->eta0 || gnew == 0.0) {
-        st->stop = 1;
-        st->status = 0;
-    } else if (st->iter >= maxit) {
-        st->stop = 1;
-        st->status = HD_NOT_CONVERGED;
+    S->a1inv = 1.0 / a1;
+    S->a2 = a2;
+    S->a3 = a3;
+    S->zscale = 1.0 / gamma;
+    S->xcoef = cn * S->eta;
+    S->eta = -sn * S->eta;
+    S->gamma_old = gamma;
+    S->gamma = gnew;
+    S->inv_gamma = gnew > 0.0 ? 1.0 / gnew : 0.0;
+    S->c_old = S->c;
+    S->c = cn;
+    S->s_old = S->s;
+    S->s = sn;
+    S->iter += 1;
+    if (fabs(S->eta) <= S->tol * S->eta0 || gnew == 0.0) {
+        S->stop = 1;
+        S->status = 0;
+    } else if (S->iter >= maxit) {
+        S->stop = 1;
+        S->status = HD_NOT_CONVERGED;
     }
 }
 
-__global__ void k_start(MinresState* st, const double* __restrict__ pu, int64_t nu, const double* __restrict__ pq,
-                        int64_t nq, double tol) {
+__global__ void k_start(MinresState* st, const double* __restrict__ pu, int64_t nu, int64_t su,
+                        const double* __restrict__ pq, int64_t nq, int64_t sq, double tol) {
+    const double* a = pu + blockIdx.x * su;
+    const double* b = pq + blockIdx.x * sq;
     double acc = 0.0;
-    for (int64_t k = threadIdx.x; k < nu; k += blockDim.x) acc += pu[k];
+    for (int64_t k = threadIdx.x; k < nu; k += blockDim.x) acc += a[k];
     double acc2 = 0.0;
-    for (int64_t k = threadIdx.x; k < nq; k += blockDim.x) acc2 += pq[k];
-    const double g2 = block_sum(acc) + block_sum(acc2);
+    for (int64_t k = threadIdx.x; k < nq; k += blockDim.x) acc2 += b[k];
+    const double s1 = block_sum(acc);
+    const double s2 = block_sum(acc2);
     if (threadIdx.x != 0) return;
+    const double g2 = s1 + s2;
     MinresState s = {};
     s.tol = tol;
     s.c = s.c_old = 1.0;
@@ -143,24 +164,27 @@ __global__ void k_start(MinresState* st, const double* __restrict__ pu, int64_t 
         s.inv_gamma = s.gamma > 0.0 ? 1.0 / s.gamma : 0.0;
         s.stop = s.gamma == 0.0;
     }
-    *st = s;
+    st[blockIdx.x] = s;
 }
 
 // v_old <- q - cv1 v - cv2 v_old  (= v_{j+1});  z_u = mdinv * v_{j+1,u}
+// (blockIdx.y = right-hand side)
 template <typename T>
 __global__ void k_vupd(int64_t N, int64_t nu, const T* __restrict__ q, const T* __restrict__ v, T* __restrict__ vo,
                        const T* __restrict__ mdinv, T* __restrict__ z, const MinresState* __restrict__ st,
                        double* __restrict__ part) {
-    if (st->stop) return;
+    const int r = blockIdx.y;
+    if (st[r].stop) return;
     __shared__ double s[BS];
-    const T cv1 = (T)st->cv1, cv2 = (T)st->cv2;
+    const T cv1 = (T)st[r].cv1, cv2 = (T)st[r].cv2;
+    const int64_t o = (int64_t)r * N;
     double contrib = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
-        const T vn = q[i] - cv1 * v[i] - cv2 * vo[i];
-        vo[i] = vn;
+        const T vn = q[o + i] - cv1 * v[o + i] - cv2 * vo[o + i];
+        vo[o + i] = vn;
         if (i < nu) {
             const T zi = mdinv[i] * vn;
-            z[i] = zi;
+            z[o + i] = zi;
             contrib += (double)zi * (double)vn;
         }
     }
@@ -170,28 +194,30 @@ __global__ void k_vupd(int64_t N, int64_t nu, const T* __restrict__ q, const T* 
         if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+    if (threadIdx.x == 0) part[(int64_t)r * RED_BLOCKS + blockIdx.x] = s[0];
 }
 
 // w_old <- (z zscale - a3 w_old - a2 w) a1inv  (= w_{j+1});  x += xcoef w_{j+1}
 template <typename T, typename X>
 __global__ void k_wupd(int64_t N, const T* __restrict__ z, T* __restrict__ wo, const T* __restrict__ w,
                        X* __restrict__ x, const MinresState* __restrict__ st) {
-    if (st->skipped) return;
+    const int r = blockIdx.y;
+    if (st[r].skipped) return;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const T zs = (T)st->zscale, a3 = (T)st->a3, a2 = (T)st->a2, a1i = (T)st->a1inv;
-    const T wn = (z[i] * zs - a3 * wo[i] - a2 * w[i]) * a1i;
-    wo[i] = wn;
-    x[i] += (X)st->xcoef * (X)wn;
+    const int64_t k = (int64_t)r * N + i;
+    const T zs = (T)st[r].zscale, a3 = (T)st[r].a3, a2 = (T)st[r].a2, a1i = (T)st[r].a1inv;
+    const T wn = (z[k] * zs - a3 * wo[k] - a2 * w[k]) * a1i;
+    wo[k] = wn;
+    x[k] += (X)st[r].xcoef * (X)wn;
 }
 
-// v = b - q (or b when q == nullptr), v_old = w = w_old = 0
+// v = b - q (or b when q == nullptr), v_old = w = w_old = 0 (all RHS)
 template <typename T, typename B>
-__global__ void k_init(int64_t N, const B* __restrict__ b, const T* __restrict__ q, T* __restrict__ v,
+__global__ void k_init(int64_t n, const B* __restrict__ b, const T* __restrict__ q, T* __restrict__ v,
                        T* __restrict__ vo, T* __restrict__ w, T* __restrict__ wo) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= N) return;
+    if (i >= n) return;
     v[i] = q ? (T)((T)b[i] - q[i]) : (T)b[i];
     vo[i] = 0;
     w[i] = 0;
@@ -199,21 +225,33 @@ __global__ void k_init(int64_t N, const B* __restrict__ b, const T* __restrict__
 }
 
 template <typename T>
-__global__ void k_zero(int64_t N, T* __restrict__ x) {
+__global__ void k_zero(int64_t n, T* __restrict__ x) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < N) x[i] = 0;
+    if (i < n) x[i] = 0;
 }
 
-// r = b - q (FP64), partial sums of r^2 and b^2
+// swap the contents of two buffers (realigns a recurrence whose executed
+// iteration count has the other parity than the host's buffer rotation)
+template <typename T>
+__global__ void k_swap(int64_t N, T* __restrict__ a, T* __restrict__ b) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const T t = a[i];
+    a[i] = b[i];
+    b[i] = t;
+}
+
+// r = b - q (FP64), per-RHS partial sums of r^2 and b^2 (blockIdx.y = RHS)
 __global__ void k_residual(int64_t N, const double* __restrict__ b, const double* __restrict__ q,
                            double* __restrict__ r, double* __restrict__ pr, double* __restrict__ pb) {
     __shared__ double s[BS];
+    const int64_t o = (int64_t)blockIdx.y * N;
     double rr = 0.0, bb = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
-        const double ri = b[i] - q[i];
-        if (r) r[i] = ri;
+        const double ri = b[o + i] - q[o + i];
+        if (r) r[o + i] = ri;
         rr += ri * ri;
-        bb += b[i] * b[i];
+        bb += b[o + i] * b[o + i];
     }
     s[threadIdx.x] = rr;
     __syncthreads();
@@ -221,7 +259,7 @@ __global__ void k_residual(int64_t N, const double* __restrict__ b, const double
         if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) pr[blockIdx.x] = s[0];
+    if (threadIdx.x == 0) pr[(int64_t)blockIdx.y * RED_BLOCKS + blockIdx.x] = s[0];
     __syncthreads();
     s[threadIdx.x] = bb;
     __syncthreads();
@@ -229,72 +267,46 @@ __global__ void k_residual(int64_t N, const double* __restrict__ b, const double
         if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) pb[blockIdx.x] = s[0];
+    if (threadIdx.x == 0) pb[(int64_t)blockIdx.y * RED_BLOCKS + blockIdx.x] = s[0];
 }
 
-// r32 = r * inv (FP64 -> FP32) and x += scale * d32
-__global__ void k_to32(int64_t N, const double* __restrict__ r, const double* __restrict__ scal, float* __restrict__ o) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < N) o[i] = (float)(r[i] / scal[0]);
+// out[2r] = ||r||, out[2r+1] = ||b|| (one block per RHS)
+__global__ void k_norms(const double* __restrict__ pr, const double* __restrict__ pb, int64_t n,
+                        double* __restrict__ out) {
+    const double* a = pr + (int64_t)blockIdx.x * RED_BLOCKS;
+    const double* b = pb + (int64_t)blockIdx.x * RED_BLOCKS;
+    double x = 0.0, y = 0.0;
+    for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+        x += a[k];
+        y += b[k];
+    }
+    const double sx = block_sum(x);
+    const double sy = block_sum(y);
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = sqrt(sx);
+        out[2 * blockIdx.x + 1] = sqrt(sy);
+    }
 }
-__global__ void k_addscaled(int64_t N, const float* __restrict__ d, const double* __restrict__ scal,
+
+// r32 = r / ||r|| (FP64 -> FP32), and x += ||r|| d32 (blockIdx.y = RHS; the
+// norm of RHS r is nrm[2r]; a zero norm gives a zero right-hand side)
+__global__ void k_to32(int64_t N, const double* __restrict__ r, const double* __restrict__ nrm,
+                       float* __restrict__ o) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double s = nrm[2 * blockIdx.y];
+    const int64_t k = (int64_t)blockIdx.y * N + i;
+    o[k] = s > 0.0 ? (float)(r[k] / s) : 0.0f;
+}
+__global__ void k_addscaled(int64_t N, const float* __restrict__ d, const double* __restrict__ nrm,
                             double* __restrict__ x) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < N) x[i] += scal[0] * (double)d[i];
-}
-__global__ void k_sqrt(double* v, int n) {
-    if (threadIdx.x < n) v[threadIdx.x] = sqrt(v[threadIdx.x]);
-}
-
-struct Work {
-    int64_t N = 0;
-    int prec = HD_F64;
-    void *v = nullptr, *vo = nullptr, *z = nullptr, *zn = nullptr, *w = nullptr, *wo = nullptr, *q = nullptr;
-    double *pd = nullptr, *pu = nullptr, *pq = nullptr;
-    int64_t nq_part = 0;
-    MinresState* st = nullptr;
-    MinresState* st_host = nullptr;
-};
-
-void free_work(Work& w) {
-    dfree(w.v);
-    dfree(w.vo);
-    dfree(w.z);
-    dfree(w.zn);
-    dfree(w.w);
-    dfree(w.wo);
-    dfree(w.q);
-    dfree(w.pd);
-    dfree(w.pu);
-    dfree(w.pq);
-    dfree(w.st);
-    if (w.st_host) (void)hipHostFree(w.st_host);
-    w = Work();
+    if (i >= N) return;
+    const int64_t k = (int64_t)blockIdx.y * N + i;
+    x[k] += nrm[2 * blockIdx.y] * (double)d[k];
 }
 
-int alloc_work(hd_ctx* c, Work& w, int prec) {
-    w.N = c->n_u + c->n_q;
-    w.prec = prec;
-    const size_t es = prec == HD_F64 ? sizeof(double) : sizeof(float);
-    void** vs[] = {&w.v, &w.vo, &w.z, &w.zn, &w.w, &w.wo, &w.q};
-    for (void** p : vs) {
-        if (hipMalloc(p, es * w.N) != hipSuccess) return set_err(c, HD_ERR_OOM, "MINRES vectors");
-    }
-    w.pd = dalloc<double>(std::max<int64_t>(c->ne, apply_partial_count(c)));
-    w.pu = dalloc<double>(nblk(w.N));
-    w.nq_part = schur_partial_count(c);
-    w.pq = dalloc<double>(std::max<int64_t>(w.nq_part, nblk(w.N)));
-    w.st = dalloc<MinresState>(1);
-    if (!w.pd || !w.pu || !w.pq || !w.st) return set_err(c, HD_ERR_OOM, "MINRES partials");
-    if (hipHostMalloc((void**)&w.st_host, sizeof(MinresState)) != hipSuccess)
-        return set_err(c, HD_ERR_OOM, "MINRES host state");
-    return HD_OK;
-}
-
-int true_residual(hd_ctx* c, Work& wk64, const double* b, const double* x, double* r, double& rel,
-                  double* rnorm_dev);
-
-// tighten the stop threshold and resume a converged recurrence
+// tighten the stop threshold of one RHS and resume its converged recurrence
 __global__ void k_retarget(MinresState* st, double tol) {
     if (st->status == 0) {
         st->tol = tol;
@@ -302,13 +314,82 @@ __global__ void k_retarget(MinresState* st, double tol) {
     }
 }
 
-// Preconditioned MINRES in precision T on A x = b (b of precision B, x of
-// precision T, x0 = 0 unless use_x0).  Returns iterations and status.
+struct Work {
+    int64_t N = 0;
+    int nrhs = 1;
+    int prec = HD_F64;
+    void *v = nullptr, *vo = nullptr, *z = nullptr, *zn = nullptr, *w = nullptr, *wo = nullptr, *q = nullptr;
+    double *pd = nullptr, *pu = nullptr, *pq = nullptr, *nrm = nullptr;
+    int64_t nd_part = 0, nq_part = 0;
+    MinresState* st = nullptr;
+    MinresState* st_host = nullptr;
+    double* nrm_host = nullptr;
+};
+
+void free_work(Work& w) {
+    for (void* p : {w.v, w.vo, w.z, w.zn, w.w, w.wo, w.q}) dfree(p);
+    dfree(w.pd);
+    dfree(w.pu);
+    dfree(w.pq);
+    dfree(w.nrm);
+    dfree(w.st);
+    if (w.st_host) (void)hipHostFree(w.st_host);
+    if (w.nrm_host) (void)hipHostFree(w.nrm_host);
+    w = Work();
+}
+
+int alloc_work(hd_ctx* c, Work& w, int prec, int nrhs) {
+    w.N = c->n_u + c->n_q;
+    w.nrhs = nrhs;
+    w.prec = prec;
+    const size_t es = prec == HD_F64 ? sizeof(double) : sizeof(float);
+    void** vs[] = {&w.v, &w.vo, &w.z, &w.zn, &w.w, &w.wo, &w.q};
+    for (void** p : vs) {
+        if (hipMalloc(p, es * w.N * nrhs) != hipSuccess) return set_err(c, HD_ERR_OOM, "MINRES vectors");
+    }
+    w.nd_part = apply_partial_count(c);
+    w.nq_part = std::max<int64_t>(schur_partial_count(c), RED_BLOCKS);
+    w.pd = dalloc<double>(w.nd_part * nrhs);
+    w.pu = dalloc<double>((int64_t)RED_BLOCKS * nrhs);
+    w.pq = dalloc<double>(w.nq_part * nrhs);
+    w.nrm = dalloc<double>(2 * nrhs);
+    w.st = dalloc<MinresState>(nrhs);
+    if (!w.pd || !w.pu || !w.pq || !w.st || !w.nrm) return set_err(c, HD_ERR_OOM, "MINRES partials");
+    if (hipHostMalloc((void**)&w.st_host, sizeof(MinresState) * nrhs) != hipSuccess ||
+        hipHostMalloc((void**)&w.nrm_host, sizeof(double) * 2 * nrhs) != hipSuccess)
+        return set_err(c, HD_ERR_OOM, "MINRES host state");
+    return HD_OK;
+}
+
+// ||b_r - A x_r|| and ||b_r|| for every RHS into wk.nrm_host (and the device
+// copy wk.nrm); r (optional) receives b - A x.
+int true_residual(hd_ctx* c, Work& wk64, const double* b, const double* x, double* r) {
+    const int64_t N = wk64.N;
+    const int nr = wk64.nrhs;
+    int rc;
+    if ((rc = launch_apply(c, HD_F64, nr, x, wk64.q, nullptr, 0, nullptr, 0, ESS_IDENTITY, nullptr, 0))) return rc;
+    hipLaunchKernelGGL(k_residual, dim3(red_grid(N), nr), dim3(BS), 0, c->stream, N, b, (const double*)wk64.q, r,
+                       wk64.pu, wk64.pq);
+    hipLaunchKernelGGL(k_norms, dim3(nr), dim3(1024), 0, c->stream, wk64.pu, wk64.pq, (int64_t)red_grid(N), wk64.nrm);
+    HD_HIP(c, hipMemcpyAsync(wk64.nrm_host, wk64.nrm, 2 * nr * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    return HD_OK;
+}
+
+inline double rel_of(const double* nrm, int r) {
+    return nrm[2 * r + 1] > 0 ? nrm[2 * r] / nrm[2 * r + 1] : nrm[2 * r];
+}
+
+// Preconditioned MINRES in precision T on A x_r = b_r for wk.nrhs right-hand
+// sides (b of precision B, x of precision T, x0 = 0 unless use_x0).
+// true_tol > 0 (FP64 only): after the |eta| stop, require the true FP64
+// residual and continue the recurrence with a tighter threshold if needed.
 template <typename T, typename B>
 int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, int maxit, int check_every,
-                int& iters, int& status, double& eta_rel, double true_tol = 0.0) {
+                std::vector<hd_solve_info>& out, double true_tol = 0.0) {
     const int prec = std::is_same<T, double>::value ? HD_F64 : HD_F32;
-    const int64_t N = wk.N, nu = c->n_u, nq = c->n_q;
+    const int64_t N = wk.N, nu = c->n_u;
+    const int nr = wk.nrhs;
     T* v = (T*)wk.v;
     T* vo = (T*)wk.vo;
     T* z = (T*)wk.z;
@@ -317,177 +398,190 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
     T* wo = (T*)wk.wo;
     T* q = (T*)wk.q;
     const T* mdinv = std::is_same<T, double>::value ? (const T*)c->d_mdinv : (const T*)c->d_mdinv32;
+    const int64_t nqp = schur_partial_count(c);
     int rc;
+    const int64_t Nt = N * nr;
     if (use_x0) {
-        if ((rc = launch_apply(c, prec, x, q, nullptr, nullptr, ESS_IDENTITY, nullptr))) return rc;
-        hipLaunchKernelGGL((k_init<T, B>), dim3(nblk(N)), dim3(BS), 0, c->stream, N, b, q, v, vo, w, wo);
+        if ((rc = launch_apply(c, prec, nr, x, q, nullptr, 0, nullptr, 0, ESS_IDENTITY, nullptr, 0))) return rc;
+        hipLaunchKernelGGL((k_init<T, B>), dim3(nblk(Nt)), dim3(BS), 0, c->stream, Nt, b, (const T*)q, v, vo, w, wo);
     } else {
-        hipLaunchKernelGGL(k_zero<T>, dim3(nblk(N)), dim3(BS), 0, c->stream, N, x);
-        hipLaunchKernelGGL((k_init<T, B>), dim3(nblk(N)), dim3(BS), 0, c->stream, N, b, (const T*)nullptr, v, vo, w,
-                           wo);
+        hipLaunchKernelGGL(k_zero<T>, dim3(nblk(Nt)), dim3(BS), 0, c->stream, Nt, x);
+        hipLaunchKernelGGL((k_init<T, B>), dim3(nblk(Nt)), dim3(BS), 0, c->stream, Nt, b, (const T*)nullptr, v, vo,
+                           w, wo);
     }
     // z_1 = B^{-1} v_1
-    if ((rc = launch_diag_prec(c, prec, v, z, wk.pu))) return rc;
-    // the diag kernel covers n_u rows; its partial count is nblk(n_u) <= nblk(N)
-    if ((rc = launch_schur_prec(c, prec, v + nu, z + nu, wk.pq, nullptr))) return rc;
-    hipLaunchKernelGGL(k_start, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)red_grid(nu), wk.pq,
-                       wk.nq_part, tol);
+    for (int r = 0; r < nr; ++r) {
+        if ((rc = launch_diag_prec(c, prec, v + r * N, z + r * N, wk.pu + (int64_t)r * RED_BLOCKS))) return rc;
+        if ((rc = launch_schur_prec(c, prec, v + r * N + nu, z + r * N + nu, wk.pq + r * wk.nq_part, nullptr)))
+            return rc;
+    }
+    hipLaunchKernelGGL(k_start, dim3(nr), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)red_grid(nu),
+                       (int64_t)RED_BLOCKS, wk.pq, nqp, wk.nq_part, tol);
     HD_HIP(c, hipGetLastError());
     const int* stop = &wk.st->stop;
-    int it_launched = 0, retargets = 0;
+    int launched = 0, retargets = 0;
     for (;;) {
-        for (int k = 0; k < check_every && it_launched < maxit; ++k, ++it_launched) {
-            if ((rc = launch_apply(c, prec, z, q, &wk.st->inv_gamma, wk.pd, ESS_IDENTITY, stop))) return rc;
-            hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pd, apply_partial_count(c));
-            hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N)), dim3(BS), 0, c->stream, N, nu, q, v, vo, mdinv, zn,
+        for (int k = 0; k < check_every && launched < maxit; ++k, ++launched) {
+            if ((rc = launch_apply(c, prec, nr, z, q, &wk.st->inv_gamma, ST_STRIDE_D, wk.pd, wk.nd_part, ESS_IDENTITY,
+                                   stop, ST_STRIDE_I)))
+                return rc;
+            hipLaunchKernelGGL(k_delta, dim3(nr), dim3(1024), 0, c->stream, wk.st, wk.pd, wk.nd_part, wk.nd_part);
+            hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N), nr), dim3(BS), 0, c->stream, N, nu, q, v, vo, mdinv, zn,
                                wk.st, wk.pu);
-            if ((rc = launch_schur_prec(c, prec, vo + nu, zn + nu, wk.pq, stop))) return rc;
-            hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)red_grid(N),
-                               wk.pq, wk.nq_part, maxit);
-            hipLaunchKernelGGL((k_wupd<T, T>), dim3(nblk(N)), dim3(BS), 0, c->stream, N, z, wo, w, x, wk.st);
+            for (int r = 0; r < nr; ++r)
+                if ((rc = launch_schur_prec(c, prec, vo + r * N + nu, zn + r * N + nu, wk.pq + r * wk.nq_part,
+                                            stop + r * ST_STRIDE_I)))
+                    return rc;
+            hipLaunchKernelGGL(k_givens, dim3(nr), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)red_grid(N),
+                               (int64_t)RED_BLOCKS, wk.pq, nqp, wk.nq_part, maxit);
+            hipLaunchKernelGGL((k_wupd<T, T>), dim3(nblk(N), nr), dim3(BS), 0, c->stream, N, z, wo, w, x, wk.st);
             std::swap(v, vo);
             std::swap(z, zn);
             std::swap(w, wo);
         }
         HD_HIP(c, hipGetLastError());
-        HD_HIP(c, hipMemcpyAsync(wk.st_host, wk.st, sizeof(MinresState), hipMemcpyDeviceToHost, c->stream));
+        HD_HIP(c, hipMemcpyAsync(wk.st_host, wk.st, nr * sizeof(MinresState), hipMemcpyDeviceToHost, c->stream));
         HD_HIP(c, hipStreamSynchronize(c->stream));
-        // iterations launched after the stop flag was raised were no-ops on
-        // the device; every executed iteration swapped each buffer pair once,
-        // so the parity of the executed count fixes the live arrangement
-        {
-            const bool odd = wk.st_host->iter % 2 != 0;
-            v = (T*)(odd ? wk.vo : wk.v);
-            vo = (T*)(odd ? wk.v : wk.vo);
-            z = (T*)(odd ? wk.zn : wk.z);
-            zn = (T*)(odd ? wk.z : wk.zn);
-            w = (T*)(odd ? wk.wo : wk.w);
-            wo = (T*)(odd ? wk.w : wk.wo);
-        }
-        if (wk.st_host->stop && wk.st_host->status == 0 && true_tol > 0.0 && retargets < 8) {
+        bool all_stop = true;
+        for (int r = 0; r < nr; ++r) all_stop = all_stop && wk.st_host[r].stop;
+        if (all_stop && true_tol > 0.0 && retargets < 8) {
             // the recurrence stops on the preconditioned residual norm; when the
-            // caller asks for a true FP64 residual, check it and, if it is not
-            // yet met, continue the same recurrence with a tighter threshold
+            // caller asks for a true FP64 residual, check it and continue the
+            // recurrences that have not met it with a tighter threshold
             if constexpr (std::is_same<T, double>::value && std::is_same<B, double>::value) {
-                double rel = 0.0;
-                if ((rc = true_residual(c, wk, b, x, nullptr, rel, nullptr))) return rc;
-                if (rel > true_tol) {
-                    const double nt = wk.st_host->tol * (true_tol / rel) * 0.7;
-                    hipLaunchKernelGGL(k_retarget, dim3(1), dim3(1), 0, c->stream, wk.st, nt);
+                if ((rc = true_residual(c, wk, b, x, nullptr))) return rc;
+                // iterations launched after a stop were no-ops for that RHS while
+                // the host kept rotating the buffers: realign each RHS to the
+                // parity of the launched count before resuming it
+                bool resumed = false;
+                for (int r = 0; r < nr; ++r) {
+                    const MinresState& s = wk.st_host[r];
+                    const double rel = rel_of(wk.nrm_host, r);
+                    if (s.status != 0 || rel <= true_tol) continue;
+                    if ((s.iter % 2) != (launched % 2)) {
+                        T* pairs[3][2] = {{v, vo}, {z, zn}, {w, wo}};
+                        for (auto& pr : pairs)
+                            hipLaunchKernelGGL(k_swap<T>, dim3(nblk(N)), dim3(BS), 0, c->stream, N, pr[0] + r * N,
+                                               pr[1] + r * N);
+                    }
+                    const double nt = s.tol * (true_tol / rel) * 0.7;
+                    hipLaunchKernelGGL(k_retarget, dim3(1), dim3(1), 0, c->stream, wk.st + r, nt);
+                    resumed = true;
+                }
+                if (resumed) {
                     ++retargets;
-                    if (it_launched < maxit) continue;
+                    if (launched < maxit) continue;
                 }
             }
         }
-        if (wk.st_host->stop || it_launched >= maxit) break;
+        if (all_stop || launched >= maxit) break;
     }
-    const MinresState& s = *wk.st_host;
-    iters = s.iter;
-    status = s.stop ? s.status : HD_NOT_CONVERGED;
-    eta_rel = s.eta0 > 0 ? std::fabs(s.eta) / s.eta0 : 0.0;
-    return HD_OK;
-}
-
-// ||b - A x|| / ||b|| in FP64; r (optional) receives b - A x; rnorm_dev gets
-// ||r|| (device scalar) when non-null
-int true_residual(hd_ctx* c, Work& wk64, const double* b, const double* x, double* r, double& rel,
-                  double* rnorm_dev) {
-    const int64_t N = c->n_u + c->n_q;
-    int rc;
-    if ((rc = launch_apply(c, HD_F64, x, wk64.q, nullptr, nullptr, ESS_IDENTITY, nullptr))) return rc;
-    hipLaunchKernelGGL(k_residual, dim3(red_grid(N)), dim3(BS), 0, c->stream, N, b, (const double*)wk64.q, r,
-                       wk64.pu, wk64.pq);
-    if ((rc = reduce_sum_partials(c, wk64.pu, red_grid(N), c->d_scal + 0))) return rc;
-    if ((rc = reduce_sum_partials(c, wk64.pq, red_grid(N), c->d_scal + 1))) return rc;
-    hipLaunchKernelGGL(k_sqrt, dim3(1), dim3(64), 0, c->stream, c->d_scal, 2);
-    double h[2];
-    HD_HIP(c, hipMemcpyAsync(h, c->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HD_HIP(c, hipStreamSynchronize(c->stream));
-    if (rnorm_dev) HD_HIP(c, hipMemcpyAsync(rnorm_dev, c->d_scal, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    rel = h[1] > 0 ? h[0] / h[1] : h[0];
+    out.resize(nr);
+    for (int r = 0; r < nr; ++r) {
+        const MinresState& s = wk.st_host[r];
+        out[r] = hd_solve_info();
+        out[r].iterations = s.iter;
+        out[r].status = s.stop ? s.status : HD_NOT_CONVERGED;
+        out[r].eta_rel = s.eta0 > 0 ? std::fabs(s.eta) / s.eta0 : 0.0;
+        out[r].outer = 1;
+    }
     return HD_OK;
 }
 
 }  // namespace
 
-int minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, double* x, hd_solve_info& info) {
-    info = hd_solve_info();
+int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* b, double* x, hd_solve_info* info) {
     auto t0 = std::chrono::steady_clock::now();
     Work w64;
-    int rc = alloc_work(c, w64, HD_F64);
+    int rc = alloc_work(c, w64, HD_F64, nrhs);
     if (rc) {
         free_work(w64);
         return rc;
     }
     const int check = prm.check_every > 0 ? prm.check_every : 8;
-    int status = 0;
+    std::vector<hd_solve_info> res(nrhs);
     if (prm.mode == HD_MODE_PLAIN64) {
-        int it = 0;
-        double er = 0;
-        rc = minres_core<double, double>(c, w64, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, it, status, er,
+        rc = minres_core<double, double>(c, w64, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, res,
                                          prm.stop_true ? prm.tol : 0.0);
-        info.iterations = it;
-        info.outer = 1;
-        info.eta_rel = er;
     } else if (prm.mode == HD_MODE_MIXED) {
         Work w32;
-        rc = alloc_work(c, w32, HD_F32);
+        rc = alloc_work(c, w32, HD_F32, nrhs);
+        const int64_t Nt = w64.N * nrhs;
         double* r = nullptr;
         float *r32 = nullptr, *d32 = nullptr;
         if (!rc) {
-            r = dalloc<double>(w64.N);
-            r32 = dalloc<float>(w64.N);
-            d32 = dalloc<float>(w64.N);
+            r = dalloc<double>(Nt);
+            r32 = dalloc<float>(Nt);
+            d32 = dalloc<float>(Nt);
             if (!r || !r32 || !d32) rc = set_err(c, HD_ERR_OOM, "refinement vectors");
         }
-        if (!rc && !prm.use_x0) {
-            hipLaunchKernelGGL(k_zero<double>, dim3(nblk(w64.N)), dim3(BS), 0, c->stream, w64.N, x);
-        }
-        int total = 0, outer = 0;
-        double rel = 1.0, er = 0.0;
-        status = HD_NOT_CONVERGED;
+        if (!rc && !prm.use_x0) hipLaunchKernelGGL(k_zero<double>, dim3(nblk(Nt)), dim3(BS), 0, c->stream, Nt, x);
+        std::vector<int> total(nrhs, 0), status(nrhs, HD_NOT_CONVERGED);
+        std::vector<double> er(nrhs, 0.0);
+        int outer = 0;
+        std::vector<hd_solve_info> inner;
         while (!rc) {
-            rc = true_residual(c, w64, b, x, r, rel, c->d_scal + 2);
+            rc = true_residual(c, w64, b, x, r);
             if (rc) break;
-            if (rel <= prm.tol) {
-                status = 0;
-                break;
+            bool all = true;
+            for (int k = 0; k < nrhs; ++k) {
+                if (status[k] < 0) continue;
+                if (rel_of(w64.nrm_host, k) <= prm.tol) {
+                    status[k] = 0;
+                    w64.nrm_host[2 * k] = 0.0;   // converged: zero right-hand side for the inner solve
+                } else {
+                    status[k] = HD_NOT_CONVERGED;
+                    all = false;
+                }
             }
-            if (outer >= prm.max_outer) break;
-            hipLaunchKernelGGL(k_to32, dim3(nblk(w64.N)), dim3(BS), 0, c->stream, w64.N, r, c->d_scal + 2, r32);
-            int it = 0, st = 0;
-            rc = minres_core<float, float>(c, w32, r32, d32, false, prm.inner_tol, prm.max_it, check, it, st, er);
+            if (all || outer >= prm.max_outer) break;
+            HD_HIP(c, hipMemcpyAsync(w64.nrm, w64.nrm_host, 2 * nrhs * sizeof(double), hipMemcpyHostToDevice,
+                                     c->stream));
+            hipLaunchKernelGGL(k_to32, dim3(nblk(w64.N), nrhs), dim3(BS), 0, c->stream, w64.N, r, w64.nrm, r32);
+            rc = minres_core<float, float>(c, w32, r32, d32, false, prm.inner_tol, prm.max_it, check, inner);
             if (rc) break;
-            total += it;
             ++outer;
-            if (st < 0) {
-                status = st;
-                break;
+            bool brk = false;
+            for (int k = 0; k < nrhs; ++k) {
+                total[k] += inner[k].iterations;
+                er[k] = inner[k].eta_rel;
+                if (inner[k].status < 0) {
+                    status[k] = inner[k].status;
+                    brk = true;
+                }
             }
-            hipLaunchKernelGGL(k_addscaled, dim3(nblk(w64.N)), dim3(BS), 0, c->stream, w64.N, d32, c->d_scal + 2, x);
+            if (brk) break;
+            hipLaunchKernelGGL(k_addscaled, dim3(nblk(w64.N), nrhs), dim3(BS), 0, c->stream, w64.N, d32, w64.nrm, x);
         }
         dfree(r);
         dfree(r32);
         dfree(d32);
         free_work(w32);
-        info.iterations = total;
-        info.outer = outer;
-        info.eta_rel = er;
+        for (int k = 0; k < nrhs; ++k) {
+            res[k].iterations = total[k];
+            res[k].outer = outer;
+            res[k].eta_rel = er[k];
+            res[k].status = status[k];
+        }
     } else {
         free_work(w64);
         return set_err(c, HD_ERR_ARG, "solve mode not supported");
     }
     if (!rc) {
-        double rel = 0;
-        rc = true_residual(c, w64, b, x, nullptr, rel, nullptr);
-        info.true_rel_res = rel;
+        rc = true_residual(c, w64, b, x, nullptr);
+        for (int k = 0; k < nrhs && !rc; ++k) res[k].true_rel_res = rel_of(w64.nrm_host, k);
     }
     free_work(w64);
     if (rc) return rc;
-    auto t1 = std::chrono::steady_clock::now();
-    info.time_s = std::chrono::duration<double>(t1 - t0).count();
-    info.status = status;
-    return status;
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = 0;
+    for (int k = 0; k < nrhs; ++k) {
+        res[k].time_s = dt;
+        if (info) info[k] = res[k];
+        if (res[k].status < 0) worst = res[k].status;
+        else if (res[k].status > 0 && worst == 0) worst = res[k].status;
+    }
+    return worst;
 }
 
 }  // namespace hd

@@ -177,17 +177,40 @@ class Context:
         self._check(self.lib.hd_sizes(self.h, ctypes.byref(nu), ctypes.byref(nq)))
         return nu.value, nq.value
 
+    def _dev(self, a, n, prec, name):
+        """Refuse a buffer the kernels would read or write out of bounds."""
+        torch = self.torch
+        want = torch.float64 if prec == HD_F64 else torch.float32
+        if not (hasattr(a, 'is_cuda') and a.is_cuda and a.is_contiguous()):
+            raise ValueError(f"{name}: a contiguous device tensor is required")
+        if a.dtype != want:
+            raise ValueError(f"{name}: dtype {a.dtype}, expected {want}")
+        if a.numel() < n:
+            raise ValueError(f"{name}: {a.numel()} entries, at least {n} required")
+
     # ---- operator ---------------------------------------------------------
     def apply_block_op(self, x, y, prec=HD_F64, nrhs=1):
+        nu, nq = self.sizes()
+        self._dev(x, nrhs * (nu + nq), prec, 'x')
+        self._dev(y, nrhs * (nu + nq), prec, 'y')
         return self._check(self.lib.hd_apply_block_op(self.h, prec, nrhs, _ptr(x), _ptr(y)))
 
     def apply_mass_inverse(self, x, y, prec=HD_F64, nrhs=1):
+        nu, nq = self.sizes()
+        self._dev(x, nrhs * nq, prec, 'x')
+        self._dev(y, nrhs * nq, prec, 'y')
         return self._check(self.lib.hd_apply_mass_inverse(self.h, prec, nrhs, _ptr(x), _ptr(y)))
 
     def apply_l2_mass_inverse(self, x, y, prec=HD_F64):
+        nu, nq = self.sizes()
+        self._dev(x, nq, prec, 'x')
+        self._dev(y, nq, prec, 'y')
         return self._check(self.lib.hd_apply_l2_mass_inverse(self.h, prec, _ptr(x), _ptr(y)))
 
     def lift_essential(self, u_bc, b):
+        nu, nq = self.sizes()
+        self._dev(u_bc, nu, HD_F64, 'u_bc')
+        self._dev(b, nu + nq, HD_F64, 'b')
         return self._check(self.lib.hd_lift_essential(self.h, _ptr(u_bc), _ptr(b)))
 
     # ---- preconditioner and solver -----------------------------------------
@@ -196,14 +219,23 @@ class Context:
         return self._check(self.lib.hd_build_precond(self.h, pp))
 
     def apply_precond(self, r, z, prec=HD_F64, nrhs=1):
+        nu, nq = self.sizes()
+        self._dev(r, nrhs * (nu + nq), prec, 'r')
+        self._dev(z, nrhs * (nu + nq), prec, 'z')
         return self._check(self.lib.hd_apply_precond(self.h, prec, nrhs, _ptr(r), _ptr(z)))
 
     def minres_solve(self, b, x, params=None, nrhs=1):
-        info = SolveInfo()
+        """Solve A x_r = b_r for nrhs right-hand sides stored one after the
+        other; returns one info dict (nrhs = 1) or a list of them."""
+        nu, nq = self.sizes()
+        self._dev(b, nrhs * (nu + nq), HD_F64, 'b')
+        self._dev(x, nrhs * (nu + nq), HD_F64, 'x')
+        info = (SolveInfo * nrhs)()
         pp = ctypes.byref(params) if params is not None else None
-        rc = self.lib.hd_minres_solve(self.h, pp, nrhs, _ptr(b), _ptr(x), ctypes.byref(info))
+        rc = self.lib.hd_minres_solve(self.h, pp, nrhs, _ptr(b), _ptr(x), info)
         self._check(rc, allow=(HD_NOT_CONVERGED,))
-        return info.as_dict()
+        out = [i.as_dict() for i in info]
+        return out[0] if nrhs == 1 else out
 
     # ---- inspection ---------------------------------------------------------
     def get_diagonals(self):
