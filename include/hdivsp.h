@@ -82,7 +82,9 @@ enum {
     HD_MODE_MIXED = 1,     /* FP64 residual refinement around FP32 MINRES
                               (FP32 vectors, operator and preconditioner;
                               FP64 dot products, recurrences and coarse solve) */
-    HD_MODE_PREC32 = 2     /* FP64 MINRES with the FP32 preconditioner */
+    HD_MODE_PREC32 = 2     /* FP64 MINRES and operator with the Schur-block
+                              V-cycle in FP32 (FP32 level matrices, FP64
+                              coarse solve); the (1,1) diagonal stays FP64 */
 };
 
 typedef struct hd_precond_params {
@@ -102,7 +104,7 @@ typedef struct hd_solve_params {
     double inner_tol;    /* HD_MODE_MIXED: inner FP32 tolerance; default 1e-5 */
     int max_outer;       /* HD_MODE_MIXED: max refinement steps; default 20 */
     int check_every;     /* iterations between host polls of the flag; default 8 */
-    int stop_true;       /* HD_MODE_PLAIN64: 0 stops when |eta| <= tol |eta_0| (the
+    int stop_true;       /* HD_MODE_PLAIN64, HD_MODE_PREC32: 0 stops when |eta| <= tol |eta_0| (the
                             preconditioned residual norm carried by the
                             recurrence); 1 also requires the true FP64
                             ||b - A x||_2 <= tol ||b||_2, tightening the

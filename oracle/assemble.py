@@ -114,6 +114,45 @@ class Mesh:
         return mask
 
 
+def constant_field_fluxes(mesh, u):
+    """RT degrees of freedom of a constant vector field u on a box mesh whose
+    vertices form a tensor grid (Cartesian, possibly non-uniform spacing).
+
+    In the interpolation-histopolation basis a face dof is the flux of the
+    field through its sub-element face (the histopolation conditions in the
+    two tangential directions, Section 2.1), oriented along +axis.  On an
+    axis-aligned cell of widths (hx, hy, hz) the x-normal sub-face
+    (i, j, k) has area hy (xi_{j+1} - xi_j) hz (xi_{k+1} - xi_k), with xi
+    the Gauss-Lobatto sub-element vertices on [0, 1]."""
+    from .basis import gauss_lobatto_points
+    P = mesh.p
+    V = mesh.vertices.reshape(mesh.nz + 1, mesh.ny + 1, mesh.nx + 1, 3)
+    xs, ys, zs = V[0, 0, :, 0], V[0, :, 0, 1], V[:, 0, 0, 2]
+    grid = np.stack(np.meshgrid(zs, ys, xs, indexing='ij')[::-1], axis=-1)
+    assert np.allclose(V, grid, rtol=0, atol=1e-12 * max(1.0, np.abs(V).max())), "tensor grid required"
+    dxi = np.diff(gauss_lobatto_points(P))
+
+    def sub_widths(coord):
+        # widths of the refined intervals along one axis: cell width x dxi
+        return (np.diff(coord)[:, None] * dxi[None, :]).ravel()
+
+    w = [sub_widths(xs), sub_widths(ys), sub_widths(zs)]
+    out = []
+    for c in range(3):
+        t = [d for d in range(3) if d != c]
+        # refined face grid: extent n_c P + 1 along c, n_d P along the others
+        area = np.outer(w[t[1]], w[t[0]])   # [k-like, j-like] for first index fastest
+        n_c = len(w[c]) + 1
+        if c == 0:
+            blk = np.broadcast_to(area[:, :, None], (len(w[2]), len(w[1]), n_c))
+        elif c == 1:
+            blk = np.broadcast_to(area[:, None, :], (len(w[2]), n_c, len(w[0])))
+        else:
+            blk = np.broadcast_to(area[None, :, :], (n_c, len(w[1]), len(w[0])))
+        out.append(u[c] * blk.ravel())
+    return np.concatenate(out)
+
+
 def divergence_algorithm1(mesh):
     """The discrete divergence D in CSR form following Algorithm 1.
 

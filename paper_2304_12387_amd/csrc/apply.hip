@@ -386,29 +386,41 @@ template <int P, typename T>
 __global__ __launch_bounds__(64) void block_apply_kernel(
     Geo g, const T* __restrict__ pa, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
     int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
-    CGParams<T> cgp, int with_c, int colour, int64_t part_offset) {
+    CGParams<T> cgp, int with_c, int colour, int64_t part_offset, unsigned nb) {
     using D = Dim<P>;
     using S = Slot<P>;
     constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC, W = S::W;
+    // Block -> (element group, right-hand side).  With several right-hand
+    // sides, the blocks of one element group are spaced 8 apart, so that they
+    // run on the same XCD (blocks are dealt to the 8 XCDs round-robin) at
+    // about the same time and the second and later reads of the group's
+    // geometric factors hit that XCD's L2.
+    unsigned grp = blockIdx.x;
+    int r = 0;
+    if (ra.nrhs > 1) {
+        const unsigned k = blockIdx.x / 8;
+        r = (int)(k % (unsigned)ra.nrhs);
+        grp = blockIdx.x % 8 + 8 * (k / (unsigned)ra.nrhs);
+    }
+    if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;   // uniform over the block
     __shared__ ElemLDS<P, T> sm[S::EPW];
     const int lane = threadIdx.x;
     const int slot = lane / W, t = lane % W;
     // elements of one colour ((ex + ey + ez) mod 2 == colour), half-row by half-row
     const int hx = (g.nx + 1) / 2;
-    const int64_t idx = (int64_t)blockIdx.x * S::EPW + slot;
+    const int64_t idx = (int64_t)grp * S::EPW + slot;
     const int64_t row = idx / hx;
     const int m = (int)(idx % hx);
     const int ey0 = (int)(row % g.ny), ez0 = (int)(row / g.ny);
     const int ex0 = 2 * m + ((colour + ey0 + ez0) & 1);
-    const bool valid = row < (int64_t)g.ny * g.nz && ex0 < g.nx;
+    const bool valid = grp < nb && row < (int64_t)g.ny * g.nz && ex0 < g.nx;
     const int ex = valid ? ex0 : 0, ey = valid ? ey0 : 0, ez = valid ? ez0 : 0;
     const int64_t ee = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);   // clamped for address arithmetic
     ElemLDS<P, T>& L = sm[slot];
     const T cM = cm[ee];
     const T kE = kap[ee];
-    // the lane's geometric factors are loaded once and serve every right-hand
-    // side; they are issued first so that they are in flight during the
-    // gather and the forward sum factorisation
+    // the lane's geometric factors, issued first so that they are in flight
+    // during the gather and the forward sum factorisation
     T G[NPA][Q];
     {
         const T* pe = pa + (size_t)ee * NPA * Q3 + (t < Q * Q ? t : 0);
@@ -417,8 +429,7 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
 #pragma unroll
             for (int c = 0; c < Q; ++c) G[m][c] = pe[m * Q3 + Q * Q * c];
     }
-    for (int r = 0; r < ra.nrhs; ++r) {
-        if (ra.done && ra.done[(int64_t)r * ra.done_stride]) continue;
+    {
         const T* __restrict__ x = xall + r * ra.ldv;
         T* __restrict__ y = yall + r * ra.ldv;
         const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
@@ -481,9 +492,9 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
                 dot += (double)v * (double)L.sq[l];
             }
         }
-        if (ra.partial) {
+        if (ra.partial && grp < nb) {
             dot = slot_sum<double, 64>(dot);
-            if (lane == 0) ra.partial[r * ra.part_stride + part_offset + blockIdx.x] = dot;
+            if (lane == 0) ra.partial[r * ra.part_stride + part_offset + grp] = dot;
         }
     }
 }
@@ -549,10 +560,13 @@ void launch_apply_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int ess_mode
     const T* kap = std::is_same<T, double>::value ? (const T*)c->d_kap : (const T*)c->d_kap32;
     const tkp<P, T> tb = (tkp<P, T>)(std::is_same<T, double>::value ? c->d_tabk64 : c->d_tabk32);
     const unsigned nb = apply_blocks_per_colour(c->nx, c->ny, c->nz, Slot<P>::EPW);
+    // several right-hand sides: element groups rounded up to a multiple of 8
+    // (the XCD count), one block per (group, right-hand side)
+    const unsigned grid = ra.nrhs > 1 ? (unsigned)(((nb + 7) / 8) * 8 * (uint64_t)ra.nrhs) : nb;
     for (int colour = 0; colour < 2; ++colour)
-        hipLaunchKernelGGL((block_apply_kernel<P, T>), dim3(nb), dim3(64), 0, c->stream, g, pa, tb, cm, kap, c->ess,
-                           ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), c->kappa_zero ? 0 : 1, colour,
-                           (int64_t)colour * nb);
+        hipLaunchKernelGGL((block_apply_kernel<P, T>), dim3(grid), dim3(64), 0, c->stream, g, pa, tb, cm, kap,
+                           c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), c->kappa_zero ? 0 : 1, colour,
+                           (int64_t)colour * nb, nb);
 }
 
 template <int P, typename T>

@@ -23,7 +23,9 @@
 //      x += c_{j+1} eta w_{j+1}
 // Mixed precision: FP64 residual refinement around an FP32 inner MINRES
 // (FP32 vectors, operator and preconditioner, FP64 inner products and
-// scalars, FP64 coarse solve).
+// scalars, FP64 coarse solve).  FP32 preconditioner: the FP64 recurrence and
+// operator with the Schur-block V-cycle in FP32 (the diagonal (1,1) block
+// stays FP64; it costs one vector pass either way).
 #include "kernels_common.hpp"
 
 #include <algorithm>
@@ -306,6 +308,33 @@ __global__ void k_addscaled(int64_t N, const float* __restrict__ d, const double
     x[k] += nrm[2 * blockIdx.y] * (double)d[k];
 }
 
+// FP32 Schur block inside an FP64 recurrence: v_q rounded to FP32 for the
+// V-cycle; the FP32 z_q widened back to FP64 with the partial sums of
+// <z_q, v_q> taken against the FP64 v_q the recurrence holds.
+__global__ void k_down(int64_t n, const double* __restrict__ v, float* __restrict__ o, const int* done) {
+    if (done && *done) return;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) o[i] = (float)v[i];
+}
+__global__ void k_up_dot(int64_t n, const float* __restrict__ z32, const double* __restrict__ v,
+                         double* __restrict__ z, double* __restrict__ part, const int* done) {
+    if (done && *done) return;
+    __shared__ double s[BS];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        const double zi = (double)z32[i];
+        z[i] = zi;
+        acc += zi * v[i];
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
 // tighten the stop threshold of one RHS and resume its converged recurrence
 __global__ void k_retarget(MinresState* st, double tol) {
     if (st->status == 0) {
@@ -324,6 +353,9 @@ struct Work {
     MinresState* st = nullptr;
     MinresState* st_host = nullptr;
     double* nrm_host = nullptr;
+    // FP32 Schur block of an FP64 recurrence: v_q and z_q in FP32, partials
+    float *t32 = nullptr, *z32 = nullptr;
+    double* p32 = nullptr;
 };
 
 void free_work(Work& w) {
@@ -333,12 +365,15 @@ void free_work(Work& w) {
     dfree(w.pq);
     dfree(w.nrm);
     dfree(w.st);
+    dfree(w.t32);
+    dfree(w.z32);
+    dfree(w.p32);
     if (w.st_host) (void)hipHostFree(w.st_host);
     if (w.nrm_host) (void)hipHostFree(w.nrm_host);
     w = Work();
 }
 
-int alloc_work(hd_ctx* c, Work& w, int prec, int nrhs) {
+int alloc_work(hd_ctx* c, Work& w, int prec, int nrhs, bool schur32 = false) {
     w.N = c->n_u + c->n_q;
     w.nrhs = nrhs;
     w.prec = prec;
@@ -358,7 +393,35 @@ int alloc_work(hd_ctx* c, Work& w, int prec, int nrhs) {
     if (hipHostMalloc((void**)&w.st_host, sizeof(MinresState) * nrhs) != hipSuccess ||
         hipHostMalloc((void**)&w.nrm_host, sizeof(double) * 2 * nrhs) != hipSuccess)
         return set_err(c, HD_ERR_OOM, "MINRES host state");
+    if (schur32) {
+        w.t32 = dalloc<float>(c->n_q);
+        w.z32 = dalloc<float>(c->n_q);
+        w.p32 = dalloc<double>(w.nq_part);
+        if (!w.t32 || !w.z32 || !w.p32) return set_err(c, HD_ERR_OOM, "FP32 Schur buffers");
+    }
     return HD_OK;
+}
+
+// z_q = S^{-1} v_q with the V-cycle in precision PT, partial sums of
+// <z_q, v_q> into part (schur_parts(c) of them)
+template <typename T, typename PT>
+int schur_step(hd_ctx* c, Work& wk, const T* vq, T* zq, double* part, const int* done) {
+    if constexpr (std::is_same<T, PT>::value) {
+        return launch_schur_prec(c, std::is_same<T, double>::value ? HD_F64 : HD_F32, vq, zq, part, done);
+    } else {
+        static_assert(std::is_same<T, double>::value && std::is_same<PT, float>::value, "FP32 V-cycle in FP64");
+        const int64_t nq = c->n_q;
+        hipLaunchKernelGGL(k_down, dim3(nblk(nq)), dim3(BS), 0, c->stream, nq, vq, wk.t32, done);
+        int rc = launch_schur_prec(c, HD_F32, wk.t32, wk.z32, wk.p32, done);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_up_dot, dim3(red_grid(nq)), dim3(BS), 0, c->stream, nq, wk.z32, vq, zq, part, done);
+        return HD_OK;
+    }
+}
+
+template <typename T, typename PT>
+int64_t schur_parts(const hd_ctx* c) {
+    return std::is_same<T, PT>::value ? schur_partial_count(c) : (int64_t)red_grid(c->n_q);
 }
 
 // ||b_r - A x_r|| and ||b_r|| for every RHS into wk.nrm_host (and the device
@@ -384,7 +447,7 @@ inline double rel_of(const double* nrm, int r) {
 // sides (b of precision B, x of precision T, x0 = 0 unless use_x0).
 // true_tol > 0 (FP64 only): after the |eta| stop, require the true FP64
 // residual and continue the recurrence with a tighter threshold if needed.
-template <typename T, typename B>
+template <typename T, typename B, typename PT = T>
 int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, int maxit, int check_every,
                 std::vector<hd_solve_info>& out, double true_tol = 0.0) {
     const int prec = std::is_same<T, double>::value ? HD_F64 : HD_F32;
@@ -398,7 +461,7 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
     T* wo = (T*)wk.wo;
     T* q = (T*)wk.q;
     const T* mdinv = std::is_same<T, double>::value ? (const T*)c->d_mdinv : (const T*)c->d_mdinv32;
-    const int64_t nqp = schur_partial_count(c);
+    const int64_t nqp = schur_parts<T, PT>(c);
     int rc;
     const int64_t Nt = N * nr;
     if (use_x0) {
@@ -412,7 +475,7 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
     // z_1 = B^{-1} v_1
     for (int r = 0; r < nr; ++r) {
         if ((rc = launch_diag_prec(c, prec, v + r * N, z + r * N, wk.pu + (int64_t)r * RED_BLOCKS))) return rc;
-        if ((rc = launch_schur_prec(c, prec, v + r * N + nu, z + r * N + nu, wk.pq + r * wk.nq_part, nullptr)))
+        if ((rc = schur_step<T, PT>(c, wk, v + r * N + nu, z + r * N + nu, wk.pq + r * wk.nq_part, nullptr)))
             return rc;
     }
     hipLaunchKernelGGL(k_start, dim3(nr), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)red_grid(nu),
@@ -429,7 +492,7 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
             hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N), nr), dim3(BS), 0, c->stream, N, nu, q, v, vo, mdinv, zn,
                                wk.st, wk.pu);
             for (int r = 0; r < nr; ++r)
-                if ((rc = launch_schur_prec(c, prec, vo + r * N + nu, zn + r * N + nu, wk.pq + r * wk.nq_part,
+                if ((rc = schur_step<T, PT>(c, wk, vo + r * N + nu, zn + r * N + nu, wk.pq + r * wk.nq_part,
                                             stop + r * ST_STRIDE_I)))
                     return rc;
             hipLaunchKernelGGL(k_givens, dim3(nr), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)red_grid(N),
@@ -493,7 +556,7 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
 int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* b, double* x, hd_solve_info* info) {
     auto t0 = std::chrono::steady_clock::now();
     Work w64;
-    int rc = alloc_work(c, w64, HD_F64, nrhs);
+    int rc = alloc_work(c, w64, HD_F64, nrhs, prm.mode == HD_MODE_PREC32);
     if (rc) {
         free_work(w64);
         return rc;
@@ -503,6 +566,9 @@ int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* 
     if (prm.mode == HD_MODE_PLAIN64) {
         rc = minres_core<double, double>(c, w64, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, res,
                                          prm.stop_true ? prm.tol : 0.0);
+    } else if (prm.mode == HD_MODE_PREC32) {
+        rc = minres_core<double, double, float>(c, w64, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, res,
+                                                prm.stop_true ? prm.tol : 0.0);
     } else if (prm.mode == HD_MODE_MIXED) {
         Work w32;
         rc = alloc_work(c, w32, HD_F32, nrhs);

@@ -113,3 +113,52 @@ def test_cfg1_minres_matches_direct_and_manufactured_error():
     e2 = manufactured.darcy_errors(prob, xd)
     for k in e1:
         assert abs(e1[k] - e2[k]) <= 1e-8 * e2[k]
+
+
+def _tensor_vertices(xs, ys, zs):
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing='ij')
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_layered_darcy_flux_boundary_reproduces_constant_flow(p):
+    """Darcy with gamma = 0, every boundary face essential with the flux of
+    u = (1, 0, 0) (the layered-reservoir boundary condition), on a
+    non-uniform tensor grid.  With constant permeability the exact velocity is
+    the constant (1, 0, 0), which RT_p reproduces, so the discrete u must be
+    its flux interpolant on every face (interior ones included): this pins the
+    flux reading of the dofs, the lifting and the singular Schur block."""
+    xs = np.array([0.0, 20.0, 50.0, 60.0])
+    ys = np.array([0.0, 10.0, 25.0, 30.0, 40.0])
+    zs = np.array([0.0, 2.0, 5.0])
+    m = assemble.Mesh(3, 4, 2, p, _tensor_vertices(xs, ys, zs))
+    k = 3.7
+    prob = assemble.Problem(m, assemble.DARCY, np.full(m.ne, k), None, ess_sides=63)
+    ubc = assemble.constant_field_fluxes(m, (1.0, 0.0, 0.0))
+    b = prob.lift_essential(np.zeros(m.n), ubc)
+    # compatibility: the net boundary flux is zero
+    assert abs(b[m.n_u:].sum()) <= 1e-10 * np.abs(b).max()
+    P = precond.BlockPreconditioner(prob)
+    assert P.singular
+    x, it, info = minres.minres(prob.apply, P, b, tol=1e-12)
+    assert info['converged']
+    assert np.abs(x[:m.n_u] - ubc).max() <= 1e-9 * np.abs(ubc).max()
+    # a second field: the flux of (0, 0, 1) is |cell| in z-sub-face units
+    fz = assemble.constant_field_fluxes(m, (0.0, 0.0, 1.0))
+    assert abs(fz[m.nface[0] + m.nface[1]:].reshape(-1, 4 * p, 3 * p)[0].sum() - 60.0 * 40.0) <= 1e-9
+
+
+def test_layered_darcy_mass_conservation():
+    """Variable permeability (a small layered field): D u = 0, so the flux
+    through every refined x-plane equals the inflow Ly Lz."""
+    cfg = inputs.darcy_layered(4, 5, 3, 2, seed=3)
+    m = assemble.Mesh(4, 5, 3, 2, cfg['vertices'])
+    prob = assemble.Problem(m, assemble.DARCY, cfg['c_mass'], None, ess_sides=63)
+    ubc = assemble.constant_field_fluxes(m, (1.0, 0.0, 0.0))
+    b = prob.lift_essential(np.zeros(m.n), ubc)
+    P = precond.BlockPreconditioner(prob)
+    x, it, info = minres.minres(prob.apply, P, b, tol=1e-12)
+    assert info['converged']
+    ux = x[:m.nface[0]].reshape(3 * 2, 5 * 2, 4 * 2 + 1)
+    plane = ux.sum(axis=(0, 1))
+    assert np.abs(plane - 5 * 10.0 * 3 * 2.0).max() <= 1e-8 * 100.0
