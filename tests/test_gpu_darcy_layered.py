@@ -1,0 +1,100 @@
+"""Layered Darcy (gamma = 0, flux boundary condition u.n = (1, 0, 0).n on
+every side, so the Schur block is singular): GPU solver against the oracle on
+a small grid, and the 60 x 220 x 85, p = 2 workload at full size through
+sampled operator rows and properties that hold at any size."""
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_context, rel, to_dev, torch_cuda
+from oracle import assemble, minres, precond
+from paper_2304_12387_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(nx, ny, nz, p=2):
+    cfg = inputs.darcy_layered(nx, ny, nz, p, seed=3)
+    m = assemble.Mesh(nx, ny, nz, p, cfg['vertices'])
+    ubc = assemble.constant_field_fluxes(m, (1.0, 0.0, 0.0))
+    return cfg, m, ubc
+
+
+def _plane_flux(x, m):
+    P = m.p
+    ux = x[:m.nface[0]].reshape(m.nz * P, m.ny * P, m.nx * P + 1)
+    return ux.sum(axis=(0, 1))
+
+
+@pytest.mark.parametrize("mode", ['plain', 'prec32'])
+def test_small_layered_matches_oracle(mode):
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    cfg, m, ubc = _setup(5, 6, 3)
+    prob = assemble.Problem(m, assemble.DARCY, cfg['c_mass'], None, ess_sides=63)
+    b = prob.lift_essential(np.zeros(m.n), ubc)
+    P = precond.BlockPreconditioner(prob, amg_kwargs=dict(max_coarse=40))
+    # FP64 recurrences reach 1e-12; with the FP32 V-cycle 1e-10 is asked for
+    tol = 1e-12 if mode == 'plain' else 1e-10
+    xo, ito, _ = minres.minres(prob.apply, P, b, tol=tol)
+    ctx = gpu_context(cfg, precond=True, params=hdivsp.precond_params(max_coarse=40))
+    bd = torch.zeros(m.n, dtype=torch.float64, device='cuda')
+    ctx.lift_essential(to_dev(ubc), bd)
+    torch.cuda.synchronize()
+    assert rel(bd.cpu().numpy(), b) <= 1e-12
+    xd = torch.zeros_like(bd)
+    md = hdivsp.HD_MODE_PLAIN64 if mode == 'plain' else hdivsp.HD_MODE_PREC32
+    info = ctx.minres_solve(bd, xd, hdivsp.solve_params(tol=tol, mode=md, max_it=3000))
+    x = xd.cpu().numpy()
+    print(mode, 'iterations gpu', info['iterations'], 'oracle', ito, flush=True)
+    assert info['status'] == 0
+    if mode == 'plain':
+        assert abs(info['iterations'] - ito) <= 2
+    else:
+        # the FP32 V-cycle perturbs the preconditioner at the 1e-7 level
+        assert abs(info['iterations'] - ito) <= max(2, ito // 10)
+    # velocity is unique (the pressure only up to a constant)
+    tu, tp = (1e-8, 1e-7) if mode == 'plain' else (1e-6, 1e-5)
+    assert rel(x[:m.n_u], xo[:m.n_u]) <= tu
+    pq, po = x[m.n_u:], xo[m.n_u:]
+    assert rel(pq - pq.mean(), po - po.mean()) <= tp
+    flux = _plane_flux(x, m)
+    assert np.abs(flux - 6 * 10.0 * 3 * 2.0).max() <= 1e-7 * 360.0
+    ctx.close()
+
+
+def test_full_size_layered_60x220x85_p2():
+    """60 x 220 x 85 cells of 20 x 10 x 2, p = 2 (36,052,000 unknowns):
+    operator rows of sampled elements (boundary ones included) against the
+    oracle, then FP64 MINRES with the FP32 Schur V-cycle to a true relative
+    residual of 1e-8, and conservation of the flux through every refined
+    x-plane."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    cfg, m, ubc = _setup(60, 220, 85)
+    print('full size', cfg['name'], m.n, flush=True)
+    ctx = gpu_context(cfg)
+    nu, nq = ctx.sizes()
+    assert (nu, nq) == (m.n_u, m.n_q) and nu + nq == 36052000
+    x = inputs.uniform_vector(nu + nq, 32)
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    ctx.apply_block_op(xd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    elems = np.array([0, 59, 60 * 219, 60 * 220 * 85 - 1, 30 + 60 * (110 + 220 * 42), 777777, 1000001])
+    qr, yq, ur, yu = assemble.apply_element_rows(m, 1, cfg['c_mass'], None, 63, x, elems)
+    assert rel(y[qr], yq) <= 1e-12
+    assert rel(y[ur], yu) <= 1e-12
+    del xd, yd
+    print('building the preconditioner', flush=True)
+    ctx.build_precond()
+    bd = torch.zeros(nu + nq, dtype=torch.float64, device='cuda')
+    ctx.lift_essential(to_dev(ubc), bd)
+    sol = torch.zeros_like(bd)
+    info = ctx.minres_solve(bd, sol, hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_PREC32, stop_true=1,
+                                                         max_it=5000))
+    print('prec32', info, flush=True)
+    assert info['status'] == 0 and info['true_rel_res'] <= 1e-8
+    flux = _plane_flux(sol.cpu().numpy(), m)
+    assert np.abs(flux - 220 * 10.0 * 85 * 2.0).max() <= 1e-7 * 374000.0
+    ctx.close()

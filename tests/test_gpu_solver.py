@@ -165,3 +165,55 @@ def test_lift_essential_matches_oracle():
     torch.cuda.synchronize()
     assert rel(bd.cpu().numpy(), ref) <= 1e-12
     ctx.close()
+
+
+def test_post_processing():
+    """Darcy: b_q = W^{-1} g^ and p_h = -W^{-1} p~ through the L2 mass inverse
+    against the oracle's sparse solves; grad-div: at the solution the second
+    block row gives C q~ = D u, i.e. the flux variable q = W_alpha^{-1} q~
+    equals the divergence of u (the post-processing check of Section 3)."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    cfg = inputs.darcy_cube_4()
+    m = assemble.Mesh(4, 4, 4, 2, cfg['vertices'])
+    prob = assemble.Problem(m, cfg['problem'], cfg['c_mass'], cfg['c_22'], cfg['ess_sides'])
+    ctx = gpu_context(cfg, precond=True)
+    gh = manufactured.l2_load(prob, manufactured.g_exact)
+    bq = torch.empty(m.n_q, dtype=torch.float64, device='cuda')
+    ctx.apply_l2_mass_inverse(to_dev(gh), bq)
+    torch.cuda.synchronize()
+    b = manufactured.darcy_rhs(prob)
+    assert rel(bq.cpu().numpy(), b[m.n_u:]) <= 1e-12
+    bd = torch.cat([torch.zeros(m.n_u, dtype=torch.float64, device='cuda'), bq])
+    xd = torch.zeros_like(bd)
+    info = ctx.minres_solve(bd, xd, hdivsp.solve_params(tol=1e-10))
+    assert info['status'] == 0
+    ph = torch.empty(m.n_q, dtype=torch.float64, device='cuda')
+    ctx.apply_l2_mass_inverse(xd[m.n_u:].contiguous(), ph)
+    torch.cuda.synchronize()
+    ph = -ph.cpu().numpy()
+    x = xd.cpu().numpy()
+    ref = -spla.spsolve(prob.W.tocsc(), x[m.n_u:])
+    assert rel(ph, ref) <= 1e-12
+    ctx.close()
+
+    case = make_case(3, 3, 2, 3, problem=0)
+    prob = oracle_problem(case)
+    ctx = gpu_context(case, precond=True, params=_params(hdivsp, 40))
+    b = inputs.graddiv_rhs(prob.mesh.n_u, prob.mesh.n_q, seed=41)
+    bd = to_dev(b)
+    xd = torch.zeros_like(bd)
+    info = ctx.minres_solve(bd, xd, hdivsp.solve_params(tol=1e-12, max_it=2000))
+    assert info['status'] == 0
+    nu = prob.mesh.n_u
+    q = torch.empty(prob.mesh.n_q, dtype=torch.float64, device='cuda')
+    ctx.apply_mass_inverse(xd[nu:].contiguous(), q)
+    u0 = xd.clone()
+    u0[nu:] = 0.0
+    du = torch.empty_like(u0)
+    ctx.apply_block_op(u0, du)
+    torch.cuda.synchronize()
+    q = q.cpu().numpy()
+    assert rel(q, du[nu:].cpu().numpy()) <= 1e-9
+    assert rel(q, prob.D @ xd[:nu].cpu().numpy()) <= 1e-9
+    ctx.close()
