@@ -93,6 +93,12 @@ typedef struct hd_precond_params {
     int max_coarse;      /* AMG coarsest size; default 1024 */
     int max_levels;      /* default 25 */
     double omega;        /* prolongator smoothing weight; default 2/3 */
+    int learned;         /* (1,1) diagonal: 0 plain diag(M) (Section 2.3); 1 diag(M)
+                            with per-element scalings from the network held by
+                            the context (hd_mlp_*), falling back to the plain
+                            diagonal with HD_FALLBACK_USED when an output is not
+                            finite; 2 with the scalings set by
+                            hd_set_diag_scalings.  Default 0 */
 } hd_precond_params;
 
 typedef struct hd_solve_params {
@@ -177,6 +183,61 @@ int hd_apply_precond(hd_ctx* ctx, int prec, int nrhs, const void* r, void* z);
  * error code otherwise. */
 int hd_minres_solve(hd_ctx* ctx, const hd_solve_params* params, int nrhs,
                     const double* b, double* x, hd_solve_info* info);
+
+/* ---- learned (1,1)-diagonal correction ---------------------------------
+ * Not in the paper: an extension of its diagonal (1,1) block (Section 2.3).
+ * Six log-scalings theta = (x-, x+, y-, y+, z-, z+) per element multiply the
+ * element's contribution to diag(M): an RT dof of component c with index i
+ * along c (Gauss-Lobatto sub-element vertex xi_i on [0, 1]) is scaled by
+ * exp((1 - xi_i) theta_{2c} + xi_i theta_{2c+1}).  The network maps
+ * x in R^27 (24 vertex offsets from the centroid divided by the mean edge
+ * length, vertex order (dz, dy, dx) with the coordinate fastest; ln alpha;
+ * ln beta; p / 6) through Linear(27,64)-GELU-Linear(64,64)-GELU-Linear(64,6)
+ * (exact GELU) to theta = clip(o, -ln 4, ln 4).  Parameters (FP32, flat):
+ * W1[64][27], b1[64], W2[64][64], b2[64], W3[6][64], b3[6]. */
+
+/* Training targets: for n single elements of order p (vertices: device
+ * [n][2][2][2][3], indexed (dz, dy, dx, coord)), theta* minimising
+ * log lambda_max - log lambda_min of the pencil (M_e, diag(s * diag M_e))
+ * for unit coefficient on sum(theta) = 0, by at most max_steps projected
+ * gradient steps with Armijo backtracking from theta = 0 (eigenpairs by
+ * Lanczos, matrix-free).  Outputs (device, caller-owned): theta [n][6];
+ * lam [n][2] = (lambda_min, lambda_max) at theta* (may be NULL); spread
+ * [n][2] = (value at 0, value at theta*) (may be NULL).  An element with a
+ * non-positive Jacobian gets NaN.  Synchronises. */
+int hd_learned_targets(hd_ctx* ctx, int p, int64_t n, const double* vertices, int max_steps,
+                       double* theta, double* lam, double* spread);
+
+/* Features x [n][27] (device, FP32) of n elements: vertices as above,
+ * alpha, beta [n] (device FP64), p_per_elem [n] (device int) or NULL with
+ * the constant p. */
+int hd_learned_features(hd_ctx* ctx, int64_t n, const double* vertices, const double* alpha,
+                        const double* beta, const int* p_per_elem, int p, float* x);
+
+/* Number of network parameters (6342). */
+int hd_mlp_param_count(void);
+/* Initialise the parameters (W ~ U(+-1/sqrt(fan_in)), b = 0) from seed, or
+ * set / get them from / to a host array; both reset the Adam state. */
+int hd_mlp_init(hd_ctx* ctx, uint64_t seed);
+int hd_mlp_set_params(hd_ctx* ctx, const float* params);
+int hd_mlp_get_params(hd_ctx* ctx, float* params);
+/* Mean squared error (over the n x 6 outputs, targets clipped to +-ln 4) of
+ * the rows x [n][27], y [n][6] (device FP32) and its gradient (host, 6342
+ * entries, may be NULL). */
+int hd_mlp_loss_grad(hd_ctx* ctx, int64_t n, const float* x, const float* y, float* loss, float* grad);
+/* Adam training (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) over
+ * `epochs` passes of shuffled mini-batches of `batch` rows; per-epoch mean
+ * training loss and validation loss (n_val rows, may be 0) into host arrays
+ * of `epochs` entries (may be NULL).  Synchronises. */
+int hd_mlp_train(hd_ctx* ctx, int64_t n, const float* x, const float* y, int64_t n_val, const float* x_val,
+                 const float* y_val, int epochs, int batch, float lr, uint64_t seed, float* train_loss,
+                 float* val_loss);
+/* theta [n][6] = clip(o, +-ln 4) for rows x [n][27] (device FP32); bf16 = 1
+ * runs the network in BF16 on the matrix cores (FP32 accumulation). */
+int hd_mlp_infer(hd_ctx* ctx, int64_t n, const float* x, float* theta, int bf16);
+/* Per-element log-scalings [ne][6] (device FP64, copied) used by
+ * hd_build_precond with learned = 2; NULL clears them. */
+int hd_set_diag_scalings(hd_ctx* ctx, const double* theta);
 
 /* ---- inspection (parity checks) ---------------------------------------- */
 

@@ -58,8 +58,9 @@ def c_tilde(prob):
     return kap / diag_W(prob)
 
 
-def schur_by_formula(prob):
-    """S~ entry by entry from eq. (approx-schur-entries).
+def schur_by_formula(prob, Md=None):
+    """S~ entry by entry from eq. (approx-schur-entries).  Md replaces
+    diag(M) as M~ when given (the learned diagonal).
 
     Row i (sub-volume): diagonal C~_ii + sum over its free faces k of 1/M~_kk;
     off-diagonal -1/M~_kk for each neighbour j sharing the free face k.
@@ -67,7 +68,7 @@ def schur_by_formula(prob):
     share a face)."""
     D = prob.D.tocsr()
     Dt = D.T.tocsr()
-    Mt = diag_M(prob)
+    Mt = diag_M(prob) if Md is None else Md
     Ct = c_tilde(prob)
     free = ~prob.ess
     n = D.shape[0]
@@ -301,13 +302,14 @@ class AMG:
 class BlockPreconditioner:
     """z = B^{-1} r = [ (tau M~)^{-1} r_u ; S^{-1} r_q ], identity on the
     essential RT dofs.  schur = 'amg' (one V-cycle), 'exact' (sparse direct
-    solve with S~) or a callable."""
+    solve with S~) or a callable.  Md: M~ to use instead of diag(M) (the
+    learned diagonal); S~ and the AMG are then built from it."""
 
-    def __init__(self, prob, tau=1.0, schur='amg', amg_kwargs=None):
+    def __init__(self, prob, tau=1.0, schur='amg', amg_kwargs=None, Md=None):
         self.prob = prob
         self.tau = tau
-        self.Md = diag_M(prob)
-        self.S = schur_by_formula(prob)
+        self.Md = diag_M(prob) if Md is None else np.asarray(Md, dtype=np.float64)
+        self.S = schur_by_formula(prob, self.Md)
         self.singular = schur_is_singular(prob)
         self.nu = prob.mesh.n_u
         if schur == 'amg':

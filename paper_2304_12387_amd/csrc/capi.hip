@@ -21,8 +21,13 @@ namespace {
 void free_mesh(hd_ctx* c) {
     dfree(c->d_pa);
     dfree(c->d_pa32);
+    dfree(c->d_vert);
+    dfree(c->d_theta);
     c->d_pa = nullptr;
     c->d_pa32 = nullptr;
+    c->d_vert = nullptr;
+    c->d_theta = nullptr;
+    c->theta_set = false;
     c->have_mesh = false;
 }
 
@@ -85,6 +90,7 @@ hd_precond_params default_precond() {
     p.max_coarse = 1024;
     p.max_levels = 25;
     p.omega = 2.0 / 3.0;
+    p.learned = 0;
     return p;
 }
 
@@ -130,6 +136,9 @@ int hd_destroy(hd_ctx* c) {
     dfree(c->d_partial);
     dfree(c->d_scal);
     dfree(c->d_flag);
+    dfree(c->d_mlp);
+    dfree(c->d_adam_m);
+    dfree(c->d_adam_v);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -185,7 +194,7 @@ int hd_setup_mesh(hd_ctx* c, int nx, int ny, int nz, int p, const double* vertic
         HD_HIP(c, hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HD_HIP(c, hipStreamSynchronize(c->stream));
     }
-    dfree(dv);
+    c->d_vert = dv;
     if (rc) return rc;
     if (bad) {
         free_mesh(c);
@@ -290,11 +299,25 @@ int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
     if (!c) return HD_ERR_ARG;
     if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
     hd_precond_params prm = params ? *params : default_precond();
-    if (!(prm.tau > 0) || !(prm.theta >= 0) || prm.max_coarse < 1 || prm.max_levels < 1 || !(prm.omega > 0))
+    if (!(prm.tau > 0) || !(prm.theta >= 0) || prm.max_coarse < 1 || prm.max_levels < 1 || !(prm.omega > 0) ||
+        prm.learned < 0 || prm.learned > 2)
         return set_err(c, HD_ERR_ARG, "bad preconditioner parameters");
+    if (prm.learned == 1 && !c->mlp_ready) return set_err(c, HD_ERR_STATE, "learned diagonal needs a network");
+    if (prm.learned == 2 && !c->theta_set) return set_err(c, HD_ERR_STATE, "hd_set_diag_scalings first");
     int rc = use_device(c);
     if (rc) return rc;
     free_prec(c);
+    c->fallback_used = false;
+    const double* theta = nullptr;
+    if (prm.learned == 1) {
+        int fb = 0;
+        if ((rc = learned_mesh_theta(c, &fb))) return rc;
+        c->theta_set = false;   // the network's scalings are not user-set ones
+        if (fb) c->fallback_used = true;
+        else theta = c->d_theta;
+    } else if (prm.learned == 2) {
+        theta = c->d_theta;
+    }
     c->tau = prm.tau;
     c->d_mdiag = dalloc<double>(c->n_u);
     c->d_mdinv = dalloc<double>(c->n_u);
@@ -307,7 +330,7 @@ int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
     if (!c->d_mdiag || !c->d_mdinv || !c->d_mdinv32 || !c->d_wdiag || !c->d_wface || !c->d_wface32 || !c->d_sdiag ||
         !c->d_sdiag32)
         return set_err(c, HD_ERR_OOM, "diagonals");
-    if ((rc = launch_diagonals(c))) return rc;
+    if ((rc = launch_diagonals(c, theta))) return rc;
     if ((rc = launch_schur(c))) return rc;
     // S~ to the host for the AMG setup
     HostCSR S;
@@ -326,6 +349,10 @@ int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
     if (rc) return set_err(c, rc, err);
     if ((rc = upload_amg(c))) return rc;
     c->have_prec = true;
+    if (c->fallback_used) {
+        c->err = "learned scalings not finite: plain diagonal used";
+        return HD_FALLBACK_USED;
+    }
     return HD_OK;
 }
 
@@ -371,6 +398,104 @@ int hd_minres_solve(hd_ctx* c, const hd_solve_params* params, int nrhs, const do
     rc = minres_solve(c, prm, nrhs, b, x, info);
     if (rc == HD_NOT_CONVERGED) c->err = "MINRES did not reach the tolerance";
     return rc;
+}
+
+int hd_learned_targets(hd_ctx* c, int p, int64_t n, const double* vertices, int max_steps, double* theta,
+                       double* lam, double* spread) {
+    if (!c) return HD_ERR_ARG;
+    if (p < 1 || p > 6) return set_err(c, HD_ERR_ARG, "p must be in 1..6");
+    if (n < 0 || max_steps < 0) return set_err(c, HD_ERR_ARG, "bad sizes");
+    if (n == 0) return HD_OK;
+    if (!vertices || !theta) return set_err(c, HD_ERR_ARG, "null pointer");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_targets(c, p, n, vertices, max_steps, theta, lam, spread);
+}
+
+int hd_learned_features(hd_ctx* c, int64_t n, const double* vertices, const double* alpha, const double* beta,
+                        const int* p_per_elem, int p, float* x) {
+    if (!c) return HD_ERR_ARG;
+    if (n < 0) return set_err(c, HD_ERR_ARG, "bad size");
+    if (n == 0) return HD_OK;
+    if (!vertices || !alpha || !beta || !x) return set_err(c, HD_ERR_ARG, "null pointer");
+    if (!p_per_elem && (p < 1 || p > 6)) return set_err(c, HD_ERR_ARG, "p must be in 1..6");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_features(c, n, vertices, alpha, beta, p_per_elem, p, x);
+}
+
+int hd_mlp_param_count(void) { return mlp_param_count(); }
+
+int hd_mlp_init(hd_ctx* c, uint64_t seed) {
+    if (!c) return HD_ERR_ARG;
+    int rc = use_device(c);
+    if (rc) return rc;
+    return mlp_init(c, seed);
+}
+
+int hd_mlp_set_params(hd_ctx* c, const float* params) {
+    if (!c) return HD_ERR_ARG;
+    if (!params) return set_err(c, HD_ERR_ARG, "null pointer");
+    for (int i = 0; i < mlp_param_count(); ++i)
+        if (!std::isfinite(params[i])) return set_err(c, HD_ERR_NONFINITE, "non-finite network parameter");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return mlp_set(c, params);
+}
+
+int hd_mlp_get_params(hd_ctx* c, float* params) {
+    if (!c) return HD_ERR_ARG;
+    if (!params) return set_err(c, HD_ERR_ARG, "null pointer");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return mlp_get(c, params);
+}
+
+int hd_mlp_loss_grad(hd_ctx* c, int64_t n, const float* x, const float* y, float* loss, float* grad) {
+    if (!c) return HD_ERR_ARG;
+    if (n < 1 || !x || !y) return set_err(c, HD_ERR_ARG, "bad arguments");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return mlp_loss_grad(c, n, x, y, loss, grad);
+}
+
+int hd_mlp_train(hd_ctx* c, int64_t n, const float* x, const float* y, int64_t n_val, const float* x_val,
+                 const float* y_val, int epochs, int batch, float lr, uint64_t seed, float* train_loss,
+                 float* val_loss) {
+    if (!c) return HD_ERR_ARG;
+    if (n < 1 || !x || !y || epochs < 0 || batch < 1 || batch > n || !(lr > 0) || n > INT32_MAX)
+        return set_err(c, HD_ERR_ARG, "bad training arguments");
+    if (n_val < 0 || (n_val > 0 && (!x_val || !y_val))) return set_err(c, HD_ERR_ARG, "bad validation arguments");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return mlp_train(c, n, x, y, n_val, x_val, y_val, epochs, batch, lr, seed, train_loss, val_loss);
+}
+
+int hd_mlp_infer(hd_ctx* c, int64_t n, const float* x, float* theta, int bf16) {
+    if (!c) return HD_ERR_ARG;
+    if (n < 0) return set_err(c, HD_ERR_ARG, "bad size");
+    if (n == 0) return HD_OK;
+    if (!x || !theta) return set_err(c, HD_ERR_ARG, "null pointer");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return mlp_infer(c, n, x, theta, bf16);
+}
+
+int hd_set_diag_scalings(hd_ctx* c, const double* theta) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_mesh) return set_err(c, HD_ERR_STATE, "hd_setup_mesh first");
+    int rc = use_device(c);
+    if (rc) return rc;
+    if (!theta) {
+        c->theta_set = false;
+        return HD_OK;
+    }
+    if (!c->d_theta) c->d_theta = dalloc<double>(c->ne * 6);
+    if (!c->d_theta) return set_err(c, HD_ERR_OOM, "scalings");
+    HD_HIP(c, hipMemcpyAsync(c->d_theta, theta, sizeof(double) * c->ne * 6, hipMemcpyDeviceToDevice, c->stream));
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    c->theta_set = true;
+    return HD_OK;
 }
 
 int hd_get_diagonals(hd_ctx* c, double* m_diag, double* w_diag) {

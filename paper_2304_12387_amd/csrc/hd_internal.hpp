@@ -32,6 +32,7 @@ struct Tables {
     T Tinv[HD_MAXP][HD_MAXP];
     T wq[HD_MAXQ];
     T xq[HD_MAXQ];
+    T gll[HD_MAXQ];   // Gauss-Lobatto sub-element vertices on [0, 1]
 };
 
 void gauss_legendre01(int n, double* x, double* w);
@@ -104,6 +105,7 @@ struct hd_ctx {
     void* d_tabk32 = nullptr;
     hd::Tables<double> tab64_host;
     hd::Tables<float> tab32_host;
+    double* d_vert = nullptr;   // [(nx+1)(ny+1)(nz+1)][3], kept for the learned features
 
     // coefficients
     bool have_coeffs = false;
@@ -133,6 +135,16 @@ struct hd_ctx {
     float* d_cinv32 = nullptr;
     bool singular = false;
     hd::HostAMG host_amg;        // kept for inspection
+
+    // learned (1,1)-diagonal correction
+    float* d_mlp = nullptr;          // network parameters (FP32, flat)
+    float* d_adam_m = nullptr;
+    float* d_adam_v = nullptr;
+    int adam_t = 0;
+    bool mlp_ready = false;
+    double* d_theta = nullptr;       // [ne][6] log-scalings used by the next hd_build_precond
+    bool theta_set = false;
+    bool fallback_used = false;
 
     // scratch
     double* d_partial = nullptr;     // per-block partial sums (>= ne and >= reduce grid)
@@ -171,7 +183,8 @@ inline void dfree(void* p) {
 
 // kernels and launchers (setup.hip)
 int launch_geometry(hd_ctx* c, const double* d_vert, int* d_bad);
-int launch_diagonals(hd_ctx* c);
+// diag(M) (with optional per-element log-scalings theta [ne][6]) and diag(W)
+int launch_diagonals(hd_ctx* c, const double* theta);
 int launch_schur(hd_ctx* c);
 int launch_ensure_partial(hd_ctx* c, int64_t n);
 
@@ -197,6 +210,21 @@ int64_t schur_partial_count(const hd_ctx* c);
 void free_levels(hd_ctx* c);
 Geo geo_of(const hd_ctx* c);
 int scan_counts(hd_ctx* c, const int32_t* cnt, int64_t n, int32_t* rp, int64_t* total_host);
+
+// learned.hip: the learned (1,1)-diagonal correction
+int mlp_param_count();
+int launch_targets(hd_ctx* c, int p, int64_t n, const double* verts, int steps, double* theta, double* lam,
+                   double* spread);
+int launch_features(hd_ctx* c, int64_t n, const double* verts, const double* alpha, const double* beta,
+                    const int* parr, int p, float* X);
+int mlp_init(hd_ctx* c, uint64_t seed);
+int mlp_set(hd_ctx* c, const float* host);
+int mlp_get(hd_ctx* c, float* host);
+int mlp_loss_grad(hd_ctx* c, int64_t n, const float* X, const float* Y, float* loss, float* grad);
+int mlp_train(hd_ctx* c, int64_t n, const float* X, const float* Y, int64_t nval, const float* Xv, const float* Yv,
+              int epochs, int batch, float lr, uint64_t seed, float* train_loss, float* val_loss);
+int mlp_infer(hd_ctx* c, int64_t n, const float* X, float* theta, int bf16);
+int learned_mesh_theta(hd_ctx* c, int* fallback);
 
 // minres.hip
 // nrhs right-hand sides stored one after the other; info: nrhs entries

@@ -93,11 +93,14 @@ __global__ void geometry_kernel(int nx, int ny, int nz, int P, const double* __r
 // are added into the zero-initialised global diagonal (at most two
 // contributions per dof, so the result does not depend on their order).
 // ---------------------------------------------------------------------------
+// With theta (per element (x-, x+, y-, y+, z-, z+) log-scalings) each local
+// diagonal entry is multiplied by exp((1 - xi_i) theta_{2c} + xi_i theta_{2c+1})
+// before it is added (the learned correction of the (1,1) block).
 template <int P>
 __global__ __launch_bounds__(64) void diag_kernel(Geo g, const double* __restrict__ pa,
                                                   const Tables<double>* __restrict__ tab,
-                                                  const double* __restrict__ cm, double* __restrict__ mdiag,
-                                                  double* __restrict__ wdiag) {
+                                                  const double* __restrict__ cm, const double* __restrict__ theta,
+                                                  double* __restrict__ mdiag, double* __restrict__ wdiag) {
     using D = Dim<P>;
     constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC;
     __shared__ double sL2[Q * (P + 1)], sH2[Q * P], in[Q3], b1[Q3], b2[Q3], loc[NC];
@@ -137,7 +140,11 @@ __global__ __launch_bounds__(64) void diag_kernel(Geo g, const double* __restric
             int i, j, k, onf, bs;
             local_ijk<P>(comp, l, i, j, k);
             const int64_t gi = rt_global<P>(g, comp, ex, ey, ez, i, j, k, onf, bs);
-            const double v = c * loc[l];
+            double v = c * loc[l];
+            if (theta) {
+                const double xi = tab->gll[comp == 0 ? i : (comp == 1 ? j : k)];
+                v *= exp((1.0 - xi) * theta[e * 6 + 2 * comp] + xi * theta[e * 6 + 2 * comp + 1]);
+            }
             if (!onf || bs >= 0) mdiag[gi] = v;
             else atomicAdd(&mdiag[gi], v);
         }
@@ -376,9 +383,9 @@ __global__ void reduce_kernel(const double* __restrict__ part, int64_t n, double
 }
 
 template <int P>
-void launch_diag_p(hd_ctx* c, Geo g) {
+void launch_diag_p(hd_ctx* c, Geo g, const double* theta) {
     hipLaunchKernelGGL((diag_kernel<P>), dim3((unsigned)c->ne), dim3(64), 0, c->stream, g, c->d_pa, c->d_tab64,
-                       c->d_cm, c->d_mdiag, c->d_wdiag);
+                       c->d_cm, theta, c->d_mdiag, c->d_wdiag);
 }
 
 }  // namespace
@@ -404,19 +411,19 @@ int launch_geometry(hd_ctx* c, const double* d_vert, int* d_bad) {
     return HD_OK;
 }
 
-int launch_diagonals(hd_ctx* c) {
+int launch_diagonals(hd_ctx* c, const double* theta) {
     Geo g = geo_of(c);
     const int bs = 256;
     // zero diag(M) (shared faces are accumulated)
     hipLaunchKernelGGL(fill_kernel<double>, dim3((unsigned)((c->n_u + bs - 1) / bs)), dim3(bs), 0, c->stream,
                        c->d_mdiag, 0.0, c->n_u);
     switch (c->p) {
-        case 1: launch_diag_p<1>(c, g); break;
-        case 2: launch_diag_p<2>(c, g); break;
-        case 3: launch_diag_p<3>(c, g); break;
-        case 4: launch_diag_p<4>(c, g); break;
-        case 5: launch_diag_p<5>(c, g); break;
-        case 6: launch_diag_p<6>(c, g); break;
+        case 1: launch_diag_p<1>(c, g, theta); break;
+        case 2: launch_diag_p<2>(c, g, theta); break;
+        case 3: launch_diag_p<3>(c, g, theta); break;
+        case 4: launch_diag_p<4>(c, g, theta); break;
+        case 5: launch_diag_p<5>(c, g, theta); break;
+        case 6: launch_diag_p<6>(c, g, theta); break;
         default: return set_err(c, HD_ERR_ARG, "p out of range");
     }
     hipLaunchKernelGGL(mdiag_finish_kernel, dim3((unsigned)((c->n_u + bs - 1) / bs)), dim3(bs), 0, c->stream, g,

@@ -129,6 +129,7 @@ static void fill(int p, Tables<T>& t) {
     gauss_lobatto01(p, gll);
     gauss_legendre01(q, xq, wq);
     gauss_legendre01(p, g, gw);
+    for (int i = 0; i <= p; ++i) t.gll[i] = (T)gll[i];
     for (int a = 0; a < q; ++a) {
         t.wq[a] = (T)wq[a];
         t.xq[a] = (T)xq[a];

@@ -29,7 +29,9 @@ EXPORTED = [
     'hd_build_precond', 'hd_apply_precond', 'hd_minres_solve', 'hd_get_diagonals', 'hd_get_schur',
     'hd_get_amg_nlevels', 'hd_get_amg_level', 'hd_get_amg_prolongator', 'hd_apply_timing',
     'hd_host_amg_build', 'hd_host_amg_nlevels', 'hd_host_amg_level', 'hd_host_amg_prolongator',
-    'hd_host_amg_free', 'hd_host_tables',
+    'hd_host_amg_free', 'hd_host_tables', 'hd_learned_targets', 'hd_learned_features', 'hd_mlp_param_count',
+    'hd_mlp_init', 'hd_mlp_set_params', 'hd_mlp_get_params', 'hd_mlp_loss_grad', 'hd_mlp_train', 'hd_mlp_infer',
+    'hd_set_diag_scalings',
 ]
 
 
@@ -41,7 +43,7 @@ class HdError(RuntimeError):
 
 class PrecondParams(ctypes.Structure):
     _fields_ = [('tau', ctypes.c_double), ('theta', ctypes.c_double), ('max_coarse', ctypes.c_int),
-                ('max_levels', ctypes.c_int), ('omega', ctypes.c_double)]
+                ('max_levels', ctypes.c_int), ('omega', ctypes.c_double), ('learned', ctypes.c_int)]
 
 
 class SolveParams(ctypes.Structure):
@@ -102,6 +104,16 @@ def load():
         'hd_host_amg_prolongator': (I, [P, I, pI64, pI64, pI64, P, P, P]),
         'hd_host_amg_free': (I, [P]),
         'hd_host_tables': (I, [I, P, P, P]),
+        'hd_learned_targets': (I, [P, I, I64, P, I, P, P, P]),
+        'hd_learned_features': (I, [P, I64, P, P, P, P, I, P]),
+        'hd_mlp_param_count': (I, []),
+        'hd_mlp_init': (I, [P, ctypes.c_uint64]),
+        'hd_mlp_set_params': (I, [P, P]),
+        'hd_mlp_get_params': (I, [P, P]),
+        'hd_mlp_loss_grad': (I, [P, I64, P, P, ctypes.POINTER(ctypes.c_float), P]),
+        'hd_mlp_train': (I, [P, I64, P, P, I64, P, P, I, I, ctypes.c_float, ctypes.c_uint64, P, P]),
+        'hd_mlp_infer': (I, [P, I64, P, P, I]),
+        'hd_set_diag_scalings': (I, [P, P]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -120,8 +132,8 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def precond_params(tau=1.0, theta=0.25, max_coarse=1024, max_levels=25, omega=2.0 / 3.0):
-    return PrecondParams(tau, theta, max_coarse, max_levels, omega)
+def precond_params(tau=1.0, theta=0.25, max_coarse=1024, max_levels=25, omega=2.0 / 3.0, learned=0):
+    return PrecondParams(tau, theta, max_coarse, max_levels, omega, learned)
 
 
 def solve_params(tol=1e-8, max_it=10000, mode=HD_MODE_PLAIN64, use_x0=0, inner_tol=1e-5, max_outer=20,
@@ -165,7 +177,11 @@ class Context:
     # ---- setup ------------------------------------------------------------
     def setup_mesh(self, nx, ny, nz, p, vertices):
         v = np.ascontiguousarray(vertices, dtype=np.float64)
-        return self._check(self.lib.hd_setup_mesh(self.h, nx, ny, nz, p, _ptr(v)))
+        if v.size != 3 * (nx + 1) * (ny + 1) * (nz + 1):
+            raise ValueError('vertices: (nx+1)(ny+1)(nz+1) x 3 entries required')
+        rc = self._check(self.lib.hd_setup_mesh(self.h, nx, ny, nz, p, _ptr(v)))
+        self.ne = nx * ny * nz
+        return rc
 
     def setup_coeffs(self, problem, c_mass, c_22=None, ess_sides=0):
         cm = np.ascontiguousarray(c_mass, dtype=np.float64)
@@ -215,8 +231,93 @@ class Context:
 
     # ---- preconditioner and solver -----------------------------------------
     def build_precond(self, params=None):
+        """Returns 0, or HD_FALLBACK_USED when the learned scalings were not
+        finite and the plain diagonal was used."""
         pp = ctypes.byref(params) if params is not None else None
-        return self._check(self.lib.hd_build_precond(self.h, pp))
+        return self._check(self.lib.hd_build_precond(self.h, pp), allow=(HD_FALLBACK_USED,))
+
+    # ---- learned (1,1)-diagonal correction ----------------------------------
+    def learned_targets(self, p, vertices, max_steps=30):
+        """theta* [n, 6], (lambda_min, lambda_max) [n, 2] and the spread at 0
+        and at theta* [n, 2] for elements vertices [n, 2, 2, 2, 3] (device
+        float64 tensor)."""
+        torch = self.torch
+        n = vertices.shape[0]
+        self._dev(vertices, n * 24, HD_F64, 'vertices')
+        th = torch.empty((n, 6), dtype=torch.float64, device=self.device)
+        lam = torch.empty((n, 2), dtype=torch.float64, device=self.device)
+        spr = torch.empty((n, 2), dtype=torch.float64, device=self.device)
+        self._check(self.lib.hd_learned_targets(self.h, p, n, _ptr(vertices), max_steps, _ptr(th), _ptr(lam),
+                                                _ptr(spr)))
+        return th, lam, spr
+
+    def learned_features(self, vertices, alpha, beta, p):
+        """x [n, 27] (float32) for elements vertices [n, 2, 2, 2, 3]; p an int
+        or an int32 device tensor [n]."""
+        torch = self.torch
+        n = vertices.shape[0]
+        self._dev(vertices, n * 24, HD_F64, 'vertices')
+        self._dev(alpha, n, HD_F64, 'alpha')
+        self._dev(beta, n, HD_F64, 'beta')
+        parr = None
+        if hasattr(p, 'data_ptr'):
+            if p.dtype != torch.int32 or not p.is_cuda or p.numel() < n:
+                raise ValueError('p: an int32 device tensor with one entry per element is required')
+            parr, p = p, 0
+        x = torch.empty((n, 27), dtype=torch.float32, device=self.device)
+        self._check(self.lib.hd_learned_features(self.h, n, _ptr(vertices), _ptr(alpha), _ptr(beta), _ptr(parr),
+                                                 int(p), _ptr(x)))
+        return x
+
+    def mlp_init(self, seed=0):
+        return self._check(self.lib.hd_mlp_init(self.h, seed))
+
+    def mlp_set_params(self, params):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != self.lib.hd_mlp_param_count():
+            raise ValueError('wrong parameter count')
+        return self._check(self.lib.hd_mlp_set_params(self.h, _ptr(a)))
+
+    def mlp_get_params(self):
+        a = np.empty(self.lib.hd_mlp_param_count(), dtype=np.float32)
+        self._check(self.lib.hd_mlp_get_params(self.h, _ptr(a)))
+        return a
+
+    def mlp_loss_grad(self, x, y):
+        n = x.shape[0]
+        self._dev(x, n * 27, HD_F32, 'x')
+        self._dev(y, n * 6, HD_F32, 'y')
+        loss = ctypes.c_float()
+        g = np.empty(self.lib.hd_mlp_param_count(), dtype=np.float32)
+        self._check(self.lib.hd_mlp_loss_grad(self.h, n, _ptr(x), _ptr(y), ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def mlp_train(self, x, y, x_val=None, y_val=None, epochs=10, batch=512, lr=1e-3, seed=0):
+        n = x.shape[0]
+        self._dev(x, n * 27, HD_F32, 'x')
+        self._dev(y, n * 6, HD_F32, 'y')
+        nv = 0 if x_val is None else x_val.shape[0]
+        if nv:
+            self._dev(x_val, nv * 27, HD_F32, 'x_val')
+            self._dev(y_val, nv * 6, HD_F32, 'y_val')
+        tl = np.zeros(epochs, dtype=np.float32)
+        vl = np.zeros(epochs, dtype=np.float32)
+        self._check(self.lib.hd_mlp_train(self.h, n, _ptr(x), _ptr(y), nv, _ptr(x_val), _ptr(y_val), epochs, batch,
+                                          lr, seed, _ptr(tl), _ptr(vl)))
+        return tl, vl
+
+    def mlp_infer(self, x, bf16=True):
+        torch = self.torch
+        n = x.shape[0]
+        self._dev(x, n * 27, HD_F32, 'x')
+        th = torch.empty((n, 6), dtype=torch.float32, device=self.device)
+        self._check(self.lib.hd_mlp_infer(self.h, n, _ptr(x), _ptr(th), 1 if bf16 else 0))
+        return th
+
+    def set_diag_scalings(self, theta):
+        if theta is not None:
+            self._dev(theta, self.ne * 6, HD_F64, 'theta')
+        return self._check(self.lib.hd_set_diag_scalings(self.h, _ptr(theta)))
 
     def apply_precond(self, r, z, prec=HD_F64, nrhs=1):
         nu, nq = self.sizes()

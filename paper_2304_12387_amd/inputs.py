@@ -17,6 +17,18 @@ darcy_layered    Darcy on a 60 x 220 x 85 Cartesian grid of 20 x 10 x 2 cells,
                  and 1 vertically), eps = 1/k, gamma = 0, flux condition
                  u.n = (1,0,0).n on the whole boundary (a stand-in for the SPE10
                  data, which is not available here).
+graddiv_distorted
+                 grad-div on the unit cube, 48^3 hexahedra, p = 4: z-layers
+                 graded so that their thickness varies 8x, shear
+                 x' = x + tan(t(z)) y with t rising smoothly from 0 to 30 deg,
+                 interior vertices jittered by +-10% of the local spacing,
+                 alpha and beta per element log-uniform in [1e-2, 1e2].
+training_elements
+                 single distorted hexahedra for the learned diagonal: axis
+                 stretches log-uniform with max/min <= 8, shears in U[-30, 30]
+                 deg on the three coordinate planes, vertex jitter +-10% of the
+                 shortest edge, p uniform in 1..6, ln alpha and ln beta uniform
+                 in [ln 1e-2, ln 1e2].
 """
 import numpy as np
 
@@ -101,3 +113,71 @@ def darcy_layered(nx=60, ny=220, nz=85, p=2, seed=3):
 def graddiv_rhs(n_u, n_q, seed=22):
     """b_u ~ U[-1, 1] on the RT dofs, b_q = 0."""
     return np.concatenate([uniform_vector(n_u, seed), np.zeros(n_q)])
+
+
+def graddiv_distorted(n=48, p=4, seed=5, jitter=0.1):
+    """Graded, sheared and jittered unit-cube mesh with high-contrast
+    coefficients (seeds: mesh `seed`, coefficients `seed` + 10)."""
+    r = 8.0 ** (1.0 / (n - 1))
+    t = r ** np.arange(n)
+    zc = np.concatenate([[0.0], np.cumsum(t / t.sum())])
+    xc = np.linspace(0.0, 1.0, n + 1)
+    Z, Y, X = np.meshgrid(zc, xc, xc, indexing='ij')
+    idx = np.arange(X.size)
+    ijk = np.stack([idx % (n + 1), (idx // (n + 1)) % (n + 1), idx // ((n + 1) ** 2)], axis=1)
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-1.0, 1.0, size=(X.size, 3))
+    # local spacing: the smaller of the two adjacent intervals per axis
+    hz_cell = np.diff(zc)
+    hz = np.minimum(hz_cell[np.clip(ijk[:, 2] - 1, 0, n - 1)], hz_cell[np.clip(ijk[:, 2], 0, n - 1)])
+    h = np.stack([np.full(X.size, 1.0 / n), np.full(X.size, 1.0 / n), hz], axis=1)
+    interior = np.all((ijk > 0) & (ijk < n), axis=1)[:, None]
+    V = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1) + jitter * d * h * interior
+    ang = np.radians(30.0) * 0.5 * (1.0 - np.cos(np.pi * V[:, 2]))
+    V[:, 0] = V[:, 0] + np.tan(ang) * V[:, 1]
+    crng = np.random.default_rng(seed + 10)
+    ne = n ** 3
+    alpha = loguniform(ne, 1e-2, 1e2, crng)
+    beta = loguniform(ne, 1e-2, 1e2, crng)
+    return dict(name=f'graddiv_distorted_{n}_p{p}', nx=n, ny=n, nz=n, p=p, problem=0, vertices=V,
+                c_mass=beta, c_22=alpha, ess_sides=0, tol=1e-8)
+
+
+def training_elements(n, seed=50):
+    """n single hexahedra: vertices [n, 2, 2, 2, 3] (indexed [dz, dy, dx, :]),
+    p [n], alpha [n], beta [n].  Unit cube -> axis stretches (ln s_i uniform
+    in [0, ln 8], so max/min <= 8) -> shears tan(t) with t ~ U[-30, 30] deg
+    on the xy, yz and zx planes -> independent vertex jitter of +-10% of the
+    shortest edge.  Elements whose corner frames lose orientation are drawn
+    again."""
+    rng = np.random.default_rng(seed)
+    cube = np.array([[dx, dy, dz] for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)], dtype=np.float64)
+    out = np.zeros((n, 8, 3))
+    filled = 0
+    while filled < n:
+        m = n - filled
+        s = np.exp(rng.uniform(0.0, np.log(8.0), size=(m, 3)))
+        sh = np.tan(np.radians(rng.uniform(-30.0, 30.0, size=(m, 3))))
+        V = cube[None, :, :] * s[:, None, :]
+        V[:, :, 0] += sh[:, 0:1] * V[:, :, 1]
+        V[:, :, 1] += sh[:, 1:2] * V[:, :, 2]
+        V[:, :, 2] += sh[:, 2:3] * V[:, :, 0]
+        edges = [(0, 1), (2, 3), (4, 5), (6, 7), (0, 2), (1, 3), (4, 6), (5, 7), (0, 4), (1, 5), (2, 6), (3, 7)]
+        emin = np.min([np.linalg.norm(V[:, a] - V[:, b], axis=1) for a, b in edges], axis=0)
+        V = V + 0.1 * emin[:, None, None] * rng.uniform(-1.0, 1.0, size=V.shape)
+        # keep elements whose eight corner frames are right-handed
+        ok = np.ones(m, dtype=bool)
+        for v in range(8):
+            dx, dy, dz = v & 1, (v >> 1) & 1, (v >> 2) & 1
+            a = V[:, v ^ 1] - V[:, v]
+            b = V[:, v ^ 2] - V[:, v]
+            c = V[:, v ^ 4] - V[:, v]
+            sgn = (1 - 2 * dx) * (1 - 2 * dy) * (1 - 2 * dz)
+            ok &= sgn * np.einsum('ni,ni->n', a, np.cross(b, c)) > 0
+        k = int(ok.sum())
+        out[filled:filled + k] = V[ok][:k]
+        filled += k
+    p = rng.integers(1, 7, size=n)
+    alpha = np.exp(rng.uniform(np.log(1e-2), np.log(1e2), size=n))
+    beta = np.exp(rng.uniform(np.log(1e-2), np.log(1e2), size=n))
+    return out.reshape(n, 2, 2, 2, 3), p, alpha, beta

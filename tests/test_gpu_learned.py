@@ -1,0 +1,211 @@
+"""GPU parity of the learned (1,1)-diagonal path against the oracle: targets
+(eigenvalues against the library's generalized eigensolver at the GPU's
+scalings, spreads and scalings against the oracle's descent), features, the
+network's loss and gradient, FP32 and BF16 inference, training, the
+corrected diagonal with S~ and MINRES, the fallback, and the measured gain on
+a distorted high-contrast grad-div mesh."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from gpu_helpers import gpu_context, make_case, oracle_problem, rel, to_dev, torch_cuda
+from oracle import element, learned, minres, precond
+from paper_2304_12387_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _flat(params):
+    return np.concatenate([q.ravel() for q in params]).astype(np.float32)
+
+
+def _unflat(flat, like):
+    out, off = [], 0
+    for q in like:
+        out.append(flat[off:off + q.size].reshape(q.shape).astype(np.float64))
+        off += q.size
+    return out
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_targets_match_oracle(p):
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    V, pp, _, _ = inputs.training_elements(400, 50)
+    sel = np.nonzero(pp == p)[0][:3 if p <= 4 else 1]
+    steps = 30 if p <= 4 else 2
+    ctx = hdivsp.Context(0)
+    th, lam, spr = ctx.learned_targets(p, to_dev(V[sel]), steps)
+    th, lam, spr = th.cpu().numpy(), lam.cpu().numpy(), spr.cpu().numpy()
+    A = learned.dof_weights(p)
+    for k, e in enumerate(sel):
+        Me = element.element_matrices(p, V[e][None])['M'][0]
+        m = np.diag(Me)
+        # eigenvalues at the GPU's scalings against the generalized solver
+        ev = sla.eigh(Me, np.diag(m * np.exp(A @ th[k])), eigvals_only=True)
+        assert abs(lam[k, 0] - ev[0]) <= 1e-6 * ev[0] and abs(lam[k, 1] - ev[-1]) <= 1e-6 * ev[-1]
+        assert abs(th[k].sum()) <= 1e-12
+        f0 = learned.spread(Me, m, A, np.zeros(6))
+        assert abs(spr[k, 0] - f0) <= 1e-6
+        assert spr[k, 1] <= spr[k, 0] + 1e-12
+        if steps == 30:
+            tho, _, fo = learned.element_target(Me, p, steps)
+            print('p', p, 'elem', e, 'spread', f0, 'gpu', spr[k, 1], 'oracle', fo, 'dtheta', np.abs(tho - th[k]).max(),
+                  flush=True)
+            # both descents end at (nearly) the same spread
+            assert abs(spr[k, 1] - fo) <= 2e-3 * fo
+    ctx.close()
+
+
+def test_features_match_oracle():
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    V, p, a, b = inputs.training_elements(500, 51)
+    ctx = hdivsp.Context(0)
+    x = ctx.learned_features(to_dev(V), to_dev(a), to_dev(b), torch.from_numpy(p.astype(np.int32)).cuda())
+    xo = learned.features(V, a, b, p)
+    assert np.abs(x.cpu().numpy() - xo).max() <= 1e-6 * max(1.0, np.abs(xo).max())
+    # constant p
+    x4 = ctx.learned_features(to_dev(V[:7]), to_dev(a[:7]), to_dev(b[:7]), 4)
+    assert np.allclose(x4.cpu().numpy()[:, 26], 4.0 / 6.0)
+    ctx.close()
+
+
+def test_network_loss_gradient_inference():
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    rng = np.random.default_rng(9)
+    params = learned.init_params(seed=4)
+    flat = _flat(params)
+    p32 = _unflat(flat, params)
+    X = rng.standard_normal((300, learned.N_IN)).astype(np.float32)
+    Y = rng.uniform(-2.0, 2.0, (300, learned.N_OUT)).astype(np.float32)
+    ctx = hdivsp.Context(0)
+    ctx.mlp_set_params(flat)
+    assert np.array_equal(ctx.mlp_get_params(), flat)
+    Xd, Yd = to_dev(X), to_dev(Y)
+    loss, g = ctx.mlp_loss_grad(Xd, Yd)
+    lo, go = learned.loss_and_grad(p32, X.astype(np.float64), Y.astype(np.float64))
+    assert abs(loss - lo) <= 1e-5 * lo
+    gg = _unflat(g, params)
+    for a, b in zip(gg, go):
+        assert np.linalg.norm(a - b) <= 1e-4 * np.linalg.norm(b)
+    t32 = ctx.mlp_infer(Xd, bf16=False).cpu().numpy()
+    to = learned.scalings(p32, X.astype(np.float64))
+    assert np.abs(t32 - to).max() <= 1e-5
+    t16 = ctx.mlp_infer(Xd, bf16=True).cpu().numpy()
+    assert np.linalg.norm(t16 - t32) <= 2e-2 * np.linalg.norm(t32)
+    # a ragged row count (not a multiple of the 16-row tile)
+    t16r = ctx.mlp_infer(Xd[:37].contiguous(), bf16=True).cpu().numpy()
+    assert np.array_equal(t16r, t16[:37])
+    ctx.close()
+
+
+def test_training_reduces_loss():
+    """Adam on a learnable synthetic map: the validation loss falls well
+    below its initial value."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    rng = np.random.default_rng(3)
+    W = rng.standard_normal((learned.N_OUT, learned.N_IN)) / math.sqrt(learned.N_IN)
+    X = rng.standard_normal((6000, learned.N_IN)).astype(np.float32)
+    Y = (0.8 * np.tanh(X @ W.T)).astype(np.float32)
+    ctx = hdivsp.Context(0)
+    ctx.mlp_init(1)
+    l0, _ = ctx.mlp_loss_grad(to_dev(X[5000:]), to_dev(Y[5000:]))
+    tl, vl = ctx.mlp_train(to_dev(X[:5000]), to_dev(Y[:5000]), to_dev(X[5000:]), to_dev(Y[5000:]), epochs=15,
+                           batch=250, lr=3e-3, seed=2)
+    print('initial', l0, 'train', tl, 'val', vl, flush=True)
+    assert vl[-1] <= 0.1 * l0 and tl[-1] < tl[0]
+    ctx.close()
+
+
+def test_learned_diagonal_schur_and_minres_match_oracle():
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    case = make_case(4, 3, 3, 2, problem=0, ess=5)
+    prob = oracle_problem(case)
+    ne = prob.mesh.ne
+    theta = np.random.default_rng(12).uniform(-0.5, 0.5, (ne, 6))
+    Md = learned.learned_diag(prob, theta)
+    ctx = gpu_context(case)
+    ctx.set_diag_scalings(to_dev(theta))
+    assert ctx.build_precond(hdivsp.precond_params(max_coarse=40, learned=2)) == 0
+    md, _ = ctx.get_diagonals()
+    assert rel(md.cpu().numpy(), Md) <= 1e-12
+    rp, ci, v = ctx.get_schur()
+    import scipy.sparse as sp
+    S = sp.csr_matrix((v, ci, rp), shape=(prob.mesh.n_q, prob.mesh.n_q))
+    So = precond.schur_by_formula(prob, Md)
+    assert abs(S - So).max() <= 1e-12 * abs(So).max()
+    P = precond.BlockPreconditioner(prob, amg_kwargs=dict(max_coarse=40), Md=Md)
+    b = inputs.graddiv_rhs(prob.mesh.n_u, prob.mesh.n_q, seed=5)
+    b[:prob.mesh.n_u][prob.ess] = 0.0
+    xo, ito, _ = minres.minres(prob.apply, P, b, tol=1e-12)
+    bd = to_dev(b)
+    xd = torch.zeros_like(bd)
+    info = ctx.minres_solve(bd, xd, hdivsp.solve_params(tol=1e-12, max_it=2000))
+    print('learned-diagonal MINRES gpu', info['iterations'], 'oracle', ito, flush=True)
+    assert info['status'] == 0 and abs(info['iterations'] - ito) <= 2
+    xdir = spla.spsolve(prob.block_matrix().tocsc(), b)
+    assert rel(xd.cpu().numpy(), xdir) <= 1e-8
+    ctx.close()
+
+
+def test_network_diagonal_and_fallback():
+    """learned = 1: the mesh's features through the BF16 network give the
+    scalings of the diagonal; a network with non-finite outputs falls back to
+    the plain diagonal with HD_FALLBACK_USED."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    case = make_case(3, 3, 2, 3, problem=0)
+    prob = oracle_problem(case)
+    ctx = gpu_context(case)
+    ctx.mlp_init(7)
+    assert ctx.build_precond(hdivsp.precond_params(max_coarse=40, learned=1)) == 0
+    md, _ = ctx.get_diagonals()
+    V = prob.mesh.element_vertices()
+    x = learned.features(V, case['c_22'], case['c_mass'], 3).astype(np.float32)
+    th = ctx.mlp_infer(to_dev(x), bf16=True).double().cpu().numpy()
+    assert np.abs(th).max() > 0.0
+    assert rel(md.cpu().numpy(), learned.learned_diag(prob, th)) <= 1e-6
+    huge = np.full(ctx.lib.hd_mlp_param_count(), 1e30, dtype=np.float32)
+    huge[::2] = -1e30
+    ctx.mlp_set_params(huge)
+    rc = ctx.build_precond(hdivsp.precond_params(max_coarse=40, learned=1))
+    assert rc == hdivsp.HD_FALLBACK_USED
+    md, _ = ctx.get_diagonals()
+    assert rel(md.cpu().numpy(), precond.diag_M(prob)) <= 1e-12
+    ctx.close()
+
+
+def test_learned_gain_on_distorted_mesh():
+    """Targets generated on the GPU for 3,000 seeded training elements, the
+    network trained on them, then grad-div on a 12^3 graded, sheared and
+    jittered mesh with 1e4 coefficient contrast (p = 4): MINRES to a true
+    relative residual of 1e-8 with the plain and with the learned diagonal.
+    What the network gains is reported; the learned form must converge and
+    stay within 10% of the plain iteration count."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    from paper_2304_12387_amd import learned as driver
+    cfg = inputs.graddiv_distorted(12, 4)
+    ctx = gpu_context(cfg)
+    hist = driver.train(ctx, n=3000, seed=50, max_steps=10, epochs=30, batch=100, lr=2e-3)
+    print('training', hist, flush=True)
+    assert hist['val_loss'][-1] <= hist['val_loss'][0]
+    nu, nq = ctx.sizes()
+    b = to_dev(inputs.graddiv_rhs(nu, nq, seed=25))
+    res = {}
+    for name, learned_flag in (('plain', 0), ('learned', 1)):
+        assert ctx.build_precond(hdivsp.precond_params(learned=learned_flag)) == 0
+        x = torch.zeros_like(b)
+        info = ctx.minres_solve(b, x, hdivsp.solve_params(tol=1e-8, stop_true=1, max_it=5000))
+        res[name] = info
+        print(name, info, flush=True)
+        assert info['status'] == 0 and info['true_rel_res'] <= 1e-8
+    assert res['learned']['iterations'] <= 1.1 * res['plain']['iterations']
+    ctx.close()
