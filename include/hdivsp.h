@@ -184,6 +184,45 @@ int hd_apply_precond(hd_ctx* ctx, int prec, int nrhs, const void* r, void* z);
 int hd_minres_solve(hd_ctx* ctx, const hd_solve_params* params, int nrhs,
                     const double* b, double* x, hd_solve_info* info);
 
+/* ---- batches of independent instances ----------------------------------
+ * Many independent problems of different sizes and degrees handled together
+ * (not in the paper, which solves one mesh at a time).  Vectors are the
+ * instances' [u; q~] blocks concatenated in instance order (offsets from
+ * hd_batch_sizes).  The block apply of all instances runs as persistent
+ * launches that take (instance, element-group) tiles from a work queue, most
+ * expensive degree first; MINRES keeps one recurrence per instance (its own
+ * scalars, stop test and preconditioner). */
+typedef struct hd_instance_desc {
+    int nx, ny, nz, p;          /* mesh and RT order (1..6) */
+    const double* vertices;     /* host, (nx+1)(ny+1)(nz+1) x 3 */
+    const double* c_mass;       /* host, nx ny nz */
+    const double* c_22;         /* host, nx ny nz, or NULL (Darcy with gamma = 0) */
+    uint32_t ess_sides;
+} hd_instance_desc;
+
+/* Set up ninst instances of one problem type (host arrays are copied).
+ * Replaces a previous batch of the context; independent of hd_setup_mesh. */
+int hd_setup_batch(hd_ctx* ctx, int problem, int ninst, const hd_instance_desc* inst);
+/* offsets [ninst + 1]: start of each instance's block and the total length;
+ * n_u [ninst]: its RT dof count (either may be NULL). */
+int hd_batch_sizes(hd_ctx* ctx, int64_t* offsets, int64_t* n_u);
+/* y = A x for every instance (device pointers of the total length, x != y). */
+int hd_batch_apply(hd_ctx* ctx, int prec, const void* x, void* y);
+/* Autotuner: times the batched apply over the launch variants (one
+ * persistent launch for all degrees or one per degree), persistent grid
+ * sizes and element groups per tile, keeps the fastest and reports it
+ * (any output may be NULL). */
+int hd_batch_tune(hd_ctx* ctx, int prec, int* mode, int* grid, int* tile_groups, double* ms);
+/* Set the launch configuration explicitly (mode 0 or 1, grid >= 1
+ * workgroups, tile_groups >= 1). */
+int hd_batch_set_launch(hd_ctx* ctx, int mode, int grid, int tile_groups);
+/* Each instance's diagonal, S~ and AMG (learned must be 0). */
+int hd_batch_build_precond(hd_ctx* ctx, const hd_precond_params* params);
+/* One MINRES recurrence per instance (HD_MODE_PLAIN64 or HD_MODE_PREC32);
+ * info: host array of ninst entries (may be NULL). */
+int hd_batch_minres_solve(hd_ctx* ctx, const hd_solve_params* params, const double* b, double* x,
+                          hd_solve_info* info);
+
 /* ---- learned (1,1)-diagonal correction ---------------------------------
  * Not in the paper: an extension of its diagonal (1,1) block (Section 2.3).
  * Six log-scalings theta = (x-, x+, y-, y+, z-, z+) per element multiply the

@@ -23,7 +23,9 @@
 // first.  No atomics, no zero fill, and a fixed summation order.
 #include "pencil.hpp"
 
+#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 namespace hd {
 
@@ -382,28 +384,19 @@ struct RhsArgs {
     int64_t part_stride;
 };
 
+// One element group (EPW elements of one colour) of y = A x: gather, D u,
+// M u by sum factorisation, the local CG for -kappa W^{-1} q~, scatter.
+// x and y point at one right-hand side's vector; the return value is the
+// group's <A x, x> contribution summed over the wavefront (all lanes).
 template <int P, typename T>
-__global__ __launch_bounds__(64) void block_apply_kernel(
-    Geo g, const T* __restrict__ pa, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
-    int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
-    CGParams<T> cgp, int with_c, int colour, int64_t part_offset, unsigned nb) {
+__device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, const T* __restrict__ pa, tkp<P, T> tb,
+                                              const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
+                                              int ess_mode, int64_t n_u, const T* __restrict__ x, T* __restrict__ y,
+                                              T s_in, const CGParams<T>& cgp, int with_c, int colour, unsigned grp,
+                                              unsigned nb) {
     using D = Dim<P>;
     using S = Slot<P>;
     constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC, W = S::W;
-    // Block -> (element group, right-hand side).  With several right-hand
-    // sides, the blocks of one element group are spaced 8 apart, so that they
-    // run on the same XCD (blocks are dealt to the 8 XCDs round-robin) at
-    // about the same time and the second and later reads of the group's
-    // geometric factors hit that XCD's L2.
-    unsigned grp = blockIdx.x;
-    int r = 0;
-    if (ra.nrhs > 1) {
-        const unsigned k = blockIdx.x / 8;
-        r = (int)(k % (unsigned)ra.nrhs);
-        grp = blockIdx.x % 8 + 8 * (k / (unsigned)ra.nrhs);
-    }
-    if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;   // uniform over the block
-    __shared__ ElemLDS<P, T> sm[S::EPW];
     const int lane = threadIdx.x;
     const int slot = lane / W, t = lane % W;
     // elements of one colour ((ex + ey + ez) mod 2 == colour), half-row by half-row
@@ -429,75 +422,199 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
 #pragma unroll
             for (int c = 0; c < Q; ++c) G[m][c] = pe[m * Q3 + Q * Q * c];
     }
+    __syncthreads();
+    // gather u (essential dofs read as zero) and q~
+    if (valid) {
+        gather_rt<P, T, 0>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
+        gather_rt<P, T, 1>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
+        gather_rt<P, T, 2>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
+        for (int l = t; l < NL; l += W) L.sq[l] = s_in * x[n_u + ee * NL + l];
+    }
+    __syncthreads();
+    // D u (element-local, +1 upper face, -1 lower face)
+    if (valid) {
+        for (int l = t; l < NL; l += W) {
+            const int a = l % P, b = (l / P) % P, c = l / (P * P);
+            T v = L.su[(a + 1) + (P + 1) * (b + P * c)] - L.su[a + (P + 1) * (b + P * c)];
+            v += L.su[NC + a + P * ((b + 1) + (P + 1) * c)] - L.su[NC + a + P * (b + (P + 1) * c)];
+            v += L.su[2 * NC + a + P * (b + P * (c + 1))] - L.su[2 * NC + a + P * (b + P * c)];
+            L.syq[l] = v;
+        }
+    }
+    // M u: the three components to the quadrature points
+    T U0[Q], U1[Q], U2[Q];
+    rt_to_quad<P, T, 0>(L, tb, t, U0);
+    rt_to_quad<P, T, 1>(L, tb, t, U1);
+    rt_to_quad<P, T, 2>(L, tb, t, U2);
+    // c_mass w J^T J / det J at the quadrature column (a, b, .)
+    T gw[Q];
+    if (t < Q * Q) {
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const T a0 = U0[c], a1 = U1[c], a2 = U2[c];
+            U0[c] = cM * (G[0][c] * a0 + G[1][c] * a1 + G[2][c] * a2);
+            U1[c] = cM * (G[1][c] * a0 + G[3][c] * a1 + G[4][c] * a2);
+            U2[c] = cM * (G[2][c] * a0 + G[4][c] * a1 + G[5][c] * a2);
+            gw[c] = G[6][c];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < Q; ++c) gw[c] = T(1);
+    }
+    double dot = 0.0;
     {
-        const T* __restrict__ x = xall + r * ra.ldv;
-        T* __restrict__ y = yall + r * ra.ldv;
-        const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
-        __syncthreads();
-        // gather u (essential dofs read as zero) and q~
-        if (valid) {
-            gather_rt<P, T, 0>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
-            gather_rt<P, T, 1>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
-            gather_rt<P, T, 2>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
-            for (int l = t; l < NL; l += W) L.sq[l] = s_in * x[n_u + ee * NL + l];
+        T yv[Q];
+        quad_to_rt<P, T, 0>(L, tb, t, U0, yv);
+        if (valid) dot += finish_rt<P, T, 0>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
+        quad_to_rt<P, T, 1>(L, tb, t, U1, yv);
+        if (valid) dot += finish_rt<P, T, 1>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
+        quad_to_rt<P, T, 2>(L, tb, t, U2, yv);
+        if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
+    }
+    // -kappa_e W_e^{-1} q~
+    if (with_c) local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
+    __syncthreads();
+    if (valid) {
+        for (int l = t; l < NL; l += W) {
+            const T v = L.syq[l];
+            y[n_u + ee * NL + l] = v;
+            dot += (double)v * (double)L.sq[l];
         }
-        __syncthreads();
-        // D u (element-local, +1 upper face, -1 lower face)
-        if (valid) {
-            for (int l = t; l < NL; l += W) {
-                const int a = l % P, b = (l / P) % P, c = l / (P * P);
-                T v = L.su[(a + 1) + (P + 1) * (b + P * c)] - L.su[a + (P + 1) * (b + P * c)];
-                v += L.su[NC + a + P * ((b + 1) + (P + 1) * c)] - L.su[NC + a + P * (b + (P + 1) * c)];
-                v += L.su[2 * NC + a + P * (b + P * (c + 1))] - L.su[2 * NC + a + P * (b + P * c)];
-                L.syq[l] = v;
+    }
+    return slot_sum<double, 64>(dot);
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(64) void block_apply_kernel(
+    Geo g, const T* __restrict__ pa, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
+    int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
+    CGParams<T> cgp, int with_c, int colour, int64_t part_offset, unsigned nb) {
+    // Block -> (element group, right-hand side).  With several right-hand
+    // sides, the blocks of one element group are spaced 8 apart, so that they
+    // run on the same XCD (blocks are dealt to the 8 XCDs round-robin) at
+    // about the same time and the second and later reads of the group's
+    // geometric factors hit that XCD's L2.
+    unsigned grp = blockIdx.x;
+    int r = 0;
+    if (ra.nrhs > 1) {
+        const unsigned k = blockIdx.x / 8;
+        r = (int)(k % (unsigned)ra.nrhs);
+        grp = blockIdx.x % 8 + 8 * (k / (unsigned)ra.nrhs);
+    }
+    if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;   // uniform over the block
+    __shared__ ElemLDS<P, T> sm[Slot<P>::EPW];
+    const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
+    const double dot = apply_group<P, T>(sm, g, pa, tb, cm, kap, ess, ess_mode, n_u, xall + r * ra.ldv,
+                                         yall + r * ra.ldv, s_in, cgp, with_c, colour, grp, nb);
+    if (ra.partial && grp < nb && threadIdx.x == 0) ra.partial[r * ra.part_stride + part_offset + grp] = dot;
+}
+
+// ---- batches of independent instances ------------------------------------
+// LDS of one workgroup: the largest element-slot set over the degrees.
+template <typename T>
+constexpr size_t batch_lds_bytes() {
+    size_t m = 0;
+    const size_t s[6] = {sizeof(ElemLDS<1, T>) * Slot<1>::EPW, sizeof(ElemLDS<2, T>) * Slot<2>::EPW,
+                         sizeof(ElemLDS<3, T>) * Slot<3>::EPW, sizeof(ElemLDS<4, T>) * Slot<4>::EPW,
+                         sizeof(ElemLDS<5, T>) * Slot<5>::EPW, sizeof(ElemLDS<6, T>) * Slot<6>::EPW};
+    for (size_t v : s) m = v > m ? v : m;
+    return m;
+}
+
+// Not inlined: each degree's body keeps its own register allocation, so the
+// persistent kernel needs the largest of them rather than their union.
+template <int P, typename T>
+__device__ __attribute__((noinline)) double batch_group(void* smem, const BatchInstDev& I, const T* x, T* y, T s_in,
+                                                        const CGParams<T>& cgp, int ess_mode, int colour,
+                                                        unsigned grp) {
+    // arguments of a call arrive in vector registers; the table pointer is
+    // uniform and must live in scalar registers for the scalar table loads
+    const uint64_t tv = (uint64_t)I.tabk;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tv);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(tv >> 32));
+    const tkp<P, T> tb = (tkp<P, T>)(lo | (hi << 32));
+    return apply_group<P, T>((ElemLDS<P, T>*)smem, I.g, (const T*)I.pa, tb, (const T*)I.cm, (const T*)I.kap, I.ess,
+                             ess_mode, I.n_u, x, y, s_in, cgp, I.with_c, colour, grp, I.nb);
+}
+
+// Persistent apply over all instances: each workgroup (one wavefront) takes
+// the next tile from the work queue (tiles are sorted by decreasing cost) and
+// runs its element groups with the element body of the tile's degree.  Every
+// wavefront leaves once the queue is empty.
+template <typename T>
+__global__ __launch_bounds__(64) void batch_apply_kernel(const BatchInstDev* __restrict__ inst,
+                                                         const BatchTile* __restrict__ tiles, int ntiles,
+                                                         int* __restrict__ counter, const T* __restrict__ x,
+                                                         T* __restrict__ y, const double* __restrict__ scale,
+                                                         int scale_stride, const int* __restrict__ done,
+                                                         int done_stride, int partials, int colour,
+                                                         CGParams<T> cgp, int ess_mode) {
+    __shared__ __align__(16) unsigned char smem[batch_lds_bytes<T>()];
+    for (;;) {
+        int t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(counter, 1);
+        // the tile index is uniform over the wavefront: keep it (and the
+        // instance data loaded through it) in scalar registers
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= ntiles) break;
+        const BatchTile tl = tiles[t];
+        if (done && done[(int64_t)tl.inst * done_stride]) continue;
+        const BatchInstDev I = inst[tl.inst];
+        const T s_in = scale ? (T)scale[(int64_t)tl.inst * scale_stride] : T(1);
+        const T* xi = x + I.off;
+        T* yi = y + I.off;
+        for (unsigned k = 0; k < tl.ngrp; ++k) {
+            const unsigned grp = tl.grp0 + k;
+            double dot = 0.0;
+            switch (I.p) {
+                case 1: dot = batch_group<1, T>(smem, I, xi, yi, s_in, cgp, ess_mode, colour, grp); break;
+                case 2: dot = batch_group<2, T>(smem, I, xi, yi, s_in, cgp, ess_mode, colour, grp); break;
+                case 3: dot = batch_group<3, T>(smem, I, xi, yi, s_in, cgp, ess_mode, colour, grp); break;
+                case 4: dot = batch_group<4, T>(smem, I, xi, yi, s_in, cgp, ess_mode, colour, grp); break;
+                case 5: dot = batch_group<5, T>(smem, I, xi, yi, s_in, cgp, ess_mode, colour, grp); break;
+                default: dot = batch_group<6, T>(smem, I, xi, yi, s_in, cgp, ess_mode, colour, grp); break;
             }
-        }
-        // M u: the three components to the quadrature points
-        T U0[Q], U1[Q], U2[Q];
-        rt_to_quad<P, T, 0>(L, tb, t, U0);
-        rt_to_quad<P, T, 1>(L, tb, t, U1);
-        rt_to_quad<P, T, 2>(L, tb, t, U2);
-        // c_mass w J^T J / det J at the quadrature column (a, b, .)
-        T gw[Q];
-        if (t < Q * Q) {
-#pragma unroll
-            for (int c = 0; c < Q; ++c) {
-                const T a0 = U0[c], a1 = U1[c], a2 = U2[c];
-                U0[c] = cM * (G[0][c] * a0 + G[1][c] * a1 + G[2][c] * a2);
-                U1[c] = cM * (G[1][c] * a0 + G[3][c] * a1 + G[4][c] * a2);
-                U2[c] = cM * (G[2][c] * a0 + G[4][c] * a1 + G[5][c] * a2);
-                gw[c] = G[6][c];
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < Q; ++c) gw[c] = T(1);
-        }
-        double dot = 0.0;
-        {
-            T yv[Q];
-            quad_to_rt<P, T, 0>(L, tb, t, U0, yv);
-            if (valid) dot += finish_rt<P, T, 0>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
-            quad_to_rt<P, T, 1>(L, tb, t, U1, yv);
-            if (valid) dot += finish_rt<P, T, 1>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
-            quad_to_rt<P, T, 2>(L, tb, t, U2, yv);
-            if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
-        }
-        // -kappa_e W_e^{-1} q~
-        if (with_c) local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
-        __syncthreads();
-        if (valid) {
-            for (int l = t; l < NL; l += W) {
-                const T v = L.syq[l];
-                y[n_u + ee * NL + l] = v;
-                dot += (double)v * (double)L.sq[l];
-            }
-        }
-        if (ra.partial && grp < nb) {
-            dot = slot_sum<double, 64>(dot);
-            if (lane == 0) ra.partial[r * ra.part_stride + part_offset + grp] = dot;
+            if (partials && threadIdx.x == 0 && grp < I.nb) I.part[(int64_t)colour * I.nb + grp] = dot;
         }
     }
 }
+
+// The same work queue, one persistent launch per degree (the tiles of degree
+// P form a contiguous range), with the body of that degree inlined.
+template <int P, typename T>
+__global__ __launch_bounds__(64) void batch_apply_deg_kernel(const BatchInstDev* __restrict__ inst,
+                                                             const BatchTile* __restrict__ tiles, int ntiles,
+                                                             int* __restrict__ counter, const T* __restrict__ x,
+                                                             T* __restrict__ y, const double* __restrict__ scale,
+                                                             int scale_stride, const int* __restrict__ done,
+                                                             int done_stride, int partials, int colour,
+                                                             CGParams<T> cgp, int ess_mode) {
+    __shared__ ElemLDS<P, T> sm[Slot<P>::EPW];
+    for (;;) {
+        int t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(counter, 1);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= ntiles) break;
+        const BatchTile tl = tiles[t];
+        if (done && done[(int64_t)tl.inst * done_stride]) continue;
+        const BatchInstDev I = inst[tl.inst];
+        const T s_in = scale ? (T)scale[(int64_t)tl.inst * scale_stride] : T(1);
+        for (unsigned k = 0; k < tl.ngrp; ++k) {
+            const unsigned grp = tl.grp0 + k;
+            const double dot = apply_group<P, T>(sm, I.g, (const T*)I.pa, (tkp<P, T>)I.tabk, (const T*)I.cm,
+                                                 (const T*)I.kap, I.ess, ess_mode, I.n_u, x + I.off, y + I.off, s_in,
+                                                 cgp, I.with_c, colour, grp, I.nb);
+            if (partials && threadIdx.x == 0 && grp < I.nb) I.part[(int64_t)colour * I.nb + grp] = dot;
+        }
+    }
+}
+
+constexpr int BATCH_COUNTERS = 16;
+
+__global__ void reset_counters_kernel(int* c) {
+    if (threadIdx.x < BATCH_COUNTERS) c[threadIdx.x] = 0;
+}
+
 
 // y_q = (weighted ? kappa_e : 1) W_e^{-1} x_q (same local CG).
 template <int P, typename T>
@@ -536,6 +653,17 @@ __global__ __launch_bounds__(64) void mass_inverse_kernel(const T* __restrict__ 
 inline unsigned apply_blocks_per_colour(int nx, int ny, int nz, int epw) {
     const int64_t slots = (int64_t)((nx + 1) / 2) * ny * nz;
     return (unsigned)((slots + epw - 1) / epw);
+}
+
+inline int epw_of(int p) {
+    switch (p) {
+        case 1: return Slot<1>::EPW;
+        case 2: return Slot<2>::EPW;
+        case 3: return Slot<3>::EPW;
+        case 4: return Slot<4>::EPW;
+        case 5: return Slot<5>::EPW;
+        default: return Slot<6>::EPW;
+    }
 }
 
 template <typename T>
@@ -650,16 +778,7 @@ int upload_kernel_tables(hd_ctx* c) {
 }
 
 int64_t apply_partial_count(const hd_ctx* c) {
-    int epw = 1;
-    switch (c->p) {
-        case 1: epw = Slot<1>::EPW; break;
-        case 2: epw = Slot<2>::EPW; break;
-        case 3: epw = Slot<3>::EPW; break;
-        case 4: epw = Slot<4>::EPW; break;
-        case 5: epw = Slot<5>::EPW; break;
-        case 6: epw = Slot<6>::EPW; break;
-    }
-    return 2 * (int64_t)apply_blocks_per_colour(c->nx, c->ny, c->nz, epw);
+    return 2 * (int64_t)apply_blocks_per_colour(c->nx, c->ny, c->nz, epw_of(c->p));
 }
 
 int launch_lift(hd_ctx* c, const double* ubc, double* b) {
@@ -710,6 +829,114 @@ int launch_mass_inverse(hd_ctx* c, int prec, const void* x, void* y, bool weight
     else
         dispatch_minv<float>(c, (const float*)x, (float*)y, weighted);
     HD_HIP(c, hipGetLastError());
+    return HD_OK;
+}
+
+
+namespace {
+
+template <int P, typename T>
+void launch_deg(hd_ctx* c, const BatchState& B, const BatchInstDev* di, int colour, const T* x, T* y,
+                const double* scale, int scale_stride, const int* done, int done_stride, bool partials) {
+    if (B.deg_nt[P] == 0) return;
+    hipLaunchKernelGGL((batch_apply_deg_kernel<P, T>), dim3(B.grid), dim3(64), 0, c->stream, di,
+                       B.d_tiles + B.deg_t0[P], B.deg_nt[P], B.d_counter + 2 + 2 * (P - 1) + colour, x, y, scale,
+                       scale_stride, done, done_stride, partials ? 1 : 0, colour, cg_params<T>(), (int)ESS_IDENTITY);
+}
+
+template <typename T>
+void launch_batch_t(hd_ctx* c, const BatchInstDev* di, const T* x, T* y, const double* scale, int scale_stride,
+                    const int* done, int done_stride, bool partials) {
+    const BatchState& B = *c->batch;
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, c->stream, B.d_counter);
+    for (int colour = 0; colour < 2; ++colour) {
+        if (B.mode == 0) {
+            hipLaunchKernelGGL(batch_apply_kernel<T>, dim3(B.grid), dim3(64), 0, c->stream, di, B.d_tiles, B.ntiles,
+                               B.d_counter + colour, x, y, scale, scale_stride, done, done_stride, partials ? 1 : 0,
+                               colour, cg_params<T>(), (int)ESS_IDENTITY);
+        } else {
+            launch_deg<6, T>(c, B, di, colour, x, y, scale, scale_stride, done, done_stride, partials);
+            launch_deg<5, T>(c, B, di, colour, x, y, scale, scale_stride, done, done_stride, partials);
+            launch_deg<4, T>(c, B, di, colour, x, y, scale, scale_stride, done, done_stride, partials);
+            launch_deg<3, T>(c, B, di, colour, x, y, scale, scale_stride, done, done_stride, partials);
+            launch_deg<2, T>(c, B, di, colour, x, y, scale, scale_stride, done, done_stride, partials);
+            launch_deg<1, T>(c, B, di, colour, x, y, scale, scale_stride, done, done_stride, partials);
+        }
+    }
+}
+
+}  // namespace
+
+int launch_batch_apply(hd_ctx* c, int prec, const void* x, void* y, const double* scale, int scale_stride,
+                       const int* done, int done_stride, bool partials) {
+    BatchState& B = *c->batch;
+    if (prec == HD_F64)
+        launch_batch_t<double>(c, B.d_inst64, (const double*)x, (double*)y, scale, scale_stride, done, done_stride,
+                               partials);
+    else
+        launch_batch_t<float>(c, B.d_inst32, (const float*)x, (float*)y, scale, scale_stride, done, done_stride,
+                              partials);
+    HD_HIP(c, hipGetLastError());
+    return HD_OK;
+}
+
+int batch_build_tiles(hd_ctx* c, int tile_groups) {
+    BatchState& B = *c->batch;
+    const int ninst = (int)B.inst.size();
+    std::vector<BatchTile> tiles;
+    std::vector<BatchInstDev> d64(ninst), d32(ninst);
+    std::vector<std::pair<int, int>> order;   // (-cost rank, instance)
+    for (int i = 0; i < ninst; ++i) {
+        hd_ctx* s = B.inst[i];
+        BatchInstDev a;
+        a.g = geo_of(s);
+        a.p = s->p;
+        a.with_c = s->kappa_zero ? 0 : 1;
+        a.ess = s->ess;
+        a.nb = apply_blocks_per_colour(s->nx, s->ny, s->nz, epw_of(s->p));
+        a.n_u = s->n_u;
+        a.off = B.off[i];
+        a.part = B.d_part + B.part_off[i];
+        BatchInstDev b = a;
+        a.pa = s->d_pa;
+        a.cm = s->d_cm;
+        a.kap = s->d_kap;
+        a.tabk = s->d_tabk64;
+        b.pa = s->d_pa32;
+        b.cm = s->d_cm32;
+        b.kap = s->d_kap32;
+        b.tabk = s->d_tabk32;
+        d64[i] = a;
+        d32[i] = b;
+        order.push_back({s->p, i});
+    }
+    // most expensive degree first, so that the long tiles start early
+    std::stable_sort(order.begin(), order.end(), [](const std::pair<int, int>& u, const std::pair<int, int>& v) {
+        return u.first > v.first;
+    });
+    for (int q = 0; q < 7; ++q) B.deg_t0[q] = B.deg_nt[q] = 0;
+    for (auto& pr : order) {
+        const int i = pr.second;
+        const unsigned nb = d64[i].nb;
+        const int p = d64[i].p;
+        if (B.deg_nt[p] == 0) B.deg_t0[p] = (int)tiles.size();
+        for (unsigned g0 = 0; g0 < nb; g0 += (unsigned)tile_groups) {
+            tiles.push_back({i, g0, std::min<unsigned>((unsigned)tile_groups, nb - g0)});
+            ++B.deg_nt[p];
+        }
+    }
+    dfree(B.d_tiles);
+    if (!B.d_inst64) B.d_inst64 = dalloc<BatchInstDev>(ninst);
+    if (!B.d_inst32) B.d_inst32 = dalloc<BatchInstDev>(ninst);
+    B.d_tiles = dalloc<BatchTile>(tiles.size());
+    if (!B.d_inst64 || !B.d_inst32 || !B.d_tiles) return set_err(c, HD_ERR_OOM, "batch tiles");
+    HD_HIP(c, hipMemcpyAsync(B.d_inst64, d64.data(), sizeof(BatchInstDev) * ninst, hipMemcpyHostToDevice, c->stream));
+    HD_HIP(c, hipMemcpyAsync(B.d_inst32, d32.data(), sizeof(BatchInstDev) * ninst, hipMemcpyHostToDevice, c->stream));
+    HD_HIP(c, hipMemcpyAsync(B.d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    B.ntiles = (int)tiles.size();
+    B.tile_groups = tile_groups;
     return HD_OK;
 }
 

@@ -83,6 +83,25 @@ int upload_f64_f32(hd_ctx* c, const double* host, int64_t n, double*& d64, float
     return HD_OK;
 }
 
+hd_precond_params default_precond();
+
+}  // namespace
+
+void hd::batch_free(hd_ctx* c) {
+    if (!c->batch) return;
+    BatchState* B = c->batch;
+    for (hd_ctx* s : B->inst) hd_destroy(s);
+    dfree(B->d_inst64);
+    dfree(B->d_inst32);
+    dfree(B->d_tiles);
+    dfree(B->d_counter);
+    dfree(B->d_part);
+    delete B;
+    c->batch = nullptr;
+}
+
+namespace {
+
 hd_precond_params default_precond() {
     hd_precond_params p;
     p.tau = 1.0;
@@ -126,6 +145,7 @@ int hd_destroy(hd_ctx* c) {
     if (!c) return HD_OK;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    batch_free(c);
     free_prec(c);
     free_coeffs(c);
     free_mesh(c);
@@ -496,6 +516,174 @@ int hd_set_diag_scalings(hd_ctx* c, const double* theta) {
     HD_HIP(c, hipStreamSynchronize(c->stream));
     c->theta_set = true;
     return HD_OK;
+}
+
+int hd_setup_batch(hd_ctx* c, int problem, int ninst, const hd_instance_desc* d) {
+    if (!c) return HD_ERR_ARG;
+    if (ninst < 1 || !d) return set_err(c, HD_ERR_ARG, "at least one instance required");
+    int rc = use_device(c);
+    if (rc) return rc;
+    batch_free(c);
+    BatchState* B = new (std::nothrow) BatchState;
+    if (!B) return set_err(c, HD_ERR_OOM, "batch");
+    c->batch = B;
+    B->off.push_back(0);
+    for (int i = 0; i < ninst && !rc; ++i) {
+        hd_ctx* s = nullptr;
+        if ((rc = hd_create(&s, c->device, (void*)c->stream))) {
+            rc = set_err(c, rc, "instance context");
+            break;
+        }
+        B->inst.push_back(s);
+        if (d[i].p < 1 || d[i].p > 6) rc = set_err(c, HD_ERR_ARG, "instance " + std::to_string(i) + ": p must be in 1..6");
+        else if ((rc = hd_setup_mesh(s, d[i].nx, d[i].ny, d[i].nz, d[i].p, d[i].vertices)) ||
+                 (rc = hd_setup_coeffs(s, problem, d[i].c_mass, d[i].c_22, d[i].ess_sides)))
+            rc = set_err(c, rc, "instance " + std::to_string(i) + ": " + s->err);
+        else
+            B->off.push_back(B->off.back() + s->n_u + s->n_q);
+    }
+    if (!rc) {
+        B->total = B->off.back();
+        int64_t np = 0;
+        for (hd_ctx* s : B->inst) {
+            B->part_off.push_back(np);
+            np += apply_partial_count(s);
+        }
+        B->d_part = dalloc<double>(np);
+        B->d_counter = dalloc<int>(16);
+        if (!B->d_part || !B->d_counter) rc = set_err(c, HD_ERR_OOM, "batch work queue");
+    }
+    if (!rc) {
+        B->grid = 2048;
+        B->mode = 0;
+        rc = batch_build_tiles(c, 1);
+    }
+    if (rc) batch_free(c);
+    return rc;
+}
+
+int hd_batch_sizes(hd_ctx* c, int64_t* offsets, int64_t* n_u) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->batch) return set_err(c, HD_ERR_STATE, "hd_setup_batch first");
+    const BatchState& B = *c->batch;
+    for (size_t i = 0; i < B.inst.size(); ++i) {
+        if (offsets) offsets[i] = B.off[i];
+        if (n_u) n_u[i] = B.inst[i]->n_u;
+    }
+    if (offsets) offsets[B.inst.size()] = B.total;
+    return HD_OK;
+}
+
+int hd_batch_apply(hd_ctx* c, int prec, const void* x, void* y) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->batch) return set_err(c, HD_ERR_STATE, "hd_setup_batch first");
+    if (prec != HD_F64 && prec != HD_F32) return set_err(c, HD_ERR_ARG, "prec");
+    if (!x || !y || x == y) return set_err(c, HD_ERR_ARG, "x, y must be distinct device pointers");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_batch_apply(c, prec, x, y, nullptr, 0, nullptr, 0, false);
+}
+
+int hd_batch_tune(hd_ctx* c, int prec, int* mode, int* grid, int* tile_groups, double* ms) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->batch) return set_err(c, HD_ERR_STATE, "hd_setup_batch first");
+    if (prec != HD_F64 && prec != HD_F32) return set_err(c, HD_ERR_ARG, "prec");
+    int rc = use_device(c);
+    if (rc) return rc;
+    BatchState& B = *c->batch;
+    const size_t es = prec == HD_F64 ? sizeof(double) : sizeof(float);
+    void *x = nullptr, *y = nullptr;
+    if (hipMalloc(&x, es * B.total) != hipSuccess || hipMalloc(&y, es * B.total) != hipSuccess) {
+        dfree(x);
+        return set_err(c, HD_ERR_OOM, "tuning vectors");
+    }
+    HD_HIP(c, hipMemsetAsync(x, 0, es * B.total, c->stream));
+    const int modes[2] = {0, 1}, groups[4] = {1, 2, 4, 8}, grids[4] = {512, 1024, 2048, 4096};
+    double best = 1e300;
+    int bm = 0, bg = 1, bgrid = 2048;
+    for (int tg : groups) {
+        if ((rc = batch_build_tiles(c, tg))) break;
+        for (int md : modes)
+            for (int gr : grids) {
+                B.mode = md;
+                B.grid = gr;
+                if ((rc = launch_batch_apply(c, prec, x, y, nullptr, 0, nullptr, 0, false))) break;
+                HD_HIP(c, hipEventRecord(c->ev0, c->stream));
+                for (int r = 0; r < 3 && !rc; ++r) rc = launch_batch_apply(c, prec, x, y, nullptr, 0, nullptr, 0, false);
+                HD_HIP(c, hipEventRecord(c->ev1, c->stream));
+                HD_HIP(c, hipEventSynchronize(c->ev1));
+                float t = 0.0f;
+                HD_HIP(c, hipEventElapsedTime(&t, c->ev0, c->ev1));
+                if (t / 3.0 < best) {
+                    best = t / 3.0;
+                    bm = md;
+                    bg = tg;
+                    bgrid = gr;
+                }
+            }
+        if (rc) break;
+    }
+    dfree(x);
+    dfree(y);
+    if (rc) return rc;
+    B.mode = bm;
+    B.grid = bgrid;
+    if ((rc = batch_build_tiles(c, bg))) return rc;
+    if (mode) *mode = bm;
+    if (grid) *grid = bgrid;
+    if (tile_groups) *tile_groups = bg;
+    if (ms) *ms = best;
+    return HD_OK;
+}
+
+int hd_batch_set_launch(hd_ctx* c, int mode, int grid, int tile_groups) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->batch) return set_err(c, HD_ERR_STATE, "hd_setup_batch first");
+    if ((mode != 0 && mode != 1) || grid < 1 || grid > (1 << 20) || tile_groups < 1 || tile_groups > 4096)
+        return set_err(c, HD_ERR_ARG, "bad launch configuration");
+    int rc = use_device(c);
+    if (rc) return rc;
+    c->batch->mode = mode;
+    c->batch->grid = grid;
+    return batch_build_tiles(c, tile_groups);
+}
+
+int hd_batch_build_precond(hd_ctx* c, const hd_precond_params* params) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->batch) return set_err(c, HD_ERR_STATE, "hd_setup_batch first");
+    if (params && params->learned != 0) return set_err(c, HD_ERR_ARG, "batched preconditioners use the plain diagonal");
+    BatchState& B = *c->batch;
+    for (size_t i = 0; i < B.inst.size(); ++i) {
+        const int rc = hd_build_precond(B.inst[i], params);
+        if (rc) return set_err(c, rc, "instance " + std::to_string(i) + ": " + B.inst[i]->err);
+    }
+    B.have_prec = true;
+    return HD_OK;
+}
+
+int hd_batch_minres_solve(hd_ctx* c, const hd_solve_params* params, const double* b, double* x,
+                          hd_solve_info* info) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->batch || !c->batch->have_prec) return set_err(c, HD_ERR_STATE, "hd_batch_build_precond first");
+    if (!b || !x || b == x) return set_err(c, HD_ERR_ARG, "b, x must be distinct device pointers");
+    hd_solve_params prm;
+    if (params) prm = *params;
+    else {
+        prm.tol = 1e-8;
+        prm.max_it = 10000;
+        prm.mode = HD_MODE_PLAIN64;
+        prm.use_x0 = 0;
+        prm.inner_tol = 1e-5;
+        prm.max_outer = 20;
+        prm.check_every = 8;
+        prm.stop_true = 0;
+    }
+    if (!(prm.tol > 0) || prm.max_it < 1) return set_err(c, HD_ERR_ARG, "bad solve parameters");
+    int rc = use_device(c);
+    if (rc) return rc;
+    rc = batch_minres_solve(c, prm, b, x, info);
+    if (rc == HD_NOT_CONVERGED) c->err = "MINRES did not reach the tolerance for every instance";
+    return rc;
 }
 
 int hd_get_diagonals(hd_ctx* c, double* m_diag, double* w_diag) {

@@ -86,6 +86,47 @@ struct DevLevel {
     float *b32 = nullptr, *x32 = nullptr, *r32 = nullptr, *z32 = nullptr;
 };
 
+// ---- batches of independent instances ----------------------------------
+// Per-instance view for the persistent batched apply (device array).
+struct BatchInstDev {
+    Geo g;
+    int p = 0;
+    int with_c = 0;
+    uint32_t ess = 0;
+    unsigned nb = 0;          // element groups per colour
+    int64_t n_u = 0;
+    int64_t off = 0;          // offset of the instance's [u; q] in the concatenated vector
+    const void* pa = nullptr; // geometric factors, kernel-precision
+    const void* cm = nullptr;
+    const void* kap = nullptr;
+    const void* tabk = nullptr;
+    double* part = nullptr;   // per-group partial sums of <A x, x> (2 nb)
+};
+// A work-queue entry: ngrp consecutive element groups of one instance.
+struct BatchTile {
+    int inst;
+    unsigned grp0, ngrp;
+};
+
+struct BatchState {
+    std::vector<hd_ctx*> inst;                // one context per instance (shares device and stream)
+    std::vector<int64_t> off;                 // ninst + 1 offsets of the concatenated vector
+    int64_t total = 0;
+    BatchInstDev* d_inst64 = nullptr;
+    BatchInstDev* d_inst32 = nullptr;
+    BatchTile* d_tiles = nullptr;
+    int ntiles = 0;
+    int* d_counter = nullptr;                 // work-queue heads: [mode 0: 2 colours][mode 1: 6 degrees x 2]
+    int deg_t0[7] = {0, 0, 0, 0, 0, 0, 0};    // tiles of degree p: [deg_t0[p], deg_t0[p] + deg_nt[p])
+    int deg_nt[7] = {0, 0, 0, 0, 0, 0, 0};
+    int mode = 0;                             // 0: one persistent launch for all degrees; 1: one per degree
+    double* d_part = nullptr;                 // all instances' apply partial sums
+    std::vector<int64_t> part_off;            // per-instance offsets into d_part (2 nb each)
+    int grid = 0;                             // persistent grid (workgroups)
+    int tile_groups = 1;                      // element groups per tile
+    bool have_prec = false;
+};
+
 }  // namespace hd
 
 struct hd_ctx {
@@ -145,6 +186,9 @@ struct hd_ctx {
     double* d_theta = nullptr;       // [ne][6] log-scalings used by the next hd_build_precond
     bool theta_set = false;
     bool fallback_used = false;
+
+    // batch of independent instances (hd_setup_batch)
+    hd::BatchState* batch = nullptr;
 
     // scratch
     double* d_partial = nullptr;     // per-block partial sums (>= ne and >= reduce grid)
@@ -225,6 +269,13 @@ int mlp_train(hd_ctx* c, int64_t n, const float* X, const float* Y, int64_t nval
               int epochs, int batch, float lr, uint64_t seed, float* train_loss, float* val_loss);
 int mlp_infer(hd_ctx* c, int64_t n, const float* X, float* theta, int bf16);
 int learned_mesh_theta(hd_ctx* c, int* fallback);
+
+// batched instances (apply.hip, minres.hip, batch.cpp)
+int launch_batch_apply(hd_ctx* c, int prec, const void* x, void* y, const double* scale, int scale_stride,
+                       const int* done, int done_stride, bool partials);
+int batch_build_tiles(hd_ctx* c, int tile_groups);
+int batch_minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, double* x, hd_solve_info* info);
+void batch_free(hd_ctx* c);
 
 // minres.hip
 // nrhs right-hand sides stored one after the other; info: nrhs entries

@@ -551,6 +551,150 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
     return HD_OK;
 }
 
+// ---- batches of independent instances ------------------------------------
+// One MINRES recurrence per instance on the concatenated vectors: the block
+// apply of all instances is one batched (persistent) launch per colour with
+// per-instance scales, stop flags and partial sums; the vector updates, the
+// reductions and the preconditioner (each instance's own diagonal and
+// V-cycle, i.e. the AMG of the block-diagonal union) run per instance.
+struct BatchWork {
+    int64_t total = 0;
+    double *v = nullptr, *vo = nullptr, *z = nullptr, *zn = nullptr, *w = nullptr, *wo = nullptr, *q = nullptr;
+    double *pu = nullptr, *pr = nullptr, *pq = nullptr, *nrm = nullptr;
+    std::vector<int64_t> pq_off, nq_part;
+    MinresState* st = nullptr;
+    MinresState* st_host = nullptr;
+    double* nrm_host = nullptr;
+    Work schur32;   // FP32 Schur buffers (sized for the largest instance)
+    ~BatchWork() {
+        for (double* p : {v, vo, z, zn, w, wo, q, pu, pr, pq, nrm}) dfree(p);
+        dfree(st);
+        if (st_host) (void)hipHostFree(st_host);
+        if (nrm_host) (void)hipHostFree(nrm_host);
+        dfree(schur32.t32);
+        dfree(schur32.z32);
+        dfree(schur32.p32);
+    }
+};
+
+int batch_true_residual(hd_ctx* c, BatchWork& W, const double* b, const double* x) {
+    const BatchState& B = *c->batch;
+    const int ni = (int)B.inst.size();
+    int rc;
+    if ((rc = launch_batch_apply(c, HD_F64, x, W.q, nullptr, 0, nullptr, 0, false))) return rc;
+    for (int i = 0; i < ni; ++i) {
+        const int64_t o = B.off[i], N = B.off[i + 1] - B.off[i];
+        hipLaunchKernelGGL(k_residual, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, b + o, (const double*)W.q + o,
+                           (double*)nullptr, W.pu + (int64_t)i * RED_BLOCKS, W.pr + (int64_t)i * RED_BLOCKS);
+        hipLaunchKernelGGL(k_norms, dim3(1), dim3(1024), 0, c->stream, W.pu + (int64_t)i * RED_BLOCKS,
+                           W.pr + (int64_t)i * RED_BLOCKS, (int64_t)red_grid(N), W.nrm + 2 * i);
+    }
+    HD_HIP(c, hipMemcpyAsync(W.nrm_host, W.nrm, 2 * ni * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    return HD_OK;
+}
+
+template <typename PT>
+int batch_minres_core(hd_ctx* c, BatchWork& W, const double* b, double* x, bool use_x0, double tol, int maxit,
+                      int check_every, double true_tol, std::vector<hd_solve_info>& out) {
+    const BatchState& B = *c->batch;
+    const int ni = (int)B.inst.size();
+    const int64_t tot = B.total;
+    double *v = W.v, *vo = W.vo, *z = W.z, *zn = W.zn, *w = W.w, *wo = W.wo, *q = W.q;
+    int rc;
+    if (use_x0) {
+        if ((rc = launch_batch_apply(c, HD_F64, x, q, nullptr, 0, nullptr, 0, false))) return rc;
+        hipLaunchKernelGGL((k_init<double, double>), dim3(nblk(tot)), dim3(BS), 0, c->stream, tot, b,
+                           (const double*)q, v, vo, w, wo);
+    } else {
+        hipLaunchKernelGGL(k_zero<double>, dim3(nblk(tot)), dim3(BS), 0, c->stream, tot, x);
+        hipLaunchKernelGGL((k_init<double, double>), dim3(nblk(tot)), dim3(BS), 0, c->stream, tot, b,
+                           (const double*)nullptr, v, vo, w, wo);
+    }
+    for (int i = 0; i < ni; ++i) {
+        hd_ctx* s = B.inst[i];
+        const int64_t o = B.off[i];
+        if ((rc = launch_diag_prec(s, HD_F64, v + o, z + o, W.pu + (int64_t)i * RED_BLOCKS))) return rc;
+        if ((rc = schur_step<double, PT>(s, W.schur32, v + o + s->n_u, z + o + s->n_u, W.pq + W.pq_off[i], nullptr)))
+            return rc;
+        hipLaunchKernelGGL(k_start, dim3(1), dim3(1024), 0, c->stream, W.st + i, W.pu + (int64_t)i * RED_BLOCKS,
+                           (int64_t)red_grid(s->n_u), (int64_t)RED_BLOCKS, W.pq + W.pq_off[i],
+                           schur_parts<double, PT>(s), W.nq_part[i], tol);
+    }
+    HD_HIP(c, hipGetLastError());
+    int launched = 0, retargets = 0;
+    for (;;) {
+        for (int k = 0; k < check_every && launched < maxit; ++k, ++launched) {
+            if ((rc = launch_batch_apply(c, HD_F64, z, q, &W.st->inv_gamma, ST_STRIDE_D, &W.st->stop, ST_STRIDE_I,
+                                         true)))
+                return rc;
+            for (int i = 0; i < ni; ++i) {
+                hd_ctx* s = B.inst[i];
+                const int64_t o = B.off[i], N = s->n_u + s->n_q, np = apply_partial_count(s);
+                const int* stop_i = &W.st[i].stop;
+                hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), 0, c->stream, W.st + i,
+                                   (const double*)(c->batch->d_part + c->batch->part_off[i]), np, np);
+                hipLaunchKernelGGL(k_vupd<double>, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, s->n_u,
+                                   (const double*)q + o, (const double*)v + o, vo + o, (const double*)s->d_mdinv,
+                                   zn + o, (const MinresState*)(W.st + i), W.pu + (int64_t)i * RED_BLOCKS);
+                if ((rc = schur_step<double, PT>(s, W.schur32, vo + o + s->n_u, zn + o + s->n_u, W.pq + W.pq_off[i],
+                                                 stop_i)))
+                    return rc;
+                hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, W.st + i,
+                                   (const double*)(W.pu + (int64_t)i * RED_BLOCKS), (int64_t)red_grid(N),
+                                   (int64_t)RED_BLOCKS, (const double*)(W.pq + W.pq_off[i]),
+                                   schur_parts<double, PT>(s), W.nq_part[i], maxit);
+                hipLaunchKernelGGL((k_wupd<double, double>), dim3(nblk(N), 1), dim3(BS), 0, c->stream, N,
+                                   (const double*)z + o, wo + o, (const double*)w + o, x + o,
+                                   (const MinresState*)(W.st + i));
+            }
+            std::swap(v, vo);
+            std::swap(z, zn);
+            std::swap(w, wo);
+        }
+        HD_HIP(c, hipGetLastError());
+        HD_HIP(c, hipMemcpyAsync(W.st_host, W.st, ni * sizeof(MinresState), hipMemcpyDeviceToHost, c->stream));
+        HD_HIP(c, hipStreamSynchronize(c->stream));
+        bool all_stop = true;
+        for (int i = 0; i < ni; ++i) all_stop = all_stop && W.st_host[i].stop;
+        if (all_stop && true_tol > 0.0 && retargets < 8) {
+            if ((rc = batch_true_residual(c, W, b, x))) return rc;
+            bool resumed = false;
+            for (int i = 0; i < ni; ++i) {
+                const MinresState& st = W.st_host[i];
+                const double rel = rel_of(W.nrm_host, i);
+                if (st.status != 0 || rel <= true_tol) continue;
+                hd_ctx* s = B.inst[i];
+                const int64_t o = B.off[i], N = s->n_u + s->n_q;
+                if ((st.iter % 2) != (launched % 2)) {
+                    double* pairs[3][2] = {{v, vo}, {z, zn}, {w, wo}};
+                    for (auto& pr : pairs)
+                        hipLaunchKernelGGL(k_swap<double>, dim3(nblk(N)), dim3(BS), 0, c->stream, N, pr[0] + o,
+                                           pr[1] + o);
+                }
+                hipLaunchKernelGGL(k_retarget, dim3(1), dim3(1), 0, c->stream, W.st + i,
+                                   st.tol * (true_tol / rel) * 0.7);
+                resumed = true;
+            }
+            if (resumed) {
+                ++retargets;
+                if (launched < maxit) continue;
+            }
+        }
+        if (all_stop || launched >= maxit) break;
+    }
+    out.resize(ni);
+    for (int i = 0; i < ni; ++i) {
+        const MinresState& st = W.st_host[i];
+        out[i] = hd_solve_info();
+        out[i].iterations = st.iter;
+        out[i].status = st.stop ? st.status : HD_NOT_CONVERGED;
+        out[i].eta_rel = st.eta0 > 0 ? std::fabs(st.eta) / st.eta0 : 0.0;
+        out[i].outer = 1;
+    }
+    return HD_OK;
+}
+
 }  // namespace
 
 int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* b, double* x, hd_solve_info* info) {
@@ -646,6 +790,63 @@ int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* 
         if (info) info[k] = res[k];
         if (res[k].status < 0) worst = res[k].status;
         else if (res[k].status > 0 && worst == 0) worst = res[k].status;
+    }
+    return worst;
+}
+
+int batch_minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, double* x, hd_solve_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    const BatchState& B = *c->batch;
+    const int ni = (int)B.inst.size();
+    if (prm.mode != HD_MODE_PLAIN64 && prm.mode != HD_MODE_PREC32)
+        return set_err(c, HD_ERR_ARG, "batched solves support HD_MODE_PLAIN64 and HD_MODE_PREC32");
+    BatchWork W;
+    W.total = B.total;
+    for (double** p : {&W.v, &W.vo, &W.z, &W.zn, &W.w, &W.wo, &W.q}) {
+        *p = dalloc<double>(B.total);
+        if (!*p) return set_err(c, HD_ERR_OOM, "batched MINRES vectors");
+    }
+    int64_t pq_tot = 0, nq_max = 0;
+    for (int i = 0; i < ni; ++i) {
+        const int64_t np = std::max<int64_t>(schur_partial_count(B.inst[i]), RED_BLOCKS);
+        W.pq_off.push_back(pq_tot);
+        W.nq_part.push_back(np);
+        pq_tot += np;
+        nq_max = std::max<int64_t>(nq_max, B.inst[i]->n_q);
+    }
+    W.pu = dalloc<double>((int64_t)RED_BLOCKS * ni);
+    W.pr = dalloc<double>((int64_t)RED_BLOCKS * ni);
+    W.pq = dalloc<double>(pq_tot);
+    W.nrm = dalloc<double>(2 * ni);
+    W.st = dalloc<MinresState>(ni);
+    if (!W.pu || !W.pr || !W.pq || !W.nrm || !W.st) return set_err(c, HD_ERR_OOM, "batched MINRES partials");
+    if (hipHostMalloc((void**)&W.st_host, sizeof(MinresState) * ni) != hipSuccess ||
+        hipHostMalloc((void**)&W.nrm_host, sizeof(double) * 2 * ni) != hipSuccess)
+        return set_err(c, HD_ERR_OOM, "batched MINRES host state");
+    if (prm.mode == HD_MODE_PREC32) {
+        int64_t npm = 0;
+        for (int i = 0; i < ni; ++i) npm = std::max(npm, W.nq_part[i]);
+        W.schur32.t32 = dalloc<float>(nq_max);
+        W.schur32.z32 = dalloc<float>(nq_max);
+        W.schur32.p32 = dalloc<double>(npm);
+        if (!W.schur32.t32 || !W.schur32.z32 || !W.schur32.p32) return set_err(c, HD_ERR_OOM, "FP32 Schur buffers");
+    }
+    const int check = prm.check_every > 0 ? prm.check_every : 8;
+    std::vector<hd_solve_info> res;
+    const double tt = prm.stop_true ? prm.tol : 0.0;
+    int rc = prm.mode == HD_MODE_PLAIN64
+                 ? batch_minres_core<double>(c, W, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, tt, res)
+                 : batch_minres_core<float>(c, W, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, tt, res);
+    if (rc) return rc;
+    if ((rc = batch_true_residual(c, W, b, x))) return rc;
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = 0;
+    for (int i = 0; i < ni; ++i) {
+        res[i].true_rel_res = rel_of(W.nrm_host, i);
+        res[i].time_s = dt;
+        if (info) info[i] = res[i];
+        if (res[i].status < 0) worst = res[i].status;
+        else if (res[i].status > 0 && worst == 0) worst = res[i].status;
     }
     return worst;
 }

@@ -31,7 +31,8 @@ EXPORTED = [
     'hd_host_amg_build', 'hd_host_amg_nlevels', 'hd_host_amg_level', 'hd_host_amg_prolongator',
     'hd_host_amg_free', 'hd_host_tables', 'hd_learned_targets', 'hd_learned_features', 'hd_mlp_param_count',
     'hd_mlp_init', 'hd_mlp_set_params', 'hd_mlp_get_params', 'hd_mlp_loss_grad', 'hd_mlp_train', 'hd_mlp_infer',
-    'hd_set_diag_scalings',
+    'hd_set_diag_scalings', 'hd_setup_batch', 'hd_batch_sizes', 'hd_batch_apply', 'hd_batch_tune',
+    'hd_batch_set_launch', 'hd_batch_build_precond', 'hd_batch_minres_solve',
 ]
 
 
@@ -50,6 +51,12 @@ class SolveParams(ctypes.Structure):
     _fields_ = [('tol', ctypes.c_double), ('max_it', ctypes.c_int), ('mode', ctypes.c_int),
                 ('use_x0', ctypes.c_int), ('inner_tol', ctypes.c_double), ('max_outer', ctypes.c_int),
                 ('check_every', ctypes.c_int), ('stop_true', ctypes.c_int)]
+
+
+class InstanceDesc(ctypes.Structure):
+    _fields_ = [('nx', ctypes.c_int), ('ny', ctypes.c_int), ('nz', ctypes.c_int), ('p', ctypes.c_int),
+                ('vertices', ctypes.c_void_p), ('c_mass', ctypes.c_void_p), ('c_22', ctypes.c_void_p),
+                ('ess_sides', ctypes.c_uint32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -114,6 +121,13 @@ def load():
         'hd_mlp_train': (I, [P, I64, P, P, I64, P, P, I, I, ctypes.c_float, ctypes.c_uint64, P, P]),
         'hd_mlp_infer': (I, [P, I64, P, P, I]),
         'hd_set_diag_scalings': (I, [P, P]),
+        'hd_setup_batch': (I, [P, I, I, ctypes.POINTER(InstanceDesc)]),
+        'hd_batch_sizes': (I, [P, P, P]),
+        'hd_batch_apply': (I, [P, I, P, P]),
+        'hd_batch_tune': (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D)]),
+        'hd_batch_set_launch': (I, [P, I, I, I]),
+        'hd_batch_build_precond': (I, [P, ctypes.POINTER(PrecondParams)]),
+        'hd_batch_minres_solve': (I, [P, ctypes.POINTER(SolveParams), P, P, ctypes.POINTER(SolveInfo)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -235,6 +249,59 @@ class Context:
         finite and the plain diagonal was used."""
         pp = ctypes.byref(params) if params is not None else None
         return self._check(self.lib.hd_build_precond(self.h, pp), allow=(HD_FALLBACK_USED,))
+
+    # ---- batches of independent instances ---------------------------------
+    def setup_batch(self, problem, instances):
+        """instances: dicts with nx, ny, nz, p, vertices, c_mass, c_22, ess_sides."""
+        keep = []
+        arr = (InstanceDesc * len(instances))()
+        for i, d in enumerate(instances):
+            v = np.ascontiguousarray(d['vertices'], dtype=np.float64)
+            cm = np.ascontiguousarray(d['c_mass'], dtype=np.float64)
+            c2 = None if d.get('c_22') is None else np.ascontiguousarray(d['c_22'], dtype=np.float64)
+            nx, ny, nz = d['nx'], d['ny'], d['nz']
+            if v.size != 3 * (nx + 1) * (ny + 1) * (nz + 1) or cm.size != nx * ny * nz or \
+                    (c2 is not None and c2.size != nx * ny * nz):
+                raise ValueError(f'instance {i}: array sizes do not match the mesh')
+            keep += [v, cm, c2]
+            arr[i] = InstanceDesc(nx, ny, nz, d['p'], v.ctypes.data, cm.ctypes.data,
+                                  None if c2 is None else c2.ctypes.data, d.get('ess_sides', 0))
+        rc = self._check(self.lib.hd_setup_batch(self.h, problem, len(instances), arr))
+        self.ninst = len(instances)
+        off = np.zeros(self.ninst + 1, dtype=np.int64)
+        nu = np.zeros(self.ninst, dtype=np.int64)
+        self._check(self.lib.hd_batch_sizes(self.h, _ptr(off), _ptr(nu)))
+        self.batch_offsets, self.batch_nu = off, nu
+        return rc
+
+    def batch_apply(self, x, y, prec=HD_F64):
+        n = int(self.batch_offsets[-1])
+        self._dev(x, n, prec, 'x')
+        self._dev(y, n, prec, 'y')
+        return self._check(self.lib.hd_batch_apply(self.h, prec, _ptr(x), _ptr(y)))
+
+    def batch_tune(self, prec=HD_F64):
+        m, g, t, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self._check(self.lib.hd_batch_tune(self.h, prec, ctypes.byref(m), ctypes.byref(g), ctypes.byref(t),
+                                           ctypes.byref(ms)))
+        return dict(mode=m.value, grid=g.value, tile_groups=t.value, ms=ms.value)
+
+    def batch_set_launch(self, mode, grid, tile_groups):
+        return self._check(self.lib.hd_batch_set_launch(self.h, mode, grid, tile_groups))
+
+    def batch_build_precond(self, params=None):
+        pp = ctypes.byref(params) if params is not None else None
+        return self._check(self.lib.hd_batch_build_precond(self.h, pp))
+
+    def batch_minres_solve(self, b, x, params=None):
+        n = int(self.batch_offsets[-1])
+        self._dev(b, n, HD_F64, 'b')
+        self._dev(x, n, HD_F64, 'x')
+        info = (SolveInfo * self.ninst)()
+        pp = ctypes.byref(params) if params is not None else None
+        rc = self.lib.hd_batch_minres_solve(self.h, pp, _ptr(b), _ptr(x), info)
+        self._check(rc, allow=(HD_NOT_CONVERGED,))
+        return [i.as_dict() for i in info]
 
     # ---- learned (1,1)-diagonal correction ----------------------------------
     def learned_targets(self, p, vertices, max_steps=30):

@@ -23,6 +23,12 @@ graddiv_distorted
                  x' = x + tan(t(z)) y with t rising smoothly from 0 to 30 deg,
                  interior vertices jittered by +-10% of the local spacing,
                  alpha and beta per element log-uniform in [1e-2, 1e2].
+batch_instances  independent grad-div problems for batching: n^3 unit-cube
+                 meshes (n uniform in [nmin, nmax]) jittered by +-10% h, p
+                 uniform in 1..6, alpha = T^3 / 3 and sigma = T^-3 with
+                 T = 2^clip(G, -1, 1), G a unit-std Gaussian field with
+                 correlation length a quarter of the domain, beta per instance
+                 log-uniform in [0.1, 10].
 training_elements
                  single distorted hexahedra for the learned diagonal: axis
                  stretches log-uniform with max/min <= 8, shears in U[-30, 30]
@@ -181,3 +187,22 @@ def training_elements(n, seed=50):
     alpha = np.exp(rng.uniform(np.log(1e-2), np.log(1e2), size=n))
     beta = np.exp(rng.uniform(np.log(1e-2), np.log(1e2), size=n))
     return out.reshape(n, 2, 2, 2, 3), p, alpha, beta
+
+
+def batch_instances(n_inst=32, seed=4, nmin=8, nmax=40, pmin=1, pmax=6):
+    """A list of instance dicts (seeds: sizes and degrees `seed`, mesh of
+    instance i `seed` + 10 + i, its field `seed` + 20 + i)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(nmin, nmax + 1, size=n_inst)
+    ps = rng.integers(pmin, pmax + 1, size=n_inst)
+    betas = np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=n_inst))
+    out = []
+    for i in range(n_inst):
+        n, p = int(ns[i]), int(ps[i])
+        G = gaussian_field((n, n, n), (0.25 * n,) * 3, 1.0, seed + 20 + i)
+        T = 2.0 ** np.clip(G, -1.0, 1.0)
+        alpha = (T ** 3 / 3.0).ravel()
+        out.append(dict(name=f'batch_{i}_{n}^3_p{p}', nx=n, ny=n, nz=n, p=p, problem=0,
+                        vertices=jittered_vertices(n, n, n, 0.1, seed + 10 + i),
+                        c_mass=np.full(n ** 3, betas[i]), c_22=alpha, ess_sides=0))
+    return out
