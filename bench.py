@@ -1,21 +1,36 @@
 """Benchmark: GDOF/s of the matrix-free RT_p block apply and MINRES
 time-to-1e-8, plain FP64 vs mixed precision, on one MI355X.
 
-Workload: grad-div on the unit cube, 32^3 hexahedra with vertices jittered by
-+-10% h, RT order p = 4 (n_u = 6,340,608, n_q = 2,097,152), alpha and beta per
-element log-uniform in [1e-2, 1e2]; right-hand side b_u ~ U[-1, 1], b_q = 0.
-Synthetic seeded inputs; setup (geometry, diagonals, S~, AMG) runs before the
-timed region and is reported separately.
+Default workload: grad-div on the unit cube, 32^3 hexahedra with vertices
+jittered by +-10% h, RT order p = 4 (n_u = 6,340,608, n_q = 2,097,152),
+alpha and beta per element log-uniform in [1e-2, 1e2]; right-hand side
+b_u ~ U[-1, 1], b_q = 0.  Synthetic seeded inputs; setup (geometry,
+diagonals, S~, AMG) runs before the timed region and is reported separately.
 
 One step = NAPPLY back-to-back FP64 block applies (HIP events on the
-library's stream bracket them), one plain FP64 MINRES solve to a relative
-residual of 1e-8 and one mixed-precision solve to the same true FP64
+library's stream bracket them), one plain FP64 MINRES solve to a true
+relative residual of 1e-8 and one mixed-precision solve to the same true FP64
 residual.  `value` is the apply throughput over the timed region:
 (n_u + n_q) * applies / apply time.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Other workloads (`--workload`, one JSON line each, no CPU baseline):
+  darcy_layered  60 x 220 x 85 cells, p = 2, layered log-normal permeability,
+                 flux boundary condition: FP64 MINRES with the FP64 and with
+                 the FP32 Schur V-cycle, time to a true residual of 1e-8.
+  batch32        32 independent grad-div instances (n^3, n in 8..40, p in
+                 1..6): autotuned persistent batched apply, FP64 and FP32.
+  multirhs64     grad-div 64^3, p = 3, 16 right-hand sides: FP32 apply.
+  distorted48    grad-div 48^3, p = 4 on a graded, sheared mesh: MINRES with
+                 the plain and with the learned (1,1) diagonal (network
+                 trained on GPU-generated targets first).
+`--pmc-run` runs two FP64 applies of the default workload and an elementwise
+kernel that reads and writes 1 GiB each (for counter collection under
+rocprofv3 and its calibration; prints nothing else).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload NAME]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +42,30 @@ sys.path.insert(0, ROOT)
 METRIC = "GDOF/s of matrix-free RT_p block apply; MINRES time-to-1e-8 plain vs mixed"
 NAPPLY = 20
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'block_apply_graddiv32_p4_traffic.json')
+KERNEL_SOURCES = ['paper_2304_12387_amd/csrc/apply.hip', 'paper_2304_12387_amd/csrc/pencil.hpp',
+                  'paper_2304_12387_amd/csrc/kernels_common.hpp', 'paper_2304_12387_amd/csrc/hd_internal.hpp']
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), 'rb') as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is missing or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get('kernel_source_sha256') != kernel_source_hash():
+        return None
+    return t.get('hbm_bytes_per_launch')
 
 
 def cpu_baseline(cfg, n_dofs, budget_s=15.0):
@@ -59,26 +98,27 @@ def cpu_baseline(cfg, n_dofs, budget_s=15.0):
                       f"{per_elem:.1f} dofs per element"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument('--gpus', type=int, default=1)
-    ap.add_argument('--steps', type=int, default=3)
-    ap.add_argument('--warmup', type=int, default=1)
-    ap.add_argument('--no-cpu', action='store_true')
-    ap.add_argument('--n', type=int, default=32)
-    ap.add_argument('--p', type=int, default=4)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU path is a "
-              f"design, not built)", file=sys.stderr)
-        sys.exit(2)
+def base_line(metric, value, unit, args, ms_per_step, config, higher=True, dtype="f64"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": higher, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
+
+def time_applies(torch, stream, fn, n):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(n):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def run_default(args, torch, hdivsp, inputs):
     import numpy as np
-    import torch
-
-    from paper_2304_12387_amd import hdivsp, inputs
-
-    torch.cuda.init()
     dev = torch.device('cuda', 0)
     stream = torch.cuda.current_stream(dev)
     cfg = inputs.graddiv_jittered(args.n, args.p)
@@ -88,17 +128,28 @@ def main():
     ctx.setup_coeffs(cfg['problem'], cfg['c_mass'], cfg['c_22'], cfg['ess_sides'])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    nu, nq = ctx.sizes()
+    N = nu + nq
+    x = torch.from_numpy(inputs.uniform_vector(N, 32)).to(dev)
+    y = torch.empty_like(x)
+    if args.pmc_run:
+        ctx.apply_block_op(x, y)
+        ctx.apply_block_op(x, y)
+        # counter calibration: an elementwise kernel that reads 1 GiB and
+        # writes 1 GiB (a plain copy would go to the DMA engines)
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        a.fill_(1.0)
+        bcopy = torch.empty_like(a)
+        torch.mul(a, 2.0, out=bcopy)
+        torch.cuda.synchronize()
+        ctx.close()
+        return None
     ctx.build_precond()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    nu, nq = ctx.sizes()
-    N = nu + nq
     ne = cfg['nx'] * cfg['ny'] * cfg['nz']
     q3 = (cfg['p'] + 1) ** 3
     bytes_per_apply = 16 * N + 8 * 7 * q3 * ne + 16 * ne
-
-    x = torch.from_numpy(inputs.uniform_vector(N, 32)).to(dev)
-    y = torch.empty_like(x)
     x32 = x.float()
     y32 = torch.empty_like(x32)
     b = torch.from_numpy(inputs.graddiv_rhs(nu, nq, 22)).to(dev)
@@ -124,15 +175,7 @@ def main():
     for _ in range(args.warmup):
         step(None)
     # FP32 apply throughput (outside the timed region)
-    ctx.apply_block_op(x32, y32, prec=hdivsp.HD_F32)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(NAPPLY):
-        ctx.apply_block_op(x32, y32, prec=hdivsp.HD_F32)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    f32_ms = ev0.elapsed_time(ev1) / NAPPLY
-
+    f32_ms = time_applies(torch, stream, lambda: ctx.apply_block_op(x32, y32, prec=hdivsp.HD_F32), NAPPLY)
     rec = {'apply_ms': [], 'plain': [], 'mixed': []}
     torch.cuda.synchronize()
     ts = time.perf_counter()
@@ -143,44 +186,217 @@ def main():
 
     apply_ms = sum(rec['apply_ms']) / (NAPPLY * args.steps)
     value = N / (apply_ms * 1e-3) / 1e9
-    achieved = bytes_per_apply / (apply_ms * 1e-3) / 1e9
+    launch_ms = apply_ms / 2.0            # two launches (colours) per apply
+    bytes_per_launch = bytes_per_apply / 2.0
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     med = lambda v: float(np.median(v))
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "GDOF/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round((te - ts) * 1e3 / args.steps, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"graddiv_jittered_{args.n}^3_p{args.p}", "nx": args.n, "p": args.p,
-                   "n_u": nu, "n_q": nq, "coefficients": "alpha, beta log-uniform [1e-2, 1e2] per element",
-                   "tol": 1e-8, "applies_per_step": NAPPLY},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"block_apply_kernel<{args.p},double>",
-                     "bytes_per_launch": bytes_per_apply, "avg_launch_ms": round(apply_ms, 5)},
-        "apply_f32_gdofs": round(N / (f32_ms * 1e-3) / 1e9, 3),
-        "minres": {
-            "plain_f64": {"time_to_1e-8_s": round(med([r['time_s'] for r in rec['plain']]), 4),
-                          "iterations": rec['plain'][-1]['iterations'],
-                          "true_rel_res": rec['plain'][-1]['true_rel_res']},
-            "mixed": {"time_to_1e-8_s": round(med([r['time_s'] for r in rec['mixed']]), 4),
-                      "iterations": rec['mixed'][-1]['iterations'], "outer": rec['mixed'][-1]['outer'],
-                      "true_rel_res": rec['mixed'][-1]['true_rel_res']},
-        },
-        "setup_s": {"mesh_coeffs": round(t1 - t0, 3), "precond": round(t2 - t1, 3)},
-        "amg_levels": ctx.amg_nlevels(),
+    out = base_line(METRIC, round(value, 3), "GDOF/s", args, round((te - ts) * 1e3 / args.steps, 3),
+                    {"workload": f"graddiv_jittered_{args.n}^3_p{args.p}", "nx": args.n, "p": args.p,
+                     "n_u": nu, "n_q": nq, "coefficients": "alpha, beta log-uniform [1e-2, 1e2] per element",
+                     "tol": 1e-8, "applies_per_step": NAPPLY})
+    traffic = measured_traffic() if (args.n, args.p) == (32, 4) else None
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                       "kernel": f"block_apply_kernel<{args.p},double>",
+                       "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(launch_ms, 5),
+                       "launches_per_apply": 2}
+    out["apply_f32_gdofs"] = round(N / (f32_ms * 1e-3) / 1e9, 3)
+    out["minres"] = {
+        "plain_f64": {"time_to_1e-8_s": round(med([r['time_s'] for r in rec['plain']]), 4),
+                      "iterations": rec['plain'][-1]['iterations'],
+                      "true_rel_res": rec['plain'][-1]['true_rel_res']},
+        "mixed": {"time_to_1e-8_s": round(med([r['time_s'] for r in rec['mixed']]), 4),
+                  "iterations": rec['mixed'][-1]['iterations'], "outer": rec['mixed'][-1]['outer'],
+                  "true_rel_res": rec['mixed'][-1]['true_rel_res']},
     }
+    out["setup_s"] = {"mesh_coeffs": round(t1 - t0, 3), "precond": round(t2 - t1, 3)}
+    out["amg_levels"] = ctx.amg_nlevels()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, N)
     ctx.close()
-    print(json.dumps(out))
+    return out
+
+
+def run_darcy_layered(args, torch, hdivsp, inputs):
+    import numpy as np
+    dev = torch.device('cuda', 0)
+    stream = torch.cuda.current_stream(dev)
+    cfg = inputs.darcy_layered()
+    ctx = hdivsp.Context(0, stream)
+    t0 = time.perf_counter()
+    ctx.setup_mesh(cfg['nx'], cfg['ny'], cfg['nz'], cfg['p'], cfg['vertices'])
+    ctx.setup_coeffs(cfg['problem'], cfg['c_mass'], None, cfg['ess_sides'])
+    ctx.build_precond()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nu, nq = ctx.sizes()
+    b = torch.zeros(nu + nq, dtype=torch.float64, device=dev)
+    ctx.lift_essential(ctx.constant_flux((1.0, 0.0, 0.0)), b)
+    res = {}
+    ts = time.perf_counter()
+    for name, mode in (('plain_f64', hdivsp.HD_MODE_PLAIN64), ('prec32', hdivsp.HD_MODE_PREC32)):
+        times = []
+        for _ in range(args.warmup + args.steps):
+            x = torch.zeros_like(b)
+            info = ctx.minres_solve(b, x, hdivsp.solve_params(tol=1e-8, mode=mode, stop_true=1, max_it=5000))
+            times.append(info['time_s'])
+        res[name] = {"time_to_1e-8_s": round(float(np.median(times[args.warmup:])), 4),
+                     "iterations": info['iterations'], "true_rel_res": info['true_rel_res']}
+    te = time.perf_counter()
+    x = torch.from_numpy(inputs.uniform_vector(nu + nq, 32)).to(dev)
+    y = torch.empty_like(x)
+    ms = time_applies(torch, stream, lambda: ctx.apply_block_op(x, y), NAPPLY)
+    out = base_line("MINRES time-to-1e-8 (s) of layered Darcy, FP32 Schur V-cycle in FP64 MINRES",
+                    res['prec32']['time_to_1e-8_s'], "s", args,
+                    round((te - ts) * 1e3 / (2 * (args.warmup + args.steps)), 3),
+                    {"workload": "darcy_layered_60x220x85_p2", "n_u": nu, "n_q": nq,
+                     "bc": "u.n = (1,0,0).n on the whole boundary"}, higher=False)
+    out["minres"] = res
+    out["apply_f64_gdofs"] = round((nu + nq) / (ms * 1e-3) / 1e9, 3)
+    out["setup_s"] = round(t1 - t0, 3)
+    out["amg_levels"] = ctx.amg_nlevels()
+    ctx.close()
+    return out
+
+
+def run_batch32(args, torch, hdivsp, inputs):
+    dev = torch.device('cuda', 0)
+    stream = torch.cuda.current_stream(dev)
+    inst = inputs.batch_instances()
+    ctx = hdivsp.Context(0, stream)
+    t0 = time.perf_counter()
+    ctx.setup_batch(0, inst)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    N = int(ctx.batch_offsets[-1])
+    res = {}
+    ts = time.perf_counter()
+    for name, prec, dt in (('f64', hdivsp.HD_F64, torch.float64), ('f32', hdivsp.HD_F32, torch.float32)):
+        tuned = ctx.batch_tune(prec)
+        x = torch.rand(N, dtype=dt, device=dev)
+        y = torch.empty_like(x)
+        ms = time_applies(torch, stream, lambda: ctx.batch_apply(x, y, prec=prec), max(args.steps, 3))
+        res[name] = {"gdofs": round(N / (ms * 1e-3) / 1e9, 3), "ms_per_apply": round(ms, 4), "tuned": tuned}
+        del x, y
+    te = time.perf_counter()
+    out = base_line("GDOF/s of the batched block apply (32 instances, persistent work queue)",
+                    res['f64']['gdofs'], "GDOF/s", args, round((te - ts) * 1e3, 3),
+                    {"workload": "batch_32_graddiv_instances_n8-40_p1-6", "total_dofs": N,
+                     "instances": [f"{d['nx']}^3 p{d['p']}" for d in inst]})
+    out["batch"] = res
+    out["setup_s"] = round(t1 - t0, 3)
+    ctx.close()
+    return out
+
+
+def run_multirhs64(args, torch, hdivsp, inputs):
+    dev = torch.device('cuda', 0)
+    stream = torch.cuda.current_stream(dev)
+    cfg = inputs.graddiv_jittered(64, 3, seed_mesh=4, seed_coef=14)
+    ctx = hdivsp.Context(0, stream)
+    ctx.setup_mesh(cfg['nx'], cfg['ny'], cfg['nz'], cfg['p'], cfg['vertices'])
+    ctx.setup_coeffs(cfg['problem'], cfg['c_mass'], cfg['c_22'], cfg['ess_sides'])
+    nu, nq = ctx.sizes()
+    N = nu + nq
+    R = 16
+    x = torch.rand(N * R, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    ts = time.perf_counter()
+    ms16 = time_applies(torch, stream, lambda: ctx.apply_block_op(x, y, prec=hdivsp.HD_F32, nrhs=R),
+                        max(args.steps, 3))
+    ms1 = time_applies(torch, stream, lambda: ctx.apply_block_op(x[:N], y[:N], prec=hdivsp.HD_F32), NAPPLY)
+    te = time.perf_counter()
+    out = base_line("GDOF/s of the FP32 block apply with 16 right-hand sides", round(N * R / (ms16 * 1e-3) / 1e9, 3),
+                    "GDOF/s", args, round((te - ts) * 1e3, 3),
+                    {"workload": "graddiv_jittered_64^3_p3_x16rhs", "n_u": nu, "n_q": nq, "nrhs": R}, dtype="f32")
+    out["single_rhs_f32_gdofs"] = round(N / (ms1 * 1e-3) / 1e9, 3)
+    ctx.close()
+    return out
+
+
+def run_distorted48(args, torch, hdivsp, inputs):
+    from paper_2304_12387_amd import learned as driver
+    dev = torch.device('cuda', 0)
+    stream = torch.cuda.current_stream(dev)
+    cfg = inputs.graddiv_distorted(48, 4)
+    ctx = hdivsp.Context(0, stream)
+    ctx.setup_mesh(cfg['nx'], cfg['ny'], cfg['nz'], cfg['p'], cfg['vertices'])
+    ctx.setup_coeffs(cfg['problem'], cfg['c_mass'], cfg['c_22'], cfg['ess_sides'])
+    t0 = time.perf_counter()
+    hist = driver.train(ctx, n=20000, seed=50, max_steps=10, epochs=20, batch=256, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    nu, nq = ctx.sizes()
+    b = torch.from_numpy(inputs.graddiv_rhs(nu, nq, 25)).to(dev)
+    # the targets themselves for the mesh's own elements (what the network
+    # would have to predict exactly): element vertices gathered from the grid
+    import numpy as np
+    n = cfg['nx']
+    Vg = np.asarray(cfg['vertices']).reshape(n + 1, n + 1, n + 1, 3)
+    Ve = np.stack([np.stack([np.stack([Vg[dz:dz + n, dy:dy + n, dx:dx + n] for dx in (0, 1)], axis=3)
+                             for dy in (0, 1)], axis=3) for dz in (0, 1)], axis=3)   # [z, y, x, dz, dy, dx, 3]
+    Ve = np.ascontiguousarray(Ve.reshape(n ** 3, 2, 2, 2, 3))
+    t0 = time.perf_counter()
+    th_mesh, _, spr_mesh = ctx.learned_targets(cfg['p'], torch.from_numpy(Ve).to(dev), 10)
+    torch.cuda.synchronize()
+    t_targets = time.perf_counter() - t0
+    ctx.set_diag_scalings(th_mesh)
+    res = {}
+    ts = time.perf_counter()
+    for name, flag in (('plain', 0), ('learned', 1), ('mesh_targets', 2)):
+        t0 = time.perf_counter()
+        rc = ctx.build_precond(hdivsp.precond_params(learned=flag))
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        x = torch.zeros_like(b)
+        info = ctx.minres_solve(b, x, hdivsp.solve_params(tol=1e-8, stop_true=1, max_it=5000))
+        res[name] = {"time_to_1e-8_s": round(info['time_s'], 4), "iterations": info['iterations'],
+                     "true_rel_res": info['true_rel_res'], "precond_setup_s": round(tb, 3), "status": rc}
+    te = time.perf_counter()
+    out = base_line("MINRES time-to-1e-8 (s) with the learned (1,1) diagonal",
+                    res['learned']['time_to_1e-8_s'], "s", args, round((te - ts) * 1e3, 3),
+                    {"workload": "graddiv_distorted_48^3_p4", "n_u": nu, "n_q": nq}, higher=False)
+    out["minres"] = res
+    out["training"] = {"elements": hist['n_train'] + hist['n_val'], "seconds": round(t_train, 2),
+                       "final_train_loss": float(hist['train_loss'][-1]),
+                       "final_val_loss": float(hist['val_loss'][-1]),
+                       "mean_spread_plain": hist['spread0'], "mean_spread_targets": hist['spread_opt']}
+    sm = spr_mesh.cpu().numpy()
+    out["mesh_targets"] = {"seconds": round(t_targets, 2), "mean_spread_plain": float(sm[:, 0].mean()),
+                           "mean_spread_targets": float(sm[:, 1].mean())}
+    ctx.close()
+    return out
+
+
+WORKLOADS = {'graddiv32': run_default, 'darcy_layered': run_darcy_layered, 'batch32': run_batch32,
+             'multirhs64': run_multirhs64, 'distorted48': run_distorted48}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=3)
+    ap.add_argument('--warmup', type=int, default=1)
+    ap.add_argument('--no-cpu', action='store_true')
+    ap.add_argument('--n', type=int, default=32)
+    ap.add_argument('--p', type=int, default=4)
+    ap.add_argument('--workload', default='graddiv32', choices=sorted(WORKLOADS))
+    ap.add_argument('--pmc-run', action='store_true')
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the multi-GPU path is a "
+              f"design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2304_12387_amd import hdivsp, inputs
+
+    torch.cuda.init()
+    fn = run_default if args.pmc_run else WORKLOADS[args.workload]
+    out = fn(args, torch, hdivsp, inputs)
+    if out is not None:
+        print(json.dumps(out))
 
 
 if __name__ == '__main__':

@@ -169,6 +169,13 @@ int hd_apply_l2_mass_inverse(hd_ctx* ctx, int prec, const void* x, void* y);
  * b_e = u_bc on essential rows.  FP64. */
 int hd_lift_essential(hd_ctx* ctx, const double* u_bc, double* b);
 
+/* RT interpolant of the constant vector field u[3] (host): every dof (device,
+ * length n_u) receives the flux of u through its sub-element face, oriented
+ * along +axis (the face dofs of the interpolation-histopolation basis,
+ * Section 2.1; exact on trilinear meshes).  Flux boundary data such as
+ * u.n = (1,0,0).n then come from hd_lift_essential. */
+int hd_constant_flux(hd_ctx* ctx, const double* u, double* dofs);
+
 /* Diagonal M~ = diag(M), the approximate Schur complement S~ in CSR form
  * (eq. approx-schur-entries, assembled row by row; 1 on essential
  * dofs of M~) and the AMG hierarchy on S~.  params may be NULL (defaults). */

@@ -23,6 +23,8 @@ void free_mesh(hd_ctx* c) {
     dfree(c->d_pa32);
     dfree(c->d_vert);
     dfree(c->d_theta);
+    dfree(c->d_theta_net);
+    c->d_theta_net = nullptr;
     c->d_pa = nullptr;
     c->d_pa32 = nullptr;
     c->d_vert = nullptr;
@@ -315,6 +317,17 @@ int hd_lift_essential(hd_ctx* c, const double* u_bc, double* b) {
     return launch_lift(c, u_bc, b);
 }
 
+int hd_constant_flux(hd_ctx* c, const double* u, double* dofs) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_mesh) return set_err(c, HD_ERR_STATE, "hd_setup_mesh first");
+    if (!u || !dofs) return set_err(c, HD_ERR_ARG, "null pointer");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(u[d])) return set_err(c, HD_ERR_NONFINITE, "non-finite field");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_constant_flux(c, u, dofs);
+}
+
 int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
     if (!c) return HD_ERR_ARG;
     if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
@@ -332,9 +345,8 @@ int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
     if (prm.learned == 1) {
         int fb = 0;
         if ((rc = learned_mesh_theta(c, &fb))) return rc;
-        c->theta_set = false;   // the network's scalings are not user-set ones
         if (fb) c->fallback_used = true;
-        else theta = c->d_theta;
+        else theta = c->d_theta_net;
     } else if (prm.learned == 2) {
         theta = c->d_theta;
     }

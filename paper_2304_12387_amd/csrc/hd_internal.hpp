@@ -183,8 +183,9 @@ struct hd_ctx {
     float* d_adam_v = nullptr;
     int adam_t = 0;
     bool mlp_ready = false;
-    double* d_theta = nullptr;       // [ne][6] log-scalings used by the next hd_build_precond
+    double* d_theta = nullptr;       // [ne][6] log-scalings set by hd_set_diag_scalings
     bool theta_set = false;
+    double* d_theta_net = nullptr;   // [ne][6] the network's scalings of the mesh
     bool fallback_used = false;
 
     // batch of independent instances (hd_setup_batch)
@@ -241,6 +242,7 @@ int launch_apply(hd_ctx* c, int prec, int nrhs, const void* x, void* y, const do
                  double* dot_partial, int64_t part_stride, int ess_mode, const int* done, int done_stride);
 int launch_mass_inverse(hd_ctx* c, int prec, const void* x, void* y, bool weighted);
 int launch_lift(hd_ctx* c, const double* ubc, double* b);
+int launch_constant_flux(hd_ctx* c, const double* u, double* out);
 int64_t apply_partial_count(const hd_ctx* c);
 int upload_kernel_tables(hd_ctx* c);
 

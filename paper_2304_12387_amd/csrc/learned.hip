@@ -1093,8 +1093,8 @@ int learned_mesh_theta(hd_ctx* c, int* fallback) {
     const int64_t ne = c->ne;
     float* X = dalloc<float>(ne * NIN);
     float* t32 = dalloc<float>(ne * NOUT);
-    if (!c->d_theta) c->d_theta = dalloc<double>(ne * 6);
-    if (!X || !t32 || !c->d_theta) {
+    if (!c->d_theta_net) c->d_theta_net = dalloc<double>(ne * 6);
+    if (!X || !t32 || !c->d_theta_net) {
         dfree(X);
         dfree(t32);
         return set_err(c, HD_ERR_OOM, "learned features");
@@ -1110,7 +1110,7 @@ int learned_mesh_theta(hd_ctx* c, int* fallback) {
     if (!rc) {
         const int64_t nt = ne * 6;
         hipLaunchKernelGGL(theta_widen_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, nt, t32,
-                           c->d_theta, c->d_flag);
+                           c->d_theta_net, c->d_flag);
         if (hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess)
             rc = set_err(c, HD_ERR_HIP, "learned scalings");

@@ -388,7 +388,82 @@ void launch_diag_p(hd_ctx* c, Geo g, const double* theta) {
                        c->d_cm, theta, c->d_mdiag, c->d_wdiag);
 }
 
+// ---------------------------------------------------------------------------
+// RT interpolant of a constant field u: every dof is the flux of u through
+// its sub-element face (the face dofs of the interpolation-histopolation
+// basis, Section 2.1), oriented along +axis.  A sub-face is a bilinear patch
+// of its element's trilinear map, whose vector area is half the cross product
+// of its diagonals, so the flux u . area is exact on any mesh of the class.
+// ---------------------------------------------------------------------------
+__device__ void map_point(const double (&X)[8][3], double a, double b, double cc, double (&out)[3]) {
+    for (int r = 0; r < 3; ++r) {
+        double s = 0.0;
+        for (int v = 0; v < 8; ++v) {
+            const int dx = v & 1, dy = (v >> 1) & 1, dz = (v >> 2) & 1;
+            s += (dx ? a : 1.0 - a) * (dy ? b : 1.0 - b) * (dz ? cc : 1.0 - cc) * X[v][r];
+        }
+        out[r] = s;
+    }
+}
+
+__global__ void constant_flux_kernel(Geo g, int P, const double* __restrict__ vert,
+                                     const Tables<double>* __restrict__ tab, double u0, double u1, double u2,
+                                     int64_t n_u, double* __restrict__ out) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n_u) return;
+    const int c = t >= g.off[2] ? 2 : (t >= g.off[1] ? 1 : 0);
+    const int64_t r = t - g.off[c];
+    const int ne[3] = {g.nx, g.ny, g.nz};
+    int64_t dim[3] = {(int64_t)g.nx * P, (int64_t)g.ny * P, (int64_t)g.nz * P};
+    dim[c] += 1;
+    const int64_t I[3] = {r % dim[0], (r / dim[0]) % dim[1], r / (dim[0] * dim[1])};
+    int e[3], loc[3];
+    for (int d = 0; d < 3; ++d) {
+        e[d] = (int)(I[d] / P);
+        if (e[d] >= ne[d]) e[d] = ne[d] - 1;   // the last face belongs to the last element
+        loc[d] = (int)(I[d] - (int64_t)e[d] * P);
+    }
+    double X[8][3];
+    for (int v = 0; v < 8; ++v) {
+        const int dx = v & 1, dy = (v >> 1) & 1, dz = (v >> 2) & 1;
+        const int64_t gv = (e[0] + dx) + (int64_t)(g.nx + 1) * ((e[1] + dy) + (int64_t)(g.ny + 1) * (e[2] + dz));
+        for (int q = 0; q < 3; ++q) X[v][q] = vert[3 * gv + q];
+    }
+    // tangential directions (a, b) with (c, a, b) cyclic, so a x b is +c
+    const int a = (c + 1) % 3, b = (c + 2) % 3;
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = tab->gll[loc[d]];
+        hi[d] = d == c ? lo[d] : tab->gll[loc[d] + 1];
+    }
+    double x00[3], x11[3], x01[3], x10[3], p[3];
+    p[c] = lo[c];
+    p[a] = lo[a]; p[b] = lo[b]; map_point(X, p[0], p[1], p[2], x00);
+    p[a] = hi[a]; p[b] = hi[b]; map_point(X, p[0], p[1], p[2], x11);
+    p[a] = lo[a]; p[b] = hi[b]; map_point(X, p[0], p[1], p[2], x01);
+    p[a] = hi[a]; p[b] = lo[b]; map_point(X, p[0], p[1], p[2], x10);
+    double d1[3], d2[3];
+    for (int q = 0; q < 3; ++q) {
+        d1[q] = x11[q] - x00[q];
+        d2[q] = x01[q] - x10[q];
+    }
+    const double A0 = 0.5 * (d1[1] * d2[2] - d1[2] * d2[1]);
+    const double A1 = 0.5 * (d1[2] * d2[0] - d1[0] * d2[2]);
+    const double A2 = 0.5 * (d1[0] * d2[1] - d1[1] * d2[0]);
+    out[t] = u0 * A0 + u1 * A1 + u2 * A2;
+}
+
 }  // namespace
+
+int launch_constant_flux(hd_ctx* c, const double* u, double* out) {
+    if (!c->d_vert) return set_err(c, HD_ERR_STATE, "mesh vertices not available");
+    Geo g = geo_of(c);
+    const int bs = 256;
+    hipLaunchKernelGGL(constant_flux_kernel, dim3((unsigned)((c->n_u + bs - 1) / bs)), dim3(bs), 0, c->stream, g,
+                       c->p, c->d_vert, c->d_tab64, u[0], u[1], u[2], c->n_u, out);
+    HD_HIP(c, hipGetLastError());
+    return HD_OK;
+}
 
 Geo geo_of(const hd_ctx* c) {
     Geo g;

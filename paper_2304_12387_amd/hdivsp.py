@@ -32,7 +32,7 @@ EXPORTED = [
     'hd_host_amg_free', 'hd_host_tables', 'hd_learned_targets', 'hd_learned_features', 'hd_mlp_param_count',
     'hd_mlp_init', 'hd_mlp_set_params', 'hd_mlp_get_params', 'hd_mlp_loss_grad', 'hd_mlp_train', 'hd_mlp_infer',
     'hd_set_diag_scalings', 'hd_setup_batch', 'hd_batch_sizes', 'hd_batch_apply', 'hd_batch_tune',
-    'hd_batch_set_launch', 'hd_batch_build_precond', 'hd_batch_minres_solve',
+    'hd_batch_set_launch', 'hd_batch_build_precond', 'hd_batch_minres_solve', 'hd_constant_flux',
 ]
 
 
@@ -121,6 +121,7 @@ def load():
         'hd_mlp_train': (I, [P, I64, P, P, I64, P, P, I, I, ctypes.c_float, ctypes.c_uint64, P, P]),
         'hd_mlp_infer': (I, [P, I64, P, P, I]),
         'hd_set_diag_scalings': (I, [P, P]),
+        'hd_constant_flux': (I, [P, P, P]),
         'hd_setup_batch': (I, [P, I, I, ctypes.POINTER(InstanceDesc)]),
         'hd_batch_sizes': (I, [P, P, P]),
         'hd_batch_apply': (I, [P, I, P, P]),
@@ -236,6 +237,16 @@ class Context:
         self._dev(x, nq, prec, 'x')
         self._dev(y, nq, prec, 'y')
         return self._check(self.lib.hd_apply_l2_mass_inverse(self.h, prec, _ptr(x), _ptr(y)))
+
+    def constant_flux(self, u):
+        """RT dofs (device tensor of n_u) of the constant field u (3 floats)."""
+        nu, _ = self.sizes()
+        uu = np.ascontiguousarray(u, dtype=np.float64)
+        if uu.size != 3:
+            raise ValueError('u: three components required')
+        out = self.torch.empty(nu, dtype=self.torch.float64, device=self.device)
+        self._check(self.lib.hd_constant_flux(self.h, _ptr(uu), _ptr(out)))
+        return out
 
     def lift_essential(self, u_bc, b):
         nu, nq = self.sizes()
