@@ -388,7 +388,7 @@ struct RhsArgs {
 // M u by sum factorisation, the local CG for -kappa W^{-1} q~, scatter.
 // x and y point at one right-hand side's vector; the return value is the
 // group's <A x, x> contribution summed over the wavefront (all lanes).
-template <int P, typename T>
+template <int P, typename T, bool HAS_C = true>
 __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, const T* __restrict__ pa, tkp<P, T> tb,
                                               const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
                                               int ess_mode, int64_t n_u, const T* __restrict__ x, T* __restrict__ y,
@@ -471,8 +471,11 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
         quad_to_rt<P, T, 2>(L, tb, t, U2, yv);
         if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
     }
-    // -kappa_e W_e^{-1} q~
-    if (with_c) local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
+    // -kappa_e W_e^{-1} q~ (compiled out of the variant for a zero (2,2) block,
+    // which then needs fewer registers and runs more wavefronts per SIMD)
+    if constexpr (HAS_C) {
+        if (with_c) local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
+    }
     __syncthreads();
     if (valid) {
         for (int l = t; l < NL; l += W) {
@@ -484,7 +487,7 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     return slot_sum<double, 64>(dot);
 }
 
-template <int P, typename T>
+template <int P, typename T, bool HAS_C>
 __global__ __launch_bounds__(64) void block_apply_kernel(
     Geo g, const T* __restrict__ pa, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
     int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
@@ -504,8 +507,8 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;   // uniform over the block
     __shared__ ElemLDS<P, T> sm[Slot<P>::EPW];
     const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
-    const double dot = apply_group<P, T>(sm, g, pa, tb, cm, kap, ess, ess_mode, n_u, xall + r * ra.ldv,
-                                         yall + r * ra.ldv, s_in, cgp, with_c, colour, grp, nb);
+    const double dot = apply_group<P, T, HAS_C>(sm, g, pa, tb, cm, kap, ess, ess_mode, n_u, xall + r * ra.ldv,
+                                                yall + r * ra.ldv, s_in, cgp, with_c, colour, grp, nb);
     if (ra.partial && grp < nb && threadIdx.x == 0) ra.partial[r * ra.part_stride + part_offset + grp] = dot;
 }
 
@@ -691,10 +694,16 @@ void launch_apply_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int ess_mode
     // several right-hand sides: element groups rounded up to a multiple of 8
     // (the XCD count), one block per (group, right-hand side)
     const unsigned grid = ra.nrhs > 1 ? (unsigned)(((nb + 7) / 8) * 8 * (uint64_t)ra.nrhs) : nb;
-    for (int colour = 0; colour < 2; ++colour)
-        hipLaunchKernelGGL((block_apply_kernel<P, T>), dim3(grid), dim3(64), 0, c->stream, g, pa, tb, cm, kap,
-                           c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), c->kappa_zero ? 0 : 1, colour,
-                           (int64_t)colour * nb, nb);
+    for (int colour = 0; colour < 2; ++colour) {
+        if (!c->kappa_zero)
+            hipLaunchKernelGGL((block_apply_kernel<P, T, true>), dim3(grid), dim3(64), 0, c->stream, g, pa, tb, cm,
+                               kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 1, colour,
+                               (int64_t)colour * nb, nb);
+        else
+            hipLaunchKernelGGL((block_apply_kernel<P, T, false>), dim3(grid), dim3(64), 0, c->stream, g, pa, tb, cm,
+                               kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 0, colour,
+                               (int64_t)colour * nb, nb);
+    }
 }
 
 template <int P, typename T>
