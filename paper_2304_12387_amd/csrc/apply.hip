@@ -414,11 +414,13 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     const T kE = kap[ee];
     // the lane's geometric factors, issued first so that they are in flight
     // during the gather and the forward sum factorisation
+    // (w / det J, the seventh factor, only feeds the local CG)
+    constexpr int NG = HAS_C ? NPA : NPA - 1;
     T G[NPA][Q];
     {
         const T* pe = pa + (size_t)ee * NPA * Q3 + (t < Q * Q ? t : 0);
 #pragma unroll
-        for (int m = 0; m < NPA; ++m)
+        for (int m = 0; m < NG; ++m)
 #pragma unroll
             for (int c = 0; c < Q; ++c) G[m][c] = pe[m * Q3 + Q * Q * c];
     }
@@ -455,7 +457,7 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
             U0[c] = cM * (G[0][c] * a0 + G[1][c] * a1 + G[2][c] * a2);
             U1[c] = cM * (G[1][c] * a0 + G[3][c] * a1 + G[4][c] * a2);
             U2[c] = cM * (G[2][c] * a0 + G[4][c] * a1 + G[5][c] * a2);
-            gw[c] = G[6][c];
+            gw[c] = HAS_C ? G[NG - 1][c] : T(1);
         }
     } else {
 #pragma unroll

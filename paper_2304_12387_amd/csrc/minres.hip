@@ -71,6 +71,20 @@ __device__ double block_sum(double v) {
     return r;
 }
 
+// First stage for long partial-sum arrays: block b of right-hand side r
+// (blockIdx.y) sums entries [b chunk, (b + 1) chunk) into out[r gridDim.x + b]
+// (fixed order, so the total stays deterministic).
+__global__ void k_sum_stage(const double* __restrict__ part, int64_t n, int64_t stride, int64_t chunk,
+                            double* __restrict__ out, const MinresState* __restrict__ st) {
+    if (st && st[blockIdx.y].stop) return;
+    const double* p = part + blockIdx.y * stride;
+    const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    double acc = 0.0;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) acc += p[k];
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
 // one block per right-hand side r: delta = sum of its apply partials
 __global__ void k_delta(MinresState* st, const double* __restrict__ part, int64_t n, int64_t stride) {
     MinresState* S = st + blockIdx.x;
@@ -350,6 +364,8 @@ struct Work {
     void *v = nullptr, *vo = nullptr, *z = nullptr, *zn = nullptr, *w = nullptr, *wo = nullptr, *q = nullptr;
     double *pd = nullptr, *pu = nullptr, *pq = nullptr, *nrm = nullptr;
     int64_t nd_part = 0, nq_part = 0;
+    double* pd2 = nullptr;       // first-stage sums of pd when it is long
+    int64_t nd_blocks = 0;       // number of first-stage blocks (0: single stage)
     MinresState* st = nullptr;
     MinresState* st_host = nullptr;
     double* nrm_host = nullptr;
@@ -361,6 +377,7 @@ struct Work {
 void free_work(Work& w) {
     for (void* p : {w.v, w.vo, w.z, w.zn, w.w, w.wo, w.q}) dfree(p);
     dfree(w.pd);
+    dfree(w.pd2);
     dfree(w.pu);
     dfree(w.pq);
     dfree(w.nrm);
@@ -385,6 +402,14 @@ int alloc_work(hd_ctx* c, Work& w, int prec, int nrhs, bool schur32 = false) {
     w.nd_part = apply_partial_count(c);
     w.nq_part = std::max<int64_t>(schur_partial_count(c), RED_BLOCKS);
     w.pd = dalloc<double>(w.nd_part * nrhs);
+    // one workgroup reduces up to a few thousand partials quickly; longer
+    // arrays (fine meshes of low degree) get a first stage of 2048 per block
+    constexpr int64_t STAGE = 2048;
+    w.nd_blocks = w.nd_part > 4 * STAGE ? std::min<int64_t>((w.nd_part + STAGE - 1) / STAGE, 1024) : 0;
+    if (w.nd_blocks) {
+        w.pd2 = dalloc<double>(w.nd_blocks * nrhs);
+        if (!w.pd2) return set_err(c, HD_ERR_OOM, "MINRES partials");
+    }
     w.pu = dalloc<double>((int64_t)RED_BLOCKS * nrhs);
     w.pq = dalloc<double>(w.nq_part * nrhs);
     w.nrm = dalloc<double>(2 * nrhs);
@@ -488,7 +513,16 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
             if ((rc = launch_apply(c, prec, nr, z, q, &wk.st->inv_gamma, ST_STRIDE_D, wk.pd, wk.nd_part, ESS_IDENTITY,
                                    stop, ST_STRIDE_I)))
                 return rc;
-            hipLaunchKernelGGL(k_delta, dim3(nr), dim3(1024), 0, c->stream, wk.st, wk.pd, wk.nd_part, wk.nd_part);
+            if (wk.nd_blocks) {
+                const int64_t chunk = (wk.nd_part + wk.nd_blocks - 1) / wk.nd_blocks;
+                hipLaunchKernelGGL(k_sum_stage, dim3((unsigned)wk.nd_blocks, nr), dim3(256), 0, c->stream, wk.pd,
+                                   wk.nd_part, wk.nd_part, chunk, wk.pd2, (const MinresState*)wk.st);
+                hipLaunchKernelGGL(k_delta, dim3(nr), dim3(1024), 0, c->stream, wk.st, wk.pd2, wk.nd_blocks,
+                                   wk.nd_blocks);
+            } else {
+                hipLaunchKernelGGL(k_delta, dim3(nr), dim3(1024), 0, c->stream, wk.st, wk.pd, wk.nd_part,
+                                   wk.nd_part);
+            }
             hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N), nr), dim3(BS), 0, c->stream, N, nu, q, v, vo, mdinv, zn,
                                wk.st, wk.pu);
             for (int r = 0; r < nr; ++r)
