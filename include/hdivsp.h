@@ -115,6 +115,10 @@ typedef struct hd_solve_params {
                             recurrence); 1 also requires the true FP64
                             ||b - A x||_2 <= tol ||b||_2, tightening the
                             threshold and continuing the same recurrence */
+    int use_graph;       /* 1: each poll period of iterations (check_every, if
+                            even) is captured once as a HIP graph and replayed;
+                            0: kernels are launched one by one.  Same results.
+                            Default 1 */
 } hd_solve_params;
 
 typedef struct hd_solve_info {

@@ -147,6 +147,7 @@ int hd_destroy(hd_ctx* c) {
     if (!c) return HD_OK;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->solve_cache) c->solve_cache_free(c->solve_cache);
     batch_free(c);
     free_prec(c);
     free_coeffs(c);
@@ -161,6 +162,7 @@ int hd_destroy(hd_ctx* c) {
     dfree(c->d_mlp);
     dfree(c->d_adam_m);
     dfree(c->d_adam_v);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -421,6 +423,7 @@ int hd_minres_solve(hd_ctx* c, const hd_solve_params* params, int nrhs, const do
         prm.max_outer = 20;
         prm.check_every = 8;
         prm.stop_true = 0;
+        prm.use_graph = 1;
     }
     if (!(prm.tol > 0) || prm.max_it < 1) return set_err(c, HD_ERR_ARG, "bad solve parameters");
     if (prm.mode == HD_MODE_MIXED && (!(prm.inner_tol > 0) || prm.max_outer < 1))
@@ -689,6 +692,7 @@ int hd_batch_minres_solve(hd_ctx* c, const hd_solve_params* params, const double
         prm.max_outer = 20;
         prm.check_every = 8;
         prm.stop_true = 0;
+        prm.use_graph = 1;
     }
     if (!(prm.tol > 0) || prm.max_it < 1) return set_err(c, HD_ERR_ARG, "bad solve parameters");
     int rc = use_device(c);

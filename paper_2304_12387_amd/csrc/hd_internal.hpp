@@ -188,6 +188,14 @@ struct hd_ctx {
     double* d_theta_net = nullptr;   // [ne][6] the network's scalings of the mesh
     bool fallback_used = false;
 
+    // private stream on which MINRES records its graphs (default priority)
+    hipStream_t cap_stream = nullptr;
+
+    // MINRES work space kept between solves (owned by the solver, released
+    // through solve_cache_free)
+    void* solve_cache = nullptr;
+    void (*solve_cache_free)(void*) = nullptr;
+
     // batch of independent instances (hd_setup_batch)
     hd::BatchState* batch = nullptr;
 

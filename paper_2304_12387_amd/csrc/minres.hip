@@ -472,9 +472,21 @@ inline double rel_of(const double* nrm, int r) {
 // sides (b of precision B, x of precision T, x0 = 0 unless use_x0).
 // true_tol > 0 (FP64 only): after the |eta| stop, require the true FP64
 // residual and continue the recurrence with a tighter threshold if needed.
+// One poll period of iterations as a replayable HIP graph: the vector
+// buffers rotate with period 2 and the period is even, so every replay sees
+// the same pointers; the recurrence state, the stop flags and the scales live
+// in device memory.  The capture is always ended, also on an error, so the
+// caller's stream never stays in capture mode.
+struct PeriodGraph {
+    hipGraphExec_t exec = nullptr;
+    ~PeriodGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+
 template <typename T, typename B, typename PT = T>
 int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, int maxit, int check_every,
-                std::vector<hd_solve_info>& out, double true_tol = 0.0) {
+                std::vector<hd_solve_info>& out, double true_tol = 0.0, bool use_graph = false) {
     const int prec = std::is_same<T, double>::value ? HD_F64 : HD_F32;
     const int64_t N = wk.N, nu = c->n_u;
     const int nr = wk.nrhs;
@@ -508,11 +520,13 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
     HD_HIP(c, hipGetLastError());
     const int* stop = &wk.st->stop;
     int launched = 0, retargets = 0;
-    for (;;) {
-        for (int k = 0; k < check_every && launched < maxit; ++k, ++launched) {
-            if ((rc = launch_apply(c, prec, nr, z, q, &wk.st->inv_gamma, ST_STRIDE_D, wk.pd, wk.nd_part, ESS_IDENTITY,
-                                   stop, ST_STRIDE_I)))
-                return rc;
+    // one MINRES iteration for every right-hand side (kernels only)
+    auto iteration = [&]() -> int {
+        int rc2;
+        {
+            if ((rc2 = launch_apply(c, prec, nr, z, q, &wk.st->inv_gamma, ST_STRIDE_D, wk.pd, wk.nd_part,
+                                    ESS_IDENTITY, stop, ST_STRIDE_I)))
+                return rc2;
             if (wk.nd_blocks) {
                 const int64_t chunk = (wk.nd_part + wk.nd_blocks - 1) / wk.nd_blocks;
                 hipLaunchKernelGGL(k_sum_stage, dim3((unsigned)wk.nd_blocks, nr), dim3(256), 0, c->stream, wk.pd,
@@ -526,15 +540,47 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
             hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N), nr), dim3(BS), 0, c->stream, N, nu, q, v, vo, mdinv, zn,
                                wk.st, wk.pu);
             for (int r = 0; r < nr; ++r)
-                if ((rc = schur_step<T, PT>(c, wk, vo + r * N + nu, zn + r * N + nu, wk.pq + r * wk.nq_part,
-                                            stop + r * ST_STRIDE_I)))
-                    return rc;
+                if ((rc2 = schur_step<T, PT>(c, wk, vo + r * N + nu, zn + r * N + nu, wk.pq + r * wk.nq_part,
+                                             stop + r * ST_STRIDE_I)))
+                    return rc2;
             hipLaunchKernelGGL(k_givens, dim3(nr), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)red_grid(N),
                                (int64_t)RED_BLOCKS, wk.pq, nqp, wk.nq_part, maxit);
             hipLaunchKernelGGL((k_wupd<T, T>), dim3(nblk(N), nr), dim3(BS), 0, c->stream, N, z, wo, w, x, wk.st);
             std::swap(v, vo);
             std::swap(z, zn);
             std::swap(w, wo);
+        }
+        return HD_OK;
+    };
+    PeriodGraph graph;
+    // (per-apply event timing synchronises inside the apply: no capture then)
+    const bool graphs = use_graph && check_every % 2 == 0 && !c->time_apply;
+    for (;;) {
+        if (graphs && maxit - launched >= check_every) {
+            if (!graph.exec) {
+                // the caller's stream may be the legacy default stream, which
+                // cannot be captured: record on a private stream of the same
+                // (default) priority, replay on the caller's
+                if (!c->cap_stream) HD_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                HD_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                hipStream_t user = c->stream;
+                c->stream = c->cap_stream;
+                int crc = HD_OK;
+                for (int k = 0; k < check_every && !crc; ++k) crc = iteration();
+                c->stream = user;
+                hipGraph_t g = nullptr;
+                const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+                if (!crc && e != hipSuccess) crc = set_err(c, HD_ERR_HIP, "MINRES graph capture");
+                if (!crc && hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0) != hipSuccess)
+                    crc = set_err(c, HD_ERR_HIP, "MINRES graph instantiation");
+                if (g) (void)hipGraphDestroy(g);
+                if (crc) return crc;
+            }
+            HD_HIP(c, hipGraphLaunch(graph.exec, c->stream));
+            launched += check_every;
+        } else {
+            for (int k = 0; k < check_every && launched < maxit; ++k, ++launched)
+                if ((rc = iteration())) return rc;
         }
         HD_HIP(c, hipGetLastError());
         HD_HIP(c, hipMemcpyAsync(wk.st_host, wk.st, nr * sizeof(MinresState), hipMemcpyDeviceToHost, c->stream));
@@ -731,34 +777,83 @@ int batch_minres_core(hd_ctx* c, BatchWork& W, const double* b, double* x, bool 
 
 }  // namespace
 
+namespace {
+
+// Work space of the solves, kept in the context between calls (vectors,
+// partial sums, pinned state) and rebuilt when the sizes change.
+struct SolveCache {
+    Work w64, w32;
+    double* r = nullptr;
+    float *r32 = nullptr, *d32 = nullptr;
+    int64_t nr = 0;
+};
+
+void free_cache(void* p) {
+    SolveCache* s = (SolveCache*)p;
+    free_work(s->w64);
+    free_work(s->w32);
+    dfree(s->r);
+    dfree(s->r32);
+    dfree(s->d32);
+    delete s;
+}
+
+SolveCache* cache_of(hd_ctx* c) {
+    if (!c->solve_cache) {
+        c->solve_cache = new SolveCache;
+        c->solve_cache_free = free_cache;
+    }
+    return (SolveCache*)c->solve_cache;
+}
+
+bool work_fits(const hd_ctx* c, const Work& w, int prec, int nrhs, bool schur32) {
+    return w.st && w.prec == prec && w.nrhs == nrhs && w.N == c->n_u + c->n_q && w.nd_part == apply_partial_count(c) &&
+           w.nq_part == std::max<int64_t>(schur_partial_count(c), RED_BLOCKS) && (!schur32 || w.t32);
+}
+
+int ensure_work(hd_ctx* c, Work& w, int prec, int nrhs, bool schur32) {
+    if (work_fits(c, w, prec, nrhs, schur32)) return HD_OK;
+    free_work(w);
+    int rc = alloc_work(c, w, prec, nrhs, schur32);
+    if (rc) free_work(w);
+    return rc;
+}
+
+}  // namespace
+
 int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* b, double* x, hd_solve_info* info) {
     auto t0 = std::chrono::steady_clock::now();
-    Work w64;
-    int rc = alloc_work(c, w64, HD_F64, nrhs, prm.mode == HD_MODE_PREC32);
-    if (rc) {
-        free_work(w64);
-        return rc;
-    }
+    SolveCache* cache = cache_of(c);
+    Work& w64 = cache->w64;
+    int rc = ensure_work(c, w64, HD_F64, nrhs, prm.mode == HD_MODE_PREC32);
+    if (rc) return rc;
     const int check = prm.check_every > 0 ? prm.check_every : 8;
     std::vector<hd_solve_info> res(nrhs);
     if (prm.mode == HD_MODE_PLAIN64) {
         rc = minres_core<double, double>(c, w64, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, res,
-                                         prm.stop_true ? prm.tol : 0.0);
+                                         prm.stop_true ? prm.tol : 0.0, prm.use_graph != 0);
     } else if (prm.mode == HD_MODE_PREC32) {
         rc = minres_core<double, double, float>(c, w64, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, res,
-                                                prm.stop_true ? prm.tol : 0.0);
+                                                prm.stop_true ? prm.tol : 0.0, prm.use_graph != 0);
     } else if (prm.mode == HD_MODE_MIXED) {
-        Work w32;
-        rc = alloc_work(c, w32, HD_F32, nrhs);
+        Work& w32 = cache->w32;
+        rc = ensure_work(c, w32, HD_F32, nrhs, false);
         const int64_t Nt = w64.N * nrhs;
-        double* r = nullptr;
-        float *r32 = nullptr, *d32 = nullptr;
-        if (!rc) {
-            r = dalloc<double>(Nt);
-            r32 = dalloc<float>(Nt);
-            d32 = dalloc<float>(Nt);
-            if (!r || !r32 || !d32) rc = set_err(c, HD_ERR_OOM, "refinement vectors");
+        if (!rc && cache->nr != Nt) {
+            dfree(cache->r);
+            dfree(cache->r32);
+            dfree(cache->d32);
+            cache->r = dalloc<double>(Nt);
+            cache->r32 = dalloc<float>(Nt);
+            cache->d32 = dalloc<float>(Nt);
+            cache->nr = Nt;
+            if (!cache->r || !cache->r32 || !cache->d32) {
+                cache->nr = 0;
+                rc = set_err(c, HD_ERR_OOM, "refinement vectors");
+            }
         }
+        double* r = cache->r;
+        float *r32 = cache->r32, *d32 = cache->d32;
         if (!rc && !prm.use_x0) hipLaunchKernelGGL(k_zero<double>, dim3(nblk(Nt)), dim3(BS), 0, c->stream, Nt, x);
         std::vector<int> total(nrhs, 0), status(nrhs, HD_NOT_CONVERGED);
         std::vector<double> er(nrhs, 0.0);
@@ -782,7 +877,8 @@ int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* 
             HD_HIP(c, hipMemcpyAsync(w64.nrm, w64.nrm_host, 2 * nrhs * sizeof(double), hipMemcpyHostToDevice,
                                      c->stream));
             hipLaunchKernelGGL(k_to32, dim3(nblk(w64.N), nrhs), dim3(BS), 0, c->stream, w64.N, r, w64.nrm, r32);
-            rc = minres_core<float, float>(c, w32, r32, d32, false, prm.inner_tol, prm.max_it, check, inner);
+            rc = minres_core<float, float>(c, w32, r32, d32, false, prm.inner_tol, prm.max_it, check, inner, 0.0,
+                                           prm.use_graph != 0);
             if (rc) break;
             ++outer;
             bool brk = false;
@@ -797,10 +893,6 @@ int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* 
             if (brk) break;
             hipLaunchKernelGGL(k_addscaled, dim3(nblk(w64.N), nrhs), dim3(BS), 0, c->stream, w64.N, d32, w64.nrm, x);
         }
-        dfree(r);
-        dfree(r32);
-        dfree(d32);
-        free_work(w32);
         for (int k = 0; k < nrhs; ++k) {
             res[k].iterations = total[k];
             res[k].outer = outer;
@@ -808,14 +900,12 @@ int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* 
             res[k].status = status[k];
         }
     } else {
-        free_work(w64);
         return set_err(c, HD_ERR_ARG, "solve mode not supported");
     }
     if (!rc) {
         rc = true_residual(c, w64, b, x, nullptr);
         for (int k = 0; k < nrhs && !rc; ++k) res[k].true_rel_res = rel_of(w64.nrm_host, k);
     }
-    free_work(w64);
     if (rc) return rc;
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     int worst = 0;

@@ -50,7 +50,7 @@ class PrecondParams(ctypes.Structure):
 class SolveParams(ctypes.Structure):
     _fields_ = [('tol', ctypes.c_double), ('max_it', ctypes.c_int), ('mode', ctypes.c_int),
                 ('use_x0', ctypes.c_int), ('inner_tol', ctypes.c_double), ('max_outer', ctypes.c_int),
-                ('check_every', ctypes.c_int), ('stop_true', ctypes.c_int)]
+                ('check_every', ctypes.c_int), ('stop_true', ctypes.c_int), ('use_graph', ctypes.c_int)]
 
 
 class InstanceDesc(ctypes.Structure):
@@ -152,8 +152,8 @@ def precond_params(tau=1.0, theta=0.25, max_coarse=1024, max_levels=25, omega=2.
 
 
 def solve_params(tol=1e-8, max_it=10000, mode=HD_MODE_PLAIN64, use_x0=0, inner_tol=1e-5, max_outer=20,
-                 check_every=8, stop_true=0):
-    return SolveParams(tol, max_it, mode, use_x0, inner_tol, max_outer, check_every, stop_true)
+                 check_every=8, stop_true=0, use_graph=1):
+    return SolveParams(tol, max_it, mode, use_x0, inner_tol, max_outer, check_every, stop_true, use_graph)
 
 
 class Context:

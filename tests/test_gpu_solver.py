@@ -217,3 +217,30 @@ def test_post_processing():
     assert rel(q, du[nu:].cpu().numpy()) <= 1e-9
     assert rel(q, prob.D @ xd[:nu].cpu().numpy()) <= 1e-9
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", ['plain', 'mixed'])
+def test_graph_replays_match_eager_launches(mode):
+    """MINRES with each poll period captured as a HIP graph and replayed
+    (with the host's synchronisation and state reads between replays) gives
+    exactly the iterations and the solution of launching the kernels one by
+    one, for several right-hand sides and an odd iteration budget."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    case = make_case(4, 4, 3, 3, problem=0)
+    prob = oracle_problem(case)
+    ctx = gpu_context(case, precond=True, params=_params(hdivsp, 40))
+    n = prob.mesh.n
+    B = np.stack([inputs.graddiv_rhs(prob.mesh.n_u, prob.mesh.n_q, seed=s) for s in (51, 52)])
+    bd = to_dev(B.reshape(-1))
+    md = hdivsp.HD_MODE_PLAIN64 if mode == 'plain' else hdivsp.HD_MODE_MIXED
+    out = {}
+    for g in (0, 1):
+        x = torch.zeros_like(bd)
+        infos = ctx.minres_solve(bd, x, hdivsp.solve_params(tol=1e-10, max_it=1001, mode=md, use_graph=g,
+                                                            stop_true=1 if mode == 'plain' else 0), nrhs=2)
+        out[g] = (x.cpu().numpy(), [i['iterations'] for i in infos], [i['status'] for i in infos])
+    print(mode, out[0][1], out[1][1], flush=True)
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2] == [0, 0]
+    assert np.array_equal(out[0][0], out[1][0])
+    ctx.close()
