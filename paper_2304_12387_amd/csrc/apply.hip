@@ -327,18 +327,57 @@ __device__ __forceinline__ void gather_rt(ElemLDS<P, T>& L, const Geo& g, int ex
     }
 }
 
+// Values the first colour left in y on the dofs of this lane's x-line of
+// component C (the second colour adds to them on shared faces).  Issued
+// before the transposed sum factorisation of C, so that the loads are in
+// flight while it runs; one batch of loads per line instead of a load, wait
+// and store per dof.
+template <int P, typename T, int C>
+__device__ __forceinline__ void prefetch_line(const Geo& g, int ex, int ey, int ez, int t, const T* __restrict__ y,
+                                              T (&old)[P + 1]) {
+    constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
+    if (t < N1 * N2) {
+        const RtLine r = rt_line<P, C>(g, ex, ey, ez, t % N1, t / N1);
+        if (C == 0) {
+            // only the two end dofs of an x-line lie on element faces
+            old[0] = y[r.base];
+            old[P] = y[r.base + P];
+        } else if (r.tan_face) {
+#pragma unroll
+            for (int i = 0; i < N0; ++i) old[i] = y[r.base + i];
+        }
+    }
+}
+
 // D^T q~ added to the x-pencil of component C, then scatter to y and the
-// local contribution to <y, x_scaled>.
+// local contribution to <y, x_scaled>.  Essential dofs (identity rows) take
+// the scaled input value.  Straight-line stores: every dof of the line is
+// written once, with the first colour's value added on shared faces.
 template <int P, typename T, int C>
 __device__ __forceinline__ double finish_rt(ElemLDS<P, T>& L, const Geo& g, int ex, int ey, int ez, int t,
-                                            T (&yv)[P + 1], uint32_t ess, int ess_mode, T s_in,
-                                            const T* __restrict__ x, T* __restrict__ y, int colour) {
+                                            const T (&yv)[P + 1], const T (&old)[P + 1], uint32_t ess, int ess_mode,
+                                            T s_in, const T* __restrict__ x, T* __restrict__ y, int colour) {
     constexpr int NC = Dim<P>::NC;
     constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
     double dot = 0.0;
     if (t >= N1 * N2) return dot;
     const int j = t % N1, k = t / N1;
     const RtLine r = rt_line<P, C>(g, ex, ey, ez, j, k);
+    unsigned ess_mask = 0, add_mask = 0;
+#pragma unroll
+    for (int i = 0; i < N0; ++i) {
+        int onf, bs;
+        rt_line_dof<P, C>(g, ex, r, i, onf, bs);
+        if (ess_mode == ESS_IDENTITY && bs >= 0 && ((ess >> (2 * C + bs)) & 1u)) ess_mask |= 1u << i;
+        // faces shared with a neighbour: the first colour stores, the
+        // second adds (face neighbours always have opposite colours)
+        if (colour == 1 && onf && bs < 0) add_mask |= 1u << i;
+    }
+    T xe[N0];
+    if (ess_mask) {
+#pragma unroll
+        for (int i = 0; i < N0; ++i) xe[i] = s_in * x[r.base + i];
+    }
 #pragma unroll
     for (int i = 0; i < N0; ++i) {
         const int tn = C == 0 ? i : (C == 1 ? j : k);   // index along the normal
@@ -349,23 +388,17 @@ __device__ __forceinline__ double finish_rt(ElemLDS<P, T>& L, const Geo& g, int 
             add += L.sq[a + P * (b + P * c)];
         }
         if (tn <= P - 1) add -= L.sq[i + P * (j + P * k)];
-        int onf, bs;
-        rt_line_dof<P, C>(g, ex, r, i, onf, bs);
-        const int64_t gidx = r.base + i;
-        const bool is_ess = ess_mode == ESS_IDENTITY && bs >= 0 && ((ess >> (2 * C + bs)) & 1u);
-        const int l = C * NC + i + N0 * t;
-        if (is_ess) {
-            const T xv = s_in * x[gidx];
-            y[gidx] = xv;
-            dot += (double)xv * (double)xv;
-        } else {
-            const T v = yv[i] + add;
-            // faces shared with a neighbour: the first colour stores, the
-            // second adds (face neighbours always have opposite colours)
-            if (colour == 1 && onf && bs < 0) y[gidx] = y[gidx] + v;
-            else y[gidx] = v;
-            dot += (double)v * (double)L.su[l];
+        T v = yv[i] + add;
+        const T ref = L.su[C * NC + i + N0 * t];
+        double d = (double)v * (double)ref;
+        if ((ess_mask >> i) & 1u) {
+            v = xe[i];
+            d = (double)v * (double)v;
+        } else if ((add_mask >> i) & 1u) {
+            v = old[i] + v;
         }
+        y[r.base + i] = v;
+        dot += d;
     }
     return dot;
 }
@@ -465,13 +498,17 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     }
     double dot = 0.0;
     {
-        T yv[Q];
+        T yv[Q], old[Q];
+        const bool pre = valid && colour == 1;
+        if (pre) prefetch_line<P, T, 0>(g, ex, ey, ez, t, y, old);
         quad_to_rt<P, T, 0>(L, tb, t, U0, yv);
-        if (valid) dot += finish_rt<P, T, 0>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
+        if (valid) dot += finish_rt<P, T, 0>(L, g, ex, ey, ez, t, yv, old, ess, ess_mode, s_in, x, y, colour);
+        if (pre) prefetch_line<P, T, 1>(g, ex, ey, ez, t, y, old);
         quad_to_rt<P, T, 1>(L, tb, t, U1, yv);
-        if (valid) dot += finish_rt<P, T, 1>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
+        if (valid) dot += finish_rt<P, T, 1>(L, g, ex, ey, ez, t, yv, old, ess, ess_mode, s_in, x, y, colour);
+        if (pre) prefetch_line<P, T, 2>(g, ex, ey, ez, t, y, old);
         quad_to_rt<P, T, 2>(L, tb, t, U2, yv);
-        if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, ess, ess_mode, s_in, x, y, colour);
+        if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, old, ess, ess_mode, s_in, x, y, colour);
     }
     // -kappa_e W_e^{-1} q~ (compiled out of the variant for a zero (2,2) block,
     // which then needs fewer registers and runs more wavefronts per SIMD)
@@ -489,6 +526,16 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     return slot_sum<double, 64>(dot);
 }
 
+// Element groups are dealt to the XCDs in contiguous chunks.  Workgroups
+// are dispatched round-robin over the 8 XCDs (block b runs on XCD b mod 8),
+// each with its own L2; neighbouring elements share cache lines of x and y,
+// so they must meet in one L2 instead of each XCD fetching the line and
+// writing back a partial one.  A bijection of [0, n).
+__device__ __forceinline__ unsigned xcd_chunk(unsigned b, unsigned n) {
+    const unsigned x = b % 8, k = b / 8;
+    return x * (n / 8) + (x < n % 8 ? x : n % 8) + k;
+}
+
 template <int P, typename T, bool HAS_C>
 __global__ __launch_bounds__(64) void block_apply_kernel(
     Geo g, const T* __restrict__ pa, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
@@ -499,12 +546,14 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     // run on the same XCD (blocks are dealt to the 8 XCDs round-robin) at
     // about the same time and the second and later reads of the group's
     // geometric factors hit that XCD's L2.
-    unsigned grp = blockIdx.x;
+    unsigned grp;
     int r = 0;
     if (ra.nrhs > 1) {
         const unsigned k = blockIdx.x / 8;
         r = (int)(k % (unsigned)ra.nrhs);
-        grp = blockIdx.x % 8 + 8 * (k / (unsigned)ra.nrhs);
+        grp = (blockIdx.x % 8) * ((nb + 7) / 8) + k / (unsigned)ra.nrhs;
+    } else {
+        grp = xcd_chunk(blockIdx.x, nb);
     }
     if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;   // uniform over the block
     __shared__ ElemLDS<P, T> sm[Slot<P>::EPW];

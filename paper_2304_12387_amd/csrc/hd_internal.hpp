@@ -172,6 +172,12 @@ struct hd_ctx {
     hd::DevCSR S;                // S~
     std::vector<hd::DevLevel> lev;
     int64_t n_coarse = 0;
+    // level 0 of the V-cycle: for each sub-volume i and direction d, the
+    // weight of the face to its lower neighbour (0 if none), [3][n_q] in the
+    // element-major L2 numbering; per-block partials of the post-smoother
+    double* d_wlo = nullptr;
+    float* d_wlo32 = nullptr;
+    double* d_s0part = nullptr;
     double* d_cinv = nullptr;
     float* d_cinv32 = nullptr;
     bool singular = false;

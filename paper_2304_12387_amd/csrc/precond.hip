@@ -71,17 +71,70 @@ __device__ __forceinline__ void for_each_coupling(const Geo& g, int64_t i, F&& f
     }
 }
 
+// Lower and upper neighbours of sub-volume i in direction d (-1 at the
+// domain boundary), in the element-major L2 numbering.
+template <int P>
+__device__ __forceinline__ void s0_neighbours(const Geo& g, int64_t i, int64_t (&lo)[3], int64_t (&up)[3]) {
+    constexpr int NL = P * P * P;
+    const int64_t e = i / NL;
+    const int l = (int)(i % NL);
+    const int a = l % P, b = (l / P) % P, c = l / (P * P);
+    const int ex = (int)(e % g.nx), ey = (int)((e / g.nx) % g.ny), ez = (int)(e / ((int64_t)g.nx * g.ny));
+    const int64_t eNL = NL, rowNL = (int64_t)g.nx * NL, planeNL = (int64_t)g.nx * g.ny * NL;
+    lo[0] = a > 0 ? i - 1 : (ex > 0 ? i - eNL + (P - 1) : -1);
+    up[0] = a < P - 1 ? i + 1 : (ex < g.nx - 1 ? i + eNL - (P - 1) : -1);
+    lo[1] = b > 0 ? i - P : (ey > 0 ? i - rowNL + (P - 1) * P : -1);
+    up[1] = b < P - 1 ? i + P : (ey < g.ny - 1 ? i + rowNL - (P - 1) * P : -1);
+    lo[2] = c > 0 ? i - P * P : (ez > 0 ? i - planeNL + (P - 1) * P * P : -1);
+    up[2] = c < P - 1 ? i + P * P : (ez < g.nz - 1 ? i + planeNL - (P - 1) * P * P : -1);
+}
+
+// Face weights by sub-volume: wlo[d * n + i] = weight of the face between i
+// and its lower neighbour in direction d (the same face as for_each_coupling
+// visits), 0 where there is none.  The upper face of i is the lower face of
+// its upper neighbour, so the level-0 kernels read both from this array in
+// the L2 numbering instead of gathering from the RT face layout.
+template <int P, typename T>
+__global__ __launch_bounds__(BS) void s0_wlo_kernel(Geo g, int64_t n, const double* __restrict__ wf,
+                                                    T* __restrict__ wlo) {
+    const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+    if (i >= n) return;
+    T w[3] = {T(0), T(0), T(0)};
+    for_each_coupling<P>(g, i, [&](int64_t k, int64_t j) {
+        // the face's direction from its RT-layout block; lower faces couple
+        // to a smaller index
+        const int d = k >= g.off[2] ? 2 : (k >= g.off[1] ? 1 : 0);
+        if (j < i) w[d] = (T)wf[k];
+    });
+    for (int dd = 0; dd < 3; ++dd) wlo[dd * n + i] = w[dd];
+}
+
+// off-diagonal part of row i of S~ applied to xval: sum over the free
+// couplings of w_k xval(j), in for_each_coupling's order (x lower, x upper,
+// y lower, ...)
+template <int P, typename T, typename F>
+__device__ __forceinline__ T s0_offdiag(const Geo& g, int64_t n, int64_t i, const T* __restrict__ wlo, F&& xval) {
+    int64_t lo[3], up[3];
+    s0_neighbours<P>(g, i, lo, up);
+    T off = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (lo[d] >= 0) off += wlo[d * n + i] * xval(lo[d]);
+        if (up[d] >= 0) off += wlo[d * n + up[d]] * xval(up[d]);
+    }
+    return off;
+}
+
 // x = dinv b;  r = b - S~ (dinv b)
 template <int P, typename T>
 __global__ __launch_bounds__(BS) void s0_pre_kernel(Geo g, int64_t n, const T* __restrict__ sdiag,
-                                                    const T* __restrict__ wf, const T* __restrict__ dinv,
+                                                    const T* __restrict__ wlo, const T* __restrict__ dinv,
                                                     const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r,
                                                     const int* __restrict__ done) {
     if (done && *done) return;
     const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
     if (i >= n) return;
-    T off = 0;
-    for_each_coupling<P>(g, i, [&](int64_t k, int64_t j) { off += wf[k] * (dinv[j] * b[j]); });
+    const T off = s0_offdiag<P, T>(g, n, i, wlo, [&](int64_t j) { return dinv[j] * b[j]; });
     const T xi = dinv[i] * b[i];
     x[i] = xi;
     r[i] = b[i] - (sdiag[i] * xi - off);
@@ -90,18 +143,18 @@ __global__ __launch_bounds__(BS) void s0_pre_kernel(Geo g, int64_t n, const T* _
 // z = x + dinv (b - S~ x), per-block partials of z (kind 1) or z b (kind 2)
 template <int P, typename T>
 __global__ __launch_bounds__(BS) void s0_post_kernel(Geo g, int64_t n, const T* __restrict__ sdiag,
-                                                     const T* __restrict__ wf, const T* __restrict__ dinv,
+                                                     const T* __restrict__ wlo, const T* __restrict__ dinv,
                                                      const T* __restrict__ b, const T* __restrict__ x,
                                                      T* __restrict__ z, double* __restrict__ part, int part_kind,
                                                      const int* __restrict__ done) {
     if (done && *done) return;
     double contrib = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
-        T off = 0;
-        for_each_coupling<P>(g, i, [&](int64_t k, int64_t j) { off += wf[k] * x[j]; });
+    const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+    if (i < n) {
+        const T off = s0_offdiag<P, T>(g, n, i, wlo, [&](int64_t j) { return x[j]; });
         const T zi = x[i] + dinv[i] * (b[i] - (sdiag[i] * x[i] - off));
         z[i] = zi;
-        contrib += part_kind == 1 ? (double)zi : (double)zi * (double)b[i];
+        contrib = part_kind == 1 ? (double)zi : (double)zi * (double)b[i];
     }
     if (part) {
         __shared__ double s[BS];
@@ -115,14 +168,45 @@ __global__ __launch_bounds__(BS) void s0_post_kernel(Geo g, int64_t n, const T* 
     }
 }
 
+// out[t] = sum of in[t q .. (t+1) q) (fixed order), t < nout: folds the
+// post-smoother's per-block partials to the RED_BLOCKS-sized set the solver
+// reduces.
+__global__ void fold_partials_kernel(int64_t nin, int64_t q, int64_t nout, const double* __restrict__ in,
+                                     double* __restrict__ out, const int* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nout) return;
+    double s = 0.0;
+    const int64_t e = (t + 1) * q < nin ? (t + 1) * q : nin;
+    for (int64_t k = t * q; k < e; ++k) s += in[k];
+    out[t] = s;
+}
+
 // Sub-wave CSR row products: a group of G lanes (G a power of two <= 64)
-// handles one row; the group sum is formed with cross-lane shuffles.
+// handles one row, each lane RU entries per pass, with all of a pass's index
+// and value loads issued before its gathers and products; the group sum is
+// formed with cross-lane shuffles.  Per lane the entries are summed in index
+// order.
+constexpr int RU = 4;
+
 template <int G, typename T, typename F>
 __device__ __forceinline__ T group_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                        const T* __restrict__ av, int64_t row, int lane, F&& xval) {
     T s = 0;
     const int32_t e = rp[row + 1];
-    for (int32_t k = rp[row] + lane; k < e; k += G) s += av[k] * xval(ci[k]);
+    for (int32_t k0 = rp[row] + lane; k0 < e; k0 += G * RU) {
+        int32_t cc[RU];
+        T vv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int32_t k = k0 + u * G;
+            cc[u] = k < e ? ci[k] : -1;
+            vv[u] = k < e ? av[k] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (cc[u] >= 0) s += vv[u] * xval(cc[u]);
+    }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
     return s;
@@ -269,11 +353,12 @@ T* pickw(double* d, float* f) {
     else return f;
 }
 
-// lanes per row for a CSR matrix: a power of two near its mean row length
+// lanes per row for a CSR matrix: the power of two for which one pass of RU
+// entries per lane covers at least three quarters of the mean row length
 inline int group_of(const DevCSR& m) {
     const double avg = m.nrows ? (double)m.nnz / (double)m.nrows : 1.0;
-    int g = 4;
-    while (g < 64 && 1.5 * g < avg) g *= 2;
+    int g = 1;
+    while (g < 64 && g * RU < 0.75 * avg) g *= 2;
     return g;
 }
 
@@ -281,6 +366,8 @@ inline unsigned gblk(int64_t rows, int g) { return (unsigned)((rows * g + BS - 1
 
 #define HD_GROUP_DISPATCH(g, KERNEL, ...)                                  \
     switch (g) {                                                           \
+        case 1: KERNEL(1, __VA_ARGS__); break;                             \
+        case 2: KERNEL(2, __VA_ARGS__); break;                             \
         case 4: KERNEL(4, __VA_ARGS__); break;                             \
         case 8: KERNEL(8, __VA_ARGS__); break;                             \
         case 16: KERNEL(16, __VA_ARGS__); break;                           \
@@ -312,9 +399,9 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
 #define POST(G, ...) hipLaunchKernelGGL((vc_post_kernel<G, T>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
     if (l == 0) {
         const T* sd = pick<T>(c->d_sdiag, c->d_sdiag32);
-        const T* wf = pick<T>(c->d_wface, c->d_wface32);
+        const T* wl = pick<T>(c->d_wlo, c->d_wlo32);
         const Geo g = geo_of(c);
-#define S0PRE(PP) hipLaunchKernelGGL((s0_pre_kernel<PP, T>), dim3(nblk(n)), dim3(BS), 0, c->stream, g, n, sd, wf, dinv, b, x, r, done)
+#define S0PRE(PP) hipLaunchKernelGGL((s0_pre_kernel<PP, T>), dim3(nblk(n)), dim3(BS), 0, c->stream, g, n, sd, wl, dinv, b, x, r, done)
         switch (c->p) {
             case 1: S0PRE(1); break;
             case 2: S0PRE(2); break;
@@ -333,9 +420,13 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
     HD_GROUP_DISPATCH(gP, PRO, n, lv.P.rp, lv.P.ci, pick<T>(lv.P.v, lv.P.v32), (const T*)zc, x, done)
     if (l == 0) {
         const T* sd = pick<T>(c->d_sdiag, c->d_sdiag32);
-        const T* wf = pick<T>(c->d_wface, c->d_wface32);
+        const T* wl = pick<T>(c->d_wlo, c->d_wlo32);
         const Geo g = geo_of(c);
-#define S0POST(PP) hipLaunchKernelGGL((s0_post_kernel<PP, T>), dim3(part ? red_grid(n) : nblk(n)), dim3(BS), 0, c->stream, g, n, sd, wf, dinv, b, (const T*)x, z, part, part_kind, done)
+        // one thread per row over the full grid; with more blocks than the
+        // solver's partial count, the block partials are folded afterwards
+        const bool fold = part && (int64_t)nblk(n) > (int64_t)red_grid(n);
+        double* bp = fold ? c->d_s0part : part;
+#define S0POST(PP) hipLaunchKernelGGL((s0_post_kernel<PP, T>), dim3(nblk(n)), dim3(BS), 0, c->stream, g, n, sd, wl, dinv, b, (const T*)x, z, bp, part_kind, done)
         switch (c->p) {
             case 1: S0POST(1); break;
             case 2: S0POST(2); break;
@@ -345,6 +436,11 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
             default: S0POST(6); break;
         }
 #undef S0POST
+        if (fold) {
+            const int64_t nin = nblk(n), nout = red_grid(n), q = (nin + nout - 1) / nout;
+            hipLaunchKernelGGL(fold_partials_kernel, dim3((unsigned)((nout + BS - 1) / BS)), dim3(BS), 0, c->stream,
+                               nin, q, nout, (const double*)c->d_s0part, part, done);
+        }
     } else {
         HD_GROUP_DISPATCH(gA, POST, n, lv.A.rp, lv.A.ci, av, dinv, b, (const T*)x, z, part, part_kind, done)
     }
@@ -495,6 +591,12 @@ void free_levels(hd_ctx* c) {
     c->lev.clear();
     dfree(c->d_cinv);
     c->d_cinv = nullptr;
+    dfree(c->d_wlo);
+    dfree(c->d_wlo32);
+    dfree(c->d_s0part);
+    c->d_wlo = nullptr;
+    c->d_wlo32 = nullptr;
+    c->d_s0part = nullptr;
 }
 
 int upload_amg(hd_ctx* c) {
@@ -553,6 +655,32 @@ int upload_amg(hd_ctx* c) {
         HD_HIP(c, hipMemcpyAsync(lv.dinv, d.data(), sizeof(double) * A.nrows, hipMemcpyHostToDevice, c->stream));
         HD_HIP(c, hipMemcpyAsync(lv.dinv32, d32.data(), sizeof(float) * A.nrows, hipMemcpyHostToDevice, c->stream));
         HD_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    {
+        // level-0 face weights by sub-volume, and the post-smoother's partials
+        const int64_t n = c->n_q;
+        c->d_wlo = dalloc<double>(3 * n);
+        c->d_wlo32 = dalloc<float>(3 * n);
+        c->d_s0part = dalloc<double>(nblk(n));
+        if (!c->d_wlo || !c->d_wlo32 || !c->d_s0part) return set_err(c, HD_ERR_OOM, "level-0 face weights");
+        const Geo g = geo_of(c);
+#define WLO(PP)                                                                                                   \
+    do {                                                                                                          \
+        hipLaunchKernelGGL((s0_wlo_kernel<PP, double>), dim3(nblk(n)), dim3(BS), 0, c->stream, g, n, c->d_wface, \
+                           c->d_wlo);                                                                             \
+        hipLaunchKernelGGL((s0_wlo_kernel<PP, float>), dim3(nblk(n)), dim3(BS), 0, c->stream, g, n, c->d_wface,  \
+                           c->d_wlo32);                                                                           \
+    } while (0)
+        switch (c->p) {
+            case 1: WLO(1); break;
+            case 2: WLO(2); break;
+            case 3: WLO(3); break;
+            case 4: WLO(4); break;
+            case 5: WLO(5); break;
+            default: WLO(6); break;
+        }
+#undef WLO
+        HD_HIP(c, hipGetLastError());
     }
     const int64_t nc = H.A.back().nrows;
     c->n_coarse = nc;
