@@ -2,7 +2,14 @@
 // saddle-point, Section 3):
 //
 //   y_u = M u + D^T q~            M by sum factorisation at the (p+1)^3
-//   y_q = D u - kappa_e W_e^{-1} q~   Gauss-Legendre points (partial assembly)
+//   y_q = D u - kappa_e W_e^{-1} q~   Gauss-Legendre points
+//
+// The geometric factors w J^T J / det J and w / det J at the quadrature points
+// are computed in the kernel from the element's 8 vertices (the map is
+// trilinear, so along a lane's quadrature column J is linear in zeta): the
+// apply streams x, y and the vertices instead of 7 (p+1)^3 stored factors
+// per element, and holds no factors in registers across the sum
+// factorisation.
 //
 // D is the +-1 sub-element incidence of the interpolation-histopolation basis
 // (Section 2.1), applied element by element as signed neighbour differences.
@@ -61,17 +68,18 @@ template <int P, typename T>
 struct ElemLDS {
     T su[Dim<P>::NRT];   // gathered RT coefficients (scaled, essential dofs zeroed)
     T sq[Dim<P>::NL];    // gathered L2 coefficients
-    T syq[Dim<P>::NL];   // L2 output
     T A1[Dim<P>::Q3];    // stage buffers
     T A2[Dim<P>::Q3];
+    T vx[24];            // element vertices X[dz][dy][dx][coordinate]
 };
 
 // ---------------------------------------------------------------------------
 // Local preconditioned CG for W_e x = rhs (Section 2.5): runs in the
 // Gauss-Legendre nodal basis; vectors live in x-pencil registers of the slot
 // (lane t < P^2 holds the x-line (., j, k), t = j + P k).  The right-hand
-// side enters as sq (IH basis) in LDS; the IH-basis solution times -kappa is
-// added into syq.  gw: w / det J at the quadrature points held as z-pencils
+// side enters as sq (IH basis) in LDS; the IH-basis solution times kappa is
+// left in A1 (L2 numbering).  gw: w / det J at the quadrature points held as
+// z-pencils
 // (lane t < Q^2 holds (a, b, .), t = a + Q b).  Every slot iterates until its
 // own residual meets the tolerance; the wavefront loops while any slot has
 // not converged.
@@ -183,7 +191,7 @@ __device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], i
         }
     }
     __syncthreads();
-    // IH-basis solution T^{-1} x: x (regs) -> y (LDS) -> z, syq -= kappa * sol
+    // IH-basis solution T^{-1} x: x (regs) -> y (LDS) -> z, A1 = kappa * sol
     if (t < P * P) {
         T o[P];
         pencil_mul<T, P, P, P, false>(x, o, Ti);
@@ -199,7 +207,7 @@ __device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], i
         using G = PencilGeom<P, P, P, 2>;
         const int b = G::base(t);
 #pragma unroll
-        for (int s = 0; s < P; ++s) L.syq[b + s * G::STRIDE] -= kE * o[s];
+        for (int s = 0; s < P; ++s) L.A1[b + s * G::STRIDE] = kE * o[s];
     }
     __syncthreads();
 #undef Ti
@@ -422,7 +430,8 @@ struct RhsArgs {
 // x and y point at one right-hand side's vector; the return value is the
 // group's <A x, x> contribution summed over the wavefront (all lanes).
 template <int P, typename T, bool HAS_C = true>
-__device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, const T* __restrict__ pa, tkp<P, T> tb,
+__device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, const double* __restrict__ vert,
+                                              tkp<P, T> tb,
                                               const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
                                               int ess_mode, int64_t n_u, const T* __restrict__ x, T* __restrict__ y,
                                               T s_in, const CGParams<T>& cgp, int with_c, int colour, unsigned grp,
@@ -445,52 +454,77 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     ElemLDS<P, T>& L = sm[slot];
     const T cM = cm[ee];
     const T kE = kap[ee];
-    // the lane's geometric factors, issued first so that they are in flight
-    // during the gather and the forward sum factorisation
-    // (w / det J, the seventh factor, only feeds the local CG)
-    constexpr int NG = HAS_C ? NPA : NPA - 1;
-    T G[NPA][Q];
-    {
-        const T* pe = pa + (size_t)ee * NPA * Q3 + (t < Q * Q ? t : 0);
-#pragma unroll
-        for (int m = 0; m < NG; ++m)
-#pragma unroll
-            for (int c = 0; c < Q; ++c) G[m][c] = pe[m * Q3 + Q * Q * c];
-    }
     __syncthreads();
-    // gather u (essential dofs read as zero) and q~
+    // gather u (essential dofs read as zero), q~ and the element's vertices
     if (valid) {
+        for (int l = t; l < 24; l += W) {
+            const int v = l / 3, r = l % 3;
+            const int dx = v & 1, dy = (v >> 1) & 1, dz = v >> 2;
+            L.vx[l] = (T)vert[3 * ((ex + dx) + (int64_t)(g.nx + 1) * ((ey + dy) + (int64_t)(g.ny + 1) * (ez + dz))) + r];
+        }
         gather_rt<P, T, 0>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
         gather_rt<P, T, 1>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
         gather_rt<P, T, 2>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
         for (int l = t; l < NL; l += W) L.sq[l] = s_in * x[n_u + ee * NL + l];
     }
     __syncthreads();
-    // D u (element-local, +1 upper face, -1 lower face)
-    if (valid) {
-        for (int l = t; l < NL; l += W) {
-            const int a = l % P, b = (l / P) % P, c = l / (P * P);
-            T v = L.su[(a + 1) + (P + 1) * (b + P * c)] - L.su[a + (P + 1) * (b + P * c)];
-            v += L.su[NC + a + P * ((b + 1) + (P + 1) * c)] - L.su[NC + a + P * (b + (P + 1) * c)];
-            v += L.su[2 * NC + a + P * (b + P * (c + 1))] - L.su[2 * NC + a + P * (b + P * c)];
-            L.syq[l] = v;
-        }
-    }
     // M u: the three components to the quadrature points
     T U0[Q], U1[Q], U2[Q];
     rt_to_quad<P, T, 0>(L, tb, t, U0);
     rt_to_quad<P, T, 1>(L, tb, t, U1);
     rt_to_quad<P, T, 2>(L, tb, t, U2);
-    // c_mass w J^T J / det J at the quadrature column (a, b, .)
+    // c_mass w J^T J / det J at the quadrature column (a, b, .), from the
+    // trilinear map: dx/dxi and dx/deta are linear in zeta, dx/dzeta is
+    // constant along the column
     T gw[Q];
     if (t < Q * Q) {
+        const int qa = t % Q, qb = t / Q;
+        const T xa = tb->xq[qa], xb = tb->xq[qb];
+        const T nx[2] = {T(1) - xa, xa}, ny[2] = {T(1) - xb, xb};
+        const T* X = L.vx;
+        T A[2][3], B[2][3], C[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int dz = 0; dz < 2; ++dz) {
+                A[dz][r] = (X[((dz * 2 + 0) * 2 + 1) * 3 + r] - X[((dz * 2 + 0) * 2 + 0) * 3 + r]) * ny[0] +
+                           (X[((dz * 2 + 1) * 2 + 1) * 3 + r] - X[((dz * 2 + 1) * 2 + 0) * 3 + r]) * ny[1];
+                B[dz][r] = (X[((dz * 2 + 1) * 2 + 0) * 3 + r] - X[((dz * 2 + 0) * 2 + 0) * 3 + r]) * nx[0] +
+                           (X[((dz * 2 + 1) * 2 + 1) * 3 + r] - X[((dz * 2 + 0) * 2 + 1) * 3 + r]) * nx[1];
+            }
+            T cz = 0;
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx)
+                    cz += (X[((2 + dy) * 2 + dx) * 3 + r] - X[(dy * 2 + dx) * 3 + r]) * nx[dx] * ny[dy];
+            C[r] = cz;
+        }
+        const T wab = tb->wq[qa] * tb->wq[qb];
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
+            const T z1 = tb->xq[c], z0 = T(1) - z1;
+            T J0[3], J1[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                J0[r] = A[0][r] * z0 + A[1][r] * z1;
+                J1[r] = B[0][r] * z0 + B[1][r] * z1;
+            }
+            // det J = J0 . (J1 x C), columns of J = d x / d (xi, eta, zeta)
+            const T det = J0[0] * (J1[1] * C[2] - J1[2] * C[1]) - J0[1] * (J1[0] * C[2] - J1[2] * C[0]) +
+                          J0[2] * (J1[0] * C[1] - J1[1] * C[0]);
+            const T s = wab * tb->wq[c] / det;
+            const T g00 = s * (J0[0] * J0[0] + J0[1] * J0[1] + J0[2] * J0[2]);
+            const T g01 = s * (J0[0] * J1[0] + J0[1] * J1[1] + J0[2] * J1[2]);
+            const T g02 = s * (J0[0] * C[0] + J0[1] * C[1] + J0[2] * C[2]);
+            const T g11 = s * (J1[0] * J1[0] + J1[1] * J1[1] + J1[2] * J1[2]);
+            const T g12 = s * (J1[0] * C[0] + J1[1] * C[1] + J1[2] * C[2]);
+            const T g22 = s * (C[0] * C[0] + C[1] * C[1] + C[2] * C[2]);
             const T a0 = U0[c], a1 = U1[c], a2 = U2[c];
-            U0[c] = cM * (G[0][c] * a0 + G[1][c] * a1 + G[2][c] * a2);
-            U1[c] = cM * (G[1][c] * a0 + G[3][c] * a1 + G[4][c] * a2);
-            U2[c] = cM * (G[2][c] * a0 + G[4][c] * a1 + G[5][c] * a2);
-            gw[c] = HAS_C ? G[NG - 1][c] : T(1);
+            U0[c] = cM * (g00 * a0 + g01 * a1 + g02 * a2);
+            U1[c] = cM * (g01 * a0 + g11 * a1 + g12 * a2);
+            U2[c] = cM * (g02 * a0 + g12 * a1 + g22 * a2);
+            gw[c] = HAS_C ? s : T(1);
         }
     } else {
 #pragma unroll
@@ -516,9 +550,15 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
         if (with_c) local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
     }
     __syncthreads();
+    // y_q = D u (element-local, +1 upper face, -1 lower face) - kappa W^{-1} q~
     if (valid) {
+        const bool cg = HAS_C && with_c && kE != T(0);
         for (int l = t; l < NL; l += W) {
-            const T v = L.syq[l];
+            const int a = l % P, b = (l / P) % P, c = l / (P * P);
+            T v = L.su[(a + 1) + (P + 1) * (b + P * c)] - L.su[a + (P + 1) * (b + P * c)];
+            v += L.su[NC + a + P * ((b + 1) + (P + 1) * c)] - L.su[NC + a + P * (b + (P + 1) * c)];
+            v += L.su[2 * NC + a + P * (b + P * (c + 1))] - L.su[2 * NC + a + P * (b + P * c)];
+            if (cg) v -= L.A1[l];
             y[n_u + ee * NL + l] = v;
             dot += (double)v * (double)L.sq[l];
         }
@@ -538,8 +578,8 @@ __device__ __forceinline__ unsigned xcd_chunk(unsigned b, unsigned n) {
 
 template <int P, typename T, bool HAS_C>
 __global__ __launch_bounds__(64) void block_apply_kernel(
-    Geo g, const T* __restrict__ pa, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
-    int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
+    Geo g, const double* __restrict__ vert, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap,
+    uint32_t ess, int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
     CGParams<T> cgp, int with_c, int colour, int64_t part_offset, unsigned nb) {
     // Block -> (element group, right-hand side).  With several right-hand
     // sides, the blocks of one element group are spaced 8 apart, so that they
@@ -558,7 +598,7 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;   // uniform over the block
     __shared__ ElemLDS<P, T> sm[Slot<P>::EPW];
     const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
-    const double dot = apply_group<P, T, HAS_C>(sm, g, pa, tb, cm, kap, ess, ess_mode, n_u, xall + r * ra.ldv,
+    const double dot = apply_group<P, T, HAS_C>(sm, g, vert, tb, cm, kap, ess, ess_mode, n_u, xall + r * ra.ldv,
                                                 yall + r * ra.ldv, s_in, cgp, with_c, colour, grp, nb);
     if (ra.partial && grp < nb && threadIdx.x == 0) ra.partial[r * ra.part_stride + part_offset + grp] = dot;
 }
@@ -587,7 +627,7 @@ __device__ __attribute__((noinline)) double batch_group(void* smem, const BatchI
     const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tv);
     const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(tv >> 32));
     const tkp<P, T> tb = (tkp<P, T>)(lo | (hi << 32));
-    return apply_group<P, T>((ElemLDS<P, T>*)smem, I.g, (const T*)I.pa, tb, (const T*)I.cm, (const T*)I.kap, I.ess,
+    return apply_group<P, T>((ElemLDS<P, T>*)smem, I.g, I.vert, tb, (const T*)I.cm, (const T*)I.kap, I.ess,
                              ess_mode, I.n_u, x, y, s_in, cgp, I.with_c, colour, grp, I.nb);
 }
 
@@ -655,7 +695,7 @@ __global__ __launch_bounds__(64) void batch_apply_deg_kernel(const BatchInstDev*
         const T s_in = scale ? (T)scale[(int64_t)tl.inst * scale_stride] : T(1);
         for (unsigned k = 0; k < tl.ngrp; ++k) {
             const unsigned grp = tl.grp0 + k;
-            const double dot = apply_group<P, T>(sm, I.g, (const T*)I.pa, (tkp<P, T>)I.tabk, (const T*)I.cm,
+            const double dot = apply_group<P, T>(sm, I.g, I.vert, (tkp<P, T>)I.tabk, (const T*)I.cm,
                                                  (const T*)I.kap, I.ess, ess_mode, I.n_u, x + I.off, y + I.off, s_in,
                                                  cgp, I.with_c, colour, grp, I.nb);
             if (partials && threadIdx.x == 0 && grp < I.nb) I.part[(int64_t)colour * I.nb + grp] = dot;
@@ -687,20 +727,17 @@ __global__ __launch_bounds__(64) void mass_inverse_kernel(const T* __restrict__ 
     const int64_t ee = valid ? e : ne - 1;
     ElemLDS<P, T>& L = sm[slot];
     if (valid)
-        for (int l = t; l < NL; l += W) {
-            L.sq[l] = x[ee * NL + l];
-            L.syq[l] = T(0);
-        }
+        for (int l = t; l < NL; l += W) L.sq[l] = x[ee * NL + l];
     T gw[Q];
     const T* pe = pa + (size_t)ee * NPA * Q3;
 #pragma unroll
     for (int c = 0; c < Q; ++c) gw[c] = t < Q * Q ? pe[6 * Q3 + t + Q * Q * c] : T(1);
     __syncthreads();
-    // syq = -(1) * W^{-1} sq  -> negate on output
+    // A1 = W^{-1} sq
     local_cg<P, T>(L, tb, gw, t, valid, T(1), cgp);
     const T s = weighted ? kap[ee] : T(1);
     if (valid)
-        for (int l = t; l < NL; l += W) y[ee * NL + l] = -s * L.syq[l];
+        for (int l = t; l < NL; l += W) y[ee * NL + l] = s * L.A1[l];
 }
 
 // blocks per colour: half-rows of ceil(nx / 2) elements, EPW elements per block
@@ -737,7 +774,6 @@ CGParams<float> cg_params<float>() { return {1e-6f, 32}; }
 template <int P, typename T>
 void launch_apply_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int ess_mode) {
     Geo g = geo_of(c);
-    const T* pa = std::is_same<T, double>::value ? (const T*)c->d_pa : (const T*)c->d_pa32;
     const T* cm = std::is_same<T, double>::value ? (const T*)c->d_cm : (const T*)c->d_cm32;
     const T* kap = std::is_same<T, double>::value ? (const T*)c->d_kap : (const T*)c->d_kap32;
     const tkp<P, T> tb = (tkp<P, T>)(std::is_same<T, double>::value ? c->d_tabk64 : c->d_tabk32);
@@ -747,11 +783,13 @@ void launch_apply_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int ess_mode
     const unsigned grid = ra.nrhs > 1 ? (unsigned)(((nb + 7) / 8) * 8 * (uint64_t)ra.nrhs) : nb;
     for (int colour = 0; colour < 2; ++colour) {
         if (!c->kappa_zero)
-            hipLaunchKernelGGL((block_apply_kernel<P, T, true>), dim3(grid), dim3(64), 0, c->stream, g, pa, tb, cm,
+            hipLaunchKernelGGL((block_apply_kernel<P, T, true>), dim3(grid), dim3(64), 0, c->stream, g, c->d_vert, tb,
+                               cm,
                                kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 1, colour,
                                (int64_t)colour * nb, nb);
         else
-            hipLaunchKernelGGL((block_apply_kernel<P, T, false>), dim3(grid), dim3(64), 0, c->stream, g, pa, tb, cm,
+            hipLaunchKernelGGL((block_apply_kernel<P, T, false>), dim3(grid), dim3(64), 0, c->stream, g, c->d_vert, tb,
+                               cm,
                                kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 0, colour,
                                (int64_t)colour * nb, nb);
     }
@@ -958,11 +996,11 @@ int batch_build_tiles(hd_ctx* c, int tile_groups) {
         a.off = B.off[i];
         a.part = B.d_part + B.part_off[i];
         BatchInstDev b = a;
-        a.pa = s->d_pa;
+        a.vert = s->d_vert;
         a.cm = s->d_cm;
         a.kap = s->d_kap;
         a.tabk = s->d_tabk64;
-        b.pa = s->d_pa32;
+        b.vert = s->d_vert;
         b.cm = s->d_cm32;
         b.kap = s->d_kap32;
         b.tabk = s->d_tabk32;

@@ -96,7 +96,7 @@ struct BatchInstDev {
     unsigned nb = 0;          // element groups per colour
     int64_t n_u = 0;
     int64_t off = 0;          // offset of the instance's [u; q] in the concatenated vector
-    const void* pa = nullptr; // geometric factors, kernel-precision
+    const double* vert = nullptr; // mesh vertices (the apply computes the geometry from them)
     const void* cm = nullptr;
     const void* kap = nullptr;
     const void* tabk = nullptr;

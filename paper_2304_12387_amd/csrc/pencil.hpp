@@ -22,6 +22,8 @@ struct TabK {
     T Bg[Q][P];        // Gauss-Legendre nodal basis at x_a
     T Bg2[Q][P];       // Bg^2
     T Ti[P][P];        // inverse change of basis IH -> GL nodal
+    T xq[Q];           // Gauss-Legendre points on [0, 1]
+    T wq[Q];           // and weights
 };
 
 template <int P, typename T>
@@ -37,6 +39,10 @@ TabK<P, T> make_tabk(const Tables<T>& t) {
     }
     for (int r = 0; r < P; ++r)
         for (int c = 0; c < P; ++c) k.Ti[r][c] = t.Tinv[r][c];
+    for (int a = 0; a <= P; ++a) {
+        k.xq[a] = t.xq[a];
+        k.wq[a] = t.wq[a];
+    }
     return k;
 }
 
