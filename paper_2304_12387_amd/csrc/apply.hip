@@ -499,8 +499,12 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
                 for (int dx = 0; dx < 2; ++dx)
                     cz += (X[((2 + dy) * 2 + dx) * 3 + r] - X[(dy * 2 + dx) * 3 + r]) * nx[dx] * ny[dy];
             C[r] = cz;
+            __builtin_amdgcn_sched_barrier(0);   // one coordinate's 8 vertex values live at a time
         }
         const T wab = tb->wq[qa] * tb->wq[qb];
+        // one quadrature point at a time: keeps the scheduler from computing
+        // every point's factors at once (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int c = 0; c < Q; ++c) {
             const T z1 = tb->xq[c], z0 = T(1) - z1;
@@ -525,6 +529,7 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
             U1[c] = cM * (g01 * a0 + g11 * a1 + g12 * a2);
             U2[c] = cM * (g02 * a0 + g12 * a1 + g22 * a2);
             gw[c] = HAS_C ? s : T(1);
+            __builtin_amdgcn_sched_barrier(0);
         }
     } else {
 #pragma unroll
