@@ -117,6 +117,18 @@ hd_precond_params default_precond() {
 
 }  // namespace
 
+namespace hd {
+namespace {
+// Deterministic input in [-1, 1) for the tuner's timing applies (a zero
+// input would end every local CG at once and time the mass part only).
+template <typename T>
+__global__ void tune_pattern_kernel(T* __restrict__ x, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) x[i] = (T)((double)((uint32_t)(i * 2654435761u) >> 8) * (1.0 / 8388608.0) - 1.0);
+}
+}  // namespace
+}  // namespace hd
+
 extern "C" {
 
 int hd_create(hd_ctx** out, int device, void* stream) {
@@ -612,7 +624,14 @@ int hd_batch_tune(hd_ctx* c, int prec, int* mode, int* grid, int* tile_groups, d
         dfree(x);
         return set_err(c, HD_ERR_OOM, "tuning vectors");
     }
-    HD_HIP(c, hipMemsetAsync(x, 0, es * B.total, c->stream));
+    {
+        const unsigned nbk = (unsigned)((B.total + 255) / 256);
+        if (prec == HD_F64)
+            hipLaunchKernelGGL(hd::tune_pattern_kernel<double>, dim3(nbk), dim3(256), 0, c->stream, (double*)x, B.total);
+        else
+            hipLaunchKernelGGL(hd::tune_pattern_kernel<float>, dim3(nbk), dim3(256), 0, c->stream, (float*)x, B.total);
+        HD_HIP(c, hipGetLastError());
+    }
     const int modes[2] = {0, 1}, groups[4] = {1, 2, 4, 8}, grids[4] = {512, 1024, 2048, 4096};
     double best = 1e300;
     int bm = 0, bg = 1, bgrid = 2048;
