@@ -11,7 +11,12 @@ One step = NAPPLY back-to-back FP64 block applies (HIP events on the
 library's stream bracket them), one plain FP64 MINRES solve to a true
 relative residual of 1e-8 and one mixed-precision solve to the same true FP64
 residual.  `value` is the apply throughput over the timed region:
-(n_u + n_q) * applies / apply time.
+(n_u + n_q) * applies / apply time.  `roofline.achieved` divides the
+fixed-layout byte count of one launch (x and y, seven stored geometric
+factors per quadrature point, two coefficients per element; half of the
+elements per launch) by the event-timed launch; the kernel computes the
+factors from the element vertices, so its measured HBM traffic
+(`roofline.traffic`, from the committed counter summary) is lower.
 
 Other workloads (`--workload`, one JSON line each, no CPU baseline):
   darcy_layered  60 x 220 x 85 cells, p = 2, layered log-normal permeability,
@@ -20,6 +25,8 @@ Other workloads (`--workload`, one JSON line each, no CPU baseline):
   batch32        32 independent grad-div instances (n^3, n in 8..40, p in
                  1..6): autotuned persistent batched apply, FP64 and FP32.
   multirhs64     grad-div 64^3, p = 3, 16 right-hand sides: FP32 apply.
+  local_inverse  grad-div on a 96^3 refined grid at p = 1, 2, 3: FP64 apply with
+                 explicit element inverses of W_e (p <= 2) against the local CG.
   distorted48    grad-div 48^3, p = 4 on a graded, sheared mesh: MINRES with
                  the plain and with the learned (1,1) diagonal (network
                  trained on GPU-generated targets first).
@@ -314,6 +321,43 @@ def run_multirhs64(args, torch, hdivsp, inputs):
     return out
 
 
+def run_local_inverse(args, torch, hdivsp, inputs):
+    """FP64 grad-div apply on the same 96^3 refined grid at p = 1, 2, 3
+    (96, 48, 32 elements per side): explicit element inverses of W_e against
+    the local CG in the (2,2) block (explicit only for p <= 2)."""
+    dev = torch.device('cuda', 0)
+    stream = torch.cuda.current_stream(dev)
+    rows = {}
+    ts = time.perf_counter()
+    for p in (1, 2, 3):
+        cfg = inputs.graddiv_jittered(96 // p, p)
+        ctx = hdivsp.Context(0, stream)
+        ctx.setup_mesh(cfg['nx'], cfg['ny'], cfg['nz'], cfg['p'], cfg['vertices'])
+        ctx.setup_coeffs(cfg['problem'], cfg['c_mass'], cfg['c_22'], cfg['ess_sides'])
+        nu, nq = ctx.sizes()
+        N = nu + nq
+        x = torch.from_numpy(inputs.uniform_vector(N, 32)).to(dev)
+        y = torch.empty_like(x)
+        row = {"n": cfg['nx'], "dofs": N}
+        modes = [('cg', hdivsp.HD_LOCAL_CG)] + ([('explicit', hdivsp.HD_LOCAL_EXPLICIT)] if p <= 2 else [])
+        for name, mode in modes:
+            ctx.set_local_solver(mode)
+            ms = time_applies(torch, stream, lambda: ctx.apply_block_op(x, y), NAPPLY)
+            row[name + "_gdofs"] = round(N / (ms * 1e-3) / 1e9, 3)
+            row[name + "_us_per_apply"] = round(ms * 1e3, 1)
+        if p <= 2:
+            row["explicit_speedup"] = round(row["cg_us_per_apply"] / row["explicit_us_per_apply"], 3)
+        rows[f"p{p}"] = row
+        del x, y
+        ctx.close()
+    te = time.perf_counter()
+    out = base_line("GDOF/s of the FP64 grad-div apply at p = 2 with explicit element inverses (local CG beside it)",
+                    rows['p2']['explicit_gdofs'], "GDOF/s", args, round((te - ts) * 1e3, 3),
+                    {"workload": "graddiv_jittered_96^3_subvolumes_p1-3", "refined_grid": 96})
+    out["local_inverse"] = rows
+    return out
+
+
 def run_distorted48(args, torch, hdivsp, inputs):
     from paper_2304_12387_amd import learned as driver
     dev = torch.device('cuda', 0)
@@ -369,7 +413,7 @@ def run_distorted48(args, torch, hdivsp, inputs):
 
 
 WORKLOADS = {'graddiv32': run_default, 'darcy_layered': run_darcy_layered, 'batch32': run_batch32,
-             'multirhs64': run_multirhs64, 'distorted48': run_distorted48}
+             'multirhs64': run_multirhs64, 'distorted48': run_distorted48, 'local_inverse': run_local_inverse}
 
 
 def main():

@@ -156,8 +156,26 @@ int hd_sizes(const hd_ctx* ctx, int64_t* n_u, int64_t* n_q);
  * pointers of length nrhs*(n_u+n_q).  Essential convention as above.
  * Matrix-free: M by sum factorisation at the quadrature points, D and D^T
  * by the +-1 sub-element incidence, C by a per-element preconditioned CG in
- * the Gauss-Legendre basis (Section 2.5, Section 3.1). */
+ * the Gauss-Legendre basis (Section 2.5, Section 3.1) or, for p <= 2, by
+ * stored explicit element inverses (hd_set_local_solver). */
 int hd_apply_block_op(hd_ctx* ctx, int prec, int nrhs, const void* x, void* y);
+
+/* How the block apply, and everything built on it, applies W_e^{-1} in the
+ * (2,2) block (Section 4, GPU acceleration of the DG mass inverse: explicit
+ * inverses applied by a batched matrix-vector product for small degrees,
+ * matrix-free local CG otherwise).
+ *   HD_LOCAL_AUTO      explicit inverses for p <= 2, local CG for p >= 3
+ *                      (the default);
+ *   HD_LOCAL_CG        local CG for every degree;
+ *   HD_LOCAL_EXPLICIT  explicit inverses (p <= 2 only, HD_ERR_ARG otherwise).
+ * The inverses (p^3 x p^3 per element, FP64 with an FP32 copy, inverted in
+ * FP64 by Gauss-Jordan elimination on the SPD element matrix) are built when
+ * coefficients with a nonzero (2,2) block are set, or by this call if they
+ * already are; the stand-alone hd_apply_mass_inverse keeps the local CG.
+ * May be called before or after hd_setup_coeffs; HD_ERR_OOM if the inverses
+ * do not fit. */
+enum { HD_LOCAL_AUTO = 0, HD_LOCAL_CG = 1, HD_LOCAL_EXPLICIT = 2 };
+int hd_set_local_solver(hd_ctx* ctx, int mode);
 
 /* y_q = C x_q = kappa_e W_e^{-1} x_q per element (the (2,2) block without
  * its sign), for nrhs L2 vectors of length n_q stored one after the other.  For HD_DARCY with gamma = 0 use
@@ -194,6 +212,9 @@ int hd_apply_precond(hd_ctx* ctx, int prec, int nrhs, const void* r, void* z);
  * error code otherwise. */
 int hd_minres_solve(hd_ctx* ctx, const hd_solve_params* params, int nrhs,
                     const double* b, double* x, hd_solve_info* info);
+/* The solver's work space (Krylov vectors, partial sums, pinned state) stays
+ * allocated in the context between calls and is rebuilt when the sizes,
+ * the precision mode or nrhs change; hd_destroy releases it. */
 
 /* ---- batches of independent instances ----------------------------------
  * Many independent problems of different sizes and degrees handled together

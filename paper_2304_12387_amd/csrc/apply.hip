@@ -44,12 +44,13 @@ struct CGParams {
     int maxit;
 };
 
-// Lanes per element: the largest pencil count of any stage is (p+1)^2; a
-// wavefront holds 64 / W elements.
+// Lanes per element: the largest pencil count of any stage is (p+1)^2, so W
+// is the smallest power of two >= (p+1)^2 (4 at p = 1, 16 at p = 2 and 3, 32
+// at p = 4 and 5, 64 at p = 6); a wavefront holds 64 / W elements.
 template <int P>
 struct Slot {
     static constexpr int Q = P + 1;
-    static constexpr int W = Q * Q <= 16 ? 16 : (Q * Q <= 32 ? 32 : 64);
+    static constexpr int W = Q * Q <= 4 ? 4 : (Q * Q <= 8 ? 8 : (Q * Q <= 16 ? 16 : (Q * Q <= 32 ? 32 : 64)));
     static constexpr int EPW = 64 / W;
 };
 
@@ -435,7 +436,7 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
                                               const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
                                               int ess_mode, int64_t n_u, const T* __restrict__ x, T* __restrict__ y,
                                               T s_in, const CGParams<T>& cgp, int with_c, int colour, unsigned grp,
-                                              unsigned nb) {
+                                              unsigned nb, const T* __restrict__ winv) {
     using D = Dim<P>;
     using S = Slot<P>;
     constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC, W = S::W;
@@ -552,7 +553,28 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     // -kappa_e W_e^{-1} q~ (compiled out of the variant for a zero (2,2) block,
     // which then needs fewer registers and runs more wavefronts per SIMD)
     if constexpr (HAS_C) {
-        if (with_c) local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
+        if (with_c) {
+            if constexpr (P <= 2) {
+                // explicit element inverse (uniform choice for the launch):
+                // A1 = kappa W_e^{-1} q~, row l of the inverse per lane
+                if (winv) {
+                    __syncthreads();
+                    if (valid && kE != T(0))
+                        for (int l = t; l < NL; l += W) {
+                            const T* wr = winv + ((size_t)ee * NL + l) * NL;
+                            T s = 0;
+#pragma unroll
+                            for (int k = 0; k < NL; ++k) s += wr[k] * L.sq[k];
+                            L.A1[l] = kE * s;
+                        }
+                    __syncthreads();
+                } else {
+                    local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
+                }
+            } else {
+                local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
+            }
+        }
     }
     __syncthreads();
     // y_q = D u (element-local, +1 upper face, -1 lower face) - kappa W^{-1} q~
@@ -585,7 +607,7 @@ template <int P, typename T, bool HAS_C>
 __global__ __launch_bounds__(64) void block_apply_kernel(
     Geo g, const double* __restrict__ vert, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap,
     uint32_t ess, int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
-    CGParams<T> cgp, int with_c, int colour, int64_t part_offset, unsigned nb) {
+    CGParams<T> cgp, int with_c, int colour, int64_t part_offset, unsigned nb, const T* __restrict__ winv) {
     // Block -> (element group, right-hand side).  With several right-hand
     // sides, the blocks of one element group are spaced 8 apart, so that they
     // run on the same XCD (blocks are dealt to the 8 XCDs round-robin) at
@@ -604,7 +626,7 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     __shared__ ElemLDS<P, T> sm[Slot<P>::EPW];
     const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
     const double dot = apply_group<P, T, HAS_C>(sm, g, vert, tb, cm, kap, ess, ess_mode, n_u, xall + r * ra.ldv,
-                                                yall + r * ra.ldv, s_in, cgp, with_c, colour, grp, nb);
+                                                yall + r * ra.ldv, s_in, cgp, with_c, colour, grp, nb, winv);
     if (ra.partial && grp < nb && threadIdx.x == 0) ra.partial[r * ra.part_stride + part_offset + grp] = dot;
 }
 
@@ -633,7 +655,7 @@ __device__ __attribute__((noinline)) double batch_group(void* smem, const BatchI
     const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(tv >> 32));
     const tkp<P, T> tb = (tkp<P, T>)(lo | (hi << 32));
     return apply_group<P, T>((ElemLDS<P, T>*)smem, I.g, I.vert, tb, (const T*)I.cm, (const T*)I.kap, I.ess,
-                             ess_mode, I.n_u, x, y, s_in, cgp, I.with_c, colour, grp, I.nb);
+                             ess_mode, I.n_u, x, y, s_in, cgp, I.with_c, colour, grp, I.nb, (const T*)I.winv);
 }
 
 // Persistent apply over all instances: each workgroup (one wavefront) takes
@@ -702,7 +724,7 @@ __global__ __launch_bounds__(64) void batch_apply_deg_kernel(const BatchInstDev*
             const unsigned grp = tl.grp0 + k;
             const double dot = apply_group<P, T>(sm, I.g, I.vert, (tkp<P, T>)I.tabk, (const T*)I.cm,
                                                  (const T*)I.kap, I.ess, ess_mode, I.n_u, x + I.off, y + I.off, s_in,
-                                                 cgp, I.with_c, colour, grp, I.nb);
+                                                 cgp, I.with_c, colour, grp, I.nb, (const T*)I.winv);
             if (partials && threadIdx.x == 0 && grp < I.nb) I.part[(int64_t)colour * I.nb + grp] = dot;
         }
     }
@@ -743,6 +765,61 @@ __global__ __launch_bounds__(64) void mass_inverse_kernel(const T* __restrict__ 
     const T s = weighted ? kap[ee] : T(1);
     if (valid)
         for (int l = t; l < NL; l += W) y[ee * NL + l] = s * L.A1[l];
+}
+
+// W_e in the interpolation-histopolation basis and its inverse, one thread
+// per element (p <= 2: at most 8 x 8):
+//   W_e[i][j] = sum_q (w / det J)_q psi_i(x_q) psi_j(x_q),
+// psi_(i0 i1 i2) = h_i0 h_i1 h_i2 at the (p+1)^3 Gauss-Legendre points, the
+// quadrature the local CG and the stored factors use; inverted in place by
+// Gauss-Jordan elimination (symmetric positive definite, no pivoting).
+template <int P>
+__global__ void local_inverse_kernel(int64_t ne, const double* __restrict__ pa, const Tables<double>* __restrict__ tab,
+                                     double* __restrict__ winv, float* __restrict__ winv32) {
+    constexpr int Q = P + 1, Q3 = Q * Q * Q, NL = P * P * P;
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const double* gw = pa + (size_t)e * NPA * Q3 + 6 * Q3;
+    double A[NL][NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+#pragma unroll
+        for (int j = 0; j < NL; ++j) A[i][j] = 0.0;
+    for (int q = 0; q < Q3; ++q) {
+        const int a = q % Q, b = (q / Q) % Q, c = q / (Q * Q);
+        double psi[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) psi[i] = tab->H[a][i % P] * tab->H[b][(i / P) % P] * tab->H[c][i / (P * P)];
+        const double g = gw[q];
+#pragma unroll
+        for (int i = 0; i < NL; ++i)
+#pragma unroll
+            for (int j = 0; j < NL; ++j) A[i][j] += g * psi[i] * psi[j];
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const double pk = 1.0 / A[k][k];
+        A[k][k] = 1.0;
+#pragma unroll
+        for (int j = 0; j < NL; ++j) A[k][j] *= pk;
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            if (i == k) continue;
+            const double f = A[i][k];
+            A[i][k] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NL; ++j) A[i][j] -= f * A[k][j];
+        }
+    }
+    double* o = winv + (size_t)e * NL * NL;
+    float* o32 = winv32 + (size_t)e * NL * NL;
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+            o[i * NL + j] = A[i][j];
+            o32[i * NL + j] = (float)A[i][j];
+        }
 }
 
 // blocks per colour: half-rows of ceil(nx / 2) elements, EPW elements per block
@@ -786,17 +863,18 @@ void launch_apply_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int ess_mode
     // several right-hand sides: element groups rounded up to a multiple of 8
     // (the XCD count), one block per (group, right-hand side)
     const unsigned grid = ra.nrhs > 1 ? (unsigned)(((nb + 7) / 8) * 8 * (uint64_t)ra.nrhs) : nb;
+    const T* winv = std::is_same<T, double>::value ? (const T*)c->d_winv : (const T*)c->d_winv32;
     for (int colour = 0; colour < 2; ++colour) {
         if (!c->kappa_zero)
             hipLaunchKernelGGL((block_apply_kernel<P, T, true>), dim3(grid), dim3(64), 0, c->stream, g, c->d_vert, tb,
                                cm,
                                kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 1, colour,
-                               (int64_t)colour * nb, nb);
+                               (int64_t)colour * nb, nb, winv);
         else
             hipLaunchKernelGGL((block_apply_kernel<P, T, false>), dim3(grid), dim3(64), 0, c->stream, g, c->d_vert, tb,
                                cm,
                                kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 0, colour,
-                               (int64_t)colour * nb, nb);
+                               (int64_t)colour * nb, nb, (const T*)nullptr);
     }
 }
 
@@ -1002,10 +1080,12 @@ int batch_build_tiles(hd_ctx* c, int tile_groups) {
         a.part = B.d_part + B.part_off[i];
         BatchInstDev b = a;
         a.vert = s->d_vert;
+        a.winv = s->d_winv;
         a.cm = s->d_cm;
         a.kap = s->d_kap;
         a.tabk = s->d_tabk64;
         b.vert = s->d_vert;
+        b.winv = s->d_winv32;
         b.cm = s->d_cm32;
         b.kap = s->d_kap32;
         b.tabk = s->d_tabk32;
@@ -1040,6 +1120,35 @@ int batch_build_tiles(hd_ctx* c, int tile_groups) {
     HD_HIP(c, hipStreamSynchronize(c->stream));
     B.ntiles = (int)tiles.size();
     B.tile_groups = tile_groups;
+    return HD_OK;
+}
+
+void free_local_inverse(hd_ctx* c) {
+    dfree(c->d_winv);
+    dfree(c->d_winv32);
+    c->d_winv = nullptr;
+    c->d_winv32 = nullptr;
+}
+
+int build_local_inverse(hd_ctx* c) {
+    free_local_inverse(c);
+    const bool want = c->p <= 2 && !c->kappa_zero && c->local_solver != HD_LOCAL_CG;
+    if (!want) return HD_OK;
+    const int64_t nl = (int64_t)c->p * c->p * c->p;
+    c->d_winv = dalloc<double>(c->ne * nl * nl);
+    c->d_winv32 = dalloc<float>(c->ne * nl * nl);
+    if (!c->d_winv || !c->d_winv32) {
+        free_local_inverse(c);
+        return set_err(c, HD_ERR_OOM, "explicit element inverses");
+    }
+    const unsigned nbk = (unsigned)((c->ne + 127) / 128);
+    if (c->p == 1)
+        hipLaunchKernelGGL(local_inverse_kernel<1>, dim3(nbk), dim3(128), 0, c->stream, c->ne, c->d_pa, c->d_tab64,
+                           c->d_winv, c->d_winv32);
+    else
+        hipLaunchKernelGGL(local_inverse_kernel<2>, dim3(nbk), dim3(128), 0, c->stream, c->ne, c->d_pa, c->d_tab64,
+                           c->d_winv, c->d_winv32);
+    HD_HIP(c, hipGetLastError());
     return HD_OK;
 }
 

@@ -34,6 +34,7 @@ void free_mesh(hd_ctx* c) {
 }
 
 void free_coeffs(hd_ctx* c) {
+    free_local_inverse(c);
     dfree(c->d_cm);
     dfree(c->d_kap);
     dfree(c->d_cm32);
@@ -55,11 +56,10 @@ void free_prec(hd_ctx* c) {
     dfree(c->d_mdinv);
     dfree(c->d_mdinv32);
     dfree(c->d_wface);
-    dfree(c->d_wface32);
     dfree(c->d_sdiag);
     dfree(c->d_sdiag32);
     c->d_mdiag = c->d_wdiag = c->d_mdinv = c->d_wface = c->d_sdiag = nullptr;
-    c->d_mdinv32 = c->d_wface32 = c->d_sdiag32 = nullptr;
+    c->d_mdinv32 = c->d_sdiag32 = nullptr;
     c->host_amg = HostAMG();
     c->have_prec = false;
 }
@@ -189,7 +189,10 @@ int hd_setup_mesh(hd_ctx* c, int nx, int ny, int nz, int p, const double* vertic
     if (p < 1 || p > 6) return set_err(c, HD_ERR_ARG, "p must be in [1, 6]");
     int rc = use_device(c);
     if (rc) return rc;
+    // everything built on the previous mesh goes (coefficients included: a
+    // failed call below must not leave an apply-able state behind)
     free_prec(c);
+    free_coeffs(c);
     free_mesh(c);
     const int64_t nv = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
     for (int64_t i = 0; i < 3 * nv; ++i)
@@ -275,7 +278,21 @@ int hd_setup_coeffs(hd_ctx* c, int problem, const double* c_mass, const double* 
         if (k != 0.0) c->kappa_zero = false;
     if ((rc = upload_f64_f32(c, c_mass, ne, c->d_cm, c->d_cm32))) return rc;
     if ((rc = upload_f64_f32(c, kap.data(), ne, c->d_kap, c->d_kap32))) return rc;
+    if ((rc = build_local_inverse(c))) return rc;
     c->have_coeffs = true;
+    return HD_OK;
+}
+
+int hd_set_local_solver(hd_ctx* c, int mode) {
+    if (!c) return HD_ERR_ARG;
+    if (mode != HD_LOCAL_AUTO && mode != HD_LOCAL_CG && mode != HD_LOCAL_EXPLICIT)
+        return set_err(c, HD_ERR_ARG, "unknown local solver mode");
+    if (mode == HD_LOCAL_EXPLICIT && c->have_mesh && c->p > 2)
+        return set_err(c, HD_ERR_ARG, "explicit element inverses are for p <= 2");
+    int rc = use_device(c);
+    if (rc) return rc;
+    c->local_solver = mode;
+    if (c->have_coeffs) return build_local_inverse(c);
     return HD_OK;
 }
 
@@ -370,10 +387,9 @@ int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
     c->d_mdinv32 = dalloc<float>(c->n_u);
     c->d_wdiag = dalloc<double>(c->n_q);
     c->d_wface = dalloc<double>(c->n_u);
-    c->d_wface32 = dalloc<float>(c->n_u);
     c->d_sdiag = dalloc<double>(c->n_q);
     c->d_sdiag32 = dalloc<float>(c->n_q);
-    if (!c->d_mdiag || !c->d_mdinv || !c->d_mdinv32 || !c->d_wdiag || !c->d_wface || !c->d_wface32 || !c->d_sdiag ||
+    if (!c->d_mdiag || !c->d_mdinv || !c->d_mdinv32 || !c->d_wdiag || !c->d_wface || !c->d_sdiag ||
         !c->d_sdiag32)
         return set_err(c, HD_ERR_OOM, "diagonals");
     if ((rc = launch_diagonals(c, theta))) return rc;

@@ -97,6 +97,7 @@ struct BatchInstDev {
     int64_t n_u = 0;
     int64_t off = 0;          // offset of the instance's [u; q] in the concatenated vector
     const double* vert = nullptr; // mesh vertices (the apply computes the geometry from them)
+    const void* winv = nullptr;   // explicit element inverses W_e^{-1} (kernel precision) or null
     const void* cm = nullptr;
     const void* kap = nullptr;
     const void* tabk = nullptr;
@@ -166,7 +167,6 @@ struct hd_ctx {
     double* d_mdinv = nullptr;   // 1 / (tau diag(M)), 1 on essential dofs
     float* d_mdinv32 = nullptr;
     double* d_wface = nullptr;   // 1 / M~_kk on free interior faces, 0 elsewhere (n_u)
-    float* d_wface32 = nullptr;
     double* d_sdiag = nullptr;   // diagonal of S~ (n_q)
     float* d_sdiag32 = nullptr;
     hd::DevCSR S;                // S~
@@ -196,6 +196,12 @@ struct hd_ctx {
 
     // private stream on which MINRES records its graphs (default priority)
     hipStream_t cap_stream = nullptr;
+
+    // explicit element inverses W_e^{-1} for p <= 2 ([N_e][p^3][p^3]), null
+    // when the local CG is used; local_solver is an HD_LOCAL_* mode
+    int local_solver = 0;
+    double* d_winv = nullptr;
+    float* d_winv32 = nullptr;
 
     // MINRES work space kept between solves (owned by the solver, released
     // through solve_cache_free)
@@ -266,6 +272,10 @@ int launch_precond(hd_ctx* c, int prec, const void* r, void* z, double* dot_part
                    const int* done);
 int launch_diag_prec(hd_ctx* c, int prec, const void* r, void* z, double* part);
 int launch_schur_prec(hd_ctx* c, int prec, const void* b, void* z, double* part, const int* done);
+// explicit element inverses of W_e for p <= 2 (built from the stored
+// factors w / det J); freed with the coefficients
+int build_local_inverse(hd_ctx* c);
+void free_local_inverse(hd_ctx* c);
 int64_t schur_partial_count(const hd_ctx* c);
 void free_levels(hd_ctx* c);
 Geo geo_of(const hd_ctx* c);

@@ -173,7 +173,7 @@ __global__ void fill_kernel(T* __restrict__ y, T v, int64_t n) {
 // essential and domain-boundary faces), the off-diagonal magnitude of S~
 __global__ void mdiag_finish_kernel(Geo g, int P, uint32_t ess, double tau, double* __restrict__ mdiag,
                                     double* __restrict__ mdinv, float* __restrict__ mdinv32,
-                                    double* __restrict__ wface, float* __restrict__ wface32, int64_t n_u) {
+                                    double* __restrict__ wface, int64_t n_u) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= n_u) return;
     const int c = t >= g.off[2] ? 2 : (t >= g.off[1] ? 1 : 0);
@@ -187,13 +187,11 @@ __global__ void mdiag_finish_kernel(Geo g, int P, uint32_t ess, double tau, doub
         mdinv[t] = 1.0;
         mdinv32[t] = 1.0f;
         wface[t] = 0.0;
-        wface32[t] = 0.0f;
     } else {
         const double m = mdiag[t];
         mdinv[t] = 1.0 / (tau * m);
         mdinv32[t] = (float)(1.0 / (tau * m));
         wface[t] = boundary ? 0.0 : 1.0 / m;
-        wface32[t] = boundary ? 0.0f : (float)(1.0 / m);
     }
 }
 
@@ -502,7 +500,7 @@ int launch_diagonals(hd_ctx* c, const double* theta) {
         default: return set_err(c, HD_ERR_ARG, "p out of range");
     }
     hipLaunchKernelGGL(mdiag_finish_kernel, dim3((unsigned)((c->n_u + bs - 1) / bs)), dim3(bs), 0, c->stream, g,
-                       c->p, c->ess, c->tau, c->d_mdiag, c->d_mdinv, c->d_mdinv32, c->d_wface, c->d_wface32, c->n_u);
+                       c->p, c->ess, c->tau, c->d_mdiag, c->d_mdinv, c->d_mdinv32, c->d_wface, c->n_u);
     HD_HIP(c, hipGetLastError());
     return HD_OK;
 }

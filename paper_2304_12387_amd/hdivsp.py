@@ -22,6 +22,7 @@ HD_GRADDIV, HD_DARCY = 0, 1
 HD_F64, HD_F32 = 0, 1
 HD_MODE_PLAIN64, HD_MODE_MIXED, HD_MODE_PREC32 = 0, 1, 2
 HD_SIDE_ALL = 63
+HD_LOCAL_AUTO, HD_LOCAL_CG, HD_LOCAL_EXPLICIT = 0, 1, 2
 
 EXPORTED = [
     'hd_create', 'hd_destroy', 'hd_last_error', 'hd_setup_mesh', 'hd_setup_coeffs', 'hd_sizes',
@@ -33,6 +34,7 @@ EXPORTED = [
     'hd_mlp_init', 'hd_mlp_set_params', 'hd_mlp_get_params', 'hd_mlp_loss_grad', 'hd_mlp_train', 'hd_mlp_infer',
     'hd_set_diag_scalings', 'hd_setup_batch', 'hd_batch_sizes', 'hd_batch_apply', 'hd_batch_tune',
     'hd_batch_set_launch', 'hd_batch_build_precond', 'hd_batch_minres_solve', 'hd_constant_flux',
+    'hd_set_local_solver',
 ]
 
 
@@ -94,6 +96,7 @@ def load():
         'hd_sizes': (I, [P, pI64, pI64]),
         'hd_apply_block_op': (I, [P, I, I, P, P]),
         'hd_apply_mass_inverse': (I, [P, I, I, P, P]),
+        'hd_set_local_solver': (I, [P, I]),
         'hd_apply_l2_mass_inverse': (I, [P, I, P, P]),
         'hd_lift_essential': (I, [P, P, P]),
         'hd_build_precond': (I, [P, ctypes.POINTER(PrecondParams)]),
@@ -225,6 +228,11 @@ class Context:
         self._dev(x, nrhs * (nu + nq), prec, 'x')
         self._dev(y, nrhs * (nu + nq), prec, 'y')
         return self._check(self.lib.hd_apply_block_op(self.h, prec, nrhs, _ptr(x), _ptr(y)))
+
+    def set_local_solver(self, mode):
+        """HD_LOCAL_AUTO (explicit W_e^{-1} for p <= 2, local CG otherwise),
+        HD_LOCAL_CG or HD_LOCAL_EXPLICIT (p <= 2)."""
+        return self._check(self.lib.hd_set_local_solver(self.h, mode))
 
     def apply_mass_inverse(self, x, y, prec=HD_F64, nrhs=1):
         nu, nq = self.sizes()
