@@ -18,7 +18,10 @@ Operator (eq. transformed-system and eq. transformed-system-darcy):
   Darcy:     M = M_{1/eps}, C = W^{-1} W_gamma W^{-1} = W_{1/gamma}^{-1}
              for piecewise-constant gamma, kappa_e = gamma_e (0 allowed)
   so in both cases C is block diagonal with blocks kappa_e W_e^{-1}, W_e the
-  unweighted element L2 mass matrix.
+  unweighted element L2 mass matrix.  Darcy with gamma varying inside the
+  elements (a continuous piecewise-trilinear field given at the vertices,
+  `gamma_vertices`): C_e = W_e^{-1} W_gamma,e W_e^{-1} in full (Section 3.3,
+  the general case of eq. transformed-system-darcy).
 Essential flux dofs (faces on the selected sides of the box) get identity rows
 and columns.
 """
@@ -203,11 +206,29 @@ def divergence_algorithm1(mesh):
     return sp.csr_matrix((A, J, I), shape=(N, mesh.n_u))
 
 
+def gamma_at_quadrature(mesh, gamma_vertices, Xq):
+    """gamma at the reference points Xq [Q, 3] of every element, by trilinear
+    interpolation of the element's 8 vertex values (the reference map's own
+    shape functions).  Returns [E, Q]."""
+    g = np.asarray(gamma_vertices, dtype=np.float64).reshape(-1)
+    assert g.size == (mesh.nx + 1) * (mesh.ny + 1) * (mesh.nz + 1)
+    ex, ey, ez = mesh.element_coords(np.arange(mesh.ne))
+    out = np.zeros((mesh.ne, Xq.shape[0]))
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                v = (ex + dx) + (mesh.nx + 1) * ((ey + dy) + (mesh.ny + 1) * (ez + dz))
+                N = ((Xq[:, 0] if dx else 1.0 - Xq[:, 0]) * (Xq[:, 1] if dy else 1.0 - Xq[:, 1]) *
+                     (Xq[:, 2] if dz else 1.0 - Xq[:, 2]))
+                out += g[v][:, None] * N[None, :]
+    return out
+
+
 class Problem:
     """Assembled matrices of one problem instance (dense per element, sparse
     globally).  Intended for the small meshes the oracle handles."""
 
-    def __init__(self, mesh, problem, c_mass, c_22=None, ess_sides=0, ref=None):
+    def __init__(self, mesh, problem, c_mass, c_22=None, ess_sides=0, ref=None, gamma_vertices=None):
         self.mesh = mesh
         self.problem = problem
         ne = mesh.ne
@@ -225,6 +246,15 @@ class Problem:
         em = element_matrices(mesh.p, V, self.c_mass, self.ref)
         self.Me, self.We, self.Be = em['M'], em['W'], em['B']
         self.detJ = em['detJ']
+        self.gamma_field = gamma_vertices is not None
+        if self.gamma_field:
+            if problem != DARCY:
+                raise ValueError("a gamma field is a Darcy coefficient")
+            self.gamma_q = gamma_at_quadrature(mesh, gamma_vertices, self.ref.Xq)
+            wd = self.ref.wq[None, :] / self.detJ
+            psi = self.ref.psi
+            self.Wge = np.einsum('eq,qa,qb->eab', self.gamma_q * wd, psi, psi)
+            self.kappa = np.ones(ne)
         self.l2g = mesh.rt_local_to_global()
         self._assemble()
 
@@ -242,9 +272,14 @@ class Problem:
         cb = np.tile(self.l2g, (1, nl)).ravel()
         self.B = sp.csr_matrix((self.Be.reshape(ne, -1).ravel(), (rb, cb)), shape=(mesh.n_q, mesh.n_u))
         self.D = divergence_algorithm1(mesh)
-        # C = blockdiag(kappa_e W_e^{-1}) via per-element inverses (dense, small)
+        # C = blockdiag(kappa_e W_e^{-1}) via per-element inverses (dense, small);
+        # with a gamma field blockdiag(W_e^{-1} W_gamma,e W_e^{-1})
         Winv = np.linalg.inv(self.We)
-        Cblocks = self.kappa[:, None, None] * Winv
+        if self.gamma_field:
+            Cblocks = Winv @ self.Wge @ Winv
+            self.Wg = sp.csr_matrix((self.Wge.reshape(ne, -1).ravel(), (r2, c2)), shape=(mesh.n_q, mesh.n_q))
+        else:
+            Cblocks = self.kappa[:, None, None] * Winv
         self.C = sp.csr_matrix((Cblocks.reshape(ne, -1).ravel(), (r2, c2)), shape=(mesh.n_q, mesh.n_q))
 
     # ---- operator ------------------------------------------------------

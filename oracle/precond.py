@@ -52,7 +52,11 @@ def diag_W(prob):
 
 def c_tilde(prob):
     """C~_ii = kappa_e / W_ii (grad-div: diag(W_alpha)^{-1}; Darcy with
-    piecewise-constant gamma: diag(W)^{-1} diag(W_gamma) diag(W)^{-1})."""
+    piecewise-constant gamma: diag(W)^{-1} diag(W_gamma) diag(W)^{-1}); with a
+    gamma field that product of diagonals itself (Section 3.3)."""
+    if getattr(prob, 'gamma_field', False):
+        w = diag_W(prob)
+        return prob.Wg.diagonal() / (w * w)
     nl = prob.mesh.p ** 3
     kap = np.repeat(prob.kappa, nl)
     return kap / diag_W(prob)
@@ -108,6 +112,8 @@ def schur_by_product(prob):
 def schur_is_singular(prob):
     """S~ has the constant null vector when C~ = 0 and no boundary face is
     free (pure flux boundary conditions, Section 4.2)."""
+    if getattr(prob, 'gamma_field', False):
+        return not np.any(prob.gamma_q != 0)
     if np.any(prob.kappa != 0):
         return False
     return bool(prob.mesh.essential_mask(63).sum() == (prob.ess & prob.mesh.essential_mask(63)).sum())

@@ -1,0 +1,75 @@
+"""Pins of the oracle's Darcy (2,2) block for a gamma that varies inside the
+elements (Section 3.3, the general case of eq. transformed-system-darcy):
+C_e = W_e^{-1} W_gamma,e W_e^{-1} with gamma the trilinear interpolant of
+vertex values.
+
+* a constant field gives gamma W^{-1}, the identity the paper proves for
+  gamma piecewise constant, and the same C~;
+* the interpolant reproduces a linear function of the physical coordinates at
+  the mapped quadrature points;
+* on box elements (constant det J) the quadrature is exact for W_gamma
+  (trilinear gamma times Q_{p-1} x Q_{p-1} has degree 2p - 1 per direction),
+  so it equals the integral by a rule with four more points;
+* C is symmetric positive definite and differs from the element-average
+  piecewise-constant block when gamma varies."""
+import numpy as np
+import pytest
+
+from oracle import assemble, basis, element, precond
+from paper_2304_12387_amd import inputs
+
+
+def _mesh(n, p, jitter=0.1, seed=3):
+    V = inputs.jittered_vertices(n, n, n, jitter, seed) if jitter else inputs.box_vertices(n, n, n)
+    return assemble.Mesh(n, n, n, p, V)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_constant_field_is_piecewise_constant_gamma(p):
+    m = _mesh(2, p)
+    cm = inputs.loguniform(m.ne, 0.1, 10.0, np.random.default_rng(1))
+    A = assemble.Problem(m, assemble.DARCY, cm, gamma_vertices=np.full((3 ** 3,), 2.5))
+    B = assemble.Problem(m, assemble.DARCY, cm, c_22=np.full(m.ne, 2.5))
+    assert abs(A.C - B.C).max() <= 1e-14 * abs(B.C).max()
+    assert np.allclose(precond.c_tilde(A), precond.c_tilde(B), rtol=1e-14, atol=0)
+
+
+def test_interpolant_reproduces_linear_functions():
+    m = _mesh(3, 2, jitter=0.15, seed=5)
+    a, b = np.array([0.7, -1.3, 2.1]), 0.4
+    g = m.vertices @ a + b
+    ref = element.RefElement(2)
+    gq = assemble.gamma_at_quadrature(m, g, ref.Xq)
+    x, _ = element.trilinear(m.element_vertices(), ref.Xq)
+    assert np.abs(gq - (x @ a + b)).max() <= 1e-14
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_quadrature_exact_on_box_elements(p):
+    m = _mesh(2, p, jitter=0.0)
+    g = np.random.default_rng(7).uniform(0.5, 2.0, (3 ** 3,))
+    prob = assemble.Problem(m, assemble.DARCY, np.ones(m.ne), gamma_vertices=g)
+    # independent integral with a (p + 5)-point rule, on the unit reference
+    # cube scaled by the box element volume (det J = h^3 constant)
+    xq, wq = basis.gauss_legendre(p + 5)
+    X = element.tensor_points(xq)
+    w = element.tensor_weights(wq)
+    psi = element.l2_reference(p, X)
+    gq = assemble.gamma_at_quadrature(m, g, X)
+    det = (1.0 / 2) ** 3
+    for e in range(m.ne):
+        Wg = np.einsum('q,qa,qb->ab', gq[e] * w / det, psi, psi)
+        assert np.abs(Wg - prob.Wge[e]).max() <= 1e-12 * np.abs(Wg).max()
+
+
+def test_block_is_spd_and_uses_the_full_form():
+    m = _mesh(2, 2)
+    g = np.exp(np.random.default_rng(11).uniform(-2.0, 2.0, (3 ** 3,)))
+    A = assemble.Problem(m, assemble.DARCY, np.ones(m.ne), gamma_vertices=g)
+    C = A.C.toarray()
+    assert np.abs(C - C.T).max() <= 1e-14 * np.abs(C).max()
+    assert np.linalg.eigvalsh(C).min() > 0
+    gbar = A.gamma_q.mean(axis=1)
+    B = assemble.Problem(m, assemble.DARCY, np.ones(m.ne), c_22=gbar)
+    assert abs(A.C - B.C).max() > 1e-3 * abs(B.C).max()
+    assert not precond.schur_is_singular(A)
