@@ -149,6 +149,21 @@ int hd_setup_mesh(hd_ctx* ctx, int nx, int ny, int nz, int p, const double* vert
 int hd_setup_coeffs(hd_ctx* ctx, int problem, const double* c_mass, const double* c_22,
                     uint32_t ess_sides);
 
+/* Darcy with gamma varying inside the elements (Section 3.3, the general case
+ * of eq. transformed-system-darcy): gamma becomes the continuous
+ * piecewise-trilinear field with the given values at the mesh vertices
+ * (host array of (nx+1)(ny+1)(nz+1) finite values >= 0, not all zero,
+ * numbered like the vertices of hd_setup_mesh), and the (2,2) block of the
+ * operator becomes the full W^{-1} W_gamma W^{-1} (W_gamma the gamma-weighted
+ * L2 mass matrix, integrated with the (p+1)^3-point rule; two local solves
+ * per element and apply), approximated in S~ by
+ * diag(W)^{-1} diag(W_gamma) diag(W)^{-1}.  Call after
+ * hd_setup_coeffs(HD_DARCY, ...) (HD_ERR_STATE otherwise); it replaces that
+ * call's gamma, drops the preconditioner (build it again), and lasts until the
+ * next hd_setup_coeffs.  hd_apply_mass_inverse is not defined for a field
+ * (HD_ERR_STATE). */
+int hd_set_gamma_field(hd_ctx* ctx, const double* gamma_vertices);
+
 /* Global sizes n_u (RT) and n_q (L2). */
 int hd_sizes(const hd_ctx* ctx, int64_t* n_u, int64_t* n_q);
 

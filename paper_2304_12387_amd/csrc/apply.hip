@@ -72,6 +72,7 @@ struct ElemLDS {
     T A1[Dim<P>::Q3];    // stage buffers
     T A2[Dim<P>::Q3];
     T vx[24];            // element vertices X[dz][dy][dx][coordinate]
+    T gv[8];             // gamma at the element vertices (Darcy with a gamma field)
 };
 
 // ---------------------------------------------------------------------------
@@ -214,6 +215,71 @@ __device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], i
 #undef Ti
 #undef Bg
 #undef Bg2
+}
+
+// sq = W_gamma A1 for one element (Darcy with gamma varying inside the
+// element, Section 3.3): the L2 coefficients in A1 to the quadrature points
+// with the histopolation table in x, y (LDS) and z (registers), times
+// gamma w / det J there (gamma the trilinear interpolant of the vertex values
+// in gv, w / det J in gw as z-pencils), and back with the transposed table.
+template <int P, typename T>
+__device__ void w_gamma(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], int t) {
+    constexpr int Q = P + 1;
+#define Hm (&tfence<P, T>(tk)->H[0][0])
+    stage_lds<T, P, P, P, 0, Q, P, false>(L.A1, L.A2, Hm, t);
+    __syncthreads();
+    stage_lds<T, Q, P, P, 1, Q, P, false>(L.A2, L.A1, Hm, t);
+    __syncthreads();
+    if (t < Q * Q) {
+        const int qa = t % Q, qb = t / Q;
+        T in[P], w[Q], o[P];
+        pencil_load<T, Q, Q, P, 2>(L.A1, t, in);
+        pencil_mul<T, P, Q, P, false>(in, w, Hm);
+        const T xa = tk->xq[qa], xb = tk->xq[qb];
+        const T nx[2] = {T(1) - xa, xa}, ny[2] = {T(1) - xb, xb};
+        T gz[2];
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+            gz[dz] = (L.gv[(dz * 2 + 0) * 2 + 0] * nx[0] + L.gv[(dz * 2 + 0) * 2 + 1] * nx[1]) * ny[0] +
+                     (L.gv[(dz * 2 + 1) * 2 + 0] * nx[0] + L.gv[(dz * 2 + 1) * 2 + 1] * nx[1]) * ny[1];
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const T z1 = tk->xq[c];
+            w[c] *= (gz[0] * (T(1) - z1) + gz[1] * z1) * gw[c];
+        }
+        pencil_mul<T, Q, P, P, true>(w, o, Hm);
+        pencil_store<T, Q, Q, Q, 2, P>(L.A2, t, o);
+    }
+    __syncthreads();
+    stage_lds<T, Q, Q, P, 1, P, P, true>(L.A2, L.A1, Hm, t);
+    __syncthreads();
+    stage_lds<T, Q, P, P, 0, P, P, true>(L.A1, L.sq, Hm, t);
+    __syncthreads();
+#undef Hm
+}
+
+// A1 = kappa W_e^{-1} sq: the explicit element inverse when given (p <= 2,
+// row l per lane), otherwise the local CG.
+template <int P, typename T>
+__device__ __forceinline__ void local_solve(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], int t, bool active,
+                                            T kE, const CGParams<T>& cgp, const T* __restrict__ winv, int64_t ee) {
+    constexpr int NL = Dim<P>::NL, W = Slot<P>::W;
+    if constexpr (P <= 2) {
+        if (winv) {
+            __syncthreads();
+            if (active)
+                for (int l = t; l < NL; l += W) {
+                    const T* wr = winv + ((size_t)ee * NL + l) * NL;
+                    T s = 0;
+#pragma unroll
+                    for (int k = 0; k < NL; ++k) s += wr[k] * L.sq[k];
+                    L.A1[l] = kE * s;
+                }
+            __syncthreads();
+            return;
+        }
+    }
+    local_cg<P, T>(L, tk, gw, t, active, kE, cgp);
 }
 
 // Forward sum factorisation of RT component C (shape N0,N1,N2) to the
@@ -430,13 +496,14 @@ struct RhsArgs {
 // M u by sum factorisation, the local CG for -kappa W^{-1} q~, scatter.
 // x and y point at one right-hand side's vector; the return value is the
 // group's <A x, x> contribution summed over the wavefront (all lanes).
-template <int P, typename T, bool HAS_C = true>
+template <int P, typename T, bool HAS_C = true, bool VARG = false>
 __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, const double* __restrict__ vert,
                                               tkp<P, T> tb,
                                               const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
                                               int ess_mode, int64_t n_u, const T* __restrict__ x, T* __restrict__ y,
                                               T s_in, const CGParams<T>& cgp, int with_c, int colour, unsigned grp,
-                                              unsigned nb, const T* __restrict__ winv) {
+                                              unsigned nb, const T* __restrict__ winv,
+                                              const double* __restrict__ gvert = nullptr) {
     using D = Dim<P>;
     using S = Slot<P>;
     constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC, W = S::W;
@@ -462,6 +529,12 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
             const int v = l / 3, r = l % 3;
             const int dx = v & 1, dy = (v >> 1) & 1, dz = v >> 2;
             L.vx[l] = (T)vert[3 * ((ex + dx) + (int64_t)(g.nx + 1) * ((ey + dy) + (int64_t)(g.ny + 1) * (ez + dz))) + r];
+        }
+        if constexpr (VARG) {
+            for (int l = t; l < 8; l += W) {
+                const int dx = l & 1, dy = (l >> 1) & 1, dz = l >> 2;
+                L.gv[l] = (T)gvert[(ex + dx) + (int64_t)(g.nx + 1) * ((ey + dy) + (int64_t)(g.ny + 1) * (ez + dz))];
+            }
         }
         gather_rt<P, T, 0>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
         gather_rt<P, T, 1>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
@@ -554,25 +627,22 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     // which then needs fewer registers and runs more wavefronts per SIMD)
     if constexpr (HAS_C) {
         if (with_c) {
-            if constexpr (P <= 2) {
-                // explicit element inverse (uniform choice for the launch):
-                // A1 = kappa W_e^{-1} q~, row l of the inverse per lane
-                if (winv) {
-                    __syncthreads();
-                    if (valid && kE != T(0))
-                        for (int l = t; l < NL; l += W) {
-                            const T* wr = winv + ((size_t)ee * NL + l) * NL;
-                            T s = 0;
+            const bool act = valid && kE != T(0);
+            if constexpr (VARG) {
+                // W^{-1} W_gamma W^{-1} q~ (kappa = 1); q~ kept in registers
+                // for the inner product of the final store
+                constexpr int NS = (NL + W - 1) / W;
+                T sqs[NS];
 #pragma unroll
-                            for (int k = 0; k < NL; ++k) s += wr[k] * L.sq[k];
-                            L.A1[l] = kE * s;
-                        }
-                    __syncthreads();
-                } else {
-                    local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
-                }
+                for (int k = 0; k < NS; ++k) sqs[k] = t + k * W < NL ? L.sq[t + k * W] : T(0);
+                local_solve<P, T>(L, tb, gw, t, act, T(1), cgp, winv, ee);
+                w_gamma<P, T>(L, tb, gw, t);
+                local_solve<P, T>(L, tb, gw, t, act, kE, cgp, winv, ee);
+#pragma unroll
+                for (int k = 0; k < NS; ++k)
+                    if (t + k * W < NL) L.sq[t + k * W] = sqs[k];
             } else {
-                local_cg<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp);
+                local_solve<P, T>(L, tb, gw, t, act, kE, cgp, winv, ee);
             }
         }
     }
@@ -603,11 +673,12 @@ __device__ __forceinline__ unsigned xcd_chunk(unsigned b, unsigned n) {
     return x * (n / 8) + (x < n % 8 ? x : n % 8) + k;
 }
 
-template <int P, typename T, bool HAS_C>
+template <int P, typename T, bool HAS_C, bool VARG = false>
 __global__ __launch_bounds__(64) void block_apply_kernel(
     Geo g, const double* __restrict__ vert, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap,
     uint32_t ess, int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
-    CGParams<T> cgp, int with_c, int colour, int64_t part_offset, unsigned nb, const T* __restrict__ winv) {
+    CGParams<T> cgp, int with_c, int colour, int64_t part_offset, unsigned nb, const T* __restrict__ winv,
+    const double* __restrict__ gvert) {
     // Block -> (element group, right-hand side).  With several right-hand
     // sides, the blocks of one element group are spaced 8 apart, so that they
     // run on the same XCD (blocks are dealt to the 8 XCDs round-robin) at
@@ -625,8 +696,9 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;   // uniform over the block
     __shared__ ElemLDS<P, T> sm[Slot<P>::EPW];
     const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
-    const double dot = apply_group<P, T, HAS_C>(sm, g, vert, tb, cm, kap, ess, ess_mode, n_u, xall + r * ra.ldv,
-                                                yall + r * ra.ldv, s_in, cgp, with_c, colour, grp, nb, winv);
+    const double dot = apply_group<P, T, HAS_C, VARG>(sm, g, vert, tb, cm, kap, ess, ess_mode, n_u, xall + r * ra.ldv,
+                                                yall + r * ra.ldv, s_in, cgp, with_c, colour, grp, nb, winv,
+                                                      gvert);
     if (ra.partial && grp < nb && threadIdx.x == 0) ra.partial[r * ra.part_stride + part_offset + grp] = dot;
 }
 
@@ -865,16 +937,20 @@ void launch_apply_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int ess_mode
     const unsigned grid = ra.nrhs > 1 ? (unsigned)(((nb + 7) / 8) * 8 * (uint64_t)ra.nrhs) : nb;
     const T* winv = std::is_same<T, double>::value ? (const T*)c->d_winv : (const T*)c->d_winv32;
     for (int colour = 0; colour < 2; ++colour) {
-        if (!c->kappa_zero)
+        if (c->gamma_field)
+            hipLaunchKernelGGL((block_apply_kernel<P, T, true, true>), dim3(grid), dim3(64), 0, c->stream, g,
+                               c->d_vert, tb, cm, kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 1,
+                               colour, (int64_t)colour * nb, nb, winv, (const double*)c->d_gv);
+        else if (!c->kappa_zero)
             hipLaunchKernelGGL((block_apply_kernel<P, T, true>), dim3(grid), dim3(64), 0, c->stream, g, c->d_vert, tb,
                                cm,
                                kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 1, colour,
-                               (int64_t)colour * nb, nb, winv);
+                               (int64_t)colour * nb, nb, winv, (const double*)nullptr);
         else
             hipLaunchKernelGGL((block_apply_kernel<P, T, false>), dim3(grid), dim3(64), 0, c->stream, g, c->d_vert, tb,
                                cm,
                                kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 0, colour,
-                               (int64_t)colour * nb, nb, (const T*)nullptr);
+                               (int64_t)colour * nb, nb, (const T*)nullptr, (const double*)nullptr);
     }
 }
 

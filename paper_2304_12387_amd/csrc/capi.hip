@@ -35,6 +35,12 @@ void free_mesh(hd_ctx* c) {
 
 void free_coeffs(hd_ctx* c) {
     free_local_inverse(c);
+    dfree(c->d_gv);
+    dfree(c->d_gv32);
+    dfree(c->d_ctil);
+    c->d_gv = c->d_ctil = nullptr;
+    c->d_gv32 = nullptr;
+    c->gamma_field = false;
     dfree(c->d_cm);
     dfree(c->d_kap);
     dfree(c->d_cm32);
@@ -283,6 +289,42 @@ int hd_setup_coeffs(hd_ctx* c, int problem, const double* c_mass, const double* 
     return HD_OK;
 }
 
+int hd_set_gamma_field(hd_ctx* c, const double* gv) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_coeffs || c->problem != HD_DARCY) return set_err(c, HD_ERR_STATE, "hd_setup_coeffs(HD_DARCY, ...) first");
+    if (!gv) return set_err(c, HD_ERR_ARG, "gamma_vertices required");
+    const int64_t nv = (int64_t)(c->nx + 1) * (c->ny + 1) * (c->nz + 1);
+    bool any = false;
+    for (int64_t i = 0; i < nv; ++i) {
+        if (!std::isfinite(gv[i])) return set_err(c, HD_ERR_NONFINITE, "non-finite gamma value");
+        if (gv[i] < 0) return set_err(c, HD_ERR_ARG, "gamma must be non-negative");
+        if (gv[i] > 0) any = true;
+    }
+    if (!any) return set_err(c, HD_ERR_ARG, "an all-zero gamma field: use hd_setup_coeffs with gamma = 0");
+    int rc = use_device(c);
+    if (rc) return rc;
+    free_prec(c);
+    dfree(c->d_gv);
+    dfree(c->d_gv32);
+    dfree(c->d_ctil);
+    c->d_gv = c->d_ctil = nullptr;
+    c->d_gv32 = nullptr;
+    c->gamma_field = false;
+    std::vector<double> ones(c->ne, 1.0);
+    if ((rc = upload_f64_f32(c, gv, nv, c->d_gv, c->d_gv32))) return rc;
+    c->d_ctil = dalloc<double>(c->n_q);
+    if (!c->d_ctil) return set_err(c, HD_ERR_OOM, "C~ of the gamma field");
+    // kappa = 1: the (2,2) block is W^{-1} W_gamma W^{-1} itself
+    dfree(c->d_kap);
+    dfree(c->d_kap32);
+    c->d_kap = nullptr;
+    c->d_kap32 = nullptr;
+    if ((rc = upload_f64_f32(c, ones.data(), c->ne, c->d_kap, c->d_kap32))) return rc;
+    c->kappa_zero = false;
+    c->gamma_field = true;
+    return build_local_inverse(c);
+}
+
 int hd_set_local_solver(hd_ctx* c, int mode) {
     if (!c) return HD_ERR_ARG;
     if (mode != HD_LOCAL_AUTO && mode != HD_LOCAL_CG && mode != HD_LOCAL_EXPLICIT)
@@ -317,6 +359,7 @@ int hd_apply_block_op(hd_ctx* c, int prec, int nrhs, const void* x, void* y) {
 int hd_apply_mass_inverse(hd_ctx* c, int prec, int nrhs, const void* x, void* y) {
     if (!c) return HD_ERR_ARG;
     if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
+    if (c->gamma_field) return set_err(c, HD_ERR_STATE, "not defined for a gamma field");
     if (nrhs < 1) return set_err(c, HD_ERR_ARG, "nrhs must be >= 1");
     if (prec != HD_F64 && prec != HD_F32) return set_err(c, HD_ERR_ARG, "prec");
     if (!x || !y) return set_err(c, HD_ERR_ARG, "null pointer");

@@ -203,6 +203,13 @@ struct hd_ctx {
     double* d_winv = nullptr;
     float* d_winv32 = nullptr;
 
+    // Darcy with gamma varying inside the elements (hd_set_gamma_field): the
+    // vertex values (FP64 / FP32) and C~ of S~ ([n_q]); kappa is 1 then
+    bool gamma_field = false;
+    double* d_gv = nullptr;
+    float* d_gv32 = nullptr;
+    double* d_ctil = nullptr;
+
     // MINRES work space kept between solves (owned by the solver, released
     // through solve_cache_free)
     void* solve_cache = nullptr;

@@ -198,7 +198,8 @@ __global__ void mdiag_finish_kernel(Geo g, int P, uint32_t ess, double tau, doub
 // ---------------------------------------------------------------------------
 // S~ rows.  Row i = sub-volume (a, b, c) of element e.  For each of its six
 // faces k: if k is free, the diagonal gains 1/M~_kk and the neighbour volume
-// across k (if any) gets the off-diagonal -1/M~_kk; C~_ii = kappa_e / W_ii.
+// across k (if any) gets the off-diagonal -1/M~_kk; C~_ii = kappa_e / W_ii, or
+// ctil[i] when given (Darcy with a gamma field).
 // ---------------------------------------------------------------------------
 struct RowEnt {
     int32_t col;
@@ -206,7 +207,8 @@ struct RowEnt {
 };
 
 __device__ int schur_row(Geo g, int P, uint32_t ess, int64_t i, const double* __restrict__ mdiag,
-                         const double* __restrict__ wdiag, const double* __restrict__ kap, RowEnt* ent) {
+                         const double* __restrict__ wdiag, const double* __restrict__ kap,
+                         const double* __restrict__ ctil, RowEnt* ent) {
     const int NL = P * P * P;
     const int64_t e = i / NL;
     const int l = (int)(i % NL);
@@ -216,7 +218,7 @@ __device__ int schur_row(Geo g, int P, uint32_t ess, int64_t i, const double* __
     const int ndim[3] = {g.nx, g.ny, g.nz};
     const int64_t estride[3] = {1, g.nx, (int64_t)g.nx * g.ny};
     const int lstride[3] = {1, P, P * P};
-    double diag = kap[e] / wdiag[i];
+    double diag = ctil ? ctil[i] : kap[e] / wdiag[i];
     int n = 0;
     for (int c = 0; c < 3; ++c) {
         for (int side = 0; side < 2; ++side) {
@@ -265,21 +267,21 @@ __device__ int schur_row(Geo g, int P, uint32_t ess, int64_t i, const double* __
 
 __global__ void schur_count_kernel(Geo g, int P, uint32_t ess, int64_t nq, const double* __restrict__ mdiag,
                                    const double* __restrict__ wdiag, const double* __restrict__ kap,
-                                   int32_t* __restrict__ cnt) {
+                                   const double* __restrict__ ctil, int32_t* __restrict__ cnt) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nq) return;
     RowEnt ent[7];
-    cnt[i] = schur_row(g, P, ess, i, mdiag, wdiag, kap, ent);
+    cnt[i] = schur_row(g, P, ess, i, mdiag, wdiag, kap, ctil, ent);
 }
 
 __global__ void schur_fill_kernel(Geo g, int P, uint32_t ess, int64_t nq, const double* __restrict__ mdiag,
                                   const double* __restrict__ wdiag, const double* __restrict__ kap,
-                                  const int32_t* __restrict__ rp, int32_t* __restrict__ ci, double* __restrict__ v,
+                                  const double* __restrict__ ctil, const int32_t* __restrict__ rp, int32_t* __restrict__ ci, double* __restrict__ v,
                                   float* __restrict__ v32, double* __restrict__ sdiag, float* __restrict__ sdiag32) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= nq) return;
     RowEnt ent[7];
-    const int n = schur_row(g, P, ess, i, mdiag, wdiag, kap, ent);
+    const int n = schur_row(g, P, ess, i, mdiag, wdiag, kap, ctil, ent);
     const int32_t o = rp[i];
     for (int k = 0; k < n; ++k) {
         ci[o + k] = ent[k].col;
@@ -521,15 +523,67 @@ int scan_counts(hd_ctx* c, const int32_t* cnt, int64_t n, int32_t* rp, int64_t* 
     return HD_OK;
 }
 
+// Darcy with a gamma field: C~_ii = diag(W_gamma)_ii / W_ii^2 (the product of
+// the diagonals of W^{-1} W_gamma W^{-1}, Section 3.3), one thread per L2 dof;
+// gamma at the quadrature points is the trilinear interpolant of the element's
+// vertex values, w / det J the stored seventh factor.
+template <int P>
+__global__ void gamma_ctil_kernel(Geo g, int64_t nq, const double* __restrict__ pa,
+                                  const Tables<double>* __restrict__ tab, const double* __restrict__ gv,
+                                  const double* __restrict__ wdiag, double* __restrict__ ctil) {
+    constexpr int Q = P + 1, Q3 = Q * Q * Q, NL = P * P * P;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const int64_t e = i / NL;
+    const int l = (int)(i % NL);
+    const int i0 = l % P, i1 = (l / P) % P, i2 = l / (P * P);
+    const int ex = (int)(e % g.nx), ey = (int)((e / g.nx) % g.ny), ez = (int)(e / ((int64_t)g.nx * g.ny));
+    double gvx[8];
+    for (int v = 0; v < 8; ++v) {
+        const int dx = v & 1, dy = (v >> 1) & 1, dz = v >> 2;
+        gvx[v] = gv[(ex + dx) + (int64_t)(g.nx + 1) * ((ey + dy) + (int64_t)(g.ny + 1) * (ez + dz))];
+    }
+    const double* gw = pa + (size_t)e * NPA * Q3 + 6 * Q3;
+    double s = 0.0;
+    for (int q = 0; q < Q3; ++q) {
+        const int a = q % Q, b = (q / Q) % Q, c = q / (Q * Q);
+        const double x = tab->xq[a], y = tab->xq[b], z = tab->xq[c];
+        double gam = 0.0;
+        for (int v = 0; v < 8; ++v)
+            gam += gvx[v] * ((v & 1) ? x : 1.0 - x) * (((v >> 1) & 1) ? y : 1.0 - y) * ((v >> 2) ? z : 1.0 - z);
+        const double h = tab->H[a][i0] * tab->H[b][i1] * tab->H[c][i2];
+        s += gam * gw[q] * h * h;
+    }
+    ctil[i] = s / (wdiag[i] * wdiag[i]);
+}
+
 int launch_schur(hd_ctx* c) {
     Geo g = geo_of(c);
     const int bs = 256;
     const int64_t n = c->n_q;
+    const double* ctil = nullptr;
+    if (c->gamma_field) {
+        const unsigned nbk = (unsigned)((n + bs - 1) / bs);
+#define GCT(PP)                                                                                                    \
+    hipLaunchKernelGGL(gamma_ctil_kernel<PP>, dim3(nbk), dim3(bs), 0, c->stream, g, n, c->d_pa, c->d_tab64, c->d_gv, \
+                       c->d_wdiag, c->d_ctil)
+        switch (c->p) {
+            case 1: GCT(1); break;
+            case 2: GCT(2); break;
+            case 3: GCT(3); break;
+            case 4: GCT(4); break;
+            case 5: GCT(5); break;
+            default: GCT(6); break;
+        }
+#undef GCT
+        HD_HIP(c, hipGetLastError());
+        ctil = c->d_ctil;
+    }
     int32_t* cnt = dalloc<int32_t>(n);
     int32_t* rp = dalloc<int32_t>(n + 1);
     if (!cnt || !rp) return set_err(c, HD_ERR_OOM, "schur row counts");
     hipLaunchKernelGGL(schur_count_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, c->stream, g, c->p,
-                       c->ess, n, c->d_mdiag, c->d_wdiag, c->d_kap, cnt);
+                       c->ess, n, c->d_mdiag, c->d_wdiag, c->d_kap, ctil, cnt);
     int64_t nnz = 0;
     int rc = scan_counts(c, cnt, n, rp, &nnz);
     dfree(cnt);
@@ -548,7 +602,8 @@ int launch_schur(hd_ctx* c) {
     S.v32 = dalloc<float>(nnz);
     if (!S.ci || !S.v || !S.v32) return set_err(c, HD_ERR_OOM, "S~ storage");
     hipLaunchKernelGGL(schur_fill_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, c->stream, g, c->p,
-                       c->ess, n, c->d_mdiag, c->d_wdiag, c->d_kap, S.rp, S.ci, S.v, S.v32, c->d_sdiag, c->d_sdiag32);
+                       c->ess, n, c->d_mdiag, c->d_wdiag, c->d_kap, ctil, S.rp, S.ci, S.v, S.v32, c->d_sdiag,
+                       c->d_sdiag32);
     HD_HIP(c, hipGetLastError());
     return HD_OK;
 }

@@ -34,7 +34,7 @@ EXPORTED = [
     'hd_mlp_init', 'hd_mlp_set_params', 'hd_mlp_get_params', 'hd_mlp_loss_grad', 'hd_mlp_train', 'hd_mlp_infer',
     'hd_set_diag_scalings', 'hd_setup_batch', 'hd_batch_sizes', 'hd_batch_apply', 'hd_batch_tune',
     'hd_batch_set_launch', 'hd_batch_build_precond', 'hd_batch_minres_solve', 'hd_constant_flux',
-    'hd_set_local_solver',
+    'hd_set_local_solver', 'hd_set_gamma_field',
 ]
 
 
@@ -97,6 +97,7 @@ def load():
         'hd_apply_block_op': (I, [P, I, I, P, P]),
         'hd_apply_mass_inverse': (I, [P, I, I, P, P]),
         'hd_set_local_solver': (I, [P, I]),
+        'hd_set_gamma_field': (I, [P, P]),
         'hd_apply_l2_mass_inverse': (I, [P, I, P, P]),
         'hd_lift_essential': (I, [P, P, P]),
         'hd_build_precond': (I, [P, ctypes.POINTER(PrecondParams)]),
@@ -228,6 +229,12 @@ class Context:
         self._dev(x, nrhs * (nu + nq), prec, 'x')
         self._dev(y, nrhs * (nu + nq), prec, 'y')
         return self._check(self.lib.hd_apply_block_op(self.h, prec, nrhs, _ptr(x), _ptr(y)))
+
+    def set_gamma_field(self, gamma_vertices):
+        """Darcy: gamma as the trilinear field of these vertex values (host
+        array, (nx+1)(ny+1)(nz+1)); the (2,2) block becomes W^-1 W_gamma W^-1."""
+        g = np.ascontiguousarray(gamma_vertices, dtype=np.float64).reshape(-1)
+        return self._check(self.lib.hd_set_gamma_field(self.h, _ptr(g)))
 
     def set_local_solver(self, mode):
         """HD_LOCAL_AUTO (explicit W_e^{-1} for p <= 2, local CG otherwise),

@@ -86,6 +86,14 @@ def gaussian_field(shape, corr_cells, sigma, seed):
     return sigma * g
 
 
+def gamma_vertex_field(nx, ny, nz, seed, sigma=1.0, corr=2.0):
+    """Positive vertex values [(nx+1)(ny+1)(nz+1)] (x fastest) of a Darcy
+    coefficient gamma that varies inside the elements: exp of a smooth
+    Gaussian field with correlation `corr` vertex spacings."""
+    z = gaussian_field((nz + 1, ny + 1, nx + 1), (corr, corr, corr), sigma, seed)
+    return np.exp(z).ravel()
+
+
 def darcy_cube_4():
     n, p = 4, 2
     return dict(name='darcy_cube_4', nx=n, ny=n, nz=n, p=p, problem=1,
