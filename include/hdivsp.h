@@ -227,6 +227,27 @@ int hd_apply_precond(hd_ctx* ctx, int prec, int nrhs, const void* r, void* z);
  * error code otherwise. */
 int hd_minres_solve(hd_ctx* ctx, const hd_solve_params* params, int nrhs,
                     const double* b, double* x, hd_solve_info* info);
+
+/* GMRES(restart), right-preconditioned with the upper block-triangular
+ * preconditioner P = [[tau M~, D^T], [0, -S^]] (Section 2.2, the remark on
+ * block-triangular preconditioners; M~ and the V-cycle S^ of
+ * hd_build_precond, which must have been called).  FP64, one right-hand side:
+ * b, x FP64 device pointers of length n_u + n_q; x holds the initial guess
+ * on entry (zeros for none) and the solution on return.  Stops when the
+ * Arnoldi residual estimate, and then the true residual, satisfy
+ * ||b - A x||_2 <= tol ||b||_2, or after max_it operator applications.  The
+ * Krylov basis ((restart + 1) vectors of n_u + n_q doubles) is allocated for
+ * the call (HD_ERR_OOM if it does not fit).  info (optional): iterations =
+ * operator applications, outer = restart cycles, eta_rel = last estimate,
+ * true_rel_res, time_s.  Returns 0, HD_NOT_CONVERGED or an error code. */
+int hd_gmres_solve(hd_ctx* ctx, double tol, int max_it, int restart, const double* b, double* x,
+                   hd_solve_info* info);
+
+/* z = P^{-1} r for the block-triangular preconditioner of hd_gmres_solve:
+ * z_q = -S^{-1} r_q (one V-cycle), z_u = (tau M~)^{-1} (r_u - D^T z_q) on free
+ * RT dofs and z_u = r_u on essential ones.  FP64 device pointers of length
+ * n_u + n_q, r != z.  HD_ERR_STATE before hd_build_precond. */
+int hd_apply_tri_precond(hd_ctx* ctx, const double* r, double* z);
 /* The solver's work space (Krylov vectors, partial sums, pinned state) stays
  * allocated in the context between calls and is rebuilt when the sizes,
  * the precision mode or nrhs change; hd_destroy releases it. */

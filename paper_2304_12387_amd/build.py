@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, 'csrc')
 BUILD = os.path.join(os.path.dirname(HERE), '_build')
 LIB = os.path.join(HERE, 'libhdivsp.so')
 
-SOURCES = ['tables.cpp', 'amg_host.cpp', 'setup.hip', 'apply.hip', 'precond.hip', 'minres.hip', 'learned.hip',
+SOURCES = ['tables.cpp', 'amg_host.cpp', 'setup.hip', 'apply.hip', 'precond.hip', 'minres.hip', 'gmres.hip',
+           'learned.hip',
            'capi.hip']
 ARCH = 'gfx950'
 FLAGS = ['-O3', '-std=c++17', '-fPIC', f'--offload-arch={ARCH}', '-munsafe-fp-atomics',

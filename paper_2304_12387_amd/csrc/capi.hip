@@ -477,6 +477,31 @@ int hd_apply_precond(hd_ctx* c, int prec, int nrhs, const void* r, void* z) {
     return HD_OK;
 }
 
+int hd_gmres_solve(hd_ctx* c, double tol, int max_it, int restart, const double* b, double* x,
+                   hd_solve_info* info) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
+    if (!b || !x || b == x) return set_err(c, HD_ERR_ARG, "b, x must be distinct device pointers");
+    if (!(tol > 0) || max_it < 1 || restart < 1 || restart > 500) return set_err(c, HD_ERR_ARG, "bad GMRES parameters");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return gmres_solve(c, tol, max_it, restart, b, x, info);
+}
+
+int hd_apply_tri_precond(hd_ctx* c, const double* r, double* z) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
+    if (!r || !z || r == z) return set_err(c, HD_ERR_ARG, "r, z must be distinct device pointers");
+    int rc = use_device(c);
+    if (rc) return rc;
+    double* s = dalloc<double>(c->n_q);
+    if (!s) return set_err(c, HD_ERR_OOM, "scratch");
+    rc = launch_tri_precond(c, r, z, s);
+    (void)hipStreamSynchronize(c->stream);
+    dfree(s);
+    return rc;
+}
+
 int hd_minres_solve(hd_ctx* c, const hd_solve_params* params, int nrhs, const double* b, double* x,
                     hd_solve_info* info) {
     if (!c) return HD_ERR_ARG;

@@ -279,6 +279,10 @@ int launch_precond(hd_ctx* c, int prec, const void* r, void* z, double* dot_part
                    const int* done);
 int launch_diag_prec(hd_ctx* c, int prec, const void* r, void* z, double* part);
 int launch_schur_prec(hd_ctx* c, int prec, const void* b, void* z, double* part, const int* done);
+// upper block-triangular preconditioner z = P^{-1} r (FP64; s_scratch: n_q)
+int launch_tri_precond(hd_ctx* c, const double* r, double* z, double* s_scratch);
+// right-preconditioned restarted GMRES with the block-triangular preconditioner
+int gmres_solve(hd_ctx* c, double tol, int max_it, int restart, const double* b, double* x, hd_solve_info* info);
 // explicit element inverses of W_e for p <= 2 (built from the stored
 // factors w / det J); freed with the coefficients
 int build_local_inverse(hd_ctx* c);

@@ -34,7 +34,7 @@ EXPORTED = [
     'hd_mlp_init', 'hd_mlp_set_params', 'hd_mlp_get_params', 'hd_mlp_loss_grad', 'hd_mlp_train', 'hd_mlp_infer',
     'hd_set_diag_scalings', 'hd_setup_batch', 'hd_batch_sizes', 'hd_batch_apply', 'hd_batch_tune',
     'hd_batch_set_launch', 'hd_batch_build_precond', 'hd_batch_minres_solve', 'hd_constant_flux',
-    'hd_set_local_solver', 'hd_set_gamma_field',
+    'hd_set_local_solver', 'hd_set_gamma_field', 'hd_gmres_solve', 'hd_apply_tri_precond',
 ]
 
 
@@ -98,6 +98,8 @@ def load():
         'hd_apply_mass_inverse': (I, [P, I, I, P, P]),
         'hd_set_local_solver': (I, [P, I]),
         'hd_set_gamma_field': (I, [P, P]),
+        'hd_gmres_solve': (I, [P, D, I, I, P, P, ctypes.POINTER(SolveInfo)]),
+        'hd_apply_tri_precond': (I, [P, P, P]),
         'hd_apply_l2_mass_inverse': (I, [P, I, P, P]),
         'hd_lift_essential': (I, [P, P, P]),
         'hd_build_precond': (I, [P, ctypes.POINTER(PrecondParams)]),
@@ -430,6 +432,25 @@ class Context:
         self._check(rc, allow=(HD_NOT_CONVERGED,))
         out = [i.as_dict() for i in info]
         return out[0] if nrhs == 1 else out
+
+    def apply_tri_precond(self, r, z):
+        """z = P^{-1} r, the block-triangular preconditioner (FP64)."""
+        nu, nq = self.sizes()
+        self._dev(r, nu + nq, HD_F64, 'r')
+        self._dev(z, nu + nq, HD_F64, 'z')
+        return self._check(self.lib.hd_apply_tri_precond(self.h, _ptr(r), _ptr(z)))
+
+    def gmres_solve(self, b, x, tol=1e-8, max_it=2000, restart=30):
+        """GMRES(restart) with the block-triangular preconditioner; x is the
+        initial guess on entry.  Returns the info dict."""
+        nu, nq = self.sizes()
+        self._dev(b, nu + nq, HD_F64, 'b')
+        self._dev(x, nu + nq, HD_F64, 'x')
+        info = SolveInfo()
+        rc = self.lib.hd_gmres_solve(self.h, float(tol), int(max_it), int(restart), _ptr(b), _ptr(x),
+                                     ctypes.byref(info))
+        self._check(rc, allow=(HD_NOT_CONVERGED,))
+        return info.as_dict()
 
     # ---- inspection ---------------------------------------------------------
     def get_diagonals(self):
