@@ -303,23 +303,33 @@ int hd_set_gamma_field(hd_ctx* c, const double* gv) {
     if (!any) return set_err(c, HD_ERR_ARG, "an all-zero gamma field: use hd_setup_coeffs with gamma = 0");
     int rc = use_device(c);
     if (rc) return rc;
+    // new arrays first; the context changes only once all of them exist
+    double *gv64 = nullptr, *kap64 = nullptr, *ctil = nullptr;
+    float *gv32 = nullptr, *kap32 = nullptr;
+    std::vector<double> ones(c->ne, 1.0);
+    rc = upload_f64_f32(c, gv, nv, gv64, gv32);
+    if (!rc) rc = upload_f64_f32(c, ones.data(), c->ne, kap64, kap32);
+    if (!rc) {
+        ctil = dalloc<double>(c->n_q);
+        if (!ctil) rc = set_err(c, HD_ERR_OOM, "C~ of the gamma field");
+    }
+    if (rc) {
+        for (double* p : {gv64, kap64, ctil}) dfree(p);
+        for (float* p : {gv32, kap32}) dfree(p);
+        return rc;
+    }
     free_prec(c);
     dfree(c->d_gv);
     dfree(c->d_gv32);
     dfree(c->d_ctil);
-    c->d_gv = c->d_ctil = nullptr;
-    c->d_gv32 = nullptr;
-    c->gamma_field = false;
-    std::vector<double> ones(c->ne, 1.0);
-    if ((rc = upload_f64_f32(c, gv, nv, c->d_gv, c->d_gv32))) return rc;
-    c->d_ctil = dalloc<double>(c->n_q);
-    if (!c->d_ctil) return set_err(c, HD_ERR_OOM, "C~ of the gamma field");
-    // kappa = 1: the (2,2) block is W^{-1} W_gamma W^{-1} itself
     dfree(c->d_kap);
     dfree(c->d_kap32);
-    c->d_kap = nullptr;
-    c->d_kap32 = nullptr;
-    if ((rc = upload_f64_f32(c, ones.data(), c->ne, c->d_kap, c->d_kap32))) return rc;
+    c->d_gv = gv64;
+    c->d_gv32 = gv32;
+    c->d_ctil = ctil;
+    // kappa = 1: the (2,2) block is W^{-1} W_gamma W^{-1} itself
+    c->d_kap = kap64;
+    c->d_kap32 = kap32;
     c->kappa_zero = false;
     c->gamma_field = true;
     return build_local_inverse(c);

@@ -64,9 +64,10 @@ __global__ void tri_u_kernel(Geo g, uint32_t ess, int64_t n_u, const double* __r
     zu[k] = mdinv[k] * (ru[k] + dt);
 }
 
-__global__ void negate_kernel(int64_t n, double* __restrict__ v) {
+// out = -a
+__global__ void negate_kernel(int64_t n, const double* __restrict__ a, double* __restrict__ out) {
     const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
-    if (i < n) v[i] = -v[i];
+    if (i < n) out[i] = -a[i];
 }
 
 // out = a - b
@@ -106,8 +107,7 @@ __global__ void mdot_final_kernel(const double* __restrict__ part, int nb, doubl
     if (threadIdx.x == 0) h[blockIdx.x] = sh[0];
 }
 
-// w -= sum_{j < m} h[j] V_j;  optionally out = w * scale_from (1 / ||w||
-// given later) is a separate kernel
+// w -= sum_{j < m} h[j] V_j
 __global__ void mupdate_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, const double* __restrict__ h,
                                int m, double* __restrict__ w) {
     const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
@@ -137,17 +137,19 @@ __global__ void axpy_kernel(int64_t n, const double* __restrict__ a, double* __r
     if (i < n) x[i] += a[i];
 }
 
+// Device work space of one solve, released on every return path.
 struct GWork {
     double* V = nullptr;     // (m + 1) x N basis
     double *w = nullptr, *z = nullptr, *s = nullptr;
     double *part = nullptr, *h = nullptr;
-    std::vector<double*> all() { return {V, w, z, s, part, h}; }
+    std::vector<double*> all() const { return {V, w, z, s, part, h}; }
+    GWork() = default;
+    GWork(const GWork&) = delete;
+    GWork& operator=(const GWork&) = delete;
+    ~GWork() {
+        for (double* p : all()) dfree(p);
+    }
 };
-
-void free_gwork(GWork& g) {
-    for (double* p : g.all()) dfree(p);
-    g = GWork();
-}
 
 }  // namespace
 
@@ -169,8 +171,7 @@ int launch_tri_precond(hd_ctx* c, const double* r, double* z, double* s_scratch)
         default: TRIU(6); break;
     }
 #undef TRIU
-    HD_HIP(c, hipMemcpyAsync(z + nu, s_scratch, sizeof(double) * nq, hipMemcpyDeviceToDevice, c->stream));
-    hipLaunchKernelGGL(negate_kernel, dim3(nblk(nq)), dim3(BS), 0, c->stream, nq, z + nu);
+    hipLaunchKernelGGL(negate_kernel, dim3(nblk(nq)), dim3(BS), 0, c->stream, nq, (const double*)s_scratch, z + nu);
     HD_HIP(c, hipGetLastError());
     return HD_OK;
 }
@@ -214,10 +215,7 @@ int gmres_solve(hd_ctx* c, double tol, int max_it, int restart, const double* b,
     W.part = dalloc<double>((int64_t)RED * (m + 1));
     W.h = dalloc<double>(m + 1);
     for (double* p : W.all())
-        if (!p) {
-            free_gwork(W);
-            return set_err(c, HD_ERR_OOM, "GMRES basis");
-        }
+        if (!p) return set_err(c, HD_ERR_OOM, "GMRES basis");
     int rc = HD_OK;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), h(m + 1), h2(m + 1), y(m);
     double bnorm = 0.0, rnorm = 0.0;
@@ -305,7 +303,6 @@ int gmres_solve(hd_ctx* c, double tol, int max_it, int restart, const double* b,
         converged = rnorm / bnorm <= tol;
     }
 done:
-    free_gwork(W);
     if (rc) return rc;
     if (info) {
         info->status = converged ? 0 : HD_NOT_CONVERGED;

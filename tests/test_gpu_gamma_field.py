@@ -128,3 +128,26 @@ def test_call_order_and_argument_errors():
         ctx.apply_mass_inverse(y.clone(), y)
     assert e.value.code == hdivsp.HD_ERR_STATE
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", ['mixed', 'prec32'])
+def test_reduced_precision_solves_with_gamma_field(mode):
+    """The FP32 applies and V-cycles of the mixed and FP32-preconditioner
+    solvers use the same gamma-field block; both reach the FP64 true
+    residual."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    case = _case(4, 3, 3, 3, 5)
+    prob = _oracle(case)
+    ctx = _context(case)
+    ctx.build_precond(hdivsp.precond_params(max_coarse=40))
+    b = np.random.default_rng(12).uniform(-1, 1, prob.mesh.n)
+    b[:prob.mesh.n_u][prob.ess] = 0.0
+    md = hdivsp.HD_MODE_MIXED if mode == 'mixed' else hdivsp.HD_MODE_PREC32
+    x = torch.zeros(prob.mesh.n, dtype=torch.float64, device='cuda')
+    info = ctx.minres_solve(to_dev(b), x, hdivsp.solve_params(tol=1e-9, max_it=5000, mode=md, stop_true=1))
+    print(mode, info, flush=True)
+    assert info['status'] == 0 and info['true_rel_res'] <= 1e-9
+    xdir = spla.spsolve(prob.block_matrix().tocsc(), b)
+    assert rel(x.cpu().numpy(), xdir) <= 1e-7
+    ctx.close()
