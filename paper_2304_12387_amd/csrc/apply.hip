@@ -679,17 +679,16 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     uint32_t ess, int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
     CGParams<T> cgp, int with_c, int colour, int64_t part_offset, unsigned nb, const T* __restrict__ winv,
     const double* __restrict__ gvert) {
-    // Block -> (element group, right-hand side).  With several right-hand
-    // sides, the blocks of one element group are spaced 8 apart, so that they
-    // run on the same XCD (blocks are dealt to the 8 XCDs round-robin) at
-    // about the same time and the second and later reads of the group's
-    // geometric factors hit that XCD's L2.
+    // Block -> (element group, right-hand side).  Each XCD (block b runs on
+    // XCD b mod 8) owns a contiguous chunk of element groups and walks it once
+    // per right-hand side, so that neighbouring groups, which share cache
+    // lines of x and y, meet in its L2 as they do with one right-hand side.
     unsigned grp;
     int r = 0;
     if (ra.nrhs > 1) {
-        const unsigned k = blockIdx.x / 8;
-        r = (int)(k % (unsigned)ra.nrhs);
-        grp = (blockIdx.x % 8) * ((nb + 7) / 8) + k / (unsigned)ra.nrhs;
+        const unsigned gpx = (nb + 7) / 8, k = blockIdx.x / 8;
+        r = (int)(k / gpx);
+        grp = (blockIdx.x % 8) * gpx + k % gpx;
     } else {
         grp = xcd_chunk(blockIdx.x, nb);
     }

@@ -53,6 +53,34 @@ def test_apply_several_rhs(c):
     ctx.close()
 
 
+def test_large_mesh_several_rhs_equal_single_calls():
+    """On a mesh of 4,096 element groups per colour (the multi-RHS block
+    mapping walks each XCD's chunk of groups once per right-hand side) every
+    right-hand side equals its single-vector call bit for bit (FP64 and
+    FP32)."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    n1 = 32
+    cfg = inputs.graddiv_jittered(n1, 2)
+    ctx = hdivsp.Context(0)
+    ctx.setup_mesh(n1, n1, n1, 2, cfg['vertices'])
+    ctx.setup_coeffs(0, cfg['c_mass'], cfg['c_22'], 0)
+    nu, nq = ctx.sizes()
+    n = nu + nq
+    R = 3
+    X = torch.from_numpy(np.random.default_rng(8).uniform(-1, 1, R * n)).cuda()
+    for prec, dt in ((hdivsp.HD_F64, torch.float64), (hdivsp.HD_F32, torch.float32)):
+        x = X.to(dt)
+        y = torch.empty_like(x)
+        ctx.apply_block_op(x, y, prec=prec, nrhs=R)
+        for r in range(R):
+            y1 = torch.empty(n, dtype=dt, device='cuda')
+            ctx.apply_block_op(x[r * n:(r + 1) * n].contiguous(), y1, prec=prec)
+            torch.cuda.synchronize()
+            assert torch.equal(y[r * n:(r + 1) * n], y1)
+    ctx.close()
+
+
 def test_precond_several_rhs():
     torch = torch_cuda()
     from paper_2304_12387_amd import hdivsp
