@@ -286,8 +286,10 @@ int hd_batch_tune(hd_ctx* ctx, int prec, int* mode, int* grid, int* tile_groups,
 int hd_batch_set_launch(hd_ctx* ctx, int mode, int grid, int tile_groups);
 /* Each instance's diagonal, S~ and AMG (learned must be 0). */
 int hd_batch_build_precond(hd_ctx* ctx, const hd_precond_params* params);
-/* One MINRES recurrence per instance (HD_MODE_PLAIN64 or HD_MODE_PREC32);
- * info: host array of ninst entries (may be NULL). */
+/* One MINRES recurrence per instance, in any HD_MODE_*.  HD_MODE_MIXED
+ * refines every instance on its own FP64 residual around one batched FP32
+ * MINRES per refinement step (instances already converged get a zero
+ * right-hand side); info: host array of ninst entries (may be NULL). */
 int hd_batch_minres_solve(hd_ctx* ctx, const hd_solve_params* params, const double* b, double* x,
                           hd_solve_info* info);
 

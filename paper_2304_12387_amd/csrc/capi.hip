@@ -808,6 +808,8 @@ int hd_batch_minres_solve(hd_ctx* c, const hd_solve_params* params, const double
         prm.use_graph = 1;
     }
     if (!(prm.tol > 0) || prm.max_it < 1) return set_err(c, HD_ERR_ARG, "bad solve parameters");
+    if (prm.mode == HD_MODE_MIXED && (!(prm.inner_tol > 0) || prm.max_outer < 1))
+        return set_err(c, HD_ERR_ARG, "HD_MODE_MIXED needs inner_tol > 0 and max_outer >= 1");
     int rc = use_device(c);
     if (rc) return rc;
     rc = batch_minres_solve(c, prm, b, x, info);

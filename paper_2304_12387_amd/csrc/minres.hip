@@ -639,7 +639,8 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
 // V-cycle, i.e. the AMG of the block-diagonal union) run per instance.
 struct BatchWork {
     int64_t total = 0;
-    double *v = nullptr, *vo = nullptr, *z = nullptr, *zn = nullptr, *w = nullptr, *wo = nullptr, *q = nullptr;
+    // the recurrence vectors, of the solve's working precision
+    void *v = nullptr, *vo = nullptr, *z = nullptr, *zn = nullptr, *w = nullptr, *wo = nullptr, *q = nullptr;
     double *pu = nullptr, *pr = nullptr, *pq = nullptr, *nrm = nullptr;
     std::vector<int64_t> pq_off, nq_part;
     MinresState* st = nullptr;
@@ -647,7 +648,8 @@ struct BatchWork {
     double* nrm_host = nullptr;
     Work schur32;   // FP32 Schur buffers (sized for the largest instance)
     ~BatchWork() {
-        for (double* p : {v, vo, z, zn, w, wo, q, pu, pr, pq, nrm}) dfree(p);
+        for (void* p : {v, vo, z, zn, w, wo, q}) dfree(p);
+        for (double* p : {pu, pr, pq, nrm}) dfree(p);
         dfree(st);
         if (st_host) (void)hipHostFree(st_host);
         if (nrm_host) (void)hipHostFree(nrm_host);
@@ -657,15 +659,19 @@ struct BatchWork {
     }
 };
 
-int batch_true_residual(hd_ctx* c, BatchWork& W, const double* b, const double* x) {
+// ||b_i - A_i x_i|| and ||b_i|| of every instance into W.nrm_host (and the
+// device copy W.nrm); r (optional) receives b - A x.  W holds FP64 vectors.
+int batch_true_residual(hd_ctx* c, BatchWork& W, const double* b, const double* x, double* r = nullptr) {
     const BatchState& B = *c->batch;
     const int ni = (int)B.inst.size();
+    const double* q = (const double*)W.q;
     int rc;
     if ((rc = launch_batch_apply(c, HD_F64, x, W.q, nullptr, 0, nullptr, 0, false))) return rc;
     for (int i = 0; i < ni; ++i) {
         const int64_t o = B.off[i], N = B.off[i + 1] - B.off[i];
-        hipLaunchKernelGGL(k_residual, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, b + o, (const double*)W.q + o,
-                           (double*)nullptr, W.pu + (int64_t)i * RED_BLOCKS, W.pr + (int64_t)i * RED_BLOCKS);
+        hipLaunchKernelGGL(k_residual, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, b + o, q + o,
+                           r ? r + o : (double*)nullptr, W.pu + (int64_t)i * RED_BLOCKS,
+                           W.pr + (int64_t)i * RED_BLOCKS);
         hipLaunchKernelGGL(k_norms, dim3(1), dim3(1024), 0, c->stream, W.pu + (int64_t)i * RED_BLOCKS,
                            W.pr + (int64_t)i * RED_BLOCKS, (int64_t)red_grid(N), W.nrm + 2 * i);
     }
@@ -674,59 +680,65 @@ int batch_true_residual(hd_ctx* c, BatchWork& W, const double* b, const double* 
     return HD_OK;
 }
 
-template <typename PT>
-int batch_minres_core(hd_ctx* c, BatchWork& W, const double* b, double* x, bool use_x0, double tol, int maxit,
+// One MINRES recurrence per instance in precision T (vectors and operator;
+// the recurrence scalars and reductions are FP64), b of precision Bv, x of
+// precision T, Schur block in precision PT.  true_tol > 0 (FP64 only): after
+// the |eta| stop, require the true FP64 residual as in the single solve.
+template <typename T, typename Bv, typename PT>
+int batch_minres_core(hd_ctx* c, BatchWork& W, const Bv* b, T* x, bool use_x0, double tol, int maxit,
                       int check_every, double true_tol, std::vector<hd_solve_info>& out) {
+    constexpr bool F64 = std::is_same<T, double>::value;
+    const int prec = F64 ? HD_F64 : HD_F32;
     const BatchState& B = *c->batch;
     const int ni = (int)B.inst.size();
     const int64_t tot = B.total;
-    double *v = W.v, *vo = W.vo, *z = W.z, *zn = W.zn, *w = W.w, *wo = W.wo, *q = W.q;
+    T *v = (T*)W.v, *vo = (T*)W.vo, *z = (T*)W.z, *zn = (T*)W.zn, *w = (T*)W.w, *wo = (T*)W.wo, *q = (T*)W.q;
     int rc;
     if (use_x0) {
-        if ((rc = launch_batch_apply(c, HD_F64, x, q, nullptr, 0, nullptr, 0, false))) return rc;
-        hipLaunchKernelGGL((k_init<double, double>), dim3(nblk(tot)), dim3(BS), 0, c->stream, tot, b,
-                           (const double*)q, v, vo, w, wo);
+        if ((rc = launch_batch_apply(c, prec, x, q, nullptr, 0, nullptr, 0, false))) return rc;
+        hipLaunchKernelGGL((k_init<T, Bv>), dim3(nblk(tot)), dim3(BS), 0, c->stream, tot, b, (const T*)q, v, vo, w,
+                           wo);
     } else {
-        hipLaunchKernelGGL(k_zero<double>, dim3(nblk(tot)), dim3(BS), 0, c->stream, tot, x);
-        hipLaunchKernelGGL((k_init<double, double>), dim3(nblk(tot)), dim3(BS), 0, c->stream, tot, b,
-                           (const double*)nullptr, v, vo, w, wo);
+        hipLaunchKernelGGL(k_zero<T>, dim3(nblk(tot)), dim3(BS), 0, c->stream, tot, x);
+        hipLaunchKernelGGL((k_init<T, Bv>), dim3(nblk(tot)), dim3(BS), 0, c->stream, tot, b, (const T*)nullptr, v,
+                           vo, w, wo);
     }
     for (int i = 0; i < ni; ++i) {
         hd_ctx* s = B.inst[i];
         const int64_t o = B.off[i];
-        if ((rc = launch_diag_prec(s, HD_F64, v + o, z + o, W.pu + (int64_t)i * RED_BLOCKS))) return rc;
-        if ((rc = schur_step<double, PT>(s, W.schur32, v + o + s->n_u, z + o + s->n_u, W.pq + W.pq_off[i], nullptr)))
+        if ((rc = launch_diag_prec(s, prec, v + o, z + o, W.pu + (int64_t)i * RED_BLOCKS))) return rc;
+        if ((rc = schur_step<T, PT>(s, W.schur32, v + o + s->n_u, z + o + s->n_u, W.pq + W.pq_off[i], nullptr)))
             return rc;
         hipLaunchKernelGGL(k_start, dim3(1), dim3(1024), 0, c->stream, W.st + i, W.pu + (int64_t)i * RED_BLOCKS,
                            (int64_t)red_grid(s->n_u), (int64_t)RED_BLOCKS, W.pq + W.pq_off[i],
-                           schur_parts<double, PT>(s), W.nq_part[i], tol);
+                           schur_parts<T, PT>(s), W.nq_part[i], tol);
     }
     HD_HIP(c, hipGetLastError());
     int launched = 0, retargets = 0;
     for (;;) {
         for (int k = 0; k < check_every && launched < maxit; ++k, ++launched) {
-            if ((rc = launch_batch_apply(c, HD_F64, z, q, &W.st->inv_gamma, ST_STRIDE_D, &W.st->stop, ST_STRIDE_I,
+            if ((rc = launch_batch_apply(c, prec, z, q, &W.st->inv_gamma, ST_STRIDE_D, &W.st->stop, ST_STRIDE_I,
                                          true)))
                 return rc;
             for (int i = 0; i < ni; ++i) {
                 hd_ctx* s = B.inst[i];
                 const int64_t o = B.off[i], N = s->n_u + s->n_q, np = apply_partial_count(s);
                 const int* stop_i = &W.st[i].stop;
+                const T* mdinv = F64 ? (const T*)s->d_mdinv : (const T*)s->d_mdinv32;
                 hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), 0, c->stream, W.st + i,
                                    (const double*)(c->batch->d_part + c->batch->part_off[i]), np, np);
-                hipLaunchKernelGGL(k_vupd<double>, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, s->n_u,
-                                   (const double*)q + o, (const double*)v + o, vo + o, (const double*)s->d_mdinv,
-                                   zn + o, (const MinresState*)(W.st + i), W.pu + (int64_t)i * RED_BLOCKS);
-                if ((rc = schur_step<double, PT>(s, W.schur32, vo + o + s->n_u, zn + o + s->n_u, W.pq + W.pq_off[i],
-                                                 stop_i)))
+                hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, s->n_u,
+                                   (const T*)q + o, (const T*)v + o, vo + o, mdinv, zn + o,
+                                   (const MinresState*)(W.st + i), W.pu + (int64_t)i * RED_BLOCKS);
+                if ((rc = schur_step<T, PT>(s, W.schur32, vo + o + s->n_u, zn + o + s->n_u, W.pq + W.pq_off[i],
+                                            stop_i)))
                     return rc;
                 hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, W.st + i,
                                    (const double*)(W.pu + (int64_t)i * RED_BLOCKS), (int64_t)red_grid(N),
                                    (int64_t)RED_BLOCKS, (const double*)(W.pq + W.pq_off[i]),
-                                   schur_parts<double, PT>(s), W.nq_part[i], maxit);
-                hipLaunchKernelGGL((k_wupd<double, double>), dim3(nblk(N), 1), dim3(BS), 0, c->stream, N,
-                                   (const double*)z + o, wo + o, (const double*)w + o, x + o,
-                                   (const MinresState*)(W.st + i));
+                                   schur_parts<T, PT>(s), W.nq_part[i], maxit);
+                hipLaunchKernelGGL((k_wupd<T, T>), dim3(nblk(N), 1), dim3(BS), 0, c->stream, N, (const T*)z + o,
+                                   wo + o, (const T*)w + o, x + o, (const MinresState*)(W.st + i));
             }
             std::swap(v, vo);
             std::swap(z, zn);
@@ -737,28 +749,30 @@ int batch_minres_core(hd_ctx* c, BatchWork& W, const double* b, double* x, bool 
         HD_HIP(c, hipStreamSynchronize(c->stream));
         bool all_stop = true;
         for (int i = 0; i < ni; ++i) all_stop = all_stop && W.st_host[i].stop;
-        if (all_stop && true_tol > 0.0 && retargets < 8) {
-            if ((rc = batch_true_residual(c, W, b, x))) return rc;
-            bool resumed = false;
-            for (int i = 0; i < ni; ++i) {
-                const MinresState& st = W.st_host[i];
-                const double rel = rel_of(W.nrm_host, i);
-                if (st.status != 0 || rel <= true_tol) continue;
-                hd_ctx* s = B.inst[i];
-                const int64_t o = B.off[i], N = s->n_u + s->n_q;
-                if ((st.iter % 2) != (launched % 2)) {
-                    double* pairs[3][2] = {{v, vo}, {z, zn}, {w, wo}};
-                    for (auto& pr : pairs)
-                        hipLaunchKernelGGL(k_swap<double>, dim3(nblk(N)), dim3(BS), 0, c->stream, N, pr[0] + o,
-                                           pr[1] + o);
+        if constexpr (F64 && std::is_same<Bv, double>::value) {
+            if (all_stop && true_tol > 0.0 && retargets < 8) {
+                if ((rc = batch_true_residual(c, W, b, x))) return rc;
+                bool resumed = false;
+                for (int i = 0; i < ni; ++i) {
+                    const MinresState& st = W.st_host[i];
+                    const double rel = rel_of(W.nrm_host, i);
+                    if (st.status != 0 || rel <= true_tol) continue;
+                    hd_ctx* s = B.inst[i];
+                    const int64_t o = B.off[i], N = s->n_u + s->n_q;
+                    if ((st.iter % 2) != (launched % 2)) {
+                        T* pairs[3][2] = {{v, vo}, {z, zn}, {w, wo}};
+                        for (auto& pr : pairs)
+                            hipLaunchKernelGGL(k_swap<T>, dim3(nblk(N)), dim3(BS), 0, c->stream, N, pr[0] + o,
+                                               pr[1] + o);
+                    }
+                    hipLaunchKernelGGL(k_retarget, dim3(1), dim3(1), 0, c->stream, W.st + i,
+                                       st.tol * (true_tol / rel) * 0.7);
+                    resumed = true;
                 }
-                hipLaunchKernelGGL(k_retarget, dim3(1), dim3(1), 0, c->stream, W.st + i,
-                                   st.tol * (true_tol / rel) * 0.7);
-                resumed = true;
-            }
-            if (resumed) {
-                ++retargets;
-                if (launched < maxit) continue;
+                if (resumed) {
+                    ++retargets;
+                    if (launched < maxit) continue;
+                }
             }
         }
         if (all_stop || launched >= maxit) break;
@@ -918,18 +932,17 @@ int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* 
     return worst;
 }
 
-int batch_minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, double* x, hd_solve_info* info) {
-    auto t0 = std::chrono::steady_clock::now();
+// Vectors (element size es), partial sums and pinned state of a batched
+// solve; schur32 adds the FP32 Schur buffers of an FP64 recurrence.
+int alloc_batch_work(hd_ctx* c, BatchWork& W, size_t es, bool schur32) {
     const BatchState& B = *c->batch;
     const int ni = (int)B.inst.size();
-    if (prm.mode != HD_MODE_PLAIN64 && prm.mode != HD_MODE_PREC32)
-        return set_err(c, HD_ERR_ARG, "batched solves support HD_MODE_PLAIN64 and HD_MODE_PREC32");
-    BatchWork W;
     W.total = B.total;
-    for (double** p : {&W.v, &W.vo, &W.z, &W.zn, &W.w, &W.wo, &W.q}) {
-        *p = dalloc<double>(B.total);
-        if (!*p) return set_err(c, HD_ERR_OOM, "batched MINRES vectors");
-    }
+    for (void** p : {&W.v, &W.vo, &W.z, &W.zn, &W.w, &W.wo, &W.q})
+        if (hipMalloc(p, es * (size_t)B.total) != hipSuccess) {
+            *p = nullptr;
+            return set_err(c, HD_ERR_OOM, "batched MINRES vectors");
+        }
     int64_t pq_tot = 0, nq_max = 0;
     for (int i = 0; i < ni; ++i) {
         const int64_t np = std::max<int64_t>(schur_partial_count(B.inst[i]), RED_BLOCKS);
@@ -947,7 +960,7 @@ int batch_minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, d
     if (hipHostMalloc((void**)&W.st_host, sizeof(MinresState) * ni) != hipSuccess ||
         hipHostMalloc((void**)&W.nrm_host, sizeof(double) * 2 * ni) != hipSuccess)
         return set_err(c, HD_ERR_OOM, "batched MINRES host state");
-    if (prm.mode == HD_MODE_PREC32) {
+    if (schur32) {
         int64_t npm = 0;
         for (int i = 0; i < ni; ++i) npm = std::max(npm, W.nq_part[i]);
         W.schur32.t32 = dalloc<float>(nq_max);
@@ -955,12 +968,110 @@ int batch_minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, d
         W.schur32.p32 = dalloc<double>(npm);
         if (!W.schur32.t32 || !W.schur32.z32 || !W.schur32.p32) return set_err(c, HD_ERR_OOM, "FP32 Schur buffers");
     }
+    return HD_OK;
+}
+
+// Device buffers released on every return path.
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    ~DevBuf() { dfree(p); }
+};
+
+// HD_MODE_MIXED for a batch: FP64 residual of every instance, FP32 batched
+// MINRES on the normalised residuals to inner_tol, FP64 update of x, until
+// each instance meets tol on its true residual (instances that have, get a
+// zero right-hand side, on which their inner recurrence stops at once).
+int batch_mixed(hd_ctx* c, BatchWork& W, const hd_solve_params& prm, const double* b, double* x, int check,
+                std::vector<hd_solve_info>& res) {
+    const BatchState& B = *c->batch;
+    const int ni = (int)B.inst.size();
+    BatchWork W32;
+    int rc = alloc_batch_work(c, W32, sizeof(float), false);
+    if (rc) return rc;
+    DevBuf<double> r;
+    DevBuf<float> r32, d32;
+    r.p = dalloc<double>(B.total);
+    r32.p = dalloc<float>(B.total);
+    d32.p = dalloc<float>(B.total);
+    if (!r.p || !r32.p || !d32.p) return set_err(c, HD_ERR_OOM, "refinement vectors");
+    if (!prm.use_x0) hipLaunchKernelGGL(k_zero<double>, dim3(nblk(B.total)), dim3(BS), 0, c->stream, B.total, x);
+    std::vector<int> total(ni, 0), status(ni, HD_NOT_CONVERGED);
+    std::vector<double> er(ni, 0.0);
+    std::vector<hd_solve_info> inner;
+    int outer = 0;
+    for (;;) {
+        if ((rc = batch_true_residual(c, W, b, x, r.p))) return rc;
+        bool all = true;
+        for (int i = 0; i < ni; ++i) {
+            if (status[i] < 0) continue;
+            if (rel_of(W.nrm_host, i) <= prm.tol) {
+                status[i] = 0;
+                W.nrm_host[2 * i] = 0.0;
+            } else {
+                status[i] = HD_NOT_CONVERGED;
+                all = false;
+            }
+        }
+        if (all || outer >= prm.max_outer) break;
+        HD_HIP(c, hipMemcpyAsync(W.nrm, W.nrm_host, 2 * ni * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        for (int i = 0; i < ni; ++i) {
+            const int64_t o = B.off[i], N = B.off[i + 1] - B.off[i];
+            hipLaunchKernelGGL(k_to32, dim3(nblk(N), 1), dim3(BS), 0, c->stream, N, (const double*)r.p + o,
+                               (const double*)W.nrm + 2 * i, r32.p + o);
+        }
+        if ((rc = batch_minres_core<float, float, float>(c, W32, r32.p, d32.p, false, prm.inner_tol, prm.max_it,
+                                                          check, 0.0, inner)))
+            return rc;
+        ++outer;
+        bool brk = false;
+        for (int i = 0; i < ni; ++i) {
+            total[i] += inner[i].iterations;
+            er[i] = inner[i].eta_rel;
+            if (inner[i].status < 0) {
+                status[i] = inner[i].status;
+                brk = true;
+            }
+        }
+        if (brk) break;
+        for (int i = 0; i < ni; ++i) {
+            const int64_t o = B.off[i], N = B.off[i + 1] - B.off[i];
+            hipLaunchKernelGGL(k_addscaled, dim3(nblk(N), 1), dim3(BS), 0, c->stream, N, (const float*)d32.p + o,
+                               (const double*)W.nrm + 2 * i, x + o);
+        }
+    }
+    HD_HIP(c, hipGetLastError());
+    res.resize(ni);
+    for (int i = 0; i < ni; ++i) {
+        res[i] = hd_solve_info();
+        res[i].iterations = total[i];
+        res[i].outer = outer;
+        res[i].eta_rel = er[i];
+        res[i].status = status[i];
+    }
+    return HD_OK;
+}
+
+int batch_minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, double* x, hd_solve_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    const BatchState& B = *c->batch;
+    const int ni = (int)B.inst.size();
+    if (prm.mode != HD_MODE_PLAIN64 && prm.mode != HD_MODE_PREC32 && prm.mode != HD_MODE_MIXED)
+        return set_err(c, HD_ERR_ARG, "solve mode not supported");
+    BatchWork W;
+    int rc = alloc_batch_work(c, W, sizeof(double), prm.mode == HD_MODE_PREC32);
+    if (rc) return rc;
     const int check = prm.check_every > 0 ? prm.check_every : 8;
     std::vector<hd_solve_info> res;
     const double tt = prm.stop_true ? prm.tol : 0.0;
-    int rc = prm.mode == HD_MODE_PLAIN64
-                 ? batch_minres_core<double>(c, W, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, tt, res)
-                 : batch_minres_core<float>(c, W, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, tt, res);
+    if (prm.mode == HD_MODE_PLAIN64)
+        rc = batch_minres_core<double, double, double>(c, W, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, tt,
+                                                       res);
+    else if (prm.mode == HD_MODE_PREC32)
+        rc = batch_minres_core<double, double, float>(c, W, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, tt,
+                                                      res);
+    else
+        rc = batch_mixed(c, W, prm, b, x, check, res);
     if (rc) return rc;
     if ((rc = batch_true_residual(c, W, b, x))) return rc;
     const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -107,3 +107,71 @@ def test_batch_minres_matches_solo_solves(mode):
             _, ito, _ = minres.minres(prob.apply, P, b[seg], tol=1e-10)
             assert abs(infos[i]['iterations'] - ito) <= 2
     ctx.close()
+
+
+def test_batch_mixed_refinement_meets_the_fp64_tolerance():
+    """HD_MODE_MIXED on a batch: each instance reaches the FP64 tolerance on
+    its own true residual and its solution matches the oracle's direct solve
+    of the same system; the inner iterations per instance stay within a few
+    of the solo mixed solve (the batched and solo FP32 operators round
+    alike up to the summation order)."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    import scipy.sparse.linalg as spla
+    I = inputs.batch_instances(n_inst=4, seed=13, nmin=2, nmax=4, pmin=1, pmax=3)
+    I[2]['ess_sides'] = 21
+    ctx = hdivsp.Context(0)
+    ctx.setup_batch(0, I)
+    pp = hdivsp.precond_params(max_coarse=40)
+    ctx.batch_build_precond(pp)
+    off = ctx.batch_offsets
+    b = np.random.default_rng(5).uniform(-1, 1, int(off[-1]))
+    probs = []
+    for i, d in enumerate(I):
+        prob = oracle_problem(d)
+        probs.append(prob)
+        if d['ess_sides']:
+            b[off[i]:off[i] + prob.mesh.n_u][prob.ess] = 0.0
+    # instance 3 starts converged: its right-hand side is zero
+    b[off[3]:off[4]] = 0.0
+    sp = hdivsp.solve_params(tol=1e-10, max_it=3000, mode=hdivsp.HD_MODE_MIXED, inner_tol=1e-5)
+    bd = to_dev(b)
+    xd = torch.full_like(bd, np.nan)
+    infos = ctx.batch_minres_solve(bd, xd, sp)
+    x = xd.cpu().numpy()
+    print('mixed', [(f['iterations'], f['outer'], f['true_rel_res']) for f in infos], flush=True)
+    for i, d in enumerate(I):
+        seg = slice(off[i], off[i + 1])
+        assert infos[i]['status'] == 0, (i, infos[i])
+        if i == 3:
+            assert infos[i]['iterations'] == 0 and np.all(x[seg] == 0.0)
+            continue
+        assert infos[i]['true_rel_res'] <= 1e-10 and infos[i]['outer'] >= 2
+        # kappa_2(A) <= 1e5 for these instances, so a true relative residual
+        # of 1e-10 bounds the relative error by 1e-5
+        ref = spla.spsolve(probs[i].block_matrix().tocsc(), b[seg])
+        assert rel(x[seg], ref) <= 1e-5, (i, rel(x[seg], ref))
+        solo = gpu_context(d, precond=True, params=pp)
+        xs = torch.zeros(int(off[i + 1] - off[i]), dtype=torch.float64, device='cuda')
+        inf = solo.minres_solve(to_dev(b[seg]), xs, sp)
+        solo.close()
+        assert inf['status'] == 0 and inf['outer'] == infos[i]['outer'], (i, inf, infos[i])
+        assert abs(inf['iterations'] - infos[i]['iterations']) <= 2 * inf['outer'], (i, inf, infos[i])
+    ctx.close()
+
+
+def test_batch_mixed_rejects_bad_refinement_parameters():
+    from paper_2304_12387_amd import hdivsp
+    I = inputs.batch_instances(n_inst=2, seed=3, nmin=2, nmax=2, pmin=1, pmax=2)
+    ctx = hdivsp.Context(0)
+    ctx.setup_batch(0, I)
+    ctx.batch_build_precond(hdivsp.precond_params(max_coarse=40))
+    torch = torch_cuda()
+    n = int(ctx.batch_offsets[-1])
+    bd = torch.ones(n, dtype=torch.float64, device='cuda')
+    xd = torch.zeros_like(bd)
+    for bad in (dict(inner_tol=0.0), dict(max_outer=0)):
+        with pytest.raises(hdivsp.HdError) as e:
+            ctx.batch_minres_solve(bd, xd, hdivsp.solve_params(mode=hdivsp.HD_MODE_MIXED, **bad))
+        assert e.value.code == hdivsp.HD_ERR_ARG
+    ctx.close()
