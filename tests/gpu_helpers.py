@@ -49,3 +49,34 @@ def to_dev(a, dtype=None):
 
 def rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
+
+
+def apply_np(ctx, x, prec=0):
+    """y = A x through the block apply (prec 0: FP64, 1: FP32) for a host
+    array x; returns y as a float64 host array."""
+    torch = torch_cuda()
+    xd = to_dev(x) if prec == 0 else to_dev(x).float()
+    yd = torch.full_like(xd, np.nan)
+    ctx.apply_block_op(xd, yd, prec=prec)
+    torch.cuda.synchronize()
+    return yd.double().cpu().numpy()
+
+
+def c_block_errors(ctx, apply_ref, n_u, n, seed=19):
+    """The (2,2) block alone.  With u = 0 the L2 rows of A x are -C q~, since
+    D u vanishes.  On random inputs C q~ is orders of magnitude smaller than
+    D u (W scales with the inverse element volume), so a check of the whole
+    vector says little about the local solves; this one isolates them.
+    Returns the relative errors of those rows in FP64 and FP32 (0 when the
+    block is zero and the GPU rows are exactly zero)."""
+    x = np.random.default_rng(seed).uniform(-1, 1, n)
+    x[:n_u] = 0.0
+    ref = apply_ref(x)[n_u:]
+    out = []
+    for prec in (0, 1):
+        y = apply_np(ctx, x, prec)[n_u:]
+        if not np.linalg.norm(ref) > 0:
+            out.append(0.0 if not np.any(y) else np.inf)
+        else:
+            out.append(rel(y, ref))
+    return out

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from gpu_helpers import gpu_context, make_case, oracle_problem, rel, to_dev, torch_cuda
+from gpu_helpers import c_block_errors, gpu_context, make_case, oracle_problem, rel, to_dev, torch_cuda
 from oracle import assemble, precond
 
 pytestmark = pytest.mark.gpu
@@ -60,6 +60,11 @@ def test_block_apply_f64_and_f32(c):
     ctx.apply_block_op(xd, yd)
     torch.cuda.synchronize()
     assert np.array_equal(yd.cpu().numpy(), y)
+    # each block row on its own, and the (2,2) block alone
+    assert rel(y[:nu], y_ref[:nu]) <= 1e-12 and rel(y[nu:], y_ref[nu:]) <= 1e-12
+    e64, e32 = c_block_errors(ctx, prob.apply, nu, nu + nq)
+    print('C block', e64, e32, flush=True)
+    assert e64 <= 1e-12 and e32 <= 1e-5, (e64, e32)
     ctx.close()
 
 
@@ -122,6 +127,17 @@ def test_full_size_graddiv_32_p4_sampled_rows_and_symmetry():
     qr, yq, ur, yu = assemble.apply_element_rows(mesh, 0, cfg['c_mass'], cfg['c_22'], 0, x, elems)
     assert rel(y[qr], yq) <= 1e-12
     assert rel(y[ur], yu) <= 1e-12
+    # the (2,2) block alone: with u = 0 the L2 rows are -C q~, which is far
+    # smaller than D u on random inputs
+    xc = x.copy()
+    xc[:nu] = 0.0
+    ycd = torch.empty_like(xd)
+    ctx.apply_block_op(to_dev(xc), ycd)
+    torch.cuda.synchronize()
+    qc, yqc, _, _ = assemble.apply_element_rows(mesh, 0, cfg['c_mass'], cfg['c_22'], 0, xc, elems)
+    print('C block rows', rel(ycd.cpu().numpy()[qc], yqc), flush=True)
+    assert rel(ycd.cpu().numpy()[qc], yqc) <= 1e-12
+    del ycd
     z = to_dev(inputs.uniform_vector(nu + nq, 33))
     az = torch.empty_like(z)
     ctx.apply_block_op(z, az)

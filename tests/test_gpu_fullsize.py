@@ -1,0 +1,132 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configurations the benchmark times, on sampled rows the oracle computes from
+the sampled elements' own matrices (all L2 rows of an element and the RT rows
+strictly inside it):
+
+* the 64^3, p = 3 grad-div mesh with 16 right-hand sides in FP32 (one
+  multi-right-hand-side launch per colour);
+* the 32 independent grad-div instances (n^3, n in 8..40, p in 1..6) in one
+  batched launch, with the autotuned configuration, in FP64 and FP32;
+* the 48^3, p = 4 distorted grad-div mesh with 1e4 coefficient contrast.
+
+Some inputs have u = 0, so that their L2 rows are -C q~ alone: on random
+inputs C q~ is orders of magnitude smaller than D u (W scales with the
+inverse element volume) and a sample of whole rows would hardly see the
+local solves.
+
+Tolerances: 1e-12 relative in FP64 and 1e-5 in FP32 over each sample."""
+import numpy as np
+import pytest
+
+from gpu_helpers import rel, torch_cuda
+from oracle import assemble
+from paper_2304_12387_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample(ne):
+    # corners of the element grid, an interior element, a ragged index
+    return np.unique(np.array([0, ne - 1, ne // 2 + 7, (3 * ne) // 4 + 1]))
+
+
+def _oracle_rows(mesh, d, x, elems):
+    return assemble.apply_element_rows(mesh, d['problem'], d['c_mass'], d['c_22'], d['ess_sides'], x, elems)
+
+
+def _check_rows(ref, y, tol, label):
+    qr, yq, ur, yu = ref
+    eq, eu = rel(y[qr], yq), rel(y[ur], yu)
+    print(label, 'L2 rows', eq, 'RT rows', eu, flush=True)
+    assert eq <= tol and eu <= tol, (label, eq, eu)
+
+
+def test_multirhs_64_p3_16_rhs_fp32():
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    cfg = inputs.graddiv_jittered(64, 3, seed_mesh=4, seed_coef=14)
+    print('full size', cfg['name'], 'x16 FP32', flush=True)
+    ctx = hdivsp.Context(0)
+    ctx.setup_mesh(cfg['nx'], cfg['ny'], cfg['nz'], cfg['p'], cfg['vertices'])
+    ctx.setup_coeffs(cfg['problem'], cfg['c_mass'], cfg['c_22'], cfg['ess_sides'])
+    nu, nq = ctx.sizes()
+    N, R = nu + nq, 16
+    X = np.random.default_rng(64).uniform(-1.0, 1.0, N * R).astype(np.float32)
+    X[15 * N:15 * N + nu] = 0.0     # right-hand side 15: the (2,2) block alone
+    xd = torch.from_numpy(X).cuda()
+    yd = torch.full_like(xd, float('nan'))
+    ctx.apply_block_op(xd, yd, prec=hdivsp.HD_F32, nrhs=R)
+    torch.cuda.synchronize()
+    Y = yd.cpu().numpy()
+    assert np.isfinite(Y).all()
+    del xd, yd
+    mesh = assemble.Mesh(64, 64, 64, 3, cfg['vertices'])
+    elems = _sample(mesh.ne)
+    for r in (0, 7, 15):
+        seg = slice(r * N, (r + 1) * N)
+        ref = _oracle_rows(mesh, cfg, X[seg].astype(np.float64), elems)
+        _check_rows(ref, Y[seg].astype(np.float64), 1e-5, f'rhs {r}')
+    ctx.close()
+
+
+def test_batch_32_instances_tuned_launch():
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    I = inputs.batch_instances()
+    print('full size batch of', len(I), 'instances', flush=True)
+    ctx = hdivsp.Context(0)
+    ctx.setup_batch(0, I)
+    off = ctx.batch_offsets
+    n = int(off[-1])
+    # FP32-representable input: the FP64 and FP32 launches see the same x
+    x = np.random.default_rng(32).uniform(-1.0, 1.0, n).astype(np.float32)
+    meshes = [assemble.Mesh(d['nx'], d['ny'], d['nz'], d['p'], d['vertices']) for d in I]
+    for i in range(1, len(I), 2):   # odd instances: the (2,2) block alone
+        x[int(off[i]):int(off[i]) + meshes[i].n_u] = 0.0
+    ys = {}
+    for prec, dt in ((hdivsp.HD_F64, torch.float64), (hdivsp.HD_F32, torch.float32)):
+        tuned = ctx.batch_tune(prec)
+        print('tuned', prec, tuned, flush=True)
+        xd = torch.from_numpy(x).cuda().to(dt)
+        yd = torch.full_like(xd, float('nan'))
+        ctx.batch_apply(xd, yd, prec=prec)
+        torch.cuda.synchronize()
+        ys[prec] = yd.cpu().numpy().astype(np.float64)
+        del xd, yd
+        assert np.isfinite(ys[prec]).all()
+    ctx.close()
+    xs = x.astype(np.float64)
+    for i, d in enumerate(I):
+        seg = slice(int(off[i]), int(off[i + 1]))
+        mesh = meshes[i]
+        # two elements at p >= 5, where the oracle's element matrices are slow
+        elems = _sample(mesh.ne)[:2] if d['p'] >= 5 else _sample(mesh.ne)
+        ref = _oracle_rows(mesh, d, xs[seg], elems)
+        _check_rows(ref, ys[hdivsp.HD_F64][seg], 1e-12, f'FP64 {d["name"]}')
+        _check_rows(ref, ys[hdivsp.HD_F32][seg], 1e-5, f'FP32 {d["name"]}')
+
+
+def test_distorted_48_p4():
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    cfg = inputs.graddiv_distorted(48, 4)
+    print('full size', cfg['name'], flush=True)
+    ctx = hdivsp.Context(0)
+    ctx.setup_mesh(cfg['nx'], cfg['ny'], cfg['nz'], cfg['p'], cfg['vertices'])
+    ctx.setup_coeffs(cfg['problem'], cfg['c_mass'], cfg['c_22'], cfg['ess_sides'])
+    nu, nq = ctx.sizes()
+    x = inputs.uniform_vector(nu + nq, 48).astype(np.float32)
+    mesh = assemble.Mesh(48, 48, 48, 4, cfg['vertices'])
+    xc = x.copy()
+    xc[:nu] = 0.0                   # the (2,2) block alone
+    for label, xi in (('whole', x), ('u = 0', xc)):
+        ref = _oracle_rows(mesh, cfg, xi.astype(np.float64), _sample(mesh.ne))
+        for prec, dt, tol in ((hdivsp.HD_F64, torch.float64, 1e-12), (hdivsp.HD_F32, torch.float32, 1e-5)):
+            xd = torch.from_numpy(xi).cuda().to(dt)
+            yd = torch.full_like(xd, float('nan'))
+            ctx.apply_block_op(xd, yd, prec=prec)
+            torch.cuda.synchronize()
+            y = yd.cpu().numpy().astype(np.float64)
+            assert np.isfinite(y).all()
+            _check_rows(ref, y, tol, f'{label} prec {prec}')
+    ctx.close()

@@ -8,7 +8,7 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from gpu_helpers import make_case, rel, to_dev, torch_cuda
+from gpu_helpers import c_block_errors, make_case, rel, to_dev, torch_cuda
 from oracle import assemble, minres, precond
 from paper_2304_12387_amd import inputs
 
@@ -60,6 +60,10 @@ def test_apply_matches_oracle(c):
         y = _apply(ctx, x)
         assert rel(y, ref) <= 1e-12, (mode, rel(y, ref))
         assert rel(_apply(ctx, x, prec=1), ref) <= 1e-5
+        # W^{-1} W_gamma W^{-1} alone (u = 0)
+        e64, e32 = c_block_errors(ctx, prob.apply, prob.mesh.n_u, prob.mesh.n)
+        print('C block', mode, e64, e32, flush=True)
+        assert e64 <= 1e-12 and e32 <= 1e-5, (mode, e64, e32)
         ctx.close()
 
 

@@ -6,7 +6,7 @@ either local solver."""
 import numpy as np
 import pytest
 
-from gpu_helpers import gpu_context, make_case, oracle_problem, rel, to_dev, torch_cuda
+from gpu_helpers import c_block_errors, gpu_context, make_case, oracle_problem, rel, to_dev, torch_cuda
 from oracle import minres, precond
 
 pytestmark = pytest.mark.gpu
@@ -43,6 +43,12 @@ def test_explicit_and_cg_agree_with_oracle(c):
     nu = prob.mesh.n_u
     assert np.array_equal(y_ex[:nu], y_cg[:nu])
     assert rel(y_ex[nu:], y_cg[nu:]) <= 1e-13
+    # the (2,2) block alone, with either local solver
+    for mode in (hdivsp.HD_LOCAL_EXPLICIT, hdivsp.HD_LOCAL_CG):
+        ctx.set_local_solver(mode)
+        e64, e32 = c_block_errors(ctx, prob.apply, nu, prob.mesh.n)
+        print('C block', mode, e64, e32, flush=True)
+        assert e64 <= 1e-12 and e32 <= 1e-5, (mode, e64, e32)
     ctx.close()
 
 
