@@ -62,6 +62,16 @@ def apply_np(ctx, x, prec=0):
     return yd.double().cpu().numpy()
 
 
+def m_block_errors(ctx, apply_ref, n_u, n, seed=18):
+    """The (1,1) block alone.  With q~ = 0 the RT rows of A x are M u, since
+    D^T q~ vanishes (M u is about h times D^T q~ on random inputs).  Returns
+    the relative errors of those rows in FP64 and FP32."""
+    x = np.random.default_rng(seed).uniform(-1, 1, n)
+    x[n_u:] = 0.0
+    ref = apply_ref(x)[:n_u]
+    return [rel(apply_np(ctx, x, prec)[:n_u], ref) for prec in (0, 1)]
+
+
 def c_block_errors(ctx, apply_ref, n_u, n, seed=19):
     """The (2,2) block alone.  With u = 0 the L2 rows of A x are -C q~, since
     D u vanishes.  On random inputs C q~ is orders of magnitude smaller than

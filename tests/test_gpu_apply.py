@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from gpu_helpers import c_block_errors, gpu_context, make_case, oracle_problem, rel, to_dev, torch_cuda
+from gpu_helpers import c_block_errors, gpu_context, m_block_errors, make_case, oracle_problem, rel, to_dev, torch_cuda
 from oracle import assemble, precond
 
 pytestmark = pytest.mark.gpu
@@ -64,6 +64,9 @@ def test_block_apply_f64_and_f32(c):
     assert rel(y[:nu], y_ref[:nu]) <= 1e-12 and rel(y[nu:], y_ref[nu:]) <= 1e-12
     e64, e32 = c_block_errors(ctx, prob.apply, nu, nu + nq)
     print('C block', e64, e32, flush=True)
+    assert e64 <= 1e-12 and e32 <= 1e-5, (e64, e32)
+    e64, e32 = m_block_errors(ctx, prob.apply, nu, nu + nq)
+    print('M block', e64, e32, flush=True)
     assert e64 <= 1e-12 and e32 <= 1e-5, (e64, e32)
     ctx.close()
 
@@ -137,6 +140,14 @@ def test_full_size_graddiv_32_p4_sampled_rows_and_symmetry():
     qc, yqc, _, _ = assemble.apply_element_rows(mesh, 0, cfg['c_mass'], cfg['c_22'], 0, xc, elems)
     print('C block rows', rel(ycd.cpu().numpy()[qc], yqc), flush=True)
     assert rel(ycd.cpu().numpy()[qc], yqc) <= 1e-12
+    # the (1,1) block alone: with q~ = 0 the RT rows are M u
+    xm = x.copy()
+    xm[nu:] = 0.0
+    ctx.apply_block_op(to_dev(xm), ycd)
+    torch.cuda.synchronize()
+    _, _, um, yum = assemble.apply_element_rows(mesh, 0, cfg['c_mass'], cfg['c_22'], 0, xm, elems)
+    print('M block rows', rel(ycd.cpu().numpy()[um], yum), flush=True)
+    assert rel(ycd.cpu().numpy()[um], yum) <= 1e-12
     del ycd
     z = to_dev(inputs.uniform_vector(nu + nq, 33))
     az = torch.empty_like(z)

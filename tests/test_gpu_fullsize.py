@@ -12,7 +12,8 @@ strictly inside it):
 Some inputs have u = 0, so that their L2 rows are -C q~ alone: on random
 inputs C q~ is orders of magnitude smaller than D u (W scales with the
 inverse element volume) and a sample of whole rows would hardly see the
-local solves.
+local solves.  Others have q~ = 0, so that their RT rows are M u alone (about
+h times D^T q~ otherwise).
 
 Tolerances: 1e-12 relative in FP64 and 1e-5 in FP32 over each sample."""
 import numpy as np
@@ -53,6 +54,7 @@ def test_multirhs_64_p3_16_rhs_fp32():
     N, R = nu + nq, 16
     X = np.random.default_rng(64).uniform(-1.0, 1.0, N * R).astype(np.float32)
     X[15 * N:15 * N + nu] = 0.0     # right-hand side 15: the (2,2) block alone
+    X[7 * N + nu:8 * N] = 0.0       # right-hand side 7: the (1,1) block alone
     xd = torch.from_numpy(X).cuda()
     yd = torch.full_like(xd, float('nan'))
     ctx.apply_block_op(xd, yd, prec=hdivsp.HD_F32, nrhs=R)
@@ -81,8 +83,10 @@ def test_batch_32_instances_tuned_launch():
     # FP32-representable input: the FP64 and FP32 launches see the same x
     x = np.random.default_rng(32).uniform(-1.0, 1.0, n).astype(np.float32)
     meshes = [assemble.Mesh(d['nx'], d['ny'], d['nz'], d['p'], d['vertices']) for d in I]
-    for i in range(1, len(I), 2):   # odd instances: the (2,2) block alone
+    for i in range(1, len(I), 4):   # the (2,2) block alone
         x[int(off[i]):int(off[i]) + meshes[i].n_u] = 0.0
+    for i in range(3, len(I), 4):   # the (1,1) block alone
+        x[int(off[i]) + meshes[i].n_u:int(off[i + 1])] = 0.0
     ys = {}
     for prec, dt in ((hdivsp.HD_F64, torch.float64), (hdivsp.HD_F32, torch.float32)):
         tuned = ctx.batch_tune(prec)
@@ -119,7 +123,9 @@ def test_distorted_48_p4():
     mesh = assemble.Mesh(48, 48, 48, 4, cfg['vertices'])
     xc = x.copy()
     xc[:nu] = 0.0                   # the (2,2) block alone
-    for label, xi in (('whole', x), ('u = 0', xc)):
+    xm = x.copy()
+    xm[nu:] = 0.0                   # the (1,1) block alone
+    for label, xi in (('whole', x), ('u = 0', xc), ('q = 0', xm)):
         ref = _oracle_rows(mesh, cfg, xi.astype(np.float64), _sample(mesh.ne))
         for prec, dt, tol in ((hdivsp.HD_F64, torch.float64, 1e-12), (hdivsp.HD_F32, torch.float32, 1e-5)):
             xd = torch.from_numpy(xi).cuda().to(dt)
