@@ -28,6 +28,9 @@ Other workloads (`--workload`, one JSON line each, no CPU baseline):
   batch32        32 independent grad-div instances (n^3, n in 8..40, p in
                  1..6): autotuned persistent batched apply, FP64 and FP32.
   multirhs64     grad-div 64^3, p = 3, 16 right-hand sides: FP32 apply.
+  batch_solve8   8 independent grad-div instances (n^3, n in 8..20, p in
+                 1..4): one batched MINRES to a true residual of 1e-8 in each
+                 mode, against the instances solved one after the other.
   local_inverse  grad-div on a 96^3 refined grid at p = 1, 2, 3: FP64 apply with
                  explicit element inverses of W_e (p <= 2) against the local CG.
   darcy_gamma32  Darcy on the jittered 32^3 p = 4 mesh with gamma varying inside
@@ -439,6 +442,74 @@ def run_darcy_gamma32(args, torch, hdivsp, inputs):
     return out
 
 
+def run_batch_solve8(args, torch, hdivsp, inputs):
+    """Eight independent grad-div instances solved to a true relative residual
+    of 1e-8 by one batched MINRES (one recurrence per instance, one batched
+    apply per iteration) in each mode, and one after the other by solo
+    solves in PLAIN64 mode.  Both use the default launch configuration."""
+    import numpy as np
+    dev = torch.device('cuda', 0)
+    stream = torch.cuda.current_stream(dev)
+    inst = inputs.batch_instances(n_inst=8, seed=4, nmin=8, nmax=20, pmin=1, pmax=4)
+    t0 = time.perf_counter()
+    ctx = hdivsp.Context(0, stream)
+    ctx.setup_batch(0, inst)
+    ctx.batch_build_precond(hdivsp.precond_params())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    off = ctx.batch_offsets
+    N = int(off[-1])
+    b_host = np.random.default_rng(40).uniform(-1.0, 1.0, N)
+    b = torch.from_numpy(b_host).to(dev)
+    x = torch.zeros_like(b)
+    modes = (('plain', hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_PLAIN64, stop_true=1)),
+             ('prec32', hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_PREC32, stop_true=1)),
+             ('mixed', hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_MIXED, inner_tol=1e-5)))
+    res = {}
+    ts = time.perf_counter()
+    for name, prm in modes:
+        runs = []
+        for rep in range(args.warmup + args.steps):
+            x.zero_()
+            torch.cuda.synchronize()
+            infos = ctx.batch_minres_solve(b, x, prm)
+            if rep >= args.warmup:
+                runs.append(infos)
+        res[name] = {"time_to_1e-8_s": round(float(np.median([r[0]['time_s'] for r in runs])), 4),
+                     "iterations": [f['iterations'] for f in runs[-1]],
+                     "worst_true_rel_res": max(f['true_rel_res'] for f in runs[-1]),
+                     "status": [f['status'] for f in runs[-1]]}
+    te = time.perf_counter()
+    ctx.close()
+    solo_t, solo_it = 0.0, []
+    pm = hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_PLAIN64, stop_true=1)
+    for i, d in enumerate(inst):
+        s = hdivsp.Context(0, stream)
+        s.setup_mesh(d['nx'], d['ny'], d['nz'], d['p'], d['vertices'])
+        s.setup_coeffs(d['problem'], d['c_mass'], d['c_22'], d['ess_sides'])
+        s.build_precond(hdivsp.precond_params())
+        bi = b[int(off[i]):int(off[i + 1])].contiguous()
+        xi = torch.zeros_like(bi)
+        ts_i = []
+        for rep in range(args.warmup + args.steps):
+            xi.zero_()
+            torch.cuda.synchronize()
+            info = s.minres_solve(bi, xi, pm)
+            if rep >= args.warmup:
+                ts_i.append(info['time_s'])
+        solo_t += float(np.median(ts_i))
+        solo_it.append(info['iterations'])
+        s.close()
+    res["solo_plain_sum"] = {"time_to_1e-8_s": round(solo_t, 4), "iterations": solo_it}
+    out = base_line("time-to-1e-8 (s) of one batched MINRES over 8 grad-div instances (PLAIN64)",
+                    res["plain"]["time_to_1e-8_s"], "s", args, round((te - ts) * 1e3 / args.steps, 3),
+                    {"workload": "batch_8_graddiv_instances_n8-20_p1-4", "total_dofs": N,
+                     "instances": [f"{d['nx']}^3 p{d['p']}" for d in inst]}, higher=False)
+    out["solvers"] = res
+    out["setup_s"] = round(t1 - t0, 3)
+    return out
+
+
 def run_gmres32(args, torch, hdivsp, inputs):
     """The default grad-div system (32^3, p = 4) solved to a true relative
     residual of 1e-8 by GMRES(m) with the block-triangular preconditioner
@@ -542,7 +613,7 @@ def run_distorted48(args, torch, hdivsp, inputs):
 
 WORKLOADS = {'graddiv32': run_default, 'darcy_layered': run_darcy_layered, 'batch32': run_batch32,
              'multirhs64': run_multirhs64, 'distorted48': run_distorted48, 'local_inverse': run_local_inverse,
-             'darcy_gamma32': run_darcy_gamma32, 'gmres32': run_gmres32}
+             'darcy_gamma32': run_darcy_gamma32, 'gmres32': run_gmres32, 'batch_solve8': run_batch_solve8}
 
 
 def main():

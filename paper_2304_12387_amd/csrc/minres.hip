@@ -686,7 +686,7 @@ int batch_true_residual(hd_ctx* c, BatchWork& W, const double* b, const double* 
 // the |eta| stop, require the true FP64 residual as in the single solve.
 template <typename T, typename Bv, typename PT>
 int batch_minres_core(hd_ctx* c, BatchWork& W, const Bv* b, T* x, bool use_x0, double tol, int maxit,
-                      int check_every, double true_tol, std::vector<hd_solve_info>& out) {
+                      int check_every, double true_tol, std::vector<hd_solve_info>& out, bool use_graph) {
     constexpr bool F64 = std::is_same<T, double>::value;
     const int prec = F64 ? HD_F64 : HD_F32;
     const BatchState& B = *c->batch;
@@ -715,34 +715,67 @@ int batch_minres_core(hd_ctx* c, BatchWork& W, const Bv* b, T* x, bool use_x0, d
     }
     HD_HIP(c, hipGetLastError());
     int launched = 0, retargets = 0;
+    // one MINRES iteration for every instance (kernels only; those of a
+    // stopped instance return at once on its stop flag)
+    auto iteration = [&]() -> int {
+        int rc2;
+        if ((rc2 = launch_batch_apply(c, prec, z, q, &W.st->inv_gamma, ST_STRIDE_D, &W.st->stop, ST_STRIDE_I, true)))
+            return rc2;
+        for (int i = 0; i < ni; ++i) {
+            hd_ctx* s = B.inst[i];
+            const int64_t o = B.off[i], N = s->n_u + s->n_q, np = apply_partial_count(s);
+            const int* stop_i = &W.st[i].stop;
+            const T* mdinv = F64 ? (const T*)s->d_mdinv : (const T*)s->d_mdinv32;
+            hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), 0, c->stream, W.st + i,
+                               (const double*)(c->batch->d_part + c->batch->part_off[i]), np, np);
+            hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, s->n_u,
+                               (const T*)q + o, (const T*)v + o, vo + o, mdinv, zn + o,
+                               (const MinresState*)(W.st + i), W.pu + (int64_t)i * RED_BLOCKS);
+            if ((rc2 = schur_step<T, PT>(s, W.schur32, vo + o + s->n_u, zn + o + s->n_u, W.pq + W.pq_off[i],
+                                        stop_i)))
+                return rc2;
+            hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, W.st + i,
+                               (const double*)(W.pu + (int64_t)i * RED_BLOCKS), (int64_t)red_grid(N),
+                               (int64_t)RED_BLOCKS, (const double*)(W.pq + W.pq_off[i]),
+                               schur_parts<T, PT>(s), W.nq_part[i], maxit);
+            hipLaunchKernelGGL((k_wupd<T, T>), dim3(nblk(N), 1), dim3(BS), 0, c->stream, N, (const T*)z + o,
+                               wo + o, (const T*)w + o, x + o, (const MinresState*)(W.st + i));
+        }
+        std::swap(v, vo);
+        std::swap(z, zn);
+        std::swap(w, wo);
+        return HD_OK;
+    };
+    PeriodGraph graph;
+    const bool graphs = use_graph && check_every % 2 == 0 && !c->time_apply;
     for (;;) {
-        for (int k = 0; k < check_every && launched < maxit; ++k, ++launched) {
-            if ((rc = launch_batch_apply(c, prec, z, q, &W.st->inv_gamma, ST_STRIDE_D, &W.st->stop, ST_STRIDE_I,
-                                         true)))
-                return rc;
-            for (int i = 0; i < ni; ++i) {
-                hd_ctx* s = B.inst[i];
-                const int64_t o = B.off[i], N = s->n_u + s->n_q, np = apply_partial_count(s);
-                const int* stop_i = &W.st[i].stop;
-                const T* mdinv = F64 ? (const T*)s->d_mdinv : (const T*)s->d_mdinv32;
-                hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), 0, c->stream, W.st + i,
-                                   (const double*)(c->batch->d_part + c->batch->part_off[i]), np, np);
-                hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, s->n_u,
-                                   (const T*)q + o, (const T*)v + o, vo + o, mdinv, zn + o,
-                                   (const MinresState*)(W.st + i), W.pu + (int64_t)i * RED_BLOCKS);
-                if ((rc = schur_step<T, PT>(s, W.schur32, vo + o + s->n_u, zn + o + s->n_u, W.pq + W.pq_off[i],
-                                            stop_i)))
-                    return rc;
-                hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, W.st + i,
-                                   (const double*)(W.pu + (int64_t)i * RED_BLOCKS), (int64_t)red_grid(N),
-                                   (int64_t)RED_BLOCKS, (const double*)(W.pq + W.pq_off[i]),
-                                   schur_parts<T, PT>(s), W.nq_part[i], maxit);
-                hipLaunchKernelGGL((k_wupd<T, T>), dim3(nblk(N), 1), dim3(BS), 0, c->stream, N, (const T*)z + o,
-                                   wo + o, (const T*)w + o, x + o, (const MinresState*)(W.st + i));
+        if (graphs && maxit - launched >= check_every) {
+            if (!graph.exec) {
+                // record on a private stream of the default priority (the
+                // caller's may be the legacy default stream), with every
+                // instance context pointed at it, then replay on the caller's
+                if (!c->cap_stream) HD_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                HD_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                const hipStream_t user = c->stream;
+                c->stream = c->cap_stream;
+                for (hd_ctx* s : B.inst) s->stream = c->cap_stream;
+                int crc = HD_OK;
+                for (int k = 0; k < check_every && !crc; ++k) crc = iteration();
+                c->stream = user;
+                for (hd_ctx* s : B.inst) s->stream = user;
+                hipGraph_t g = nullptr;
+                const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+                if (!crc && e != hipSuccess) crc = set_err(c, HD_ERR_HIP, "batched MINRES graph capture");
+                if (!crc && hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0) != hipSuccess)
+                    crc = set_err(c, HD_ERR_HIP, "batched MINRES graph instantiation");
+                if (g) (void)hipGraphDestroy(g);
+                if (crc) return crc;
             }
-            std::swap(v, vo);
-            std::swap(z, zn);
-            std::swap(w, wo);
+            HD_HIP(c, hipGraphLaunch(graph.exec, c->stream));
+            launched += check_every;
+        } else {
+            for (int k = 0; k < check_every && launched < maxit; ++k, ++launched)
+                if ((rc = iteration())) return rc;
         }
         HD_HIP(c, hipGetLastError());
         HD_HIP(c, hipMemcpyAsync(W.st_host, W.st, ni * sizeof(MinresState), hipMemcpyDeviceToHost, c->stream));
@@ -1021,7 +1054,7 @@ int batch_mixed(hd_ctx* c, BatchWork& W, const hd_solve_params& prm, const doubl
                                (const double*)W.nrm + 2 * i, r32.p + o);
         }
         if ((rc = batch_minres_core<float, float, float>(c, W32, r32.p, d32.p, false, prm.inner_tol, prm.max_it,
-                                                          check, 0.0, inner)))
+                                                          check, 0.0, inner, prm.use_graph != 0)))
             return rc;
         ++outer;
         bool brk = false;
@@ -1066,10 +1099,10 @@ int batch_minres_solve(hd_ctx* c, const hd_solve_params& prm, const double* b, d
     const double tt = prm.stop_true ? prm.tol : 0.0;
     if (prm.mode == HD_MODE_PLAIN64)
         rc = batch_minres_core<double, double, double>(c, W, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, tt,
-                                                       res);
+                                                       res, prm.use_graph != 0);
     else if (prm.mode == HD_MODE_PREC32)
         rc = batch_minres_core<double, double, float>(c, W, b, x, prm.use_x0 != 0, prm.tol, prm.max_it, check, tt,
-                                                      res);
+                                                      res, prm.use_graph != 0);
     else
         rc = batch_mixed(c, W, prm, b, x, check, res);
     if (rc) return rc;

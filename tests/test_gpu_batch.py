@@ -175,3 +175,33 @@ def test_batch_mixed_rejects_bad_refinement_parameters():
             ctx.batch_minres_solve(bd, xd, hdivsp.solve_params(mode=hdivsp.HD_MODE_MIXED, **bad))
         assert e.value.code == hdivsp.HD_ERR_ARG
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", ['plain', 'prec32', 'mixed'])
+def test_batch_graph_replays_match_eager_launches(mode):
+    """The batched recurrence replays each poll period as a HIP graph; with
+    graphs off the same kernels run eagerly.  Every mode gives the same
+    iterations and the same solution bit for bit, over two solves in a row
+    (each solve replays its graph several times)."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    I = inputs.batch_instances(n_inst=3, seed=17, nmin=2, nmax=4, pmin=1, pmax=3)
+    ctx = hdivsp.Context(0)
+    ctx.setup_batch(0, I)
+    ctx.batch_build_precond(hdivsp.precond_params(max_coarse=40))
+    n = int(ctx.batch_offsets[-1])
+    b = to_dev(np.random.default_rng(23).uniform(-1, 1, n))
+    md = {'plain': hdivsp.HD_MODE_PLAIN64, 'prec32': hdivsp.HD_MODE_PREC32, 'mixed': hdivsp.HD_MODE_MIXED}[mode]
+    out = []
+    for use_graph in (0, 1, 1):
+        x = torch.full_like(b, np.nan)
+        sp = hdivsp.solve_params(tol=1e-10, max_it=3000, mode=md, use_graph=use_graph, check_every=4)
+        infos = ctx.batch_minres_solve(b, x, sp)
+        torch.cuda.synchronize()
+        assert all(f['status'] == 0 for f in infos), infos
+        out.append(([f['iterations'] for f in infos], x.cpu().numpy()))
+    print(mode, out[0][0], flush=True)
+    for its, x in out[1:]:
+        assert its == out[0][0]
+        assert np.array_equal(x, out[0][1])
+    ctx.close()
