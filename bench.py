@@ -445,8 +445,9 @@ def run_darcy_gamma32(args, torch, hdivsp, inputs):
 def run_batch_solve8(args, torch, hdivsp, inputs):
     """Eight independent grad-div instances solved to a true relative residual
     of 1e-8 by one batched MINRES (one recurrence per instance, one batched
-    apply per iteration) in each mode, and one after the other by solo
-    solves in PLAIN64 mode.  Both use the default launch configuration."""
+    apply per iteration, in the launch configuration the tuner picks for
+    FP64) in each mode, and one after the other by solo solves in PLAIN64
+    mode."""
     import numpy as np
     dev = torch.device('cuda', 0)
     stream = torch.cuda.current_stream(dev)
@@ -455,6 +456,7 @@ def run_batch_solve8(args, torch, hdivsp, inputs):
     ctx = hdivsp.Context(0, stream)
     ctx.setup_batch(0, inst)
     ctx.batch_build_precond(hdivsp.precond_params())
+    tuned = ctx.batch_tune(hdivsp.HD_F64)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     off = ctx.batch_offsets
@@ -506,6 +508,7 @@ def run_batch_solve8(args, torch, hdivsp, inputs):
                     {"workload": "batch_8_graddiv_instances_n8-20_p1-4", "total_dofs": N,
                      "instances": [f"{d['nx']}^3 p{d['p']}" for d in inst]}, higher=False)
     out["solvers"] = res
+    out["batch_launch"] = tuned
     out["setup_s"] = round(t1 - t0, 3)
     return out
 

@@ -276,13 +276,14 @@ int hd_setup_batch(hd_ctx* ctx, int problem, int ninst, const hd_instance_desc* 
 int hd_batch_sizes(hd_ctx* ctx, int64_t* offsets, int64_t* n_u);
 /* y = A x for every instance (device pointers of the total length, x != y). */
 int hd_batch_apply(hd_ctx* ctx, int prec, const void* x, void* y);
-/* Autotuner: times the batched apply over the launch variants (one
- * persistent launch for all degrees or one per degree), persistent grid
- * sizes and element groups per tile, keeps the fastest and reports it
+/* Autotuner: times the batched apply over the launch variants (mode 0: one
+ * persistent launch for all degrees; 1: one persistent launch per degree;
+ * 2: each instance's own full-grid launch, one per instance), persistent
+ * grid sizes and element groups per tile, keeps the fastest and reports it
  * (any output may be NULL). */
 int hd_batch_tune(hd_ctx* ctx, int prec, int* mode, int* grid, int* tile_groups, double* ms);
-/* Set the launch configuration explicitly (mode 0 or 1, grid >= 1
- * workgroups, tile_groups >= 1). */
+/* Set the launch configuration explicitly (mode 0, 1 or 2, grid >= 1
+ * workgroups, tile_groups >= 1; mode 2 uses neither). */
 int hd_batch_set_launch(hd_ctx* ctx, int mode, int grid, int tile_groups);
 /* Each instance's diagonal, S~ and AMG (learned must be 0). */
 int hd_batch_build_precond(hd_ctx* ctx, const hd_precond_params* params);

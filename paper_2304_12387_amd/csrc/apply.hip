@@ -1126,6 +1126,21 @@ void launch_batch_t(hd_ctx* c, const BatchInstDev* di, const T* x, T* y, const d
 int launch_batch_apply(hd_ctx* c, int prec, const void* x, void* y, const double* scale, int scale_stride,
                        const int* done, int done_stride, bool partials) {
     BatchState& B = *c->batch;
+    if (B.mode == 2) {
+        // each instance's own full-grid apply on its segment (the per-instance
+        // partial sums have the layout of a single apply)
+        const size_t es = prec == HD_F64 ? sizeof(double) : sizeof(float);
+        for (size_t i = 0; i < B.inst.size(); ++i) {
+            hd_ctx* s = B.inst[i];
+            const size_t o = es * (size_t)B.off[i];
+            const int rc = launch_apply(s, prec, 1, (const char*)x + o, (char*)y + o,
+                                        scale ? scale + (size_t)scale_stride * i : nullptr, scale_stride,
+                                        partials ? B.d_part + B.part_off[i] : nullptr, apply_partial_count(s),
+                                        ESS_IDENTITY, done ? done + (size_t)done_stride * i : nullptr, done_stride);
+            if (rc) return set_err(c, rc, "instance " + std::to_string(i) + ": " + s->err);
+        }
+        return HD_OK;
+    }
     if (prec == HD_F64)
         launch_batch_t<double>(c, B.d_inst64, (const double*)x, (double*)y, scale, scale_stride, done, done_stride,
                                partials);

@@ -726,13 +726,15 @@ int hd_batch_tune(hd_ctx* c, int prec, int* mode, int* grid, int* tile_groups, d
             hipLaunchKernelGGL(hd::tune_pattern_kernel<float>, dim3(nbk), dim3(256), 0, c->stream, (float*)x, B.total);
         HD_HIP(c, hipGetLastError());
     }
-    const int modes[2] = {0, 1}, groups[4] = {1, 2, 4, 8}, grids[4] = {512, 1024, 2048, 4096};
+    const int modes[3] = {0, 1, 2}, groups[4] = {1, 2, 4, 8}, grids[4] = {512, 1024, 2048, 4096};
     double best = 1e300;
     int bm = 0, bg = 1, bgrid = 2048;
     for (int tg : groups) {
         if ((rc = batch_build_tiles(c, tg))) break;
         for (int md : modes)
             for (int gr : grids) {
+                // one launch per instance: no grid or tile to choose
+                if (md == 2 && (tg != groups[0] || gr != grids[0])) continue;
                 B.mode = md;
                 B.grid = gr;
                 if ((rc = launch_batch_apply(c, prec, x, y, nullptr, 0, nullptr, 0, false))) break;
@@ -767,7 +769,7 @@ int hd_batch_tune(hd_ctx* c, int prec, int* mode, int* grid, int* tile_groups, d
 int hd_batch_set_launch(hd_ctx* c, int mode, int grid, int tile_groups) {
     if (!c) return HD_ERR_ARG;
     if (!c->batch) return set_err(c, HD_ERR_STATE, "hd_setup_batch first");
-    if ((mode != 0 && mode != 1) || grid < 1 || grid > (1 << 20) || tile_groups < 1 || tile_groups > 4096)
+    if (mode < 0 || mode > 2 || grid < 1 || grid > (1 << 20) || tile_groups < 1 || tile_groups > 4096)
         return set_err(c, HD_ERR_ARG, "bad launch configuration");
     int rc = use_device(c);
     if (rc) return rc;

@@ -21,8 +21,9 @@ def _instances():
     return I
 
 
-@pytest.mark.parametrize("launch", [(0, 2048, 1), (0, 7, 3), (1, 1024, 1), (1, 5, 2)],
-                         ids=['one_launch', 'one_launch_small_grid', 'per_degree', 'per_degree_small_grid'])
+@pytest.mark.parametrize("launch", [(0, 2048, 1), (0, 7, 3), (1, 1024, 1), (1, 5, 2), (2, 1, 1)],
+                         ids=['one_launch', 'one_launch_small_grid', 'per_degree', 'per_degree_small_grid',
+                              'per_instance'])
 def test_batch_apply_matches_each_instance(launch):
     torch = torch_cuda()
     from paper_2304_12387_amd import hdivsp
