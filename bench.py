@@ -26,7 +26,8 @@ Other workloads (`--workload`, one JSON line each, no CPU baseline):
                  flux boundary condition: FP64 MINRES with the FP64 and with
                  the FP32 Schur V-cycle, time to a true residual of 1e-8.
   batch32        32 independent grad-div instances (n^3, n in 8..40, p in
-                 1..6): autotuned persistent batched apply, FP64 and FP32.
+                 1..6): batched apply in the autotuned launch mode (persistent
+                 work queue, or each instance's own launch), FP64 and FP32.
   multirhs64     grad-div 64^3, p = 3, 16 right-hand sides: FP32 apply.
   batch_solve8   8 independent grad-div instances (n^3, n in 8..20, p in
                  1..4): one batched MINRES to a true residual of 1e-8 in each
@@ -311,7 +312,7 @@ def run_batch32(args, torch, hdivsp, inputs):
         res[name] = {"gdofs": round(N / (ms * 1e-3) / 1e9, 3), "ms_per_apply": round(ms, 4), "tuned": tuned}
         del x, y
     te = time.perf_counter()
-    out = base_line("GDOF/s of the batched block apply (32 instances, persistent work queue)",
+    out = base_line("GDOF/s of the batched block apply (32 instances, autotuned launch)",
                     res['f64']['gdofs'], "GDOF/s", args, round((te - ts) * 1e3, 3),
                     {"workload": "batch_32_graddiv_instances_n8-40_p1-6", "total_dofs": N,
                      "instances": [f"{d['nx']}^3 p{d['p']}" for d in inst]})
