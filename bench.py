@@ -4,9 +4,9 @@ time-to-1e-8, plain FP64 vs mixed precision, on one MI355X.
 Default workload (`--workload graddiv32`): grad-div on the unit cube, 32^3
 hexahedra with vertices jittered by +-10% h, RT order p = 4 (n_u = 6,340,608,
 n_q = 2,097,152), alpha and beta per element log-uniform in [1e-2, 1e2];
-right-hand side
-b_u ~ U[-1, 1], b_q = 0.  Synthetic seeded inputs; setup (geometry,
-diagonals, S~, AMG) runs before the timed region and is reported separately.
+right-hand side b_u ~ U[-1, 1], b_q = 0.  Synthetic seeded inputs; setup
+(geometry, diagonals, S~, AMG) runs before the timed region and is reported
+separately.
 
 One step = NAPPLY back-to-back FP64 block applies (HIP events on the
 library's stream bracket them), one plain FP64 MINRES solve to a true
