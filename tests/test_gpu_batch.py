@@ -178,17 +178,20 @@ def test_batch_mixed_rejects_bad_refinement_parameters():
     ctx.close()
 
 
+@pytest.mark.parametrize("launch", [0, 2], ids=['persistent', 'per_instance'])
 @pytest.mark.parametrize("mode", ['plain', 'prec32', 'mixed'])
-def test_batch_graph_replays_match_eager_launches(mode):
+def test_batch_graph_replays_match_eager_launches(mode, launch):
     """The batched recurrence replays each poll period as a HIP graph; with
-    graphs off the same kernels run eagerly.  Every mode gives the same
-    iterations and the same solution bit for bit, over two solves in a row
-    (each solve replays its graph several times)."""
+    graphs off the same kernels run eagerly.  In both launch modes of the
+    apply (persistent work queue, each instance's own launch) every mode
+    gives the same iterations and the same solution bit for bit, over two
+    solves in a row (each solve replays its graph several times)."""
     torch = torch_cuda()
     from paper_2304_12387_amd import hdivsp
     I = inputs.batch_instances(n_inst=3, seed=17, nmin=2, nmax=4, pmin=1, pmax=3)
     ctx = hdivsp.Context(0)
     ctx.setup_batch(0, I)
+    ctx.batch_set_launch(launch, 2048, 1)
     ctx.batch_build_precond(hdivsp.precond_params(max_coarse=40))
     n = int(ctx.batch_offsets[-1])
     b = to_dev(np.random.default_rng(23).uniform(-1, 1, n))
