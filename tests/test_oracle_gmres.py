@@ -6,7 +6,11 @@ on block-triangular preconditioners in Section 2.2).
 * GMRES solves to the sparse direct solution with the practical (M~, AMG)
   triangular preconditioner, restarted or not;
 * GMRES without a preconditioner on a diagonal matrix with k distinct
-  eigenvalues converges in k iterations (Krylov dimension)."""
+  eigenvalues converges in k iterations (Krylov dimension);
+* each residual GMRES reports is the least-squares minimum over its Krylov
+  space (Saad and Schultz's defining property), recomputed by brute force from
+  an explicit Krylov basis and a QR projection, both for the first cycle and
+  across a restart."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -63,3 +67,41 @@ def test_krylov_dimension_bound():
     b = np.random.default_rng(5).uniform(-1, 1, d.size)
     x, it, info = gmres.gmres(lambda v: A @ v, lambda v: v, b, tol=1e-12)
     assert it == 4 and np.allclose(x, b / d, rtol=1e-10)
+
+
+def _min_residuals(AP, r0, k):
+    """min over y in K_j(AP, r0) of ||r0 - AP y|| / ||r0|| for j = 1..k, from
+    an explicit (column-normalised) Krylov basis and a QR projection."""
+    cols, out = [], []
+    v = r0 / np.linalg.norm(r0)
+    for _ in range(k):
+        cols.append(v)
+        W = np.column_stack([AP(c) for c in cols])
+        Q, _ = np.linalg.qr(W)
+        res = r0 - Q @ (Q.T @ r0)
+        out.append(np.linalg.norm(res) / np.linalg.norm(r0))
+        v = AP(v)
+        v = v / np.linalg.norm(v)
+    return np.array(out)
+
+
+def test_residuals_are_the_krylov_least_squares_minima():
+    prob = _problem(0, 2, 5, n=(2, 2, 2), seed=7)
+    P = gmres.TriangularPreconditioner(prob, amg_kwargs=dict(max_coarse=20))
+    b = np.random.default_rng(8).uniform(-1, 1, prob.mesh.n)
+    b[:prob.mesh.n_u][prob.ess] = 0.0
+    AP = lambda v: prob.apply(P(v))
+    k = 8
+    # one cycle: GMRES(k) from x0 = 0 against the minima over K_j(AP, b)
+    _, _, info = gmres.gmres(prob.apply, P, b, tol=1e-30, restart=k, maxiter=k)
+    ref = _min_residuals(AP, b, k)
+    assert np.allclose(info['res'][1:k + 1], ref, rtol=1e-8, atol=0), (info['res'][1:k + 1], ref)
+    # a restart: the second cycle minimises over K_j(AP, r_k) with r_k the
+    # residual of the first cycle's iterate
+    x1, _, _ = gmres.gmres(prob.apply, P, b, tol=1e-30, restart=k, maxiter=k)
+    r1 = b - prob.apply(x1)
+    _, _, info2 = gmres.gmres(prob.apply, P, b, tol=1e-30, restart=k, maxiter=2 * k)
+    ref2 = _min_residuals(AP, r1, 4) * np.linalg.norm(r1) / np.linalg.norm(b)
+    assert np.allclose(info2['res'][k + 1:k + 5], ref2, rtol=1e-7, atol=0), (info2['res'][k + 1:k + 5], ref2)
+    # the residuals never increase
+    assert np.all(np.diff(info2['res']) <= 1e-12)
