@@ -142,14 +142,25 @@ const char* hd_last_error(const hd_ctx* ctx);
  * det J <= 0 at quadrature points and vertices with HD_ERR_MESH. */
 int hd_setup_mesh(hd_ctx* ctx, int nx, int ny, int nz, int p, const double* vertices);
 
-/* Coefficients per element (host arrays of length nx*ny*nz, copied).
+/* Coefficients per element and the problem type, which fix the blocks of
+ * the transformed system (Section 2.3, eq. transformed-system, grad-div;
+ * Section 2.4, eq. transformed-system-darcy, Darcy with piecewise-constant
+ * gamma): M = M_beta or M_{1/eps}, and the (2,2) block C = kappa_e W_e^{-1}
+ * with kappa = 1/alpha (grad-div) or gamma (Darcy).
  * problem = HD_GRADDIV: c_mass = beta > 0, c_22 = alpha > 0 (required).
  * problem = HD_DARCY:   c_mass = 1/eps > 0, c_22 = gamma >= 0 or NULL (0).
- * ess_sides: bit mask of box sides whose RT dofs are essential. */
+ * c_mass, c_22: host arrays of nx*ny*nz finite values in element order
+ * (e = ex + nx (ey + ny ez)), copied; the caller keeps ownership.
+ * ess_sides: bit mask of box sides (HD_SIDE_*) whose RT dofs are essential
+ * (identity rows and columns of the operator).
+ * Errors: HD_ERR_STATE before hd_setup_mesh; HD_ERR_ARG for an unknown
+ * problem, a NULL c_mass (or c_22 for grad-div), ess_sides > 63 or an
+ * out-of-range value; HD_ERR_NONFINITE for a non-finite value.  Drops any
+ * preconditioner (build it again). */
 int hd_setup_coeffs(hd_ctx* ctx, int problem, const double* c_mass, const double* c_22,
                     uint32_t ess_sides);
 
-/* Darcy with gamma varying inside the elements (Section 3.3, the general case
+/* Darcy with gamma varying inside the elements (Section 2.4, the general case
  * of eq. transformed-system-darcy): gamma becomes the continuous
  * piecewise-trilinear field with the given values at the mesh vertices
  * (host array of (nx+1)(ny+1)(nz+1) finite values >= 0, not all zero,
@@ -164,7 +175,11 @@ int hd_setup_coeffs(hd_ctx* ctx, int problem, const double* c_mass, const double
  * (HD_ERR_STATE). */
 int hd_set_gamma_field(hd_ctx* ctx, const double* gamma_vertices);
 
-/* Global sizes n_u (RT) and n_q (L2). */
+/* Global sizes of the two blocks of the unknown (Section 2: RT_p velocity
+ * dofs, one per sub-element face of the refined grid, and L2 dofs, p^3 per
+ * element): n_u and n_q written to the host pointers (either may be NULL).
+ * A vector of the system is [u; q~], n_u + n_q long.  HD_ERR_STATE before
+ * hd_setup_mesh. */
 int hd_sizes(const hd_ctx* ctx, int64_t* n_u, int64_t* n_q);
 
 /* y = A x (eq. transformed-saddle-point, Section 3).  x != y, device
@@ -176,7 +191,7 @@ int hd_sizes(const hd_ctx* ctx, int64_t* n_u, int64_t* n_q);
 int hd_apply_block_op(hd_ctx* ctx, int prec, int nrhs, const void* x, void* y);
 
 /* How the block apply, and everything built on it, applies W_e^{-1} in the
- * (2,2) block (Section 4, GPU acceleration of the DG mass inverse: explicit
+ * (2,2) block (Section 3.1, GPU acceleration of the DG mass inverse: explicit
  * inverses applied by a batched matrix-vector product for small degrees,
  * matrix-free local CG otherwise).
  *   HD_LOCAL_AUTO      explicit inverses for p <= 2, local CG for p >= 3
@@ -201,9 +216,16 @@ int hd_apply_mass_inverse(hd_ctx* ctx, int prec, int nrhs, const void* x, void* 
  * right-hand sides or p = W^{-1} p~ in post-processing (Section 3). */
 int hd_apply_l2_mass_inverse(hd_ctx* ctx, int prec, const void* x, void* y);
 
-/* b <- lifted right-hand side for essential values u_bc (device, length
- * n_u, only essential entries read): b_f -= (A_full [u_bc;0])_f on free rows,
- * b_e = u_bc on essential rows.  FP64. */
+/* Essential flux boundary conditions in the block system (Section 2:
+ * u.n prescribed on part of the boundary; Section 4.2 uses it for the
+ * layered Darcy problem): b <- lifted right-hand side for the essential
+ * values u_bc, b_f -= (A_full [u_bc; 0])_f on free rows and b_e = u_bc on
+ * essential rows, so that the solution of the system with identity
+ * essential rows takes the prescribed values.  u_bc: FP64 device array of
+ * length n_u (only essential entries are read); b: FP64 device array of
+ * length n_u + n_q, updated in place; both caller-owned.  Asynchronous on
+ * the context's stream.  HD_ERR_STATE before hd_setup_coeffs, HD_ERR_ARG
+ * for NULL pointers. */
 int hd_lift_essential(hd_ctx* ctx, const double* u_bc, double* b);
 
 /* RT interpolant of the constant vector field u[3] (host): every dof (device,
@@ -218,13 +240,31 @@ int hd_constant_flux(hd_ctx* ctx, const double* u, double* dofs);
  * dofs of M~) and the AMG hierarchy on S~.  params may be NULL (defaults). */
 int hd_build_precond(hd_ctx* ctx, const hd_precond_params* params);
 
-/* z = B^{-1} r.  Device pointers of length nrhs*(n_u+n_q). */
+/* z = B^{-1} r with the block-diagonal preconditioner
+ * B = diag(tau M~, S^) (Section 2.2, Prop. 1 and the remark on tau;
+ * Section 2.3, eq. approx-schur): z_u = (tau M~)^{-1} r_u and
+ * z_q = one AMG V-cycle on S~ applied to r_q (constants removed when S~ is
+ * singular).  r, z: distinct caller-owned device arrays of nrhs*(n_u+n_q)
+ * values of precision prec (HD_F64 or HD_F32), right-hand sides stored one
+ * after the other.  Asynchronous on the context's stream.  HD_ERR_STATE
+ * before hd_build_precond, HD_ERR_ARG for bad pointers, prec or nrhs. */
 int hd_apply_precond(hd_ctx* ctx, int prec, int nrhs, const void* r, void* z);
 
-/* Block-preconditioned MINRES on A x = b.  b, x: FP64 device pointers of
- * length nrhs*(n_u+n_q).  info: host array of nrhs entries (may be NULL).
- * Returns 0 when every right-hand side converged, HD_NOT_CONVERGED or an
- * error code otherwise. */
+/* Block-preconditioned MINRES on A x = b (Section 2.2: MINRES for the
+ * symmetric indefinite saddle-point system with the block-diagonal
+ * preconditioner of hd_apply_precond; Section 3: one operator apply and one
+ * preconditioner apply per iteration).  Stops when the preconditioned
+ * residual norm the recurrence carries falls below tol times its initial
+ * value, and with stop_true also checks the true FP64 relative residual.
+ * params may be NULL (defaults of hd_solve_params); mode selects FP64,
+ * mixed-precision refinement or the FP32 Schur V-cycle.
+ * b, x: distinct caller-owned FP64 device arrays of nrhs*(n_u+n_q) values,
+ * right-hand sides one after the other; x is read as the initial guess when
+ * use_x0 is set.  info: host array of nrhs entries (may be NULL).
+ * Synchronises the stream before returning.  Returns 0 when every
+ * right-hand side converged, HD_NOT_CONVERGED (> 0) when one reached
+ * max_it, HD_ERR_BREAKDOWN on a Lanczos breakdown, HD_ERR_STATE before
+ * hd_build_precond, HD_ERR_ARG for bad arguments. */
 int hd_minres_solve(hd_ctx* ctx, const hd_solve_params* params, int nrhs,
                     const double* b, double* x, hd_solve_info* info);
 

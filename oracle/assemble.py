@@ -20,7 +20,7 @@ Operator (eq. transformed-system and eq. transformed-system-darcy):
   so in both cases C is block diagonal with blocks kappa_e W_e^{-1}, W_e the
   unweighted element L2 mass matrix.  Darcy with gamma varying inside the
   elements (a continuous piecewise-trilinear field given at the vertices,
-  `gamma_vertices`): C_e = W_e^{-1} W_gamma,e W_e^{-1} in full (Section 3.3,
+  `gamma_vertices`): C_e = W_e^{-1} W_gamma,e W_e^{-1} in full (Section 2.4,
   the general case of eq. transformed-system-darcy).
 Essential flux dofs (faces on the selected sides of the box) get identity rows
 and columns.
@@ -325,42 +325,52 @@ class Problem:
 
 
 def apply_element_rows(mesh, problem, c_mass, c_22, ess_sides, x, elems):
-    """Rows of y = A x owned by the listed elements, computed from those
-    elements' matrices only (for sampled checks on meshes too large to
-    assemble).  Returns (q_rows, y_q, u_rows, y_u): all L2 rows of the
-    elements, and the RT rows that lie strictly inside them."""
-    from .element import element_matrices
-    elems = np.asarray(elems)
+    """Rows of y = A x at the dofs of the listed elements, computed from
+    element matrices only (for sampled checks on meshes too large to
+    assemble): every L2 row of the elements and every RT row of theirs.
+
+    An RT dof on a face shared with a neighbour is a sum over both elements
+    (M = sum_e E_e^T M_e E_e and D^T likewise, Section 3 eq.
+    transformed-saddle-point), so the face neighbours' matrices are formed
+    too.  Essential rows copy the input, as in `Problem.apply`.  Returns
+    (q_rows, y_q, u_rows, y_u), rows in increasing order."""
+    from .element import element_matrices, reference_divergence
+    elems = np.unique(np.asarray(elems, dtype=np.int64))
     p = mesh.p
     nl = p ** 3
-    V = mesh.element_vertices(elems)
-    em = element_matrices(p, V, np.asarray(c_mass)[elems])
-    if problem == GRADDIV:
-        kap = 1.0 / np.asarray(c_22)[elems]
-    else:
-        kap = np.zeros(len(elems)) if c_22 is None else np.asarray(c_22)[elems]
-    l2g = mesh.rt_local_to_global(elems)
-    ess = mesh.essential_mask(ess_sides)
     nu = mesh.n_u
-    from .element import reference_divergence
+    # the sampled elements and their face neighbours
+    ex, ey, ez = mesh.element_coords(elems)
+    work = [elems]
+    for coord, n, stride in ((ex, mesh.nx, 1), (ey, mesh.ny, mesh.nx), (ez, mesh.nz, mesh.nx * mesh.ny)):
+        work.append(elems[coord > 0] - stride)
+        work.append(elems[coord < n - 1] + stride)
+    work = np.unique(np.concatenate(work))
+    V = mesh.element_vertices(work)
+    em = element_matrices(p, V, np.asarray(c_mass)[work])
+    if problem == GRADDIV:
+        kap = 1.0 / np.asarray(c_22)[work]
+    else:
+        kap = np.zeros(len(work)) if c_22 is None else np.asarray(c_22)[work]
+    l2g = mesh.rt_local_to_global(work)
+    ess = mesh.essential_mask(ess_sides)
     D = reference_divergence(p)
-    q_rows, y_q, u_rows, y_u = [], [], [], []
-    # RT dofs strictly interior to an element: normal index not 0 or p
-    from .element import rt_shapes
-    interior = []
-    for comp, shp in enumerate(rt_shapes(p)):
-        kk, jj, ii = np.meshgrid(np.arange(shp[2]), np.arange(shp[1]), np.arange(shp[0]), indexing='ij')
-        t = [ii, jj, kk][comp].ravel()
-        interior.append((t > 0) & (t < p))
-    interior = np.concatenate(interior)
-    for n, e in enumerate(elems):
+    yu_e = np.zeros((len(work), l2g.shape[1]))
+    q_rows, y_q = [], []
+    sampled = np.isin(work, elems)
+    for n, e in enumerate(work):
         xu = x[l2g[n]].copy()
         xu[ess[l2g[n]]] = 0.0
         xq = x[nu + e * nl: nu + (e + 1) * nl]
-        yu = em['M'][n] @ xu + D.T @ xq
-        yq = D @ xu - kap[n] * np.linalg.solve(em['W'][n], xq)
-        q_rows.append(nu + e * nl + np.arange(nl))
-        y_q.append(yq)
-        u_rows.append(l2g[n][interior])
-        y_u.append(yu[interior])
-    return (np.concatenate(q_rows), np.concatenate(y_q), np.concatenate(u_rows), np.concatenate(y_u))
+        yu_e[n] = em['M'][n] @ xu + D.T @ xq
+        if sampled[n]:
+            q_rows.append(nu + e * nl + np.arange(nl))
+            y_q.append(D @ xu - kap[n] * np.linalg.solve(em['W'][n], xq))
+    # sum the element contributions per global RT dof
+    rows_all, inv = np.unique(l2g.ravel(), return_inverse=True)
+    acc = np.zeros(len(rows_all))
+    np.add.at(acc, inv, yu_e.ravel())
+    u_rows = np.unique(l2g[sampled].ravel())
+    y_u = acc[np.searchsorted(rows_all, u_rows)]
+    y_u[ess[u_rows]] = x[u_rows][ess[u_rows]]
+    return np.concatenate(q_rows), np.concatenate(y_q), u_rows, y_u

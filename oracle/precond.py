@@ -53,7 +53,7 @@ def diag_W(prob):
 def c_tilde(prob):
     """C~_ii = kappa_e / W_ii (grad-div: diag(W_alpha)^{-1}; Darcy with
     piecewise-constant gamma: diag(W)^{-1} diag(W_gamma) diag(W)^{-1}); with a
-    gamma field that product of diagonals itself (Section 3.3)."""
+    gamma field that product of diagonals itself (Section 2.4)."""
     if getattr(prob, 'gamma_field', False):
         w = diag_W(prob)
         return prob.Wg.diagonal() / (w * w)

@@ -218,7 +218,7 @@ __device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], i
 }
 
 // sq = W_gamma A1 for one element (Darcy with gamma varying inside the
-// element, Section 3.3): the L2 coefficients in A1 to the quadrature points
+// element, Section 2.4): the L2 coefficients in A1 to the quadrature points
 // with the histopolation table in x, y (LDS) and z (registers), times
 // gamma w / det J there (gamma the trilinear interpolant of the vertex values
 // in gv, w / det J in gw as z-pencils), and back with the transposed table.

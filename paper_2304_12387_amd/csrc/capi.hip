@@ -713,49 +713,62 @@ int hd_batch_tune(hd_ctx* c, int prec, int* mode, int* grid, int* tile_groups, d
     if (rc) return rc;
     BatchState& B = *c->batch;
     const size_t es = prec == HD_F64 ? sizeof(double) : sizeof(float);
-    void *x = nullptr, *y = nullptr;
-    if (hipMalloc(&x, es * B.total) != hipSuccess || hipMalloc(&y, es * B.total) != hipSuccess) {
-        dfree(x);
+    // tuning vectors, freed on every return path
+    struct Vecs {
+        void* x = nullptr;
+        void* y = nullptr;
+        ~Vecs() {
+            dfree(x);
+            dfree(y);
+        }
+    } v;
+    if (hipMalloc(&v.x, es * B.total) != hipSuccess || hipMalloc(&v.y, es * B.total) != hipSuccess)
         return set_err(c, HD_ERR_OOM, "tuning vectors");
-    }
     {
         const unsigned nbk = (unsigned)((B.total + 255) / 256);
         if (prec == HD_F64)
-            hipLaunchKernelGGL(hd::tune_pattern_kernel<double>, dim3(nbk), dim3(256), 0, c->stream, (double*)x, B.total);
+            hipLaunchKernelGGL(hd::tune_pattern_kernel<double>, dim3(nbk), dim3(256), 0, c->stream, (double*)v.x,
+                               B.total);
         else
-            hipLaunchKernelGGL(hd::tune_pattern_kernel<float>, dim3(nbk), dim3(256), 0, c->stream, (float*)x, B.total);
+            hipLaunchKernelGGL(hd::tune_pattern_kernel<float>, dim3(nbk), dim3(256), 0, c->stream, (float*)v.x,
+                               B.total);
         HD_HIP(c, hipGetLastError());
     }
     const int modes[3] = {0, 1, 2}, groups[4] = {1, 2, 4, 8}, grids[4] = {512, 1024, 2048, 4096};
     double best = 1e300;
     int bm = 0, bg = 1, bgrid = 2048;
+    // average time of 3 applies after one warm-up in the current launch
+    // configuration; the first failing launch ends the whole search
+    auto time_one = [&](float& t) -> int {
+        int r = launch_batch_apply(c, prec, v.x, v.y, nullptr, 0, nullptr, 0, false);
+        if (r) return r;
+        HD_HIP(c, hipEventRecord(c->ev0, c->stream));
+        for (int k = 0; k < 3; ++k)
+            if ((r = launch_batch_apply(c, prec, v.x, v.y, nullptr, 0, nullptr, 0, false))) return r;
+        HD_HIP(c, hipEventRecord(c->ev1, c->stream));
+        HD_HIP(c, hipEventSynchronize(c->ev1));
+        HD_HIP(c, hipEventElapsedTime(&t, c->ev0, c->ev1));
+        t /= 3.0f;
+        return HD_OK;
+    };
     for (int tg : groups) {
-        if ((rc = batch_build_tiles(c, tg))) break;
+        if ((rc = batch_build_tiles(c, tg))) return rc;
         for (int md : modes)
             for (int gr : grids) {
                 // one launch per instance: no grid or tile to choose
                 if (md == 2 && (tg != groups[0] || gr != grids[0])) continue;
                 B.mode = md;
                 B.grid = gr;
-                if ((rc = launch_batch_apply(c, prec, x, y, nullptr, 0, nullptr, 0, false))) break;
-                HD_HIP(c, hipEventRecord(c->ev0, c->stream));
-                for (int r = 0; r < 3 && !rc; ++r) rc = launch_batch_apply(c, prec, x, y, nullptr, 0, nullptr, 0, false);
-                HD_HIP(c, hipEventRecord(c->ev1, c->stream));
-                HD_HIP(c, hipEventSynchronize(c->ev1));
                 float t = 0.0f;
-                HD_HIP(c, hipEventElapsedTime(&t, c->ev0, c->ev1));
-                if (t / 3.0 < best) {
-                    best = t / 3.0;
+                if ((rc = time_one(t))) return rc;
+                if (t < best) {
+                    best = t;
                     bm = md;
                     bg = tg;
                     bgrid = gr;
                 }
             }
-        if (rc) break;
     }
-    dfree(x);
-    dfree(y);
-    if (rc) return rc;
     B.mode = bm;
     B.grid = bgrid;
     if ((rc = batch_build_tiles(c, bg))) return rc;

@@ -524,7 +524,7 @@ int scan_counts(hd_ctx* c, const int32_t* cnt, int64_t n, int32_t* rp, int64_t* 
 }
 
 // Darcy with a gamma field: C~_ii = diag(W_gamma)_ii / W_ii^2 (the product of
-// the diagonals of W^{-1} W_gamma W^{-1}, Section 3.3), one thread per L2 dof;
+// the diagonals of W^{-1} W_gamma W^{-1}, Section 2.4), one thread per L2 dof;
 // gamma at the quadrature points is the trilinear interpolant of the element's
 // vertex values, w / det J the stored seventh factor.
 template <int P>

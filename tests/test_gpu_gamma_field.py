@@ -1,4 +1,4 @@
-"""Darcy with gamma varying inside the elements (Section 3.3, the general
+"""Darcy with gamma varying inside the elements (Section 2.4, the general
 (2,2) block W^{-1} W_gamma W^{-1}): the GPU block apply (local CG and, for
 p <= 2, explicit element inverses), S~ with C~ = diag(W)^{-1} diag(W_gamma)
 diag(W)^{-1} and MINRES against the oracle; a constant field against the

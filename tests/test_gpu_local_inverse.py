@@ -1,5 +1,5 @@
 """Explicit element inverses W_e^{-1} for p <= 2 (the small-degree choice for
-the (2,2) block of the GPU acceleration of the DG mass inverse, Section 4)
+the (2,2) block of the GPU acceleration of the DG mass inverse, Section 3.1)
 against the local CG and the oracle: the block apply in FP64 and FP32, the
 mode switch in both directions, the rejection above p = 2, and MINRES with
 either local solver."""

@@ -148,6 +148,14 @@ def test_mixed_precision_refinement():
     assert np.linalg.norm(b - A @ xmn) <= 1e-8 * np.linalg.norm(b) * 1.0001
     xdir = spla.spsolve(A.tocsc(), b)
     assert rel(xmn, xdir) <= 1e-5
+    # at tol 1e-12 the refined mixed solution meets the final-solution bar
+    # (1e-8 relative to the direct solve), like the plain FP64 one
+    xm12 = torch.zeros_like(bd)
+    im12 = ctx.minres_solve(bd, xm12, hdivsp.solve_params(tol=1e-12, mode=hdivsp.HD_MODE_MIXED, inner_tol=1e-5,
+                                                          max_it=5000))
+    print('mixed 1e-12', im12, flush=True)
+    assert im12['status'] == 0 and im12['true_rel_res'] <= 1e-12
+    assert rel(xm12.cpu().numpy(), xdir) <= 1e-8
     ctx.close()
 
 

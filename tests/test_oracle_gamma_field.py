@@ -1,5 +1,5 @@
 """Pins of the oracle's Darcy (2,2) block for a gamma that varies inside the
-elements (Section 3.3, the general case of eq. transformed-system-darcy):
+elements (Section 2.4, the general case of eq. transformed-system-darcy):
 C_e = W_e^{-1} W_gamma,e W_e^{-1} with gamma the trilinear interpolant of
 vertex values.
 
