@@ -288,6 +288,22 @@ int hd_gmres_solve(hd_ctx* ctx, double tol, int max_it, int restart, const doubl
  * RT dofs and z_u = r_u on essential ones.  FP64 device pointers of length
  * n_u + n_q, r != z.  HD_ERR_STATE before hd_build_precond. */
 int hd_apply_tri_precond(hd_ctx* ctx, const double* r, double* z);
+
+/* hd_apply_tri_precond without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments, result and kernels, but
+ * the V-cycle output it needs (n_q values) lives in a fixed device array of
+ * the library of 2^24 FP64 values (128 MiB), which every device the library
+ * runs on holds until the process ends.  Calls no hipMalloc, hipFree or
+ * allocating routine and does not synchronise (asynchronous on the
+ * context's stream).  All calls on one device share that array and leave
+ * the last call's contents in it; nothing in it needs to start at zero.
+ * Calls that overlap in time on one device (other streams, other contexts
+ * or threads) race on it and must be serialised by the caller.
+ * HD_ERR_ARG if n_q > 2^24 or for bad pointers (r != z, both FP64 device
+ * arrays of n_u + n_q values, caller-owned); HD_ERR_STATE before
+ * hd_setup_mesh or hd_build_precond. */
+int hd_apply_tri_precond_noalloc(hd_ctx* ctx, const double* r, double* z);
 /* The solver's work space (Krylov vectors, partial sums, pinned state) stays
  * allocated in the context between calls and is rebuilt when the sizes,
  * the precision mode or nrhs change; hd_destroy releases it. */

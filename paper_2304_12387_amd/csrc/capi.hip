@@ -1,9 +1,41 @@
 // extern "C" entry points of libhdivsp (declared in include/hdivsp.h).
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "hd_internal.hpp"
+
+// Fixed device storage of hd_apply_tri_precond_noalloc: the V-cycle output
+// s = S^{-1} r_q (n_q values) that hd_apply_tri_precond allocates per call.
+// Each device the library runs on holds its own copy for the life of the
+// process.  In host code `scratch` is only a host-side stand-in for the
+// symbol: its device address is looked up once per device, with that device
+// current, in hd_create, and only that address is passed to kernels.
+static constexpr int64_t NOALLOC_MAX_NQ = int64_t(1) << 24;
+static __device__ __align__(256) double scratch[NOALLOC_MAX_NQ];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;   // per device ordinal; nullptr until looked up
+
+// Device address of `scratch` on the current device `device` (looked up on
+// the first call for that device).
+int scratch_lookup(int device, double** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+    if (!g_scratch_dev[device]) {
+        double* ptr = nullptr;
+        if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return HD_ERR_HIP;
+        g_scratch_dev[device] = ptr;
+    }
+    *out = g_scratch_dev[device];
+    return HD_OK;
+}
+
+}  // namespace
 
 namespace hd {
 
@@ -157,6 +189,10 @@ int hd_create(hd_ctx** out, int device, void* stream) {
         return HD_ERR_HIP;
     }
     (void)hipMemset(c->d_scal, 0, 16 * sizeof(double));
+    if (scratch_lookup(device, &c->d_noalloc) != HD_OK) {
+        hd_destroy(c);
+        return HD_ERR_HIP;
+    }
     *out = c;
     return HD_OK;
 }
@@ -463,6 +499,9 @@ int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
     rc = build_amg_host(S, prm, c->singular, c->host_amg, err);
     if (rc) return set_err(c, rc, err);
     if ((rc = upload_amg(c))) return rc;
+    // the V-cycle's partial sums (singular S~): sized here so that applying
+    // the preconditioner never allocates
+    if ((rc = launch_ensure_partial(c, schur_partial_count(c)))) return rc;
     c->have_prec = true;
     if (c->fallback_used) {
         c->err = "learned scalings not finite: plain diagonal used";
@@ -485,6 +524,19 @@ int hd_apply_precond(hd_ctx* c, int prec, int nrhs, const void* r, void* z) {
         if ((rc = launch_precond(c, prec, (const char*)r + off, (char*)z + off, nullptr, nullptr, nullptr))) return rc;
     }
     return HD_OK;
+}
+
+int hd_apply_tri_precond_noalloc(hd_ctx* c, const double* r, double* z) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_mesh) return set_err(c, HD_ERR_STATE, "hd_setup_mesh first");
+    if (c->n_q > NOALLOC_MAX_NQ)
+        return set_err(c, HD_ERR_ARG, "n_q = " + std::to_string(c->n_q) + " exceeds the fixed scratch of " +
+                                          std::to_string(NOALLOC_MAX_NQ) + " values");
+    if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
+    if (!r || !z || r == z) return set_err(c, HD_ERR_ARG, "r, z must be distinct device pointers");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_tri_precond(c, r, z, c->d_noalloc);
 }
 
 int hd_gmres_solve(hd_ctx* c, double tol, int max_it, int restart, const double* b, double* x,

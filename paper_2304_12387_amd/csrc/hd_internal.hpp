@@ -221,6 +221,7 @@ struct hd_ctx {
     // scratch
     double* d_partial = nullptr;     // per-block partial sums (>= ne and >= reduce grid)
     int64_t partial_cap = 0;
+    double* d_noalloc = nullptr;     // device address of the library's fixed scratch on this device (not owned)
     double* d_scal = nullptr;        // small device scalar block
     int* d_flag = nullptr;
 

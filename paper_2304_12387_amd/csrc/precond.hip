@@ -486,9 +486,10 @@ int schur_apply(hd_ctx* c, const T* b, T* z, double* part, const int* done) {
         return HD_OK;
     }
     const int64_t np = post_partials(c);
-    int rc = launch_ensure_partial(c, np);
-    if (rc) return rc;
+    // sized by hd_build_precond
+    if (np > c->partial_cap) return set_err(c, HD_ERR_STATE, "partial-sum buffer smaller than the V-cycle needs");
     double* zs = c->d_partial;
+    int rc;
     rc = cycle<T>(c, 0, b, z, one_level ? nullptr : zs, 1, done);
     if (rc) return rc;
     if (one_level)

@@ -35,6 +35,7 @@ EXPORTED = [
     'hd_set_diag_scalings', 'hd_setup_batch', 'hd_batch_sizes', 'hd_batch_apply', 'hd_batch_tune',
     'hd_batch_set_launch', 'hd_batch_build_precond', 'hd_batch_minres_solve', 'hd_constant_flux',
     'hd_set_local_solver', 'hd_set_gamma_field', 'hd_gmres_solve', 'hd_apply_tri_precond',
+    'hd_apply_tri_precond_noalloc',
 ]
 
 
@@ -100,6 +101,7 @@ def load():
         'hd_set_gamma_field': (I, [P, P]),
         'hd_gmres_solve': (I, [P, D, I, I, P, P, ctypes.POINTER(SolveInfo)]),
         'hd_apply_tri_precond': (I, [P, P, P]),
+        'hd_apply_tri_precond_noalloc': (I, [P, P, P]),
         'hd_apply_l2_mass_inverse': (I, [P, I, P, P]),
         'hd_lift_essential': (I, [P, P, P]),
         'hd_build_precond': (I, [P, ctypes.POINTER(PrecondParams)]),
@@ -439,6 +441,14 @@ class Context:
         self._dev(r, nu + nq, HD_F64, 'r')
         self._dev(z, nu + nq, HD_F64, 'z')
         return self._check(self.lib.hd_apply_tri_precond(self.h, _ptr(r), _ptr(z)))
+
+    def apply_tri_precond_noalloc(self, r, z):
+        """hd_apply_tri_precond_noalloc: the same z = P^{-1} r with the V-cycle
+        output in the library's fixed device array (no allocation)."""
+        nu, nq = self.sizes()
+        self._dev(r, nu + nq, HD_F64, 'r')
+        self._dev(z, nu + nq, HD_F64, 'z')
+        return self._check(self.lib.hd_apply_tri_precond_noalloc(self.h, _ptr(r), _ptr(z)))
 
     def gmres_solve(self, b, x, tol=1e-8, max_it=2000, restart=30):
         """GMRES(restart) with the block-triangular preconditioner; x is the
