@@ -30,6 +30,8 @@ Other workloads (`--workload`, one JSON line each, no CPU baseline):
                  1..6): batched apply in the autotuned launch mode (persistent
                  work queue, or each instance's own launch), FP64 and FP32.
   multirhs64     grad-div 64^3, p = 3, 16 right-hand sides: FP32 apply.
+  batch32_solve  the 32 instances of batch32 by one batched MINRES to a true
+                 residual of 1e-8 (PLAIN64 and MIXED), per-instance iterations.
   batch_solve8   8 independent grad-div instances (n^3, n in 8..20, p in
                  1..4): one batched MINRES to a true residual of 1e-8 in each
                  mode, against the instances solved one after the other.
@@ -646,9 +648,56 @@ def run_distorted48(args, torch, hdivsp, inputs):
     return out
 
 
+def run_batch32_solve(args, torch, hdivsp, inputs):
+    """The 32 independent grad-div instances of the batched apply solved by
+    one batched MINRES to a true relative residual of 1e-8 (PLAIN64, then
+    MIXED): per-instance iterations and residuals, the batched set-up (the
+    instances' AMG hierarchies built on the GPU) timed separately."""
+    import numpy as np
+    dev = torch.device('cuda', 0)
+    stream = torch.cuda.current_stream(dev)
+    inst = inputs.batch_instances()
+    ctx = hdivsp.Context(0, stream)
+    t0 = time.perf_counter()
+    ctx.setup_batch(0, inst)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.batch_build_precond(hdivsp.precond_params())
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tuned = ctx.batch_tune(hdivsp.HD_F64)
+    off = ctx.batch_offsets
+    N = int(off[-1])
+    b = torch.from_numpy(np.random.default_rng(41).uniform(-1.0, 1.0, N)).to(dev)
+    x = torch.zeros_like(b)
+    res = {}
+    ts = time.perf_counter()
+    for name, prm in (('plain', hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_PLAIN64, stop_true=1)),
+                      ('mixed', hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_MIXED, inner_tol=1e-5))):
+        x.zero_()
+        torch.cuda.synchronize()
+        infos = ctx.batch_minres_solve(b, x, prm)
+        res[name] = {"time_to_1e-8_s": round(infos[0]['time_s'], 4),
+                     "iterations": [f['iterations'] for f in infos],
+                     "worst_true_rel_res": max(f['true_rel_res'] for f in infos),
+                     "status": [f['status'] for f in infos]}
+        print(f"batch32 {name}: {res[name]['time_to_1e-8_s']} s", file=sys.stderr, flush=True)
+    te = time.perf_counter()
+    out = base_line("time-to-1e-8 (s) of one batched MINRES over 32 grad-div instances (PLAIN64)",
+                    res['plain']['time_to_1e-8_s'], "s", args, round((te - ts) * 1e3, 3),
+                    {"workload": "batch_32_graddiv_instances_n8-40_p1-6", "total_dofs": N,
+                     "instances": [f"{d['nx']}^3 p{d['p']}" for d in inst]}, higher=False)
+    out["solvers"] = res
+    out["batch_launch"] = tuned
+    out["setup_s"] = {"mesh_coeffs": round(t1 - t0, 3), "precond": round(t2 - t1, 3)}
+    ctx.close()
+    return out
+
+
 WORKLOADS = {'graddiv32': run_default, 'darcy_layered': run_darcy_layered, 'batch32': run_batch32,
              'multirhs64': run_multirhs64, 'distorted48': run_distorted48, 'local_inverse': run_local_inverse,
-             'darcy_gamma32': run_darcy_gamma32, 'gmres32': run_gmres32, 'batch_solve8': run_batch_solve8}
+             'darcy_gamma32': run_darcy_gamma32, 'gmres32': run_gmres32, 'batch_solve8': run_batch_solve8,
+             'batch32_solve': run_batch32_solve}
 
 
 def main():

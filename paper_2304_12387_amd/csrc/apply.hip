@@ -135,6 +135,10 @@ __device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], i
     rz = slot_sum<T, W>(rz);
     const T rr0 = rz;
     bool done = !active || !(rr0 > T(0));
+    // the loop's only table, read once (wavefront-uniform: scalar registers)
+    T bgr[Q * P];
+#pragma unroll
+    for (int k = 0; k < Q * P; ++k) bgr[k] = Bg[k];
     for (int it = 0; it < cgp.maxit; ++it) {
         if (__all(done)) break;
         __syncthreads();
@@ -142,29 +146,29 @@ __device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], i
         // z^T (regs) -> y^T (LDS) -> x^T (regs)
         if (t < P * P) {
             T o[Q];
-            pencil_mul<T, P, Q, P, false>(pv, o, Bg);
+            pencil_mul<T, P, Q, P, false>(pv, o, bgr);
             pencil_store<T, P, P, P, 0, Q>(L.A1, t, o);
         }
         __syncthreads();
-        stage_lds<T, Q, P, P, 1, Q, P, false>(L.A1, L.A2, Bg, t);
+        stage_lds<T, Q, P, P, 1, Q, P, false>(L.A1, L.A2, bgr, t);
         __syncthreads();
         if (t < Q * Q) {
             T in[P], w[Q], o[P];
             pencil_load<T, Q, Q, P, 2>(L.A2, t, in);
-            pencil_mul<T, P, Q, P, false>(in, w, Bg);
+            pencil_mul<T, P, Q, P, false>(in, w, bgr);
 #pragma unroll
             for (int c = 0; c < Q; ++c) w[c] *= gw[c];
-            pencil_mul<T, Q, P, P, true>(w, o, Bg);
+            pencil_mul<T, Q, P, P, true>(w, o, bgr);
             pencil_store<T, Q, Q, Q, 2, P>(L.A1, t, o);
         }
         __syncthreads();
-        stage_lds<T, Q, Q, P, 1, P, P, true>(L.A1, L.A2, Bg, t);
+        stage_lds<T, Q, Q, P, 1, P, P, true>(L.A1, L.A2, bgr, t);
         __syncthreads();
         T pAp = 0;
         if (t < P * P) {
             T in[Q];
             pencil_load<T, Q, P, P, 0>(L.A2, t, in);
-            pencil_mul<T, Q, P, P, true>(in, Ap, Bg);
+            pencil_mul<T, Q, P, P, true>(in, Ap, bgr);
 #pragma unroll
             for (int s = 0; s < P; ++s) pAp += pv[s] * Ap[s];
         }

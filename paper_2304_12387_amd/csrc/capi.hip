@@ -98,7 +98,6 @@ void free_prec(hd_ctx* c) {
     dfree(c->d_sdiag32);
     c->d_mdiag = c->d_wdiag = c->d_mdinv = c->d_wface = c->d_sdiag = nullptr;
     c->d_mdinv32 = c->d_sdiag32 = nullptr;
-    c->host_amg = HostAMG();
     c->have_prec = false;
 }
 
@@ -483,22 +482,11 @@ int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
         return set_err(c, HD_ERR_OOM, "diagonals");
     if ((rc = launch_diagonals(c, theta))) return rc;
     if ((rc = launch_schur(c))) return rc;
-    // S~ to the host for the AMG setup
-    HostCSR S;
-    S.nrows = S.ncols = c->n_q;
-    S.rp.resize(c->n_q + 1);
-    S.ci.resize(c->S.nnz);
-    S.v.resize(c->S.nnz);
-    HD_HIP(c, hipMemcpyAsync(S.rp.data(), c->S.rp, sizeof(int32_t) * (c->n_q + 1), hipMemcpyDeviceToHost, c->stream));
-    HD_HIP(c, hipMemcpyAsync(S.ci.data(), c->S.ci, sizeof(int32_t) * c->S.nnz, hipMemcpyDeviceToHost, c->stream));
-    HD_HIP(c, hipMemcpyAsync(S.v.data(), c->S.v, sizeof(double) * c->S.nnz, hipMemcpyDeviceToHost, c->stream));
-    HD_HIP(c, hipStreamSynchronize(c->stream));
     // S~ is singular when C~ = 0 and every boundary face is essential
     c->singular = c->kappa_zero && c->ess == HD_SIDE_ALL;
-    std::string err;
-    rc = build_amg_host(S, prm, c->singular, c->host_amg, err);
-    if (rc) return set_err(c, rc, err);
-    if ((rc = upload_amg(c))) return rc;
+    // the AMG hierarchy of S~, built on the device
+    if ((rc = build_amg_gpu(c, prm))) return rc;
+    if ((rc = finish_levels(c))) return rc;
     // the V-cycle's partial sums (singular S~): sized here so that applying
     // the preconditioner never allocates
     if ((rc = launch_ensure_partial(c, schur_partial_count(c)))) return rc;
@@ -910,36 +898,50 @@ int hd_get_schur(hd_ctx* c, int64_t* nnz, int32_t* rowptr, int32_t* col, double*
 int hd_get_amg_nlevels(hd_ctx* c, int* nlevels) {
     if (!c || !nlevels) return HD_ERR_ARG;
     if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
-    *nlevels = (int)c->host_amg.A.size();
+    *nlevels = (int)c->lev.size();
     return HD_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// a device CSR matrix to caller-owned host arrays (each may be NULL)
+int copy_dev_csr(hd_ctx* c, const DevCSR& M, int64_t* nrows, int64_t* ncols, int64_t* nnz, int32_t* rowptr,
+                 int32_t* col, double* val) {
+    if (nrows) *nrows = M.nrows;
+    if (ncols) *ncols = M.ncols;
+    if (nnz) *nnz = M.nnz;
+    if (rowptr)
+        HD_HIP(c, hipMemcpyAsync(rowptr, M.rp, sizeof(int32_t) * (M.nrows + 1), hipMemcpyDeviceToHost, c->stream));
+    if (col && M.nnz)
+        HD_HIP(c, hipMemcpyAsync(col, M.ci, sizeof(int32_t) * M.nnz, hipMemcpyDeviceToHost, c->stream));
+    if (val && M.nnz) HD_HIP(c, hipMemcpyAsync(val, M.v, sizeof(double) * M.nnz, hipMemcpyDeviceToHost, c->stream));
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    return HD_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int hd_get_amg_level(hd_ctx* c, int level, int64_t* n, int64_t* nnz, int32_t* rowptr, int32_t* col, double* val) {
     if (!c) return HD_ERR_ARG;
     if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
-    if (level < 0 || level >= (int)c->host_amg.A.size()) return set_err(c, HD_ERR_ARG, "level");
-    const HostCSR& A = c->host_amg.A[level];
-    if (n) *n = A.nrows;
-    if (nnz) *nnz = A.nnz();
-    if (rowptr) std::memcpy(rowptr, A.rp.data(), sizeof(int32_t) * (A.nrows + 1));
-    if (col) std::memcpy(col, A.ci.data(), sizeof(int32_t) * A.nnz());
-    if (val) std::memcpy(val, A.v.data(), sizeof(double) * A.nnz());
-    return HD_OK;
+    if (level < 0 || level >= (int)c->lev.size()) return set_err(c, HD_ERR_ARG, "level");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return copy_dev_csr(c, c->lev[level].A, n, nullptr, nnz, rowptr, col, val);
 }
 
 int hd_get_amg_prolongator(hd_ctx* c, int level, int64_t* nrows, int64_t* ncols, int64_t* nnz, int32_t* rowptr,
                            int32_t* col, double* val) {
     if (!c) return HD_ERR_ARG;
     if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
-    if (level < 0 || level >= (int)c->host_amg.P.size()) return set_err(c, HD_ERR_ARG, "level");
-    const HostCSR& P = c->host_amg.P[level];
-    if (nrows) *nrows = P.nrows;
-    if (ncols) *ncols = P.ncols;
-    if (nnz) *nnz = P.nnz();
-    if (rowptr) std::memcpy(rowptr, P.rp.data(), sizeof(int32_t) * (P.nrows + 1));
-    if (col) std::memcpy(col, P.ci.data(), sizeof(int32_t) * P.nnz());
-    if (val) std::memcpy(val, P.v.data(), sizeof(double) * P.nnz());
-    return HD_OK;
+    if (level < 0 || level + 1 >= (int)c->lev.size()) return set_err(c, HD_ERR_ARG, "level");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return copy_dev_csr(c, c->lev[level].P, nrows, ncols, nnz, rowptr, col, val);
 }
 
 int hd_apply_timing(hd_ctx* c, int reset, double* avg_ms, int64_t* count) {

@@ -181,7 +181,6 @@ struct hd_ctx {
     double* d_cinv = nullptr;
     float* d_cinv32 = nullptr;
     bool singular = false;
-    hd::HostAMG host_amg;        // kept for inspection
 
     // learned (1,1)-diagonal correction
     float* d_mlp = nullptr;          // network parameters (FP32, flat)
@@ -274,8 +273,10 @@ int launch_constant_flux(hd_ctx* c, const double* u, double* out);
 int64_t apply_partial_count(const hd_ctx* c);
 int upload_kernel_tables(hd_ctx* c);
 
-// precond.hip
-int upload_amg(hd_ctx* c);
+// precond.hip: work vectors and l1 diagonals of the levels in c->lev
+int finish_levels(hd_ctx* c);
+// amg_gpu.hip: the smoothed-aggregation hierarchy of S~ built on the device
+int build_amg_gpu(hd_ctx* c, const hd_precond_params& prm);
 int launch_precond(hd_ctx* c, int prec, const void* r, void* z, double* dot_partial_u, double* dot_partial_q,
                    const int* done);
 int launch_diag_prec(hd_ctx* c, int prec, const void* r, void* z, double* part);

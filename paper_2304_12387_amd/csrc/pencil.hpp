@@ -120,10 +120,58 @@ __device__ __forceinline__ void stage_lds(const T* src, T* dst, BP Bm, int t) {
     }
 }
 
+// Lane exchanges for the slot reductions, on the 32-bit halves of a value:
+// DPP moves inside rows of 16 lanes (no LDS access) and ds_swizzle across
+// the two rows of a 32-lane group.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_x(double v) {
+    return __hiloint2double(dpp_i<CTRL>(__double2hiint(v)), dpp_i<CTRL>(__double2loint(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_x(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+// lane l <- lane l ^ XOR inside each group of 32 lanes (swizzle bit mode)
+template <int XOR>
+__device__ __forceinline__ double swz_x(double v) {
+    constexpr int pat = 0x1F | (XOR << 10);
+    return __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(v), pat),
+                            __builtin_amdgcn_ds_swizzle(__double2loint(v), pat));
+}
+template <int XOR>
+__device__ __forceinline__ float swz_x(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (XOR << 10)));
+}
+
+// Sum over the aligned group of W lanes (W = 4, 8, 16, 32 or 64), returned
+// to every lane of the group; a fixed order, so it is reproducible.
 template <typename T, int W>
 __device__ __forceinline__ T slot_sum(T v) {
-#pragma unroll
-    for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+    static_assert(W == 4 || W == 8 || W == 16 || W == 32 || W == 64, "slot width");
+    v += dpp_x<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_x<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+    if constexpr (W == 8) v += swz_x<4>(v);
+    if constexpr (W >= 16) {
+        v += dpp_x<0x124>(v);   // row_ror:4
+        v += dpp_x<0x128>(v);   // row_ror:8
+    }
+    if constexpr (W >= 32) v += swz_x<16>(v);
+    if constexpr (W == 64) {
+        if constexpr (sizeof(T) == 8) {
+            const double a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                              __builtin_amdgcn_readlane(__double2loint(v), 0));
+            const double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
+                                              __builtin_amdgcn_readlane(__double2loint(v), 32));
+            v = a + b;
+        } else {
+            v = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)) +
+                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+        }
+    }
     return v;
 }
 

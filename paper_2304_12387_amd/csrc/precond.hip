@@ -538,30 +538,6 @@ int launch_precond(hd_ctx* c, int prec, const void* r, void* z, double* dot_part
 
 namespace {
 
-template <typename F>
-__global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) b[i] = (float)a[i];
-}
-
-int upload_csr(hd_ctx* c, const HostCSR& h, DevCSR& d) {
-    d.nrows = h.nrows;
-    d.ncols = h.ncols;
-    d.nnz = h.nnz();
-    d.rp = dalloc<int32_t>(h.nrows + 1);
-    d.ci = dalloc<int32_t>(d.nnz);
-    d.v = dalloc<double>(d.nnz);
-    d.v32 = dalloc<float>(d.nnz);
-    if (!d.rp || !d.ci || !d.v || !d.v32) return set_err(c, HD_ERR_OOM, "AMG level storage");
-    HD_HIP(c, hipMemcpyAsync(d.rp, h.rp.data(), sizeof(int32_t) * (h.nrows + 1), hipMemcpyHostToDevice, c->stream));
-    if (d.nnz) {
-        HD_HIP(c, hipMemcpyAsync(d.ci, h.ci.data(), sizeof(int32_t) * d.nnz, hipMemcpyHostToDevice, c->stream));
-        HD_HIP(c, hipMemcpyAsync(d.v, h.v.data(), sizeof(double) * d.nnz, hipMemcpyHostToDevice, c->stream));
-        hipLaunchKernelGGL(to_f32_kernel<float>, dim3(nblk(d.nnz)), dim3(BS), 0, c->stream, d.v, d.v32, d.nnz);
-    }
-    return HD_OK;
-}
-
 void free_csr(DevCSR& d) {
     dfree(d.rp);
     dfree(d.ci);
@@ -600,62 +576,38 @@ void free_levels(hd_ctx* c) {
     c->d_s0part = nullptr;
 }
 
-int upload_amg(hd_ctx* c) {
-    free_levels(c);
-    const HostAMG& H = c->host_amg;
-    const int L = (int)H.A.size();
-    c->lev.resize(L);
-    for (int l = 0; l < L; ++l) {
-        DevLevel& lv = c->lev[l];
-        const HostCSR& A = H.A[l];
-        int rc;
-        if (l == 0) lv.A = c->S;
-        else if ((rc = upload_csr(c, A, lv.A))) return rc;
-        if (l < L - 1) {
-            if ((rc = upload_csr(c, H.P[l], lv.P))) return rc;
-            HostCSR R;
-            // transpose on the host
-            R.nrows = H.P[l].ncols;
-            R.ncols = H.P[l].nrows;
-            R.rp.assign(R.nrows + 1, 0);
-            for (int32_t j : H.P[l].ci) R.rp[j + 1]++;
-            for (int64_t i = 0; i < R.nrows; ++i) R.rp[i + 1] += R.rp[i];
-            R.ci.resize(H.P[l].ci.size());
-            R.v.resize(H.P[l].v.size());
-            std::vector<int32_t> pos(R.rp.begin(), R.rp.end() - 1);
-            for (int64_t i = 0; i < H.P[l].nrows; ++i)
-                for (int32_t k = H.P[l].rp[i]; k < H.P[l].rp[i + 1]; ++k) {
-                    const int32_t j = H.P[l].ci[k];
-                    R.ci[pos[j]] = (int32_t)i;
-                    R.v[pos[j]] = H.P[l].v[k];
-                    pos[j]++;
-                }
-            if ((rc = upload_csr(c, R, lv.R))) return rc;
-        }
-        // l1 diagonal
-        std::vector<double> d(A.nrows);
-        std::vector<float> d32(A.nrows);
-        for (int64_t i = 0; i < A.nrows; ++i) {
-            double s = 0.0;
-            for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) s += std::fabs(A.v[k]);
-            d[i] = 1.0 / s;
-            d32[i] = (float)(1.0 / s);
-        }
-        lv.dinv = dalloc<double>(A.nrows);
-        lv.dinv32 = dalloc<float>(A.nrows);
-        lv.b = dalloc<double>(A.nrows);
-        lv.x = dalloc<double>(A.nrows);
-        lv.r = dalloc<double>(A.nrows);
-        lv.z = dalloc<double>(A.nrows);
-        lv.b32 = dalloc<float>(A.nrows);
-        lv.x32 = dalloc<float>(A.nrows);
-        lv.r32 = dalloc<float>(A.nrows);
-        lv.z32 = dalloc<float>(A.nrows);
+__global__ void l1_diag_kernel(int64_t n, const int32_t* __restrict__ rp, const double* __restrict__ v,
+                               double* __restrict__ d, float* __restrict__ d32) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) s = __dadd_rn(s, fabs(v[k]));
+    const double r = __ddiv_rn(1.0, s);
+    d[i] = r;
+    d32[i] = (float)r;
+}
+
+// Work vectors and l1 diagonals of every level of c->lev, the level-0 face
+// weights by sub-volume and the post-smoother's partials; FP32 copies of the
+// coarse inverse.  The level matrices and c->d_cinv are already on the device.
+int finish_levels(hd_ctx* c) {
+    for (auto& lv : c->lev) {
+        const int64_t n = lv.A.nrows;
+        lv.dinv = dalloc<double>(n);
+        lv.dinv32 = dalloc<float>(n);
+        lv.b = dalloc<double>(n);
+        lv.x = dalloc<double>(n);
+        lv.r = dalloc<double>(n);
+        lv.z = dalloc<double>(n);
+        lv.b32 = dalloc<float>(n);
+        lv.x32 = dalloc<float>(n);
+        lv.r32 = dalloc<float>(n);
+        lv.z32 = dalloc<float>(n);
         if (!lv.dinv || !lv.dinv32 || !lv.b || !lv.x || !lv.r || !lv.z || !lv.b32 || !lv.x32 || !lv.r32 || !lv.z32)
             return set_err(c, HD_ERR_OOM, "AMG work vectors");
-        HD_HIP(c, hipMemcpyAsync(lv.dinv, d.data(), sizeof(double) * A.nrows, hipMemcpyHostToDevice, c->stream));
-        HD_HIP(c, hipMemcpyAsync(lv.dinv32, d32.data(), sizeof(float) * A.nrows, hipMemcpyHostToDevice, c->stream));
-        HD_HIP(c, hipStreamSynchronize(c->stream));
+        hipLaunchKernelGGL(l1_diag_kernel, dim3(nblk(n)), dim3(BS), 0, c->stream, n, lv.A.rp, lv.A.v, lv.dinv,
+                           lv.dinv32);
+        HD_HIP(c, hipGetLastError());
     }
     {
         // level-0 face weights by sub-volume, and the post-smoother's partials
@@ -683,12 +635,6 @@ int upload_amg(hd_ctx* c) {
 #undef WLO
         HD_HIP(c, hipGetLastError());
     }
-    const int64_t nc = H.A.back().nrows;
-    c->n_coarse = nc;
-    c->d_cinv = dalloc<double>(nc * nc);
-    if (!c->d_cinv) return set_err(c, HD_ERR_OOM, "coarse inverse");
-    HD_HIP(c, hipMemcpyAsync(c->d_cinv, H.coarse_inv.data(), sizeof(double) * nc * nc, hipMemcpyHostToDevice,
-                             c->stream));
     HD_HIP(c, hipStreamSynchronize(c->stream));
     return HD_OK;
 }
