@@ -13,9 +13,10 @@ import numpy as np
 from . import inputs
 
 
-def build_dataset(ctx, n, seed=50, max_steps=30):
+def build_dataset(ctx, n, seed=50, max_steps=30, progress=None):
     """Features x [n, 27] (float32), targets theta* [n, 6] (float32) and
-    the spreads (at 0, at theta*) [n, 2] of n seeded training elements."""
+    the spreads (at 0, at theta*) [n, 2] of n seeded training elements.
+    `progress(msg)`, if given, is called after each degree's targets."""
     import torch
     V, p, alpha, beta = inputs.training_elements(n, seed)
     dev = ctx.device
@@ -30,17 +31,20 @@ def build_dataset(ctx, n, seed=50, max_steps=30):
         it = torch.from_numpy(idx).to(dev)
         theta[it] = th
         spread[it] = spr
+        if progress:
+            torch.cuda.synchronize(dev)
+            progress(f'targets p={pp}: {len(idx)} elements')
     Vd = torch.from_numpy(np.ascontiguousarray(V)).to(dev)
     x = ctx.learned_features(Vd, torch.from_numpy(alpha).to(dev), torch.from_numpy(beta).to(dev),
                              torch.from_numpy(p.astype(np.int32)).to(dev))
     return x, theta.float().contiguous(), spread
 
 
-def train(ctx, n=200000, seed=50, max_steps=30, epochs=20, batch=512, lr=1e-3, val_frac=0.1):
+def train(ctx, n=200000, seed=50, max_steps=30, epochs=20, batch=512, lr=1e-3, val_frac=0.1, progress=None):
     """Generate the data set, initialise the network from `seed` and train it;
     returns per-epoch training and validation losses and the data set's
     mean spread before and after the target scalings."""
-    x, y, spread = build_dataset(ctx, n, seed, max_steps)
+    x, y, spread = build_dataset(ctx, n, seed, max_steps, progress)
     nv = int(round(val_frac * n))
     nt = n - nv
     ctx.mlp_init(seed)
