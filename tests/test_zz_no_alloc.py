@@ -66,11 +66,11 @@ def test_noalloc_errors():
     assert lib.hd_apply_tri_precond_noalloc(ctx.h, _ptr(r), _ptr(r)) == hdivsp.HD_ERR_ARG
     assert lib.hd_apply_tri_precond_noalloc(ctx.h, None, _ptr(z)) == hdivsp.HD_ERR_ARG
     ctx.close()
-    # n_q = 33^3 * 8^3 = 18,399,744 > 2^24: rejected before any kernel
+    # n_q = 43^3 * 6^3 = 17,173,512 > 2^24: rejected before any kernel
     from paper_2304_12387_amd import inputs
-    n = 33
+    n = 43
     big = hdivsp.Context(0)
-    big.setup_mesh(n, n, n, 8, inputs.box_vertices(n, n, n))
+    big.setup_mesh(n, n, n, 6, inputs.box_vertices(n, n, n))
     assert big.sizes()[1] > 1 << 24
     rc = lib.hd_apply_tri_precond_noalloc(big.h, _ptr(r), _ptr(z))
     assert rc == hdivsp.HD_ERR_ARG and b'exceeds' in lib.hd_last_error(big.h)
