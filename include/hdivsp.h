@@ -160,6 +160,50 @@ int hd_setup_mesh(hd_ctx* ctx, int nx, int ny, int nz, int p, const double* vert
 int hd_setup_coeffs(hd_ctx* ctx, int problem, const double* c_mass, const double* c_22,
                     uint32_t ess_sides);
 
+/* Unstructured hexahedral mesh (Section 3.2, Algorithm 1: D from element-to-
+ * dof index arrays and orientation signs; Section 4.1 solves on such a mesh)
+ * instead of hd_setup_mesh.  vertices: host array [nv][3]; elements: host
+ * array [ne][8] of vertex numbers in the reference order v = dx + 2 dy + 4 dz
+ * (the trilinear map must keep det J > 0); both copied.  Faces are matched
+ * by their four vertex numbers (a face shared by more than two elements, or
+ * with a repeated vertex, is HD_ERR_MESH).  Each face carries a canonical
+ * frame fixed by its vertex numbers: origin at its smallest-numbered vertex,
+ * first axis towards the smaller-numbered of the origin's two neighbours on
+ * the face, second axis towards the other, normal = first x second; its RT
+ * dofs are the sub-face fluxes along that normal.
+ * Numbering of the RT block: the face dofs face by face (faces in the order
+ * of their first appearance over (element, local face 2 d + s), local face
+ * (d, s) the side x_d = s), p^2 per face, first frame index fastest; then
+ * the interior dofs element by element, 3 (p-1) p^2 each: component c, the
+ * index along c from 1 to p-1 fastest, then the two others in increasing
+ * axis order.  The L2 block is element-major as on structured meshes.  The
+ * operator, the preconditioner and MINRES then work as on structured
+ * meshes (the L2 rows of S~ through the same index arrays; level 0 of the
+ * V-cycle as a CSR level).  hd_setup_coeffs takes per-element arrays in
+ * element order and ess_sides 0 or HD_SIDE_ALL (every boundary face
+ * essential); hd_set_essential_dofs selects any other set.  Structured-only
+ * calls (gamma fields, the learned diagonal, the block-triangular
+ * preconditioner and GMRES, hd_constant_flux, hd_lift_essential, batches)
+ * return HD_ERR_STATE.  Errors: HD_ERR_ARG for bad sizes, p outside [1, 6]
+ * or vertex numbers out of range; HD_ERR_NONFINITE; HD_ERR_MESH. */
+int hd_setup_mesh_unstructured(hd_ctx* ctx, int64_t nv, const double* vertices, int64_t ne,
+                               const int64_t* elements, int p);
+
+/* Essential RT dofs of an unstructured mesh (identity rows and columns):
+ * host array of n_u bytes, nonzero = essential, copied.  Call after
+ * hd_setup_coeffs (HD_ERR_STATE otherwise, or on a structured mesh); drops the
+ * preconditioner.  The Schur approximation is taken as singular (constants
+ * removed, Section 4.2) when the (2,2) block is zero and every dof on a
+ * boundary face is essential. */
+int hd_set_essential_dofs(hd_ctx* ctx, const uint8_t* mask);
+
+/* The element-to-dof map of an unstructured mesh: host array [ne][3 p^2 (p+1)]
+ * (local RT dofs component-major, each component's tensor index with its
+ * first index fastest), entry g where the element's local dof equals global
+ * dof g and ~g (bitwise complement, negative) where it equals -g.
+ * HD_ERR_STATE before hd_setup_mesh_unstructured. */
+int hd_get_dof_map(hd_ctx* ctx, int32_t* l2g);
+
 /* Darcy with gamma varying inside the elements (Section 2.4, the general case
  * of eq. transformed-system-darcy): gamma becomes the continuous
  * piecewise-trilinear field with the given values at the mesh vertices
@@ -444,6 +488,13 @@ int hd_host_amg_level(const hd_host_amg* h, int level, int64_t* n, int64_t* nnz,
 int hd_host_amg_prolongator(const hd_host_amg* h, int level, int64_t* nrows, int64_t* ncols,
                             int64_t* nnz, int32_t* rowptr, int32_t* col, double* val);
 int hd_host_amg_free(hd_host_amg* h);
+
+/* The RT numbering of an unstructured mesh as hd_setup_mesh_unstructured
+ * builds it, on the host only (no device, no context): n_u and, when l2g is
+ * not NULL, the element-to-dof map of hd_get_dof_map ([ne][3 p^2 (p+1)]).
+ * Errors as hd_setup_mesh_unstructured for the element array. */
+int hd_host_unstructured_map(int64_t nv, int64_t ne, const int64_t* elements, int p, int64_t* n_u,
+                             int32_t* l2g);
 
 /* 1D tables of degree p as computed by the library (host, no device):
  * Gauss-Lobatto points (p+1), Gauss-Legendre points and weights (p+1). */

@@ -256,155 +256,6 @@ class UnstructuredProblem:
         return np.concatenate([yu, yq])
 
 
-# ---- meshes -------------------------------------------------------------------
-
-def from_structured(nx, ny, nz, vertices):
-    """Element-to-vertex array of a structured nx x ny x nz box mesh (vertex
-    (ix, iy, iz) numbered ix + (nx+1)(iy + (ny+1) iz), as oracle.assemble)."""
-    el = []
-    for ez in range(nz):
-        for ey in range(ny):
-            for ex in range(nx):
-                el.append([(ex + (v & 1)) + (nx + 1) * ((ey + ((v >> 1) & 1)) + (ny + 1) * (ez + (v >> 2)))
-                           for v in range(8)])
-    return np.asarray(vertices, dtype=np.float64).reshape(-1, 3), np.asarray(el, dtype=np.int64)
-
-
-def cube_rotations():
-    """The 24 orientation-preserving symmetries of the reference cube as
-    permutations of its 8 vertices: new_local[v] = old_local[perm[v]]."""
-    mats = []
-    for perm in ([0, 1, 2], [0, 2, 1], [1, 0, 2], [1, 2, 0], [2, 0, 1], [2, 1, 0]):
-        for signs in np.ndindex(2, 2, 2):
-            R = np.zeros((3, 3), dtype=np.int64)
-            for r in range(3):
-                R[r, perm[r]] = 1 if signs[r] == 0 else -1
-            if round(np.linalg.det(R)) == 1:
-                mats.append(R)
-    out = []
-    for R in mats:
-        # vertex at reference point x goes to R (x - 1/2) + 1/2
-        p = []
-        for v in range(8):
-            x = REF_VERTS[v] * 2 - 1
-            y = (R @ x + 1) // 2
-            p.append(int(y[0] + 2 * y[1] + 4 * y[2]))
-        out.append(np.array(p))
-    return out
-
-
-def scramble(vertices, elements, seed):
-    """The same mesh with the vertices and the elements renumbered at random
-    and every element's vertex list turned by a random rotation of the
-    reference cube (orientation preserving, so det J stays positive)."""
-    rng = np.random.default_rng(seed)
-    nv = vertices.shape[0]
-    vperm = rng.permutation(nv)            # old vertex v -> new number vperm[v]
-    newV = np.empty_like(vertices)
-    newV[vperm] = vertices
-    rots = cube_rotations()
-    el = vperm[elements]
-    out = np.empty_like(el)
-    for e in range(el.shape[0]):
-        r = rots[rng.integers(len(rots))]
-        # local vertex v of the turned element is the old local vertex r^-1[v]
-        inv = np.empty(8, dtype=np.int64)
-        inv[r] = np.arange(8)
-        out[e] = el[e][inv]
-    eperm = rng.permutation(el.shape[0])
-    return newV, out[eperm], eperm
-
-
-def o_grid(n, m, nz, seed=0, jitter=0.05):
-    """An O-grid hexahedral mesh of a cylinder-like domain: a central n x n
-    block and four n x m blocks around it, extruded over nz layers.  The four
-    corners of the central block have 3 neighbouring vertices in the cross
-    section instead of 4 (an unstructured mesh).  Interior vertices are
-    jittered by +-jitter of the spacing (seeded)."""
-    rng = np.random.default_rng(seed)
-    pts = {}
-    coords = []
-
-    def vid(key, xy):
-        if key not in pts:
-            pts[key] = len(coords)
-            coords.append(xy)
-        return pts[key]
-
-    # cross-section vertices: central square [-a, a]^2, outer ring radius R
-    a, R = 0.5, 1.5
-    quads = []
-    # central block
-    g = np.linspace(-a, a, n + 1)
-    for j in range(n):
-        for i in range(n):
-            q = [('c', i + di, j + dj) for (di, dj) in ((0, 0), (1, 0), (0, 1), (1, 1))]
-            quads.append(q)
-    # boundary of the central block, counter-clockwise, 4n points
-    def square_pt(t):
-        # t in [0, 4n): side 0 bottom (left->right), 1 right (bottom->top), 2 top (right->left), 3 left
-        s, r = divmod(t, n)
-        if s == 0:
-            return ('c', r, 0)
-        if s == 1:
-            return ('c', n, r)
-        if s == 2:
-            return ('c', n - r, n)
-        return ('c', 0, n - r)
-
-    def square_xy(t):
-        key = square_pt(t)
-        return np.array([g[key[1]], g[key[2]]])
-
-    for t in range(4 * n):
-        for k in range(m):
-            q = []
-            for (dt, dk) in ((0, 0), (1, 0), (0, 1), (1, 1)):
-                tt = (t + dt) % (4 * n)
-                kk = k + dk
-                q.append(square_pt(tt) if kk == 0 else ('r', tt, kk))
-            quads.append(q)
-    # coordinates
-    cross = {}
-    for j in range(n + 1):
-        for i in range(n + 1):
-            cross[('c', i, j)] = np.array([g[i], g[j]])
-    for t in range(4 * n):
-        inner = square_xy(t)
-        ang = np.arctan2(inner[1], inner[0])
-        outer = R * np.array([np.cos(ang), np.sin(ang)])
-        for kk in range(1, m + 1):
-            s = kk / m
-            cross[('r', t, kk)] = (1 - s) * inner + s * outer
-    keys2 = list(cross.keys())
-    idx2 = {k: i for i, k in enumerate(keys2)}
-    xy = np.array([cross[k] for k in keys2])
-    # jitter cross-section vertices that are not on the outer circle and not
-    # on the central block's corners
-    interior = np.array([not (k[0] == 'r' and k[2] == m) for k in keys2])
-    h = 2 * a / n
-    xy = xy + interior[:, None] * rng.uniform(-jitter * h, jitter * h, xy.shape)
-    zs = np.linspace(0.0, 1.0, nz + 1)
-    nv2 = len(keys2)
-    V = np.zeros(((nz + 1) * nv2, 3))
-    for kz in range(nz + 1):
-        V[kz * nv2:(kz + 1) * nv2, :2] = xy
-        V[kz * nv2:(kz + 1) * nv2, 2] = zs[kz]
-    el = []
-    for kz in range(nz):
-        for q in quads:
-            v = [idx2[k] for k in q]      # (0,0), (1,0), (0,1), (1,1) in the quad's own frame
-            x0 = xy[v[0]]
-            d1, d2 = xy[v[1]] - x0, xy[v[2]] - x0
-            cr = d1[0] * d2[1] - d1[1] * d2[0]
-            if cr < 0:                    # keep the cross-section quad counter-clockwise
-                v = [v[0], v[2], v[1], v[3]]
-            bot = [kz * nv2 + w for w in v]
-            top = [(kz + 1) * nv2 + w for w in v]
-            el.append(bot + top)
-    return V, np.asarray(el, dtype=np.int64)
-
-
 # ---- geometric signatures (for checks) -----------------------------------------
 
 def flux_normal(J, comps):

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, 'csrc')
 BUILD = os.path.join(os.path.dirname(HERE), '_build')
 LIB = os.path.join(HERE, 'libhdivsp.so')
 
-SOURCES = ['tables.cpp', 'amg_host.cpp', 'amg_gpu.hip', 'setup.hip', 'apply.hip', 'precond.hip', 'minres.hip', 'gmres.hip',
+SOURCES = ['tables.cpp', 'amg_host.cpp', 'unstructured.cpp', 'amg_gpu.hip', 'setup.hip', 'apply.hip', 'precond.hip', 'minres.hip', 'gmres.hip',
            'learned.hip',
            'capi.hip']
 ARCH = 'gfx950'

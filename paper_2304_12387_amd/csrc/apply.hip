@@ -44,14 +44,22 @@ struct CGParams {
     int maxit;
 };
 
-// Lanes per element: the largest pencil count of any stage is (p+1)^2, so W
-// is the smallest power of two >= (p+1)^2 (4 at p = 1, 16 at p = 2 and 3, 32
-// at p = 4 and 5, 64 at p = 6); a wavefront holds 64 / W elements.
+// Lanes per element slot W (a power of two dividing 64; a wavefront holds
+// EPW = 64 / W elements).  A stage with more pencils than W takes them in
+// passes of W; in particular the (p+1)^2 quadrature columns are held QC per
+// lane (column t + W c on lane t).  The vectors of the local CG live in the
+// p^2 x-pencils, so W >= p^2.  W is the smallest power of two >= (p+1)^2, so
+// that one pass covers every stage (4 at p = 1, 16 at p = 2 and 3, 32 at
+// p = 4, 64 at p = 5 and 6); at p = 4, 16-lane slots with two passes (four
+// elements per wavefront) measured 7% slower: they need twice the LDS and
+// registers per wavefront, which halves the wavefronts per SIMD.
 template <int P>
 struct Slot {
     static constexpr int Q = P + 1;
-    static constexpr int W = Q * Q <= 4 ? 4 : (Q * Q <= 8 ? 8 : (Q * Q <= 16 ? 16 : (Q * Q <= 32 ? 32 : 64)));
+    static constexpr int W = Q * Q <= 4 ? 4 : (Q * Q <= 16 ? 16 : (Q * Q <= 32 ? 32 : 64));
     static constexpr int EPW = 64 / W;
+    static constexpr int QC = (Q * Q + W - 1) / W;
+    static_assert(P * P <= W && 64 % W == 0, "slot width");
 };
 
 template <int P, typename T>
@@ -87,18 +95,18 @@ struct ElemLDS {
 // not converged.
 // ---------------------------------------------------------------------------
 template <int P, typename T>
-__device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], int t, bool active, T kE,
+__device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[Slot<P>::QC][P + 1], int t, bool active, T kE,
                          const CGParams<T>& cgp) {
     constexpr int Q = P + 1;
-    constexpr int W = Slot<P>::W;
+    constexpr int W = Slot<P>::W, QC = Slot<P>::QC;
 #define Ti (&tfence<P, T>(tk)->Ti[0][0])
 #define Bg (&tfence<P, T>(tk)->Bg[0][0])
 #define Bg2 (&tfence<P, T>(tk)->Bg2[0][0])
     T r[P], z[P], pv[P], x[P], dW[P], Ap[P];
     // rhs in the GL nodal basis: T^{-T} sq, contracted z, y, then x
-    stage_lds<T, P, P, P, 2, P, P, true>(L.sq, L.A1, Ti, t);
+    stage_lds<T, P, P, P, 2, P, P, true, W>(L.sq, L.A1, Ti, t);
     __syncthreads();
-    stage_lds<T, P, P, P, 1, P, P, true>(L.A1, L.A2, Ti, t);
+    stage_lds<T, P, P, P, 1, P, P, true, W>(L.A1, L.A2, Ti, t);
     __syncthreads();
     if (t < P * P) {
         T in[P];
@@ -107,13 +115,17 @@ __device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], i
     }
     __syncthreads();
     // Jacobi diagonal of the GL mass: (Bg^2)^T applied to gw in z, y, x
-    if (t < Q * Q) {
-        T o[P];
-        pencil_mul<T, Q, P, P, true>(gw, o, Bg2);
-        pencil_store<T, Q, Q, Q, 2, P>(L.A1, t, o);
+#pragma unroll
+    for (int cc = 0; cc < QC; ++cc) {
+        const int col = t + cc * W;
+        if (col < Q * Q) {
+            T o[P];
+            pencil_mul<T, Q, P, P, true>(gw[cc], o, Bg2);
+            pencil_store<T, Q, Q, Q, 2, P>(L.A1, col, o);
+        }
     }
     __syncthreads();
-    stage_lds<T, Q, Q, P, 1, P, P, true>(L.A1, L.A2, Bg2, t);
+    stage_lds<T, Q, Q, P, 1, P, P, true, W>(L.A1, L.A2, Bg2, t);
     __syncthreads();
     T rz = 0;
     if (t < P * P) {
@@ -150,19 +162,23 @@ __device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], i
             pencil_store<T, P, P, P, 0, Q>(L.A1, t, o);
         }
         __syncthreads();
-        stage_lds<T, Q, P, P, 1, Q, P, false>(L.A1, L.A2, bgr, t);
+        stage_lds<T, Q, P, P, 1, Q, P, false, W>(L.A1, L.A2, bgr, t);
         __syncthreads();
-        if (t < Q * Q) {
-            T in[P], w[Q], o[P];
-            pencil_load<T, Q, Q, P, 2>(L.A2, t, in);
-            pencil_mul<T, P, Q, P, false>(in, w, bgr);
 #pragma unroll
-            for (int c = 0; c < Q; ++c) w[c] *= gw[c];
-            pencil_mul<T, Q, P, P, true>(w, o, bgr);
-            pencil_store<T, Q, Q, Q, 2, P>(L.A1, t, o);
+        for (int cc = 0; cc < QC; ++cc) {
+            const int col = t + cc * W;
+            if (col < Q * Q) {
+                T in[P], w[Q], o[P];
+                pencil_load<T, Q, Q, P, 2>(L.A2, col, in);
+                pencil_mul<T, P, Q, P, false>(in, w, bgr);
+#pragma unroll
+                for (int c = 0; c < Q; ++c) w[c] *= gw[cc][c];
+                pencil_mul<T, Q, P, P, true>(w, o, bgr);
+                pencil_store<T, Q, Q, Q, 2, P>(L.A1, col, o);
+            }
         }
         __syncthreads();
-        stage_lds<T, Q, Q, P, 1, P, P, true>(L.A1, L.A2, bgr, t);
+        stage_lds<T, Q, Q, P, 1, P, P, true, W>(L.A1, L.A2, bgr, t);
         __syncthreads();
         T pAp = 0;
         if (t < P * P) {
@@ -204,7 +220,7 @@ __device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], i
         pencil_store<T, P, P, P, 0, P>(L.A1, t, o);
     }
     __syncthreads();
-    stage_lds<T, P, P, P, 1, P, P, false>(L.A1, L.A2, Ti, t);
+    stage_lds<T, P, P, P, 1, P, P, false, W>(L.A1, L.A2, Ti, t);
     __syncthreads();
     if (t < P * P && active) {
         T in[P], o[P];
@@ -227,37 +243,42 @@ __device__ void local_cg(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], i
 // gamma w / det J there (gamma the trilinear interpolant of the vertex values
 // in gv, w / det J in gw as z-pencils), and back with the transposed table.
 template <int P, typename T>
-__device__ void w_gamma(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], int t) {
+__device__ void w_gamma(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[Slot<P>::QC][P + 1], int t) {
     constexpr int Q = P + 1;
+    constexpr int W = Slot<P>::W, QC = Slot<P>::QC;
 #define Hm (&tfence<P, T>(tk)->H[0][0])
-    stage_lds<T, P, P, P, 0, Q, P, false>(L.A1, L.A2, Hm, t);
+    stage_lds<T, P, P, P, 0, Q, P, false, W>(L.A1, L.A2, Hm, t);
     __syncthreads();
-    stage_lds<T, Q, P, P, 1, Q, P, false>(L.A2, L.A1, Hm, t);
+    stage_lds<T, Q, P, P, 1, Q, P, false, W>(L.A2, L.A1, Hm, t);
     __syncthreads();
-    if (t < Q * Q) {
-        const int qa = t % Q, qb = t / Q;
-        T in[P], w[Q], o[P];
-        pencil_load<T, Q, Q, P, 2>(L.A1, t, in);
-        pencil_mul<T, P, Q, P, false>(in, w, Hm);
-        const T xa = tk->xq[qa], xb = tk->xq[qb];
-        const T nx[2] = {T(1) - xa, xa}, ny[2] = {T(1) - xb, xb};
-        T gz[2];
 #pragma unroll
-        for (int dz = 0; dz < 2; ++dz)
-            gz[dz] = (L.gv[(dz * 2 + 0) * 2 + 0] * nx[0] + L.gv[(dz * 2 + 0) * 2 + 1] * nx[1]) * ny[0] +
-                     (L.gv[(dz * 2 + 1) * 2 + 0] * nx[0] + L.gv[(dz * 2 + 1) * 2 + 1] * nx[1]) * ny[1];
+    for (int cc = 0; cc < QC; ++cc) {
+        const int col = t + cc * W;
+        if (col < Q * Q) {
+            const int qa = col % Q, qb = col / Q;
+            T in[P], w[Q], o[P];
+            pencil_load<T, Q, Q, P, 2>(L.A1, col, in);
+            pencil_mul<T, P, Q, P, false>(in, w, Hm);
+            const T xa = tk->xq[qa], xb = tk->xq[qb];
+            const T nx[2] = {T(1) - xa, xa}, ny[2] = {T(1) - xb, xb};
+            T gz[2];
 #pragma unroll
-        for (int c = 0; c < Q; ++c) {
-            const T z1 = tk->xq[c];
-            w[c] *= (gz[0] * (T(1) - z1) + gz[1] * z1) * gw[c];
+            for (int dz = 0; dz < 2; ++dz)
+                gz[dz] = (L.gv[(dz * 2 + 0) * 2 + 0] * nx[0] + L.gv[(dz * 2 + 0) * 2 + 1] * nx[1]) * ny[0] +
+                         (L.gv[(dz * 2 + 1) * 2 + 0] * nx[0] + L.gv[(dz * 2 + 1) * 2 + 1] * nx[1]) * ny[1];
+#pragma unroll
+            for (int c = 0; c < Q; ++c) {
+                const T z1 = tk->xq[c];
+                w[c] *= (gz[0] * (T(1) - z1) + gz[1] * z1) * gw[cc][c];
+            }
+            pencil_mul<T, Q, P, P, true>(w, o, Hm);
+            pencil_store<T, Q, Q, Q, 2, P>(L.A2, col, o);
         }
-        pencil_mul<T, Q, P, P, true>(w, o, Hm);
-        pencil_store<T, Q, Q, Q, 2, P>(L.A2, t, o);
     }
     __syncthreads();
-    stage_lds<T, Q, Q, P, 1, P, P, true>(L.A2, L.A1, Hm, t);
+    stage_lds<T, Q, Q, P, 1, P, P, true, W>(L.A2, L.A1, Hm, t);
     __syncthreads();
-    stage_lds<T, Q, P, P, 0, P, P, true>(L.A1, L.sq, Hm, t);
+    stage_lds<T, Q, P, P, 0, P, P, true, W>(L.A1, L.sq, Hm, t);
     __syncthreads();
 #undef Hm
 }
@@ -265,7 +286,7 @@ __device__ void w_gamma(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], in
 // A1 = kappa W_e^{-1} sq: the explicit element inverse when given (p <= 2,
 // row l per lane), otherwise the local CG.
 template <int P, typename T>
-__device__ __forceinline__ void local_solve(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[P + 1], int t, bool active,
+__device__ __forceinline__ void local_solve(ElemLDS<P, T>& L, tkp<P, T> tk, const T (&gw)[Slot<P>::QC][P + 1], int t, bool active,
                                             T kE, const CGParams<T>& cgp, const T* __restrict__ winv, int64_t ee) {
     constexpr int NL = Dim<P>::NL, W = Slot<P>::W;
     if constexpr (P <= 2) {
@@ -288,22 +309,26 @@ __device__ __forceinline__ void local_solve(ElemLDS<P, T>& L, tkp<P, T> tk, cons
 
 // Forward sum factorisation of RT component C (shape N0,N1,N2) to the
 // quadrature points: x and y through LDS, z into registers (z-pencil of the
-// quadrature point column (a, b, .) for lane t = a + Q b).
+// quadrature point column (a, b, .), column t + W c in U[c] of lane t).
 template <int P, typename T, int C>
-__device__ __forceinline__ void rt_to_quad(ElemLDS<P, T>& L, tkp<P, T> tk, int t, T (&U)[P + 1]) {
-    constexpr int Q = P + 1, NC = Dim<P>::NC;
+__device__ __forceinline__ void rt_to_quad(ElemLDS<P, T>& L, tkp<P, T> tk, int t, T (&U)[Slot<P>::QC][P + 1]) {
+    constexpr int Q = P + 1, NC = Dim<P>::NC, W = Slot<P>::W, QC = Slot<P>::QC;
     constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
 #define B0 (C == 0 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
 #define B1 (C == 1 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
 #define B2 (C == 2 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
-    stage_lds<T, N0, N1, N2, 0, Q, N0, false>(L.su + C * NC, L.A1, B0, t);
+    stage_lds<T, N0, N1, N2, 0, Q, N0, false, W>(L.su + C * NC, L.A1, B0, t);
     __syncthreads();
-    stage_lds<T, Q, N1, N2, 1, Q, N1, false>(L.A1, L.A2, B1, t);
+    stage_lds<T, Q, N1, N2, 1, Q, N1, false, W>(L.A1, L.A2, B1, t);
     __syncthreads();
-    if (t < Q * Q) {
-        T in[N2];
-        pencil_load<T, Q, Q, N2, 2>(L.A2, t, in);
-        pencil_mul<T, N2, Q, N2, false>(in, U, B2);
+#pragma unroll
+    for (int cc = 0; cc < QC; ++cc) {
+        const int col = t + cc * W;
+        if (col < Q * Q) {
+            T in[N2];
+            pencil_load<T, Q, Q, N2, 2>(L.A2, col, in);
+            pencil_mul<T, N2, Q, N2, false>(in, U[cc], B2);
+        }
     }
     __syncthreads();
 #undef B0
@@ -311,35 +336,103 @@ __device__ __forceinline__ void rt_to_quad(ElemLDS<P, T>& L, tkp<P, T> tk, int t
 #undef B2
 }
 
-// Transpose of rt_to_quad for component C: from z-pencil registers V to
-// x-pencil registers y (lane t = j + N1 k holds (., j, k), N0 values).
+// Transpose of the z and y stages of rt_to_quad for component C: from the
+// z-pencil registers V to the (Q, N1, N2) array in A1, whose x-lines
+// finish_rt contracts.
 template <int P, typename T, int C>
-__device__ __forceinline__ void quad_to_rt(ElemLDS<P, T>& L, tkp<P, T> tk, int t, const T (&V)[P + 1],
-                                           T (&y)[P + 1]) {
-    constexpr int Q = P + 1;
-    constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
-#define B0 (C == 0 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
+__device__ __forceinline__ void quad_to_rt(ElemLDS<P, T>& L, tkp<P, T> tk, int t, const T (&V)[Slot<P>::QC][P + 1]) {
+    constexpr int Q = P + 1, W = Slot<P>::W, QC = Slot<P>::QC;
+    constexpr int N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
 #define B1 (C == 1 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
 #define B2 (C == 2 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0])
-    if (t < Q * Q) {
-        T o[N2];
-        pencil_mul<T, Q, N2, N2, true>(V, o, B2);
-        pencil_store<T, Q, Q, Q, 2, N2>(L.A2, t, o);
-    }
-    __syncthreads();
-    stage_lds<T, Q, Q, N2, 1, N1, N1, true>(L.A2, L.A1, B1, t);
-    __syncthreads();
-    if (t < N1 * N2) {
-        T in[Q], o[N0];
-        pencil_load<T, Q, N1, N2, 0>(L.A1, t, in);
-        pencil_mul<T, Q, N0, N0, true>(in, o, B0);
 #pragma unroll
-        for (int s = 0; s < N0; ++s) y[s] = o[s];
+    for (int cc = 0; cc < QC; ++cc) {
+        const int col = t + cc * W;
+        if (col < Q * Q) {
+            T o[N2];
+            pencil_mul<T, Q, N2, N2, true>(V[cc], o, B2);
+            pencil_store<T, Q, Q, Q, 2, N2>(L.A2, col, o);
+        }
     }
     __syncthreads();
-#undef B0
+    stage_lds<T, Q, Q, N2, 1, N1, N1, true, W>(L.A2, L.A1, B1, t);
+    __syncthreads();
 #undef B1
 #undef B2
+}
+
+// At each quadrature column (a, b, .) of lane t: U = c_mass (w J^T J / det J) U
+// for the three components, and gw = w / det J (1 without a (2,2) block).
+// The factors come from the trilinear map of the element vertices in L.vx:
+// dx/dxi and dx/deta are linear in zeta and dx/dzeta is constant along the
+// column.
+template <int P, typename T, bool HAS_C>
+__device__ __forceinline__ void quad_factors(ElemLDS<P, T>& L, tkp<P, T> tb, int t, T cM, T (&U0)[Slot<P>::QC][P + 1],
+                                             T (&U1)[Slot<P>::QC][P + 1], T (&U2)[Slot<P>::QC][P + 1],
+                                             T (&gw)[Slot<P>::QC][P + 1]) {
+    constexpr int Q = P + 1, W = Slot<P>::W, QC = Slot<P>::QC;
+#pragma unroll
+    for (int cc = 0; cc < QC; ++cc) {
+        const int col = t + cc * W;
+        if (col < Q * Q) {
+            const int qa = col % Q, qb = col / Q;
+            const T xa = tb->xq[qa], xb = tb->xq[qb];
+            const T nx[2] = {T(1) - xa, xa}, ny[2] = {T(1) - xb, xb};
+            const T* X = L.vx;
+            T A[2][3], B[2][3], C[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+#pragma unroll
+                for (int dz = 0; dz < 2; ++dz) {
+                    A[dz][r] = (X[((dz * 2 + 0) * 2 + 1) * 3 + r] - X[((dz * 2 + 0) * 2 + 0) * 3 + r]) * ny[0] +
+                               (X[((dz * 2 + 1) * 2 + 1) * 3 + r] - X[((dz * 2 + 1) * 2 + 0) * 3 + r]) * ny[1];
+                    B[dz][r] = (X[((dz * 2 + 1) * 2 + 0) * 3 + r] - X[((dz * 2 + 0) * 2 + 0) * 3 + r]) * nx[0] +
+                               (X[((dz * 2 + 1) * 2 + 1) * 3 + r] - X[((dz * 2 + 0) * 2 + 1) * 3 + r]) * nx[1];
+                }
+                T cz = 0;
+#pragma unroll
+                for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 2; ++dx)
+                        cz += (X[((2 + dy) * 2 + dx) * 3 + r] - X[(dy * 2 + dx) * 3 + r]) * nx[dx] * ny[dy];
+                C[r] = cz;
+                __builtin_amdgcn_sched_barrier(0);   // one coordinate's 8 vertex values live at a time
+            }
+            const T wab = tb->wq[qa] * tb->wq[qb];
+            // one quadrature point at a time: keeps the scheduler from
+            // computing every point's factors at once (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int c = 0; c < Q; ++c) {
+                const T z1 = tb->xq[c], z0 = T(1) - z1;
+                T J0[3], J1[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    J0[r] = A[0][r] * z0 + A[1][r] * z1;
+                    J1[r] = B[0][r] * z0 + B[1][r] * z1;
+                }
+                // det J = J0 . (J1 x C), columns of J = d x / d (xi, eta, zeta)
+                const T det = J0[0] * (J1[1] * C[2] - J1[2] * C[1]) - J0[1] * (J1[0] * C[2] - J1[2] * C[0]) +
+                              J0[2] * (J1[0] * C[1] - J1[1] * C[0]);
+                const T s = wab * tb->wq[c] / det;
+                const T g00 = s * (J0[0] * J0[0] + J0[1] * J0[1] + J0[2] * J0[2]);
+                const T g01 = s * (J0[0] * J1[0] + J0[1] * J1[1] + J0[2] * J1[2]);
+                const T g02 = s * (J0[0] * C[0] + J0[1] * C[1] + J0[2] * C[2]);
+                const T g11 = s * (J1[0] * J1[0] + J1[1] * J1[1] + J1[2] * J1[2]);
+                const T g12 = s * (J1[0] * C[0] + J1[1] * C[1] + J1[2] * C[2]);
+                const T g22 = s * (C[0] * C[0] + C[1] * C[1] + C[2] * C[2]);
+                const T a0 = U0[cc][c], a1 = U1[cc][c], a2 = U2[cc][c];
+                U0[cc][c] = cM * (g00 * a0 + g01 * a1 + g02 * a2);
+                U1[cc][c] = cM * (g01 * a0 + g11 * a1 + g12 * a2);
+                U2[cc][c] = cM * (g02 * a0 + g12 * a1 + g22 * a2);
+                gw[cc][c] = HAS_C ? s : T(1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < Q; ++c) gw[cc][c] = T(1);
+        }
+    }
 }
 
 // Global position of the x-line (., j, k) of RT component C in element
@@ -428,18 +521,26 @@ __device__ __forceinline__ void prefetch_line(const Geo& g, int ex, int ey, int 
     }
 }
 
-// D^T q~ added to the x-pencil of component C, then scatter to y and the
-// local contribution to <y, x_scaled>.  Essential dofs (identity rows) take
-// the scaled input value.  Straight-line stores: every dof of the line is
-// written once, with the first colour's value added on shared faces.
+// x-line t of component C: the last stage of the transposed sum
+// factorisation (from the (Q, N1, N2) array in A1), D^T q~ added, scatter
+// to y and the local contribution to <y, x_scaled>.  Essential dofs
+// (identity rows) take the scaled input value.  Straight-line stores: every
+// dof of the line is written once, with the first colour's value (`old`)
+// added on shared faces.
 template <int P, typename T, int C>
-__device__ __forceinline__ double finish_rt(ElemLDS<P, T>& L, const Geo& g, int ex, int ey, int ez, int t,
-                                            const T (&yv)[P + 1], const T (&old)[P + 1], uint32_t ess, int ess_mode,
-                                            T s_in, const T* __restrict__ x, T* __restrict__ y, int colour) {
-    constexpr int NC = Dim<P>::NC;
+__device__ __forceinline__ double finish_rt(ElemLDS<P, T>& L, tkp<P, T> tk, const Geo& g, int ex, int ey, int ez,
+                                            int t, const T (&old)[P + 1], uint32_t ess, int ess_mode, T s_in,
+                                            const T* __restrict__ x, T* __restrict__ y, int colour) {
+    constexpr int NC = Dim<P>::NC, Q = P + 1;
     constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
     double dot = 0.0;
     if (t >= N1 * N2) return dot;
+    T yv[N0];
+    {
+        T in[Q];
+        pencil_load<T, Q, N1, N2, 0>(L.A1, t, in);
+        pencil_mul<T, Q, N0, N0, true>(in, yv, C == 0 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0]);
+    }
     const int j = t % N1, k = t / N1;
     const RtLine r = rt_line<P, C>(g, ex, ey, ez, j, k);
     unsigned ess_mask = 0, add_mask = 0;
@@ -547,86 +648,53 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     }
     __syncthreads();
     // M u: the three components to the quadrature points
-    T U0[Q], U1[Q], U2[Q];
+    constexpr int QC = S::QC;
+    T U0[QC][Q], U1[QC][Q], U2[QC][Q];
     rt_to_quad<P, T, 0>(L, tb, t, U0);
     rt_to_quad<P, T, 1>(L, tb, t, U1);
     rt_to_quad<P, T, 2>(L, tb, t, U2);
-    // c_mass w J^T J / det J at the quadrature column (a, b, .), from the
-    // trilinear map: dx/dxi and dx/deta are linear in zeta, dx/dzeta is
-    // constant along the column
-    T gw[Q];
-    if (t < Q * Q) {
-        const int qa = t % Q, qb = t / Q;
-        const T xa = tb->xq[qa], xb = tb->xq[qb];
-        const T nx[2] = {T(1) - xa, xa}, ny[2] = {T(1) - xb, xb};
-        const T* X = L.vx;
-        T A[2][3], B[2][3], C[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-#pragma unroll
-            for (int dz = 0; dz < 2; ++dz) {
-                A[dz][r] = (X[((dz * 2 + 0) * 2 + 1) * 3 + r] - X[((dz * 2 + 0) * 2 + 0) * 3 + r]) * ny[0] +
-                           (X[((dz * 2 + 1) * 2 + 1) * 3 + r] - X[((dz * 2 + 1) * 2 + 0) * 3 + r]) * ny[1];
-                B[dz][r] = (X[((dz * 2 + 1) * 2 + 0) * 3 + r] - X[((dz * 2 + 0) * 2 + 0) * 3 + r]) * nx[0] +
-                           (X[((dz * 2 + 1) * 2 + 1) * 3 + r] - X[((dz * 2 + 0) * 2 + 1) * 3 + r]) * nx[1];
-            }
-            T cz = 0;
-#pragma unroll
-            for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 2; ++dx)
-                    cz += (X[((2 + dy) * 2 + dx) * 3 + r] - X[(dy * 2 + dx) * 3 + r]) * nx[dx] * ny[dy];
-            C[r] = cz;
-            __builtin_amdgcn_sched_barrier(0);   // one coordinate's 8 vertex values live at a time
-        }
-        const T wab = tb->wq[qa] * tb->wq[qb];
-        // one quadrature point at a time: keeps the scheduler from computing
-        // every point's factors at once (register pressure)
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int c = 0; c < Q; ++c) {
-            const T z1 = tb->xq[c], z0 = T(1) - z1;
-            T J0[3], J1[3];
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                J0[r] = A[0][r] * z0 + A[1][r] * z1;
-                J1[r] = B[0][r] * z0 + B[1][r] * z1;
-            }
-            // det J = J0 . (J1 x C), columns of J = d x / d (xi, eta, zeta)
-            const T det = J0[0] * (J1[1] * C[2] - J1[2] * C[1]) - J0[1] * (J1[0] * C[2] - J1[2] * C[0]) +
-                          J0[2] * (J1[0] * C[1] - J1[1] * C[0]);
-            const T s = wab * tb->wq[c] / det;
-            const T g00 = s * (J0[0] * J0[0] + J0[1] * J0[1] + J0[2] * J0[2]);
-            const T g01 = s * (J0[0] * J1[0] + J0[1] * J1[1] + J0[2] * J1[2]);
-            const T g02 = s * (J0[0] * C[0] + J0[1] * C[1] + J0[2] * C[2]);
-            const T g11 = s * (J1[0] * J1[0] + J1[1] * J1[1] + J1[2] * J1[2]);
-            const T g12 = s * (J1[0] * C[0] + J1[1] * C[1] + J1[2] * C[2]);
-            const T g22 = s * (C[0] * C[0] + C[1] * C[1] + C[2] * C[2]);
-            const T a0 = U0[c], a1 = U1[c], a2 = U2[c];
-            U0[c] = cM * (g00 * a0 + g01 * a1 + g02 * a2);
-            U1[c] = cM * (g01 * a0 + g11 * a1 + g12 * a2);
-            U2[c] = cM * (g02 * a0 + g12 * a1 + g22 * a2);
-            gw[c] = HAS_C ? s : T(1);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < Q; ++c) gw[c] = T(1);
-    }
+    T gw[QC][Q];
+    quad_factors<P, T, HAS_C>(L, tb, t, cM, U0, U1, U2, gw);
     double dot = 0.0;
     {
-        T yv[Q], old[Q];
+        // the first colour's values on this lane's lines, loaded before the
+        // transposed sum factorisation so that they arrive while it runs
         const bool pre = valid && colour == 1;
-        if (pre) prefetch_line<P, T, 0>(g, ex, ey, ez, t, y, old);
-        quad_to_rt<P, T, 0>(L, tb, t, U0, yv);
-        if (valid) dot += finish_rt<P, T, 0>(L, g, ex, ey, ez, t, yv, old, ess, ess_mode, s_in, x, y, colour);
-        if (pre) prefetch_line<P, T, 1>(g, ex, ey, ez, t, y, old);
-        quad_to_rt<P, T, 1>(L, tb, t, U1, yv);
-        if (valid) dot += finish_rt<P, T, 1>(L, g, ex, ey, ez, t, yv, old, ess, ess_mode, s_in, x, y, colour);
-        if (pre) prefetch_line<P, T, 2>(g, ex, ey, ez, t, y, old);
-        quad_to_rt<P, T, 2>(L, tb, t, U2, yv);
-        if (valid) dot += finish_rt<P, T, 2>(L, g, ex, ey, ez, t, yv, old, ess, ess_mode, s_in, x, y, colour);
+        constexpr int LC0 = (P * P + W - 1) / W, LC12 = ((P + 1) * P + W - 1) / W;
+        T old0[LC0][Q], old1[LC12][Q], old2[LC12][Q];
+        if (pre) {
+#pragma unroll
+            for (int lc = 0; lc < LC0; ++lc) prefetch_line<P, T, 0>(g, ex, ey, ez, t + lc * W, y, old0[lc]);
+        }
+        quad_to_rt<P, T, 0>(L, tb, t, U0);
+        if (valid) {
+#pragma unroll
+            for (int lc = 0; lc < LC0; ++lc)
+                dot += finish_rt<P, T, 0>(L, tb, g, ex, ey, ez, t + lc * W, old0[lc], ess, ess_mode, s_in, x, y, colour);
+        }
+        if (pre) {
+#pragma unroll
+            for (int lc = 0; lc < LC12; ++lc) prefetch_line<P, T, 1>(g, ex, ey, ez, t + lc * W, y, old1[lc]);
+        }
+        quad_to_rt<P, T, 1>(L, tb, t, U1);
+        if (valid) {
+#pragma unroll
+            for (int lc = 0; lc < LC12; ++lc)
+                dot += finish_rt<P, T, 1>(L, tb, g, ex, ey, ez, t + lc * W, old1[lc], ess, ess_mode, s_in, x, y, colour);
+        }
+        if (pre) {
+#pragma unroll
+            for (int lc = 0; lc < LC12; ++lc) prefetch_line<P, T, 2>(g, ex, ey, ez, t + lc * W, y, old2[lc]);
+        }
+        quad_to_rt<P, T, 2>(L, tb, t, U2);
+        if (valid) {
+#pragma unroll
+            for (int lc = 0; lc < LC12; ++lc)
+                dot += finish_rt<P, T, 2>(L, tb, g, ex, ey, ez, t + lc * W, old2[lc], ess, ess_mode, s_in, x, y, colour);
+        }
     }
+    // finish_rt read A1, which the local solve overwrites
+    __syncthreads();
     // -kappa_e W_e^{-1} q~ (compiled out of the variant for a zero (2,2) block,
     // which then needs fewer registers and runs more wavefronts per SIMD)
     if constexpr (HAS_C) {
@@ -667,16 +735,6 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     return slot_sum<double, 64>(dot);
 }
 
-// Element groups are dealt to the XCDs in contiguous chunks.  Workgroups
-// are dispatched round-robin over the 8 XCDs (block b runs on XCD b mod 8),
-// each with its own L2; neighbouring elements share cache lines of x and y,
-// so they must meet in one L2 instead of each XCD fetching the line and
-// writing back a partial one.  A bijection of [0, n).
-__device__ __forceinline__ unsigned xcd_chunk(unsigned b, unsigned n) {
-    const unsigned x = b % 8, k = b / 8;
-    return x * (n / 8) + (x < n % 8 ? x : n % 8) + k;
-}
-
 template <int P, typename T, bool HAS_C, bool VARG = false>
 __global__ __launch_bounds__(64) void block_apply_kernel(
     Geo g, const double* __restrict__ vert, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap,
@@ -694,6 +752,8 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
         r = (int)(k / gpx);
         grp = (blockIdx.x % 8) * gpx + k % gpx;
     } else {
+        // element groups dealt to the XCDs in contiguous chunks: neighbouring
+        // groups share cache lines of x and y and meet in one L2
         grp = xcd_chunk(blockIdx.x, nb);
     }
     if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;   // uniform over the block
@@ -703,6 +763,169 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
                                                 yall + r * ra.ldv, s_in, cgp, with_c, colour, grp, nb, winv,
                                                       gvert);
     if (ra.partial && grp < nb && threadIdx.x == 0) ra.partial[r * ra.part_stride + part_offset + grp] = dot;
+}
+
+// ---- unstructured hexahedral meshes --------------------------------------
+// Element-to-dof index arrays instead of structured index arithmetic
+// (Section 3.2, Algorithm 1): the local RT dof l of element e is
+// sign * u[g] with l2g[e][l] = g (sign +1) or ~g (sign -1).  There is no
+// two-colouring on a general mesh, so one launch covers all elements and
+// shared faces are summed with FP64 atomic adds into y_u, which
+// uns_init_kernel has set to 0 (and to the scaled input on essential dofs,
+// whose identity rows the element kernel skips).  At most two elements add
+// to a dof, and two-term sums do not depend on the order.
+struct UnsArgs {
+    const int32_t* l2g;    // [ne][NRT]
+    const double* evx;     // [ne][8][3] element vertex coordinates
+    const uint8_t* essm;   // [n_u] essential RT dofs
+};
+
+// D^T q~ added to x-line t of component C (from the (Q, N1, N2) array in A1),
+// then added to y through the index array.
+template <int P, typename T, int C>
+__device__ __forceinline__ void finish_uns(ElemLDS<P, T>& L, tkp<P, T> tk, const UnsArgs& ua, int64_t ee, int t,
+                                           T* __restrict__ y) {
+    constexpr int NC = Dim<P>::NC, NRT = Dim<P>::NRT, Q = P + 1;
+    constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
+    if (t >= N1 * N2) return;
+    T yv[N0];
+    {
+        T in[Q];
+        pencil_load<T, Q, N1, N2, 0>(L.A1, t, in);
+        pencil_mul<T, Q, N0, N0, true>(in, yv, C == 0 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0]);
+    }
+    const int j = t % N1, k = t / N1;
+#pragma unroll
+    for (int i = 0; i < N0; ++i) {
+        const int tn = C == 0 ? i : (C == 1 ? j : k);   // index along the normal
+        int a = i, b = j, c = k;
+        T add = 0;
+        if (tn >= 1) {
+            if (C == 0) a = i - 1; else if (C == 1) b = j - 1; else c = k - 1;
+            add += L.sq[a + P * (b + P * c)];
+        }
+        if (tn <= P - 1) add -= L.sq[i + P * (j + P * k)];
+        const int32_t m = ua.l2g[ee * NRT + C * NC + i + N0 * t];
+        const int32_t g = m < 0 ? ~m : m;
+        if (ua.essm[g]) continue;
+        const T v = m < 0 ? -(yv[i] + add) : yv[i] + add;
+        if (tn == 0 || tn == P) atomicAdd(&y[g], v);   // a face dof: shared with the neighbour
+        else y[g] = v;                                  // interior: this element's own
+    }
+}
+
+template <int P, typename T, bool HAS_C>
+__global__ __launch_bounds__(64) void block_apply_uns_kernel(UnsArgs ua, int64_t ne, tkp<P, T> tb,
+                                                             const T* __restrict__ cm, const T* __restrict__ kap,
+                                                             int64_t n_u, const T* __restrict__ xall,
+                                                             T* __restrict__ yall, RhsArgs ra, CGParams<T> cgp,
+                                                             int with_c, const T* __restrict__ winv) {
+    using D = Dim<P>;
+    using S = Slot<P>;
+    constexpr int Q = D::Q, NL = D::NL, NC = D::NC, NRT = D::NRT, W = S::W, QC = S::QC;
+    const int r = blockIdx.y;
+    if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;   // uniform over the block
+    __shared__ ElemLDS<P, T> sm[S::EPW];
+    const T* __restrict__ x = xall + r * ra.ldv;
+    T* __restrict__ y = yall + r * ra.ldv;
+    const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
+    const int lane = threadIdx.x;
+    const int slot = lane / W, t = lane % W;
+    const int64_t e0 = (int64_t)xcd_chunk(blockIdx.x, gridDim.x) * S::EPW + slot;
+    const bool valid = e0 < ne;
+    const int64_t ee = valid ? e0 : 0;
+    ElemLDS<P, T>& L = sm[slot];
+    const T cM = cm[ee];
+    const T kE = kap[ee];
+    if (valid) {
+        for (int l = t; l < 24; l += W) L.vx[l] = (T)ua.evx[24 * ee + l];
+        const int32_t* m = ua.l2g + ee * NRT;
+        for (int l = t; l < NRT; l += W) {
+            const int32_t v = m[l];
+            const int32_t g = v < 0 ? ~v : v;
+            const T xv = s_in * x[g];
+            L.su[l] = ua.essm[g] ? T(0) : (v < 0 ? -xv : xv);
+        }
+        for (int l = t; l < NL; l += W) L.sq[l] = s_in * x[n_u + ee * NL + l];
+    }
+    __syncthreads();
+    T U0[QC][Q], U1[QC][Q], U2[QC][Q];
+    rt_to_quad<P, T, 0>(L, tb, t, U0);
+    rt_to_quad<P, T, 1>(L, tb, t, U1);
+    rt_to_quad<P, T, 2>(L, tb, t, U2);
+    T gw[QC][Q];
+    quad_factors<P, T, HAS_C>(L, tb, t, cM, U0, U1, U2, gw);
+    constexpr int LC0 = (P * P + W - 1) / W, LC12 = ((P + 1) * P + W - 1) / W;
+    quad_to_rt<P, T, 0>(L, tb, t, U0);
+    if (valid) {
+#pragma unroll
+        for (int lc = 0; lc < LC0; ++lc) finish_uns<P, T, 0>(L, tb, ua, ee, t + lc * W, y);
+    }
+    quad_to_rt<P, T, 1>(L, tb, t, U1);
+    if (valid) {
+#pragma unroll
+        for (int lc = 0; lc < LC12; ++lc) finish_uns<P, T, 1>(L, tb, ua, ee, t + lc * W, y);
+    }
+    quad_to_rt<P, T, 2>(L, tb, t, U2);
+    if (valid) {
+#pragma unroll
+        for (int lc = 0; lc < LC12; ++lc) finish_uns<P, T, 2>(L, tb, ua, ee, t + lc * W, y);
+    }
+    __syncthreads();
+    if constexpr (HAS_C) {
+        if (with_c) local_solve<P, T>(L, tb, gw, t, valid && kE != T(0), kE, cgp, winv, ee);
+    }
+    __syncthreads();
+    if (valid) {
+        const bool cg = HAS_C && with_c && kE != T(0);
+        for (int l = t; l < NL; l += W) {
+            const int a = l % P, b = (l / P) % P, c = l / (P * P);
+            T v = L.su[(a + 1) + (P + 1) * (b + P * c)] - L.su[a + (P + 1) * (b + P * c)];
+            v += L.su[NC + a + P * ((b + 1) + (P + 1) * c)] - L.su[NC + a + P * (b + (P + 1) * c)];
+            v += L.su[2 * NC + a + P * (b + P * (c + 1))] - L.su[2 * NC + a + P * (b + P * c)];
+            if (cg) v -= L.A1[l];
+            y[n_u + ee * NL + l] = v;
+        }
+    }
+}
+
+// y_u = 0 on free dofs and the scaled input on essential ones (identity
+// rows), for each right-hand side (blockIdx.y)
+template <typename T>
+__global__ void uns_init_kernel(int64_t n_u, const uint8_t* __restrict__ essm, const T* __restrict__ xall,
+                                T* __restrict__ yall, RhsArgs ra) {
+    const int r = blockIdx.y;
+    if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;
+    const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
+    const T* x = xall + r * ra.ldv;
+    T* y = yall + r * ra.ldv;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_u; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = essm[i] ? s_in * x[i] : T(0);
+}
+
+constexpr unsigned UNS_DOT_BLOCKS = 1024;
+
+// per-block partial sums of <y, s_in x> over the whole vector, for each
+// right-hand side (blockIdx.y); the apply's fused inner product on
+// structured meshes
+template <typename T>
+__global__ void uns_dot_kernel(int64_t N, const T* __restrict__ xall, const T* __restrict__ yall, RhsArgs ra) {
+    const int r = blockIdx.y;
+    if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;
+    const double s_in = ra.scale ? ra.scale[(int64_t)r * ra.scale_stride] : 1.0;
+    const T* x = xall + r * ra.ldv;
+    const T* y = yall + r * ra.ldv;
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        acc += (double)y[i] * (s_in * (double)x[i]);
+    __shared__ double sh[256];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ra.partial[r * ra.part_stride + blockIdx.x] = sh[0];
 }
 
 // ---- batches of independent instances ------------------------------------
@@ -830,10 +1053,14 @@ __global__ __launch_bounds__(64) void mass_inverse_kernel(const T* __restrict__ 
     ElemLDS<P, T>& L = sm[slot];
     if (valid)
         for (int l = t; l < NL; l += W) L.sq[l] = x[ee * NL + l];
-    T gw[Q];
+    T gw[S::QC][Q];
     const T* pe = pa + (size_t)ee * NPA * Q3;
 #pragma unroll
-    for (int c = 0; c < Q; ++c) gw[c] = t < Q * Q ? pe[6 * Q3 + t + Q * Q * c] : T(1);
+    for (int cc = 0; cc < S::QC; ++cc) {
+        const int col = t + cc * W;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) gw[cc][c] = col < Q * Q ? pe[6 * Q3 + col + Q * Q * c] : T(1);
+    }
     __syncthreads();
     // A1 = W^{-1} sq
     local_cg<P, T>(L, tb, gw, t, valid, T(1), cgp);
@@ -958,6 +1185,28 @@ void launch_apply_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int ess_mode
 }
 
 template <int P, typename T>
+void launch_apply_uns_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra) {
+    const T* cm = std::is_same<T, double>::value ? (const T*)c->d_cm : (const T*)c->d_cm32;
+    const T* kap = std::is_same<T, double>::value ? (const T*)c->d_kap : (const T*)c->d_kap32;
+    const tkp<P, T> tb = (tkp<P, T>)(std::is_same<T, double>::value ? c->d_tabk64 : c->d_tabk32);
+    const T* winv = std::is_same<T, double>::value ? (const T*)c->d_winv : (const T*)c->d_winv32;
+    const UnsArgs ua = {c->d_l2g, c->d_evx, c->d_essm};
+    const unsigned nb = (unsigned)((c->ne + Slot<P>::EPW - 1) / Slot<P>::EPW);
+    const int64_t N = c->n_u + c->n_q;
+    hipLaunchKernelGGL(uns_init_kernel<T>, dim3((unsigned)std::min<int64_t>((c->n_u + 255) / 256, 4096), ra.nrhs),
+                       dim3(256), 0, c->stream, c->n_u, (const uint8_t*)c->d_essm, x, y, ra);
+    if (!c->kappa_zero)
+        hipLaunchKernelGGL((block_apply_uns_kernel<P, T, true>), dim3(nb, ra.nrhs), dim3(64), 0, c->stream, ua, c->ne,
+                           tb, cm, kap, c->n_u, x, y, ra, cg_params<T>(), 1, winv);
+    else
+        hipLaunchKernelGGL((block_apply_uns_kernel<P, T, false>), dim3(nb, ra.nrhs), dim3(64), 0, c->stream, ua,
+                           c->ne, tb, cm, kap, c->n_u, x, y, ra, cg_params<T>(), 0, (const T*)nullptr);
+    if (ra.partial)
+        hipLaunchKernelGGL(uns_dot_kernel<T>, dim3(UNS_DOT_BLOCKS, ra.nrhs), dim3(256), 0, c->stream, N, x,
+                           (const T*)y, ra);
+}
+
+template <int P, typename T>
 void launch_minv_p(hd_ctx* c, const T* x, T* y, bool weighted) {
     const T* pa = std::is_same<T, double>::value ? (const T*)c->d_pa : (const T*)c->d_pa32;
     const T* kap = std::is_same<T, double>::value ? (const T*)c->d_kap : (const T*)c->d_kap32;
@@ -969,6 +1218,17 @@ void launch_minv_p(hd_ctx* c, const T* x, T* y, bool weighted) {
 
 template <typename T>
 void dispatch_apply(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int em) {
+    if (c->unstructured) {
+        switch (c->p) {
+            case 1: launch_apply_uns_p<1, T>(c, x, y, ra); break;
+            case 2: launch_apply_uns_p<2, T>(c, x, y, ra); break;
+            case 3: launch_apply_uns_p<3, T>(c, x, y, ra); break;
+            case 4: launch_apply_uns_p<4, T>(c, x, y, ra); break;
+            case 5: launch_apply_uns_p<5, T>(c, x, y, ra); break;
+            case 6: launch_apply_uns_p<6, T>(c, x, y, ra); break;
+        }
+        return;
+    }
     switch (c->p) {
         case 1: launch_apply_p<1, T>(c, x, y, ra, em); break;
         case 2: launch_apply_p<2, T>(c, x, y, ra, em); break;
@@ -1038,6 +1298,7 @@ int upload_kernel_tables(hd_ctx* c) {
 }
 
 int64_t apply_partial_count(const hd_ctx* c) {
+    if (c->unstructured) return UNS_DOT_BLOCKS;
     return 2 * (int64_t)apply_blocks_per_colour(c->nx, c->ny, c->nz, epw_of(c->p));
 }
 

@@ -54,6 +54,16 @@ void free_mesh(hd_ctx* c) {
     dfree(c->d_pa);
     dfree(c->d_pa32);
     dfree(c->d_vert);
+    dfree(c->d_evx);
+    dfree(c->d_l2g);
+    dfree(c->d_rdof);
+    dfree(c->d_rnbr);
+    dfree(c->d_essm);
+    c->d_evx = nullptr;
+    c->d_l2g = c->d_rdof = c->d_rnbr = nullptr;
+    c->d_essm = nullptr;
+    c->unstructured = false;
+    c->u_boundary_dof.clear();
     dfree(c->d_theta);
     dfree(c->d_theta_net);
     c->d_theta_net = nullptr;
@@ -103,6 +113,23 @@ void free_prec(hd_ctx* c) {
 
 int use_device(hd_ctx* c) {
     HD_HIP(c, hipSetDevice(c->device));
+    return HD_OK;
+}
+
+// the essential-dof mask of an unstructured mesh (n_u bytes, host) to the
+// device, and whether every boundary dof is essential (a singular S~ when
+// C~ = 0, as with HD_SIDE_ALL on a box)
+int upload_essential_mask(hd_ctx* c, const uint8_t* m) {
+    if (!c->d_essm) c->d_essm = dalloc<uint8_t>(c->n_u);
+    if (!c->d_essm) return set_err(c, HD_ERR_OOM, "essential mask");
+    HD_HIP(c, hipMemcpy(c->d_essm, m, (size_t)c->n_u, hipMemcpyHostToDevice));
+    bool all = true;
+    for (int64_t i = 0; i < c->n_u; ++i)
+        if (c->u_boundary_dof[i] && !m[i]) {
+            all = false;
+            break;
+        }
+    c->ess = all ? HD_SIDE_ALL : 0;
     return HD_OK;
 }
 
@@ -294,6 +321,8 @@ int hd_setup_coeffs(hd_ctx* c, int problem, const double* c_mass, const double* 
     if (!c_mass) return set_err(c, HD_ERR_ARG, "c_mass required");
     if (problem == HD_GRADDIV && !c_22) return set_err(c, HD_ERR_ARG, "grad-div needs alpha (c_22)");
     if (ess_sides > 63) return set_err(c, HD_ERR_ARG, "ess_sides must be a 6-bit mask");
+    if (c->unstructured && ess_sides != 0 && ess_sides != HD_SIDE_ALL)
+        return set_err(c, HD_ERR_ARG, "on an unstructured mesh ess_sides is 0 or HD_SIDE_ALL (every boundary face)");
     int rc = use_device(c);
     if (rc) return rc;
     const int64_t ne = c->ne;
@@ -320,12 +349,127 @@ int hd_setup_coeffs(hd_ctx* c, int problem, const double* c_mass, const double* 
     if ((rc = upload_f64_f32(c, c_mass, ne, c->d_cm, c->d_cm32))) return rc;
     if ((rc = upload_f64_f32(c, kap.data(), ne, c->d_kap, c->d_kap32))) return rc;
     if ((rc = build_local_inverse(c))) return rc;
+    if (c->unstructured) {
+        std::vector<uint8_t> m(c->n_u, 0);
+        if (ess_sides == HD_SIDE_ALL) m = c->u_boundary_dof;
+        if ((rc = upload_essential_mask(c, m.data()))) return rc;
+    }
     c->have_coeffs = true;
+    return HD_OK;
+}
+
+int hd_setup_mesh_unstructured(hd_ctx* c, int64_t nv, const double* vertices, int64_t ne, const int64_t* elements,
+                               int p) {
+    if (!c) return HD_ERR_ARG;
+    if (nv < 8 || ne < 1 || !vertices || !elements) return set_err(c, HD_ERR_ARG, "bad mesh sizes");
+    if (p < 1 || p > 6) return set_err(c, HD_ERR_ARG, "p must be in [1, 6]");
+    if (ne > (int64_t)INT32_MAX / 8) return set_err(c, HD_ERR_ARG, "too many elements");
+    int rc = use_device(c);
+    if (rc) return rc;
+    free_prec(c);
+    free_coeffs(c);
+    free_mesh(c);
+    for (int64_t i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(vertices[i])) return set_err(c, HD_ERR_NONFINITE, "non-finite vertex coordinate");
+    UnstructuredMap m;
+    std::string err;
+    if ((rc = build_unstructured_numbering(nv, ne, elements, p, m, err))) return set_err(c, rc, err);
+    std::vector<int32_t> rdof, rnbr;
+    build_unstructured_rows(m, ne, p, rdof, rnbr);
+    // element vertex coordinates [ne][8][3]
+    std::vector<double> evx((size_t)(24 * ne));
+    for (int64_t e = 0; e < ne; ++e)
+        for (int v = 0; v < 8; ++v)
+            for (int r = 0; r < 3; ++r) evx[(size_t)(24 * e + 3 * v + r)] = vertices[3 * elements[8 * e + v] + r];
+    c->unstructured = true;
+    c->nx = (int)ne;   // the element count as an nx x 1 x 1 grid for the element-local kernels
+    c->ny = c->nz = 1;
+    c->p = p;
+    c->ne = ne;
+    c->n_u = m.n_u;
+    c->n_q = m.n_q;
+    c->n_face_dofs = m.n_face_dofs;
+    c->nface[0] = m.n_u;
+    c->nface[1] = c->nface[2] = 0;
+    c->u_boundary_dof.assign((size_t)m.n_u, 0);
+    for (int64_t f = 0; f < m.nfaces; ++f)
+        if (m.boundary_face[f])
+            for (int k = 0; k < p * p; ++k) c->u_boundary_dof[(size_t)(f * p * p + k)] = 1;
+    Tables<double>& t64 = c->tab64_host;
+    Tables<float>& t32 = c->tab32_host;
+    build_tables(p, t64, t32);
+    if (!c->d_tab64) c->d_tab64 = dalloc<Tables<double>>(1);
+    if (!c->d_tab32) c->d_tab32 = dalloc<Tables<float>>(1);
+    if (!c->d_tab64 || !c->d_tab32) return set_err(c, HD_ERR_OOM, "tables");
+    HD_HIP(c, hipMemcpyAsync(c->d_tab64, &t64, sizeof(t64), hipMemcpyHostToDevice, c->stream));
+    HD_HIP(c, hipMemcpyAsync(c->d_tab32, &t32, sizeof(t32), hipMemcpyHostToDevice, c->stream));
+    if ((rc = upload_kernel_tables(c))) return rc;
+    const int64_t q3 = (int64_t)(p + 1) * (p + 1) * (p + 1);
+    c->d_pa = dalloc<double>(ne * NPA * q3);
+    c->d_pa32 = dalloc<float>(ne * NPA * q3);
+    c->d_evx = dalloc<double>(24 * ne);
+    c->d_l2g = dalloc<int32_t>(m.l2g.size());
+    c->d_rdof = dalloc<int32_t>(rdof.size());
+    c->d_rnbr = dalloc<int32_t>(rnbr.size());
+    if (!c->d_pa || !c->d_pa32 || !c->d_evx || !c->d_l2g || !c->d_rdof || !c->d_rnbr) {
+        free_mesh(c);
+        return set_err(c, HD_ERR_OOM, "unstructured mesh arrays");
+    }
+    HD_HIP(c, hipMemcpyAsync(c->d_evx, evx.data(), sizeof(double) * evx.size(), hipMemcpyHostToDevice, c->stream));
+    HD_HIP(c, hipMemcpyAsync(c->d_l2g, m.l2g.data(), sizeof(int32_t) * m.l2g.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HD_HIP(c, hipMemcpyAsync(c->d_rdof, rdof.data(), sizeof(int32_t) * rdof.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HD_HIP(c, hipMemcpyAsync(c->d_rnbr, rnbr.data(), sizeof(int32_t) * rnbr.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HD_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+    rc = launch_geometry(c, nullptr, c->d_flag);
+    int bad = 0;
+    if (!rc) {
+        HD_HIP(c, hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HD_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    if (rc) {
+        free_mesh(c);
+        return rc;
+    }
+    if (bad) {
+        free_mesh(c);
+        return set_err(c, HD_ERR_MESH, "Jacobian determinant <= 0 in some element");
+    }
+    if ((rc = launch_ensure_partial(c, std::max<int64_t>(c->ne, apply_partial_count(c))))) return rc;
+    c->have_mesh = true;
+    c->have_coeffs = false;
+    return HD_OK;
+}
+
+int hd_set_essential_dofs(hd_ctx* c, const uint8_t* mask) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_coeffs || !c->unstructured)
+        return set_err(c, HD_ERR_STATE, "hd_setup_mesh_unstructured and hd_setup_coeffs first");
+    if (!mask) return set_err(c, HD_ERR_ARG, "mask required");
+    int rc = use_device(c);
+    if (rc) return rc;
+    free_prec(c);
+    std::vector<uint8_t> m(mask, mask + c->n_u);
+    for (auto& b : m) b = b ? 1 : 0;
+    return upload_essential_mask(c, m.data());
+}
+
+int hd_get_dof_map(hd_ctx* c, int32_t* l2g) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_mesh || !c->unstructured) return set_err(c, HD_ERR_STATE, "hd_setup_mesh_unstructured first");
+    if (!l2g) return set_err(c, HD_ERR_ARG, "l2g required");
+    int rc = use_device(c);
+    if (rc) return rc;
+    const int64_t nrt = 3LL * c->p * c->p * (c->p + 1);
+    HD_HIP(c, hipMemcpy(l2g, c->d_l2g, sizeof(int32_t) * nrt * c->ne, hipMemcpyDeviceToHost));
     return HD_OK;
 }
 
 int hd_set_gamma_field(hd_ctx* c, const double* gv) {
     if (!c) return HD_ERR_ARG;
+    if (c->unstructured) return set_err(c, HD_ERR_STATE, "gamma fields need a structured mesh");
     if (!c->have_coeffs || c->problem != HD_DARCY) return set_err(c, HD_ERR_STATE, "hd_setup_coeffs(HD_DARCY, ...) first");
     if (!gv) return set_err(c, HD_ERR_ARG, "gamma_vertices required");
     const int64_t nv = (int64_t)(c->nx + 1) * (c->ny + 1) * (c->nz + 1);
@@ -429,6 +573,7 @@ int hd_apply_l2_mass_inverse(hd_ctx* c, int prec, const void* x, void* y) {
 
 int hd_lift_essential(hd_ctx* c, const double* u_bc, double* b) {
     if (!c) return HD_ERR_ARG;
+    if (c->unstructured) return set_err(c, HD_ERR_STATE, "hd_lift_essential works on structured box meshes");
     if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
     if (!u_bc || !b) return set_err(c, HD_ERR_ARG, "null pointer");
     int rc = use_device(c);
@@ -438,6 +583,7 @@ int hd_lift_essential(hd_ctx* c, const double* u_bc, double* b) {
 
 int hd_constant_flux(hd_ctx* c, const double* u, double* dofs) {
     if (!c) return HD_ERR_ARG;
+    if (c->unstructured) return set_err(c, HD_ERR_STATE, "hd_constant_flux works on structured box meshes");
     if (!c->have_mesh) return set_err(c, HD_ERR_STATE, "hd_setup_mesh first");
     if (!u || !dofs) return set_err(c, HD_ERR_ARG, "null pointer");
     for (int d = 0; d < 3; ++d)
@@ -454,6 +600,7 @@ int hd_build_precond(hd_ctx* c, const hd_precond_params* params) {
     if (!(prm.tau > 0) || !(prm.theta >= 0) || prm.max_coarse < 1 || prm.max_levels < 1 || !(prm.omega > 0) ||
         prm.learned < 0 || prm.learned > 2)
         return set_err(c, HD_ERR_ARG, "bad preconditioner parameters");
+    if (prm.learned != 0 && c->unstructured) return set_err(c, HD_ERR_STATE, "the learned diagonal needs a structured mesh");
     if (prm.learned == 1 && !c->mlp_ready) return set_err(c, HD_ERR_STATE, "learned diagonal needs a network");
     if (prm.learned == 2 && !c->theta_set) return set_err(c, HD_ERR_STATE, "hd_set_diag_scalings first");
     int rc = use_device(c);
@@ -516,6 +663,7 @@ int hd_apply_precond(hd_ctx* c, int prec, int nrhs, const void* r, void* z) {
 
 int hd_apply_tri_precond_noalloc(hd_ctx* c, const double* r, double* z) {
     if (!c) return HD_ERR_ARG;
+    if (c->unstructured) return set_err(c, HD_ERR_STATE, "the block-triangular preconditioner needs a structured mesh");
     if (!c->have_mesh) return set_err(c, HD_ERR_STATE, "hd_setup_mesh first");
     if (c->n_q > NOALLOC_MAX_NQ)
         return set_err(c, HD_ERR_ARG, "n_q = " + std::to_string(c->n_q) + " exceeds the fixed scratch of " +
@@ -530,6 +678,7 @@ int hd_apply_tri_precond_noalloc(hd_ctx* c, const double* r, double* z) {
 int hd_gmres_solve(hd_ctx* c, double tol, int max_it, int restart, const double* b, double* x,
                    hd_solve_info* info) {
     if (!c) return HD_ERR_ARG;
+    if (c->unstructured) return set_err(c, HD_ERR_STATE, "the block-triangular preconditioner needs a structured mesh");
     if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
     if (!b || !x || b == x) return set_err(c, HD_ERR_ARG, "b, x must be distinct device pointers");
     if (!(tol > 0) || max_it < 1 || restart < 1 || restart > 500) return set_err(c, HD_ERR_ARG, "bad GMRES parameters");
@@ -540,6 +689,7 @@ int hd_gmres_solve(hd_ctx* c, double tol, int max_it, int restart, const double*
 
 int hd_apply_tri_precond(hd_ctx* c, const double* r, double* z) {
     if (!c) return HD_ERR_ARG;
+    if (c->unstructured) return set_err(c, HD_ERR_STATE, "the block-triangular preconditioner needs a structured mesh");
     if (!c->have_prec) return set_err(c, HD_ERR_STATE, "hd_build_precond first");
     if (!r || !z || r == z) return set_err(c, HD_ERR_ARG, "r, z must be distinct device pointers");
     int rc = use_device(c);
@@ -664,6 +814,7 @@ int hd_mlp_infer(hd_ctx* c, int64_t n, const float* x, float* theta, int bf16) {
 
 int hd_set_diag_scalings(hd_ctx* c, const double* theta) {
     if (!c) return HD_ERR_ARG;
+    if (c->unstructured) return set_err(c, HD_ERR_STATE, "the learned diagonal needs a structured mesh");
     if (!c->have_mesh) return set_err(c, HD_ERR_STATE, "hd_setup_mesh first");
     int rc = use_device(c);
     if (rc) return rc;

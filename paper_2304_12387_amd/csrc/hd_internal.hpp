@@ -61,6 +61,23 @@ struct HostAMG {
 int build_amg_host(const HostCSR& S, const hd_precond_params& prm, bool singular, HostAMG& out,
                    std::string& err);
 
+// Unstructured hexahedral mesh: faces and the element-to-dof index arrays
+// (unstructured.cpp).  l2g[e][NRT] holds the global RT dof of each local dof,
+// bitwise complemented (~g, a negative value) where the element's local dof
+// is minus the global one.
+struct UnstructuredMap {
+    int64_t nfaces = 0, n_face_dofs = 0, n_u = 0, n_q = 0;
+    std::vector<uint8_t> boundary_face;    // [nfaces]
+    std::vector<int32_t> elem_face;        // [ne][6] global face of local face (d, s), slot 2 d + s
+    std::vector<int32_t> l2g;              // [ne][NRT]
+};
+int build_unstructured_numbering(int64_t nv, int64_t ne, const int64_t* elem, int P, UnstructuredMap& out,
+                                 std::string& err);
+// per L2 row and face slot 2 d + side: the signed RT dof of D's entry and
+// the sub-volume across it (-1: none)
+int build_unstructured_rows(const UnstructuredMap& m, int64_t ne, int P, std::vector<int32_t>& row_dof,
+                            std::vector<int32_t>& row_nbr);
+
 // Structured-mesh geometry passed to kernels: element counts and the offsets
 // of the x-, y- and z-normal RT dof blocks.
 struct Geo {
@@ -148,6 +165,17 @@ struct hd_ctx {
     hd::Tables<double> tab64_host;
     hd::Tables<float> tab32_host;
     double* d_vert = nullptr;   // [(nx+1)(ny+1)(nz+1)][3], kept for the learned features
+
+    // unstructured hexahedral mesh (hd_setup_mesh_unstructured); nx = ne,
+    // ny = nz = 1 then, and the structured index arithmetic is not used
+    bool unstructured = false;
+    int64_t n_face_dofs = 0;
+    double* d_evx = nullptr;        // [ne][8][3] element vertex coordinates
+    int32_t* d_l2g = nullptr;       // [ne][NRT] signed element-to-dof map
+    int32_t* d_rdof = nullptr;      // [n_q][6] signed RT dof of each sub-volume face slot
+    int32_t* d_rnbr = nullptr;      // [n_q][6] sub-volume across it, -1 if none
+    uint8_t* d_essm = nullptr;      // [n_u] essential RT dofs (identity rows)
+    std::vector<uint8_t> u_boundary_dof;   // [n_u] dofs on boundary faces (host)
 
     // coefficients
     bool have_coeffs = false;

@@ -86,6 +86,17 @@ __device__ __forceinline__ bool rt_is_essential(const Geo& g, int P, uint32_t es
     return (coord == 0 && ((ess >> (2 * c)) & 1u)) || (coord == nal && ((ess >> (2 * c + 1)) & 1u));
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on
+// XCD b mod 8), each with its own L2.  xcd_chunk maps block b to a logical
+// block so that each XCD takes a contiguous chunk of [0, n): work that
+// shares cache lines with its neighbours (elements sharing faces, matrix
+// rows reading nearby columns) meets in one L2 instead of each XCD fetching
+// the line.  A bijection of [0, n).
+__device__ __forceinline__ unsigned xcd_chunk(unsigned b, unsigned n) {
+    const unsigned x = b % 8, k = b / 8;
+    return x * (n / 8) + (x < n % 8 ? x : n % 8) + k;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

@@ -109,14 +109,19 @@ __device__ __forceinline__ void pencil_store(T* dst, int t, const T (&v)[M]) {
 }
 
 // Full LDS -> LDS stage: contract `src` (N0,N1,N2) along DIM to extent M.
-template <typename T, int N0, int N1, int N2, int DIM, int M, int LDB, bool TR, typename BP>
+// A team of W lanes (t in [0, W)) takes the pencils in passes of W.
+template <typename T, int N0, int N1, int N2, int DIM, int M, int LDB, bool TR, int W, typename BP>
 __device__ __forceinline__ void stage_lds(const T* src, T* dst, BP Bm, int t) {
     using G = PencilGeom<N0, N1, N2, DIM>;
-    if (t < G::NP) {
-        T in[G::K], out[M];
-        pencil_load<T, N0, N1, N2, DIM>(src, t, in);
-        pencil_mul<T, G::K, M, LDB, TR>(in, out, Bm);
-        pencil_store<T, N0, N1, N2, DIM, M>(dst, t, out);
+#pragma unroll
+    for (int pass = 0; pass < (G::NP + W - 1) / W; ++pass) {
+        const int tt = t + pass * W;
+        if (tt < G::NP) {
+            T in[G::K], out[M];
+            pencil_load<T, N0, N1, N2, DIM>(src, tt, in);
+            pencil_mul<T, G::K, M, LDB, TR>(in, out, Bm);
+            pencil_store<T, N0, N1, N2, DIM, M>(dst, tt, out);
+        }
     }
 }
 

@@ -13,6 +13,7 @@
 // keep the coarse solve in FP64.
 #include "kernels_common.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(BS) void s0_pre_kernel(Geo g, int64_t n, const T* _
                                                     const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r,
                                                     const int* __restrict__ done) {
     if (done && *done) return;
-    const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+    const int64_t i = xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)BS + threadIdx.x;
     if (i >= n) return;
     const T off = s0_offdiag<P, T>(g, n, i, wlo, [&](int64_t j) { return dinv[j] * b[j]; });
     const T xi = dinv[i] * b[i];
@@ -149,7 +150,8 @@ __global__ __launch_bounds__(BS) void s0_post_kernel(Geo g, int64_t n, const T* 
                                                      const int* __restrict__ done) {
     if (done && *done) return;
     double contrib = 0.0;
-    const int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x;
+    const unsigned lb = xcd_chunk(blockIdx.x, gridDim.x);
+    const int64_t i = lb * (int64_t)BS + threadIdx.x;
     if (i < n) {
         const T off = s0_offdiag<P, T>(g, n, i, wlo, [&](int64_t j) { return x[j]; });
         const T zi = x[i] + dinv[i] * (b[i] - (sdiag[i] * x[i] - off));
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(BS) void s0_post_kernel(Geo g, int64_t n, const T* 
             if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
             __syncthreads();
         }
-        if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+        if (threadIdx.x == 0) part[lb] = s[0];
     }
 }
 
@@ -212,8 +214,9 @@ __device__ __forceinline__ T group_row(const int32_t* __restrict__ rp, const int
     return s;
 }
 
-// block-wide sum of one value per row (lane 0 of each group contributes)
-__device__ __forceinline__ void block_partial(double v, double* __restrict__ part) {
+// block-wide sum of one value per row (lane 0 of each group contributes),
+// stored in part[slot]
+__device__ __forceinline__ void block_partial(double v, double* __restrict__ part, unsigned slot) {
     __shared__ double s[BS];
     s[threadIdx.x] = v;
     __syncthreads();
@@ -221,7 +224,7 @@ __device__ __forceinline__ void block_partial(double v, double* __restrict__ par
         if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+    if (threadIdx.x == 0) part[slot] = s[0];
 }
 
 // x = dinv b;  r = b - A (dinv b)
@@ -231,7 +234,7 @@ __global__ __launch_bounds__(BS) void vc_pre_kernel(int64_t n, const int32_t* __
                                                     const T* __restrict__ dinv, const T* __restrict__ b,
                                                     T* __restrict__ x, T* __restrict__ r, const int* __restrict__ done) {
     if (done && *done) return;
-    const int64_t row = (blockIdx.x * (int64_t)BS + threadIdx.x) / G;
+    const int64_t row = (xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)BS + threadIdx.x) / G;
     const int lane = threadIdx.x % G;
     if (row >= n) return;
     const T s = group_row<G, T>(rp, ci, av, row, lane, [&](int32_t j) { return dinv[j] * b[j]; });
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(BS) void vc_spmv_kernel(int64_t n, const int32_t* _
                                                      const T* __restrict__ x, T* __restrict__ y,
                                                      const int* __restrict__ done) {
     if (done && *done) return;
-    const int64_t row = (blockIdx.x * (int64_t)BS + threadIdx.x) / G;
+    const int64_t row = (xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)BS + threadIdx.x) / G;
     const int lane = threadIdx.x % G;
     if (row >= n) return;
     const T s = group_row<G, T>(rp, ci, mv, row, lane, [&](int32_t j) { return x[j]; });
@@ -268,7 +271,8 @@ __global__ __launch_bounds__(BS) void vc_post_kernel(int64_t n, const int32_t* _
                                                      double* __restrict__ part, int part_kind,
                                                      const int* __restrict__ done) {
     if (done && *done) return;
-    const int64_t row = (blockIdx.x * (int64_t)BS + threadIdx.x) / G;
+    const unsigned lb = xcd_chunk(blockIdx.x, gridDim.x);
+    const int64_t row = (lb * (int64_t)BS + threadIdx.x) / G;
     const int lane = threadIdx.x % G;
     double contrib = 0.0;
     if (row < n) {
@@ -279,7 +283,7 @@ __global__ __launch_bounds__(BS) void vc_post_kernel(int64_t n, const int32_t* _
             contrib = part_kind == 1 ? (double)zi : (double)zi * (double)b[row];
         }
     }
-    if (part) block_partial(contrib, part);
+    if (part) block_partial(contrib, part, lb);
 }
 
 // z -= mean (mean = sum / n from a device scalar), partial sums of z * b
@@ -397,7 +401,7 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
 #define RES(G, ...) hipLaunchKernelGGL((vc_spmv_kernel<G, T, false>), dim3(gblk(lv.R.nrows, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
 #define PRO(G, ...) hipLaunchKernelGGL((vc_spmv_kernel<G, T, true>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
 #define POST(G, ...) hipLaunchKernelGGL((vc_post_kernel<G, T>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
-    if (l == 0) {
+    if (l == 0 && !c->unstructured) {
         const T* sd = pick<T>(c->d_sdiag, c->d_sdiag32);
         const T* wl = pick<T>(c->d_wlo, c->d_wlo32);
         const Geo g = geo_of(c);
@@ -418,7 +422,7 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
     int rc = cycle<T>(c, l + 1, bc, zc, nullptr, 0, done);
     if (rc) return rc;
     HD_GROUP_DISPATCH(gP, PRO, n, lv.P.rp, lv.P.ci, pick<T>(lv.P.v, lv.P.v32), (const T*)zc, x, done)
-    if (l == 0) {
+    if (l == 0 && !c->unstructured) {
         const T* sd = pick<T>(c->d_sdiag, c->d_sdiag32);
         const T* wl = pick<T>(c->d_wlo, c->d_wlo32);
         const Geo g = geo_of(c);
@@ -442,7 +446,16 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
                                nin, q, nout, (const double*)c->d_s0part, part, done);
         }
     } else {
-        HD_GROUP_DISPATCH(gA, POST, n, lv.A.rp, lv.A.ci, av, dinv, b, (const T*)x, z, part, part_kind, done)
+        // a CSR level (level 0 of an unstructured mesh too): with more blocks
+        // than the solver's partial count, the block partials are folded
+        const bool fold = part && (int64_t)gblk(n, gA) > (int64_t)red_grid(n);
+        double* bp = fold ? c->d_s0part : part;
+        HD_GROUP_DISPATCH(gA, POST, n, lv.A.rp, lv.A.ci, av, dinv, b, (const T*)x, z, bp, part_kind, done)
+        if (fold) {
+            const int64_t nin = gblk(n, gA), nout = red_grid(n), q = (nin + nout - 1) / nout;
+            hipLaunchKernelGGL(fold_partials_kernel, dim3((unsigned)((nout + BS - 1) / BS)), dim3(BS), 0, c->stream,
+                               nin, q, nout, (const double*)c->d_s0part, part, done);
+        }
     }
 #undef PRE
 #undef RES
@@ -609,7 +622,12 @@ int finish_levels(hd_ctx* c) {
                            lv.dinv32);
         HD_HIP(c, hipGetLastError());
     }
-    {
+    if (c->unstructured) {
+        // level 0 is a CSR level: only the post-smoother's partials
+        const int64_t n = c->n_q;
+        c->d_s0part = dalloc<double>(std::max<int64_t>(nblk(n), gblk(n, group_of(c->lev[0].A))));
+        if (!c->d_s0part) return set_err(c, HD_ERR_OOM, "level-0 partials");
+    } else {
         // level-0 face weights by sub-volume, and the post-smoother's partials
         const int64_t n = c->n_q;
         c->d_wlo = dalloc<double>(3 * n);

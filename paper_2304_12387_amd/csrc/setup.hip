@@ -15,9 +15,11 @@ namespace {
 // points followed by the 8 vertices.  Writes w J^T J / det J (6 entries) and
 // w / det J per quadrature point, flags det J <= 0 (or non-finite).
 // ---------------------------------------------------------------------------
+// With evx (unstructured meshes) the element's vertices are read from
+// evx[e][v][r], v = dx + 2 dy + 4 dz, instead of the structured grid.
 __global__ void geometry_kernel(int nx, int ny, int nz, int P, const double* __restrict__ vert,
-                                const Tables<double>* __restrict__ tab, double* __restrict__ pa,
-                                float* __restrict__ pa32, int* __restrict__ bad) {
+                                const double* __restrict__ evx, const Tables<double>* __restrict__ tab,
+                                double* __restrict__ pa, float* __restrict__ pa32, int* __restrict__ bad) {
     const int Q = P + 1, Q3 = Q * Q * Q, NP = Q3 + 8;
     const int64_t ne = (int64_t)nx * ny * nz;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -29,6 +31,10 @@ __global__ void geometry_kernel(int nx, int ny, int nz, int P, const double* __r
     for (int dz = 0; dz < 2; ++dz)
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
+                if (evx) {
+                    for (int r = 0; r < 3; ++r) X[dz][dy][dx][r] = evx[24 * e + 3 * (dx + 2 * dy + 4 * dz) + r];
+                    continue;
+                }
                 const int64_t v = (ex + dx) + (int64_t)(nx + 1) * ((ey + dy) + (int64_t)(ny + 1) * (ez + dz));
                 for (int r = 0; r < 3; ++r) X[dz][dy][dx][r] = vert[3 * v + r];
             }
@@ -96,11 +102,14 @@ __global__ void geometry_kernel(int nx, int ny, int nz, int P, const double* __r
 // With theta (per element (x-, x+, y-, y+, z-, z+) log-scalings) each local
 // diagonal entry is multiplied by exp((1 - xi_i) theta_{2c} + xi_i theta_{2c+1})
 // before it is added (the learned correction of the (1,1) block).
+// On unstructured meshes (l2g given) the entries are added through the
+// element-to-dof map instead.
 template <int P>
 __global__ __launch_bounds__(64) void diag_kernel(Geo g, const double* __restrict__ pa,
                                                   const Tables<double>* __restrict__ tab,
                                                   const double* __restrict__ cm, const double* __restrict__ theta,
-                                                  double* __restrict__ mdiag, double* __restrict__ wdiag) {
+                                                  const int32_t* __restrict__ l2g, double* __restrict__ mdiag,
+                                                  double* __restrict__ wdiag) {
     using D = Dim<P>;
     constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC;
     __shared__ double sL2[Q * (P + 1)], sH2[Q * P], in[Q3], b1[Q3], b2[Q3], loc[NC];
@@ -139,6 +148,11 @@ __global__ __launch_bounds__(64) void diag_kernel(Geo g, const double* __restric
         for (int l = tid; l < NC; l += 64) {
             int i, j, k, onf, bs;
             local_ijk<P>(comp, l, i, j, k);
+            if (l2g) {
+                const int32_t m = l2g[e * D::NRT + comp * NC + l];
+                atomicAdd(&mdiag[m < 0 ? ~m : m], c * loc[l]);
+                continue;
+            }
             const int64_t gi = rt_global<P>(g, comp, ex, ey, ez, i, j, k, onf, bs);
             double v = c * loc[l];
             if (theta) {
@@ -192,6 +206,25 @@ __global__ void mdiag_finish_kernel(Geo g, int P, uint32_t ess, double tau, doub
         mdinv[t] = 1.0 / (tau * m);
         mdinv32[t] = (float)(1.0 / (tau * m));
         wface[t] = boundary ? 0.0 : 1.0 / m;
+    }
+}
+
+// the same on an unstructured mesh: essential dofs from the mask; the face
+// weights are not used there (level 0 of the V-cycle is a CSR level)
+__global__ void mdiag_finish_uns_kernel(const uint8_t* __restrict__ essm, double tau, double* __restrict__ mdiag,
+                                        double* __restrict__ mdinv, float* __restrict__ mdinv32,
+                                        double* __restrict__ wface, int64_t n_u) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n_u) return;
+    wface[t] = 0.0;
+    if (essm[t]) {
+        mdiag[t] = 1.0;
+        mdinv[t] = 1.0;
+        mdinv32[t] = 1.0f;
+    } else {
+        const double m = mdiag[t];
+        mdinv[t] = 1.0 / (tau * m);
+        mdinv32[t] = (float)(1.0 / (tau * m));
     }
 }
 
@@ -263,6 +296,82 @@ __device__ int schur_row(Geo g, int P, uint32_t ess, int64_t i, const double* __
         ent[b + 1] = x;
     }
     return n;
+}
+
+// Row i of S~ on an unstructured mesh, from its six (signed RT dof,
+// neighbour) slots: S~_ij = sum over the free dofs k shared by i and j of
+// D_ik D_jk / M~_kk (the product is -1 for the two sub-volumes of a face),
+// C~_ii on the diagonal.  Columns sorted; repeated columns summed.
+__device__ int schur_row_uns(int64_t i, const int32_t* __restrict__ rdof, const int32_t* __restrict__ rnbr,
+                             const uint8_t* __restrict__ essm, int NL, const double* __restrict__ mdiag,
+                             const double* __restrict__ wdiag, const double* __restrict__ kap,
+                             const double* __restrict__ ctil, RowEnt* ent) {
+    double diag = ctil ? ctil[i] : kap[i / NL] / wdiag[i];
+    int n = 0;
+    for (int sl = 0; sl < 6; ++sl) {
+        const int32_t v = rdof[6 * i + sl];
+        const int32_t k = v < 0 ? ~v : v;
+        if (essm[k]) continue;
+        const double wk = 1.0 / mdiag[k];
+        diag += wk;
+        const int32_t j = rnbr[6 * i + sl];
+        if (j < 0) continue;
+        // sign of D_jk: the slot of j that holds k
+        double sj = 0.0;
+        for (int s2 = 0; s2 < 6; ++s2) {
+            const int32_t w = rdof[6 * (int64_t)j + s2];
+            if ((w < 0 ? ~w : w) == k) sj = w < 0 ? -1.0 : 1.0;
+        }
+        const double si = v < 0 ? -1.0 : 1.0;
+        ent[n].col = j;
+        ent[n].val = si * sj * wk;
+        ++n;
+    }
+    ent[n].col = (int32_t)i;
+    ent[n].val = diag;
+    ++n;
+    for (int a = 1; a < n; ++a) {
+        RowEnt x = ent[a];
+        int b = a - 1;
+        while (b >= 0 && ent[b].col > x.col) {
+            ent[b + 1] = ent[b];
+            --b;
+        }
+        ent[b + 1] = x;
+    }
+    int m = 0;
+    for (int a = 0; a < n; ++a) {
+        if (m > 0 && ent[m - 1].col == ent[a].col) ent[m - 1].val += ent[a].val;
+        else ent[m++] = ent[a];
+    }
+    return m;
+}
+
+__global__ void schur_uns_kernel(int64_t nq, int NL, const int32_t* __restrict__ rdof,
+                                 const int32_t* __restrict__ rnbr, const uint8_t* __restrict__ essm,
+                                 const double* __restrict__ mdiag, const double* __restrict__ wdiag,
+                                 const double* __restrict__ kap, const double* __restrict__ ctil,
+                                 int32_t* __restrict__ cnt, const int32_t* __restrict__ rp, int32_t* __restrict__ ci,
+                                 double* __restrict__ v, float* __restrict__ v32, double* __restrict__ sdiag,
+                                 float* __restrict__ sdiag32) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    RowEnt ent[7];
+    const int n = schur_row_uns(i, rdof, rnbr, essm, NL, mdiag, wdiag, kap, ctil, ent);
+    if (cnt) {
+        cnt[i] = n;
+        return;
+    }
+    const int32_t o = rp[i];
+    for (int k = 0; k < n; ++k) {
+        ci[o + k] = ent[k].col;
+        v[o + k] = ent[k].val;
+        v32[o + k] = (float)ent[k].val;
+        if (ent[k].col == (int32_t)i) {
+            sdiag[i] = ent[k].val;
+            sdiag32[i] = (float)ent[k].val;
+        }
+    }
 }
 
 __global__ void schur_count_kernel(Geo g, int P, uint32_t ess, int64_t nq, const double* __restrict__ mdiag,
@@ -385,7 +494,7 @@ __global__ void reduce_kernel(const double* __restrict__ part, int64_t n, double
 template <int P>
 void launch_diag_p(hd_ctx* c, Geo g, const double* theta) {
     hipLaunchKernelGGL((diag_kernel<P>), dim3((unsigned)c->ne), dim3(64), 0, c->stream, g, c->d_pa, c->d_tab64,
-                       c->d_cm, theta, c->d_mdiag, c->d_wdiag);
+                       c->d_cm, theta, c->unstructured ? c->d_l2g : nullptr, c->d_mdiag, c->d_wdiag);
 }
 
 // ---------------------------------------------------------------------------
@@ -481,7 +590,8 @@ int launch_geometry(hd_ctx* c, const double* d_vert, int* d_bad) {
     const int64_t nt = c->ne * (Q * Q * Q + 8);
     const int bs = 256;
     hipLaunchKernelGGL(geometry_kernel, dim3((unsigned)((nt + bs - 1) / bs)), dim3(bs), 0, c->stream, c->nx, c->ny,
-                       c->nz, c->p, d_vert, c->d_tab64, c->d_pa, c->d_pa32, d_bad);
+                       c->nz, c->p, d_vert, c->unstructured ? c->d_evx : nullptr, c->d_tab64, c->d_pa, c->d_pa32,
+                       d_bad);
     HD_HIP(c, hipGetLastError());
     return HD_OK;
 }
@@ -501,8 +611,12 @@ int launch_diagonals(hd_ctx* c, const double* theta) {
         case 6: launch_diag_p<6>(c, g, theta); break;
         default: return set_err(c, HD_ERR_ARG, "p out of range");
     }
-    hipLaunchKernelGGL(mdiag_finish_kernel, dim3((unsigned)((c->n_u + bs - 1) / bs)), dim3(bs), 0, c->stream, g,
-                       c->p, c->ess, c->tau, c->d_mdiag, c->d_mdinv, c->d_mdinv32, c->d_wface, c->n_u);
+    if (c->unstructured)
+        hipLaunchKernelGGL(mdiag_finish_uns_kernel, dim3((unsigned)((c->n_u + bs - 1) / bs)), dim3(bs), 0, c->stream,
+                           c->d_essm, c->tau, c->d_mdiag, c->d_mdinv, c->d_mdinv32, c->d_wface, c->n_u);
+    else
+        hipLaunchKernelGGL(mdiag_finish_kernel, dim3((unsigned)((c->n_u + bs - 1) / bs)), dim3(bs), 0, c->stream, g,
+                           c->p, c->ess, c->tau, c->d_mdiag, c->d_mdinv, c->d_mdinv32, c->d_wface, c->n_u);
     HD_HIP(c, hipGetLastError());
     return HD_OK;
 }
@@ -581,9 +695,20 @@ int launch_schur(hd_ctx* c) {
     }
     int32_t* cnt = dalloc<int32_t>(n);
     int32_t* rp = dalloc<int32_t>(n + 1);
-    if (!cnt || !rp) return set_err(c, HD_ERR_OOM, "schur row counts");
-    hipLaunchKernelGGL(schur_count_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, c->stream, g, c->p,
-                       c->ess, n, c->d_mdiag, c->d_wdiag, c->d_kap, ctil, cnt);
+    if (!cnt || !rp) {
+        dfree(cnt);
+        dfree(rp);
+        return set_err(c, HD_ERR_OOM, "schur row counts");
+    }
+    const int NL = c->p * c->p * c->p;
+    if (c->unstructured)
+        hipLaunchKernelGGL(schur_uns_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, c->stream, n, NL,
+                           c->d_rdof, c->d_rnbr, c->d_essm, c->d_mdiag, c->d_wdiag, c->d_kap, ctil, cnt,
+                           (const int32_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, (float*)nullptr,
+                           (double*)nullptr, (float*)nullptr);
+    else
+        hipLaunchKernelGGL(schur_count_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, c->stream, g, c->p,
+                           c->ess, n, c->d_mdiag, c->d_wdiag, c->d_kap, ctil, cnt);
     int64_t nnz = 0;
     int rc = scan_counts(c, cnt, n, rp, &nnz);
     dfree(cnt);
@@ -601,9 +726,14 @@ int launch_schur(hd_ctx* c) {
     S.v = dalloc<double>(nnz);
     S.v32 = dalloc<float>(nnz);
     if (!S.ci || !S.v || !S.v32) return set_err(c, HD_ERR_OOM, "S~ storage");
-    hipLaunchKernelGGL(schur_fill_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, c->stream, g, c->p,
-                       c->ess, n, c->d_mdiag, c->d_wdiag, c->d_kap, ctil, S.rp, S.ci, S.v, S.v32, c->d_sdiag,
-                       c->d_sdiag32);
+    if (c->unstructured)
+        hipLaunchKernelGGL(schur_uns_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, c->stream, n, NL,
+                           c->d_rdof, c->d_rnbr, c->d_essm, c->d_mdiag, c->d_wdiag, c->d_kap, ctil, (int32_t*)nullptr,
+                           (const int32_t*)S.rp, S.ci, S.v, S.v32, c->d_sdiag, c->d_sdiag32);
+    else
+        hipLaunchKernelGGL(schur_fill_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, c->stream, g, c->p,
+                           c->ess, n, c->d_mdiag, c->d_wdiag, c->d_kap, ctil, S.rp, S.ci, S.v, S.v32, c->d_sdiag,
+                           c->d_sdiag32);
     HD_HIP(c, hipGetLastError());
     return HD_OK;
 }

@@ -35,7 +35,8 @@ EXPORTED = [
     'hd_set_diag_scalings', 'hd_setup_batch', 'hd_batch_sizes', 'hd_batch_apply', 'hd_batch_tune',
     'hd_batch_set_launch', 'hd_batch_build_precond', 'hd_batch_minres_solve', 'hd_constant_flux',
     'hd_set_local_solver', 'hd_set_gamma_field', 'hd_gmres_solve', 'hd_apply_tri_precond',
-    'hd_apply_tri_precond_noalloc',
+    'hd_apply_tri_precond_noalloc', 'hd_setup_mesh_unstructured', 'hd_set_essential_dofs', 'hd_get_dof_map',
+    'hd_host_unstructured_map',
 ]
 
 
@@ -94,6 +95,9 @@ def load():
         'hd_last_error': (ctypes.c_char_p, [P]),
         'hd_setup_mesh': (I, [P, I, I, I, I, P]),
         'hd_setup_coeffs': (I, [P, I, P, P, ctypes.c_uint32]),
+        'hd_setup_mesh_unstructured': (I, [P, I64, P, I64, P, I]),
+        'hd_set_essential_dofs': (I, [P, P]),
+        'hd_get_dof_map': (I, [P, P]),
         'hd_sizes': (I, [P, pI64, pI64]),
         'hd_apply_block_op': (I, [P, I, I, P, P]),
         'hd_apply_mass_inverse': (I, [P, I, I, P, P]),
@@ -119,6 +123,7 @@ def load():
         'hd_host_amg_prolongator': (I, [P, I, pI64, pI64, pI64, P, P, P]),
         'hd_host_amg_free': (I, [P]),
         'hd_host_tables': (I, [I, P, P, P]),
+        'hd_host_unstructured_map': (I, [I64, I64, P, I, pI64, P]),
         'hd_learned_targets': (I, [P, I, I64, P, I, P, P, P]),
         'hd_learned_features': (I, [P, I64, P, P, P, P, I, P]),
         'hd_mlp_param_count': (I, []),
@@ -205,6 +210,26 @@ class Context:
         rc = self._check(self.lib.hd_setup_mesh(self.h, nx, ny, nz, p, _ptr(v)))
         self.ne = nx * ny * nz
         return rc
+
+    def setup_mesh_unstructured(self, vertices, elements, p):
+        v = np.ascontiguousarray(vertices, dtype=np.float64).reshape(-1, 3)
+        el = np.ascontiguousarray(elements, dtype=np.int64).reshape(-1, 8)
+        rc = self._check(self.lib.hd_setup_mesh_unstructured(self.h, v.shape[0], _ptr(v), el.shape[0], _ptr(el), p))
+        self.ne = el.shape[0]
+        self.p_uns = p
+        return rc
+
+    def set_essential_dofs(self, mask):
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        if m.size != self.sizes()[0]:
+            raise ValueError('mask: n_u entries required')
+        return self._check(self.lib.hd_set_essential_dofs(self.h, _ptr(m)))
+
+    def get_dof_map(self):
+        p = self.p_uns
+        out = np.empty((self.ne, 3 * p * p * (p + 1)), dtype=np.int32)
+        self._check(self.lib.hd_get_dof_map(self.h, _ptr(out)))
+        return out
 
     def setup_coeffs(self, problem, c_mass, c_22=None, ess_sides=0):
         cm = np.ascontiguousarray(c_mass, dtype=np.float64)
@@ -524,6 +549,19 @@ def host_tables(p):
     if rc:
         raise HdError(rc, 'hd_host_tables')
     return gll, x, w
+
+
+def host_unstructured_map(nv, elements, p):
+    """The library's RT numbering of an unstructured mesh, computed on the
+    host: (n_u, element-to-dof map [ne][3 p^2 (p+1)], ~g for sign -1)."""
+    lib = load()
+    el = np.ascontiguousarray(elements, dtype=np.int64).reshape(-1, 8)
+    nu = ctypes.c_int64()
+    out = np.empty((el.shape[0], 3 * p * p * (p + 1)), dtype=np.int32)
+    rc = lib.hd_host_unstructured_map(nv, el.shape[0], _ptr(el), p, ctypes.byref(nu), _ptr(out))
+    if rc:
+        raise HdError(rc, 'hd_host_unstructured_map')
+    return nu.value, out
 
 
 def host_amg(rowptr, col, val, singular=False, params=None):

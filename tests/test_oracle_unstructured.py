@@ -89,8 +89,8 @@ def test_scrambled_structured_mesh_is_the_same_problem(p, problem):
     c_22 = inputs.loguniform(ne, 1e-2, 1e2, rng) if problem == un.GRADDIV else rng.uniform(0.5, 2.0, ne)
     sm = assemble.Mesh(nx, ny, nz, p, V)
     sprob = assemble.Problem(sm, problem, c_mass, c_22, 0)
-    Vv, el = un.from_structured(nx, ny, nz, V)
-    V2, el2, eperm = un.scramble(Vv, el, seed + 1)
+    Vv, el = inputs.from_structured(nx, ny, nz, V)
+    V2, el2, eperm = inputs.scramble(Vv, el, seed + 1)
     m = un.HexMesh(V2, el2, p)
     assert (m.sgn < 0).any(), "the rotations must flip some orientations"
     uprob = un.UnstructuredProblem(m, problem, c_mass[eperm], c_22[eperm])
@@ -102,7 +102,7 @@ def test_scrambled_structured_mesh_is_the_same_problem(p, problem):
 
 
 def _o_grid_problem(p, problem=un.GRADDIV, seed=3):
-    V, el = un.o_grid(2, 1, 2, seed=seed)
+    V, el = inputs.o_grid(2, 1, 2, seed=seed)
     m = un.HexMesh(V, el, p)
     rng = np.random.default_rng(seed)
     c_mass = inputs.loguniform(m.ne, 1e-1, 1e1, rng)
@@ -111,7 +111,7 @@ def _o_grid_problem(p, problem=un.GRADDIV, seed=3):
 
 
 def test_o_grid_is_unstructured():
-    V, el = un.o_grid(2, 1, 2)
+    V, el = inputs.o_grid(2, 1, 2)
     m = un.HexMesh(V, el, 1)
     # vertices of the cross section with 3 (not 4) edges at the central block's corners
     counts = np.bincount(el[:, :4].ravel(), minlength=V.shape[0])
@@ -126,8 +126,8 @@ def test_divergence_is_signed_incidence(p):
             m, prob, _, _ = _o_grid_problem(p)
         else:
             V = inputs.jittered_vertices(2, 2, 2, 0.1, 5)
-            Vv, el = un.from_structured(2, 2, 2, V)
-            V2, el2, _ = un.scramble(Vv, el, 9)
+            Vv, el = inputs.from_structured(2, 2, 2, V)
+            V2, el2, _ = inputs.scramble(Vv, el, 9)
             m = un.HexMesh(V2, el2, p)
             prob = un.UnstructuredProblem(m, un.GRADDIV, np.ones(m.ne), np.ones(m.ne))
         Dq = np.linalg.solve(prob.W.toarray(), prob.B.toarray())
