@@ -141,6 +141,109 @@ def element_targets(V, p):
 
 
 # ---------------------------------------------------------------------------
+# second target: the element's saddle-point pencil, which sees alpha and beta
+# ---------------------------------------------------------------------------
+# For one element in isolation (all of its RT dofs free), the transformed
+# grad-div block (Section 3, eq. transformed-saddle-point)
+#     A_e = [[beta M1, D^T], [D, -(1/alpha) W^{-1}]]
+# (M1 the unit-coefficient RT mass matrix, D the +-1 incidence, W the L2 mass
+# matrix) and the block-diagonal preconditioner of Section 2.3 with the
+# scaled diagonal
+#     B_e(theta) = diag(Md, C~ + D Md^{-1} D^T),  Md = s_dof beta diag(M1),
+#     C~ = (1/alpha) diag(W)^{-1}.
+# The target minimises f2 = log max|lambda| - log min|lambda| over the
+# eigenvalues of A_e v = lambda B_e v, over all of theta (a common factor of
+# the six scalings is not neutral here: it moves weight between the (1,1)
+# block and the Schur block).  For B-normalised v = (v_u, v_q),
+#     d lambda / d theta_j = -lambda v^T (dB / d theta_j) v,
+#     v^T (dB/dtheta_j) v = sum a_dj Md_d v_u,d^2 - sum a_dj (D^T v_q)_d^2 / Md_d,
+# with a_dj the weight of theta_j in log s_dof.
+
+def saddle_blocks(M1, W, D, alpha, beta):
+    """A_e and the pieces of B_e that do not depend on theta."""
+    Winv = np.linalg.inv(W)
+    A = np.block([[beta * M1, D.T], [D, -(1.0 / alpha) * Winv]])
+    m = beta * np.diag(M1)
+    ct = (1.0 / alpha) / np.diag(W)
+    return A, m, ct
+
+
+def saddle_pencil(A, m, ct, D, Aw, theta, exact=None):
+    """Eigenvalues and B-normalised eigenvectors of A v = lambda B(theta) v.
+    exact = (M, S): use the exact blocks M and S = C + D M^{-1} D^T instead
+    (the setting of Prop. 1)."""
+    import scipy.linalg as sla
+    nu = D.shape[1]
+    if exact is not None:
+        Bm = sla.block_diag(exact[0], exact[1])
+        md = None
+    else:
+        md = m * np.exp(Aw @ theta)
+        S = np.diag(ct) + (D / md[None, :]) @ D.T
+        Bm = sla.block_diag(np.diag(md), S)
+    lam, V = sla.eigh(A, Bm)
+    return lam, V, md, nu
+
+
+def saddle_spread_gradient(A, m, ct, D, Aw, theta):
+    """f2(theta) and its gradient."""
+    lam, V, md, nu = saddle_pencil(A, m, ct, D, Aw, theta)
+    a = np.abs(lam)
+    i_hi, i_lo = int(np.argmax(a)), int(np.argmin(a))
+    f = math.log(a[i_hi]) - math.log(a[i_lo])
+
+    def vdb(v):
+        vu, vq = v[:nu], v[nu:]
+        dq = D.T @ vq
+        return Aw.T @ (md * vu ** 2) - Aw.T @ (dq ** 2 / md)
+
+    # d log|lambda| / d theta = -v^T dB v
+    g = -vdb(V[:, i_hi]) + vdb(V[:, i_lo])
+    return f, g
+
+
+def saddle_target(A, m, ct, D, p, max_steps=MAX_STEPS):
+    """Gradient-descent minimiser of f2 from theta = 0 (Armijo rule as in
+    element_target, without the projection), with f2 at 0 and at the end."""
+    Aw = dof_weights(p)
+    theta = np.zeros(6)
+    f, g = saddle_spread_gradient(A, m, ct, D, Aw, theta)
+    f0 = f
+    eta = 1.0
+    for _ in range(max_steps):
+        gg = float(g @ g)
+        if gg <= 1e-24:
+            break
+        accepted = False
+        for _ in range(20):
+            trial = theta - eta * g
+            ft, gt = saddle_spread_gradient(A, m, ct, D, Aw, trial)
+            if ft <= f - ARMIJO * eta * gg:
+                accepted = True
+                break
+            eta *= 0.5
+        if not accepted:
+            break
+        theta, f, g = trial, ft, gt
+        eta = min(2.0 * eta, 4.0)
+    return theta, f0, f
+
+
+def saddle_targets(V, p, alpha, beta, max_steps=MAX_STEPS):
+    """theta* [E, 6] and f2 at 0 and at theta* [E, 2] for elements
+    V [E, 2, 2, 2, 3] with coefficients alpha, beta [E]."""
+    from .element import reference_divergence
+    mats = element_matrices(p, V)
+    D = reference_divergence(p)
+    th = np.zeros((len(V), 6))
+    fs = np.zeros((len(V), 2))
+    for e in range(len(V)):
+        A, m, ct = saddle_blocks(mats['M'][e], mats['W'][e], D, alpha[e], beta[e])
+        th[e], fs[e, 0], fs[e, 1] = saddle_target(A, m, ct, D, p, max_steps)
+    return th, fs
+
+
+# ---------------------------------------------------------------------------
 # features
 # ---------------------------------------------------------------------------
 _EDGES = [((0, 0, 0), (0, 0, 1)), ((0, 1, 0), (0, 1, 1)), ((1, 0, 0), (1, 0, 1)), ((1, 1, 0), (1, 1, 1)),
