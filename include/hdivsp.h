@@ -234,6 +234,19 @@ int hd_sizes(const hd_ctx* ctx, int64_t* n_u, int64_t* n_q);
  * stored explicit element inverses (hd_set_local_solver). */
 int hd_apply_block_op(hd_ctx* ctx, int prec, int nrhs, const void* x, void* y);
 
+/* y = A x for nrhs right-hand sides stored interleaved: entry (dof d, right-
+ * hand side r) at d * nrhs + r, for x and y alike (device pointers of
+ * nrhs * (n_u + n_q) values of the given precision, x != y, caller-owned;
+ * asynchronous on the context's stream).  The same operator as
+ * hd_apply_block_op (eq. transformed-saddle-point, Section 3; the (2,2) block
+ * always by the local CG of Section 2.5), computed with the right-hand sides
+ * side by side: the element's geometric factors are formed once for all of
+ * them and every LDS and global access reads the right-hand sides of a dof
+ * together.  Structured meshes with piecewise-constant coefficients only
+ * (HD_ERR_STATE on an unstructured mesh or with a gamma field); HD_ERR_ARG for
+ * nrhs < 1, a bad precision or bad pointers. */
+int hd_apply_block_op_interleaved(hd_ctx* ctx, int prec, int nrhs, const void* x, void* y);
+
 /* How the block apply, and everything built on it, applies W_e^{-1} in the
  * (2,2) block (Section 3.1, GPU acceleration of the DG mass inverse: explicit
  * inverses applied by a batched matrix-vector product for small degrees,

@@ -32,6 +32,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 namespace hd {
@@ -928,6 +929,383 @@ __global__ void uns_dot_kernel(int64_t N, const T* __restrict__ xall, const T* _
     if (threadIdx.x == 0) ra.partial[r * ra.part_stride + blockIdx.x] = sh[0];
 }
 
+// ---- several right-hand sides interleaved ([dof][nrhs]) --------------------
+// y[d nrhs + r] = (A x_r)[d]: the RT_p and L2 dofs with their right-hand sides
+// next to each other (the layout the element kernels read with whole cache
+// lines).  One element per workgroup of 256 threads; thread t works on
+// right-hand side r0 + t % NR of pencil slot t / NR (PS = 256 / NR slots), so
+// the NR lanes of a slot read and write consecutive LDS words (every LDS
+// tensor keeps the NR right-hand sides of a value together).  The geometric
+// factors of the element are computed once, into LDS, and shared by the NR
+// right-hand sides; each right-hand side runs its own local CG.
+constexpr int IL_T = 256;
+
+template <int P, typename T, int NR>
+struct IlLDS {
+    T su[Dim<P>::NRT * NR];   // gathered RT coefficients (scaled, essential dofs zeroed)
+    T sq[Dim<P>::NL * NR];    // gathered L2 coefficients
+    T A1[Dim<P>::Q3 * NR];    // stage buffers
+    T A2[Dim<P>::Q3 * NR];
+    T G[7][Dim<P>::Q3];       // c_mass w J^T J / det J (6) and w / det J at the quadrature points
+    T dW[Dim<P>::NL];         // reciprocal Jacobi diagonal of the local CG
+    T vx[24];
+    double red[IL_T];         // per-slot partial sums of the CG's inner products
+};
+
+// stage over the NR right-hand sides: pencils of (N0, N1, N2) along DIM
+// contracted to extent M, slot ps taking pencils ps, ps + PS, ...
+template <typename T, int NR, int N0, int N1, int N2, int DIM, int M, int LDB, bool TR, typename BP>
+__device__ __forceinline__ void stage_il(const T* src, T* dst, BP Bm, int ps, int r) {
+    constexpr int PS = IL_T / NR;
+    using G = PencilGeom<N0, N1, N2, DIM>;
+    constexpr int O0 = DIM == 0 ? M : N0, O1 = DIM == 1 ? M : N1, O2 = DIM == 2 ? M : N2;
+    using GO = PencilGeom<O0, O1, O2, DIM>;
+#pragma unroll
+    for (int pass = 0; pass < (G::NP + PS - 1) / PS; ++pass) {
+        const int pp = ps + pass * PS;
+        if (pp < G::NP) {
+            T in[G::K], out[M];
+            const int b = G::base(pp);
+#pragma unroll
+            for (int k = 0; k < G::K; ++k) in[k] = src[(b + k * G::STRIDE) * NR + r];
+            pencil_mul<T, G::K, M, LDB, TR>(in, out, Bm);
+            const int bo = GO::base(pp);
+#pragma unroll
+            for (int o = 0; o < M; ++o) dst[(bo + o * GO::STRIDE) * NR + r] = out[o];
+        }
+    }
+}
+
+// sum over the pencil slots ps < NS of v, per right-hand side (all lanes of a
+// right-hand side get the same sum, in a fixed order)
+template <int NR, int NS>
+__device__ __forceinline__ double il_sum(double* red, double v, int ps, int r) {
+    __syncthreads();
+    red[ps * NR + r] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) s += red[k * NR + r];
+    return s;
+}
+
+template <int P, typename T, int NR, bool HAS_C>
+__global__ __launch_bounds__(IL_T) void block_apply_il_kernel(
+    Geo g, const double* __restrict__ vert, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap,
+    uint32_t ess, int64_t n_u, const T* __restrict__ x, T* __restrict__ y, int ldr, CGParams<T> cgp, int with_c,
+    int colour, unsigned nb) {
+    // ldr right-hand sides; lanes past the last one (a partial chunk) read
+    // the last one and store nothing
+    using D = Dim<P>;
+    constexpr int Q = D::Q, Q3 = D::Q3, NL = D::NL, NC = D::NC, PS = IL_T / NR;
+    static_assert(P * P <= PS && Q * Q <= PS, "pencil slots");
+    __shared__ IlLDS<P, T, NR> L;
+    const int t = threadIdx.x, ps = t / NR, r = t % NR;
+    const bool live = (int)blockIdx.y * NR + r < ldr;
+    const int rx = live ? (int)blockIdx.y * NR + r : ldr - 1;   // this lane's right-hand side
+    // element of this colour: half-row by half-row, XCD-contiguous chunks
+    const unsigned idx = xcd_chunk(blockIdx.x, nb);
+    const int hx = (g.nx + 1) / 2;
+    const int64_t row = idx / hx;
+    const int m = (int)(idx % hx);
+    const int ey = (int)(row % g.ny), ez = (int)(row / g.ny);
+    const int ex = 2 * m + ((colour + ey + ez) & 1);
+    if (ex >= g.nx) return;   // uniform over the workgroup
+    const int64_t ee = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);
+    const T cM = cm[ee];
+    const T kE = kap[ee];
+    // gather: vertices, u (essential dofs read as zero) line by line, q~
+    if (t < 24) {
+        const int v = t / 3, c = t % 3;
+        const int dx = v & 1, dy = (v >> 1) & 1, dz = v >> 2;
+        L.vx[t] = (T)vert[3 * ((ex + dx) + (int64_t)(g.nx + 1) * ((ey + dy) + (int64_t)(g.ny + 1) * (ez + dz))) + c];
+    }
+    {
+        auto body = [&](auto cc) {
+            constexpr int C = decltype(cc)::value;
+            constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
+            for (int tt = ps; tt < N1 * N2; tt += PS) {
+                const int j = tt % N1, k = tt / N1;
+                const RtLine rl = rt_line<P, C>(g, ex, ey, ez, j, k);
+#pragma unroll
+                for (int i = 0; i < N0; ++i) {
+                    int onf, bs;
+                    rt_line_dof<P, C>(g, ex, rl, i, onf, bs);
+                    const bool is_ess = bs >= 0 && ((ess >> (2 * C + bs)) & 1u);
+                    const T v = x[(rl.base + i) * ldr + rx];
+                    L.su[(C * NC + N0 * tt + i) * NR + r] = is_ess ? T(0) : v;
+                }
+            }
+        };
+        body(std::integral_constant<int, 0>{});
+        body(std::integral_constant<int, 1>{});
+        body(std::integral_constant<int, 2>{});
+    }
+    for (int l = ps; l < NL; l += PS) L.sq[l * NR + r] = x[(n_u + ee * NL + l) * ldr + rx];
+    __syncthreads();
+    // geometric factors at the quadrature points, once for all right-hand sides
+    for (int pt = t; pt < Q3; pt += IL_T) {
+        const int a = pt % Q, b = (pt / Q) % Q, c = pt / (Q * Q);
+        const T xi[3] = {tb->xq[a], tb->xq[b], tb->xq[c]};
+        T J[3][3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const int dx = v & 1, dy = (v >> 1) & 1, dz = v >> 2;
+                const T Nx = dx ? xi[0] : T(1) - xi[0], Ny = dy ? xi[1] : T(1) - xi[1], Nz = dz ? xi[2] : T(1) - xi[2];
+                const T gx = dx ? T(1) : T(-1), gy = dy ? T(1) : T(-1), gz = dz ? T(1) : T(-1);
+                const T X = L.vx[3 * v + q];
+                s0 += gx * Ny * Nz * X;
+                s1 += Nx * gy * Nz * X;
+                s2 += Nx * Ny * gz * X;
+            }
+            J[q][0] = s0;
+            J[q][1] = s1;
+            J[q][2] = s2;
+        }
+        const T det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        const T sw = tb->wq[a] * tb->wq[b] * tb->wq[c] / det;
+        const int rr[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int mm = 0; mm < 6; ++mm) {
+            T sj = 0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) sj += J[q][rr[mm]] * J[q][cc[mm]];
+            L.G[mm][pt] = cM * sw * sj;
+        }
+        L.G[6][pt] = sw;
+    }
+    // M u: each component to the quadrature points (z-pencils in registers:
+    // slot ps < Q^2 holds the column (a, b) = (ps % Q, ps / Q))
+    T U[3][Q];
+    {
+        auto body = [&](auto cc) {
+            constexpr int C = decltype(cc)::value;
+            constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
+            const auto B0 = C == 0 ? &tfence<P, T>(tb)->L[0][0] : &tfence<P, T>(tb)->H[0][0];
+            stage_il<T, NR, N0, N1, N2, 0, Q, N0, false>(L.su + C * NC * NR, L.A1, B0, ps, r);
+            __syncthreads();
+            const auto B1 = C == 1 ? &tfence<P, T>(tb)->L[0][0] : &tfence<P, T>(tb)->H[0][0];
+            stage_il<T, NR, Q, N1, N2, 1, Q, N1, false>(L.A1, L.A2, B1, ps, r);
+            __syncthreads();
+            if (ps < Q * Q) {
+                const auto B2 = C == 2 ? &tfence<P, T>(tb)->L[0][0] : &tfence<P, T>(tb)->H[0][0];
+                T in[N2];
+#pragma unroll
+                for (int k = 0; k < N2; ++k) in[k] = L.A2[(ps + Q * Q * k) * NR + r];
+                pencil_mul<T, N2, Q, N2, false>(in, U[C], B2);
+            }
+            __syncthreads();
+        };
+        body(std::integral_constant<int, 0>{});
+        body(std::integral_constant<int, 1>{});
+        body(std::integral_constant<int, 2>{});
+    }
+    if (ps < Q * Q) {
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            const int pt = ps + Q * Q * c;
+            const T a0 = U[0][c], a1 = U[1][c], a2 = U[2][c];
+            U[0][c] = L.G[0][pt] * a0 + L.G[1][pt] * a1 + L.G[2][pt] * a2;
+            U[1][c] = L.G[1][pt] * a0 + L.G[3][pt] * a1 + L.G[4][pt] * a2;
+            U[2][c] = L.G[2][pt] * a0 + L.G[4][pt] * a1 + L.G[5][pt] * a2;
+        }
+    }
+    // back to the RT dofs, D^T q~ added, scatter (colour 1 adds on shared faces)
+    {
+        auto body = [&](auto cc) {
+            constexpr int C = decltype(cc)::value;
+            constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
+            const auto B1 = C == 1 ? &tfence<P, T>(tb)->L[0][0] : &tfence<P, T>(tb)->H[0][0];
+            if (ps < Q * Q) {
+                const auto B2 = C == 2 ? &tfence<P, T>(tb)->L[0][0] : &tfence<P, T>(tb)->H[0][0];
+                T o[N2];
+                pencil_mul<T, Q, N2, N2, true>(U[C], o, B2);
+#pragma unroll
+                for (int k = 0; k < N2; ++k) L.A2[(ps + Q * Q * k) * NR + r] = o[k];
+            }
+            __syncthreads();
+            stage_il<T, NR, Q, Q, N2, 1, N1, N1, true>(L.A2, L.A1, B1, ps, r);
+            __syncthreads();
+            const auto B0 = C == 0 ? &tfence<P, T>(tb)->L[0][0] : &tfence<P, T>(tb)->H[0][0];
+            for (int tt = ps; tt < N1 * N2; tt += PS) {
+                const int j = tt % N1, k = tt / N1;
+                T in[Q], yv[N0];
+                using GQ = PencilGeom<Q, N1, N2, 0>;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) in[q] = L.A1[(GQ::base(tt) + q) * NR + r];
+                pencil_mul<T, Q, N0, N0, true>(in, yv, B0);
+                const RtLine rl = rt_line<P, C>(g, ex, ey, ez, j, k);
+#pragma unroll
+                for (int i = 0; i < N0; ++i) {
+                    int onf, bs;
+                    rt_line_dof<P, C>(g, ex, rl, i, onf, bs);
+                    const int64_t gi = (rl.base + i) * ldr + rx;
+                    if (!live) continue;
+                    if (bs >= 0 && ((ess >> (2 * C + bs)) & 1u)) {
+                        y[gi] = x[gi];   // identity row
+                        continue;
+                    }
+                    const int tn = C == 0 ? i : (C == 1 ? j : k);
+                    int a = i, b = j, c = k;
+                    T add = 0;
+                    if (tn >= 1) {
+                        if (C == 0) a = i - 1; else if (C == 1) b = j - 1; else c = k - 1;
+                        add += L.sq[(a + P * (b + P * c)) * NR + r];
+                    }
+                    if (tn <= P - 1) add -= L.sq[(i + P * (j + P * k)) * NR + r];
+                    const T v = yv[i] + add;
+                    y[gi] = (colour == 1 && onf && bs < 0) ? y[gi] + v : v;
+                }
+            }
+            __syncthreads();
+        };
+        body(std::integral_constant<int, 0>{});
+        body(std::integral_constant<int, 1>{});
+        body(std::integral_constant<int, 2>{});
+    }
+    // -kappa_e W_e^{-1} q~ by a local CG per right-hand side (Section 2.5)
+    if constexpr (HAS_C) {
+        if (with_c && kE != T(0)) {
+            const auto Ti = &tfence<P, T>(tb)->Ti[0][0];
+            const auto Bg = &tfence<P, T>(tb)->Bg[0][0];
+            const auto Bg2 = &tfence<P, T>(tb)->Bg2[0][0];
+            // Jacobi diagonal (Bg^2)^T gw, shared by the right-hand sides: the
+            // threads of right-hand side 0 form it through the stage buffers
+            if (ps < Q * Q && r == 0) {
+                T gw[Q], o[P];
+#pragma unroll
+                for (int c = 0; c < Q; ++c) gw[c] = L.G[6][ps + Q * Q * c];
+                pencil_mul<T, Q, P, P, true>(gw, o, Bg2);
+#pragma unroll
+                for (int k = 0; k < P; ++k) L.A1[(ps + Q * Q * k) * NR] = o[k];
+            }
+            __syncthreads();
+            if (r == 0) stage_il<T, NR, Q, Q, P, 1, P, P, true>(L.A1, L.A2, Bg2, ps, 0);
+            __syncthreads();
+            if (ps < P * P && r == 0) {
+                T in[Q], o[P];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) in[q] = L.A2[(ps * Q + q) * NR];
+                pencil_mul<T, Q, P, P, true>(in, o, Bg2);
+#pragma unroll
+                for (int k = 0; k < P; ++k) L.dW[ps * P + k] = T(1) / o[k];
+            }
+            // right-hand side T^{-T} q~: z, y, x
+            stage_il<T, NR, P, P, P, 2, P, P, true>(L.sq, L.A1, Ti, ps, r);
+            __syncthreads();
+            stage_il<T, NR, P, P, P, 1, P, P, true>(L.A1, L.A2, Ti, ps, r);
+            __syncthreads();
+            T rv[P], zv[P], pv[P], xv[P], dW[P], Ap[P];
+            double rz = 0.0;
+            if (ps < P * P) {
+                T in[P];
+#pragma unroll
+                for (int k = 0; k < P; ++k) in[k] = L.A2[(ps * P + k) * NR + r];
+                pencil_mul<T, P, P, P, true>(in, rv, Ti);
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    dW[k] = L.dW[ps * P + k];
+                    zv[k] = rv[k] * dW[k];
+                    pv[k] = zv[k];
+                    xv[k] = 0;
+                    rz += (double)(rv[k] * zv[k]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < P; ++k) rv[k] = zv[k] = pv[k] = xv[k] = dW[k] = Ap[k] = T(0);
+            }
+            T rzt = (T)il_sum<NR, P * P>(L.red, rz, ps, r);
+            const T rr0 = rzt;
+            bool done = !(rr0 > T(0));
+            for (int it = 0; it < cgp.maxit; ++it) {
+                if (!__syncthreads_or(!done)) break;
+                if (ps < P * P) {
+                    T o[Q];
+                    pencil_mul<T, P, Q, P, false>(pv, o, Bg);
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) L.A1[(ps * Q + q) * NR + r] = o[q];
+                }
+                __syncthreads();
+                stage_il<T, NR, Q, P, P, 1, Q, P, false>(L.A1, L.A2, Bg, ps, r);
+                __syncthreads();
+                if (ps < Q * Q) {
+                    T in[P], w[Q], o[P];
+#pragma unroll
+                    for (int k = 0; k < P; ++k) in[k] = L.A2[(ps + Q * Q * k) * NR + r];
+                    pencil_mul<T, P, Q, P, false>(in, w, Bg);
+#pragma unroll
+                    for (int c = 0; c < Q; ++c) w[c] *= L.G[6][ps + Q * Q * c];
+                    pencil_mul<T, Q, P, P, true>(w, o, Bg);
+#pragma unroll
+                    for (int k = 0; k < P; ++k) L.A1[(ps + Q * Q * k) * NR + r] = o[k];
+                }
+                __syncthreads();
+                stage_il<T, NR, Q, Q, P, 1, P, P, true>(L.A1, L.A2, Bg, ps, r);
+                __syncthreads();
+                double pAp = 0.0;
+                if (ps < P * P) {
+                    T in[Q];
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) in[q] = L.A2[(ps * Q + q) * NR + r];
+                    pencil_mul<T, Q, P, P, true>(in, Ap, Bg);
+#pragma unroll
+                    for (int k = 0; k < P; ++k) pAp += (double)(pv[k] * Ap[k]);
+                }
+                const T pApt = (T)il_sum<NR, P * P>(L.red, pAp, ps, r);
+                const T alpha = rzt / pApt;
+                double rzn = 0.0;
+                if (!done && ps < P * P) {
+#pragma unroll
+                    for (int k = 0; k < P; ++k) {
+                        xv[k] += alpha * pv[k];
+                        rv[k] -= alpha * Ap[k];
+                        zv[k] = rv[k] * dW[k];
+                        rzn += (double)(rv[k] * zv[k]);
+                    }
+                }
+                const T rznt = (T)il_sum<NR, P * P>(L.red, rzn, ps, r);
+                if (!done) {
+                    if (rznt <= cgp.tol * cgp.tol * rr0) {
+                        done = true;
+                    } else {
+                        const T beta = rznt / rzt;
+                        rzt = rznt;
+#pragma unroll
+                        for (int k = 0; k < P; ++k) pv[k] = zv[k] + beta * pv[k];
+                    }
+                }
+            }
+            __syncthreads();
+            // IH-basis solution T^{-1} x: x (regs) -> y -> z, A1 = kappa sol
+            if (ps < P * P) {
+                T o[P];
+                pencil_mul<T, P, P, P, false>(xv, o, Ti);
+#pragma unroll
+                for (int k = 0; k < P; ++k) L.A1[(ps * P + k) * NR + r] = o[k];
+            }
+            __syncthreads();
+            stage_il<T, NR, P, P, P, 1, P, P, false>(L.A1, L.A2, Ti, ps, r);
+            __syncthreads();
+            stage_il<T, NR, P, P, P, 2, P, P, false>(L.A2, L.A1, Ti, ps, r);
+            __syncthreads();
+        }
+    }
+    // y_q = D u - kappa W^{-1} q~
+    const bool cg = HAS_C && with_c && kE != T(0);
+    for (int l = ps; l < NL; l += PS) {
+        const int a = l % P, b = (l / P) % P, c = l / (P * P);
+        T v = L.su[((a + 1) + (P + 1) * (b + P * c)) * NR + r] - L.su[(a + (P + 1) * (b + P * c)) * NR + r];
+        v += L.su[(NC + a + P * ((b + 1) + (P + 1) * c)) * NR + r] - L.su[(NC + a + P * (b + (P + 1) * c)) * NR + r];
+        v += L.su[(2 * NC + a + P * (b + P * (c + 1))) * NR + r] - L.su[(2 * NC + a + P * (b + P * c)) * NR + r];
+        if (cg) v -= kE * L.A1[l * NR + r];
+        if (live) y[(n_u + ee * NL + l) * ldr + rx] = v;
+    }
+}
+
 // ---- batches of independent instances ------------------------------------
 // LDS of one workgroup: the largest element-slot set over the degrees.
 template <typename T>
@@ -1206,6 +1584,38 @@ void launch_apply_uns_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra) {
                            (const T*)y, ra);
 }
 
+// Right-hand sides per workgroup of the interleaved apply: the largest of
+// 16, 8, 4, 2, 1 whose pencil slots hold the (p+1)^2 quadrature columns and
+// whose LDS stays within 48 KB.
+template <int P, typename T>
+constexpr int il_nr() {
+    constexpr int Q = P + 1;
+    int nr = 16;
+    while (nr > 1 && (Q * Q > IL_T / nr || sizeof(T) * (size_t)((Dim<P>::NRT + Dim<P>::NL + 2 * Dim<P>::Q3) * nr +
+                                                                 8 * Dim<P>::Q3 + 24) + 8 * IL_T > 48 * 1024))
+        nr /= 2;
+    return nr;
+}
+
+template <int P, typename T>
+void launch_apply_il_p(hd_ctx* c, const T* x, T* y, int nrhs) {
+    constexpr int NR = il_nr<P, T>();
+    Geo g = geo_of(c);
+    const T* cm = std::is_same<T, double>::value ? (const T*)c->d_cm : (const T*)c->d_cm32;
+    const T* kap = std::is_same<T, double>::value ? (const T*)c->d_kap : (const T*)c->d_kap32;
+    const tkp<P, T> tb = (tkp<P, T>)(std::is_same<T, double>::value ? c->d_tabk64 : c->d_tabk32);
+    const unsigned nb = apply_blocks_per_colour(c->nx, c->ny, c->nz, 1);
+    const dim3 grid(nb, (unsigned)((nrhs + NR - 1) / NR));
+    for (int colour = 0; colour < 2; ++colour) {
+        if (!c->kappa_zero)
+            hipLaunchKernelGGL((block_apply_il_kernel<P, T, NR, true>), grid, dim3(IL_T), 0, c->stream, g, c->d_vert,
+                               tb, cm, kap, c->ess, c->n_u, x, y, nrhs, cg_params<T>(), 1, colour, nb);
+        else
+            hipLaunchKernelGGL((block_apply_il_kernel<P, T, NR, false>), grid, dim3(IL_T), 0, c->stream, g,
+                               c->d_vert, tb, cm, kap, c->ess, c->n_u, x, y, nrhs, cg_params<T>(), 0, colour, nb);
+    }
+}
+
 template <int P, typename T>
 void launch_minv_p(hd_ctx* c, const T* x, T* y, bool weighted) {
     const T* pa = std::is_same<T, double>::value ? (const T*)c->d_pa : (const T*)c->d_pa32;
@@ -1341,6 +1751,22 @@ int launch_apply(hd_ctx* c, int prec, int nrhs, const void* x, void* y, const do
         c->apply_ms_sum += ms;
         c->apply_count += 1;
     }
+    return HD_OK;
+}
+
+int launch_apply_interleaved(hd_ctx* c, int prec, int nrhs, const void* x, void* y) {
+    const bool f64 = prec == HD_F64;
+    switch (c->p) {
+#define IL(PP)                                                                                               \
+    case PP:                                                                                                 \
+        if (f64) launch_apply_il_p<PP, double>(c, (const double*)x, (double*)y, nrhs);                     \
+        else launch_apply_il_p<PP, float>(c, (const float*)x, (float*)y, nrhs);                            \
+        break;
+        IL(1) IL(2) IL(3) IL(4) IL(5) IL(6)
+#undef IL
+        default: return set_err(c, HD_ERR_ARG, "p out of range");
+    }
+    HD_HIP(c, hipGetLastError());
     return HD_OK;
 }
 

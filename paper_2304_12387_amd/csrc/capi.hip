@@ -545,6 +545,21 @@ int hd_apply_block_op(hd_ctx* c, int prec, int nrhs, const void* x, void* y) {
     return launch_apply(c, prec, nrhs, x, y, nullptr, 0, nullptr, 0, ESS_IDENTITY, nullptr, 0);
 }
 
+int hd_apply_block_op_interleaved(hd_ctx* c, int prec, int nrhs, const void* x, void* y) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");
+    if (c->unstructured || c->gamma_field)
+        return set_err(c, HD_ERR_STATE, "the interleaved layout needs a structured mesh without a gamma field");
+    if (nrhs < 1) return set_err(c, HD_ERR_ARG, "nrhs must be >= 1");
+    if ((int64_t)nrhs * (c->n_u + c->n_q) > (int64_t)INT32_MAX * 4)
+        return set_err(c, HD_ERR_ARG, "nrhs too large");
+    if (prec != HD_F64 && prec != HD_F32) return set_err(c, HD_ERR_ARG, "prec");
+    if (!x || !y || x == y) return set_err(c, HD_ERR_ARG, "x, y must be distinct device pointers");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_apply_interleaved(c, prec, nrhs, x, y);
+}
+
 int hd_apply_mass_inverse(hd_ctx* c, int prec, int nrhs, const void* x, void* y) {
     if (!c) return HD_ERR_ARG;
     if (!c->have_coeffs) return set_err(c, HD_ERR_STATE, "mesh and coefficients first");

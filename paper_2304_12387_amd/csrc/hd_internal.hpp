@@ -296,6 +296,8 @@ enum { ESS_NONE = 0, ESS_IDENTITY = 1 };
 int launch_apply(hd_ctx* c, int prec, int nrhs, const void* x, void* y, const double* in_scale, int scale_stride,
                  double* dot_partial, int64_t part_stride, int ess_mode, const int* done, int done_stride);
 int launch_mass_inverse(hd_ctx* c, int prec, const void* x, void* y, bool weighted);
+// y = A x for nrhs right-hand sides interleaved ([dof][nrhs])
+int launch_apply_interleaved(hd_ctx* c, int prec, int nrhs, const void* x, void* y);
 int launch_lift(hd_ctx* c, const double* ubc, double* b);
 int launch_constant_flux(hd_ctx* c, const double* u, double* out);
 int64_t apply_partial_count(const hd_ctx* c);

@@ -227,8 +227,9 @@ __device__ __forceinline__ void block_partial(double v, double* __restrict__ par
     if (threadIdx.x == 0) part[slot] = s[0];
 }
 
-// x = dinv b;  r = b - A (dinv b)
-template <int G, typename T>
+// x = dinv b;  r = b - A (dinv b).  With XPRE the restriction that produced
+// b has already written x = dinv b, and only x is gathered.
+template <int G, typename T, bool XPRE>
 __global__ __launch_bounds__(BS) void vc_pre_kernel(int64_t n, const int32_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ci, const T* __restrict__ av,
                                                     const T* __restrict__ dinv, const T* __restrict__ b,
@@ -237,18 +238,22 @@ __global__ __launch_bounds__(BS) void vc_pre_kernel(int64_t n, const int32_t* __
     const int64_t row = (xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)BS + threadIdx.x) / G;
     const int lane = threadIdx.x % G;
     if (row >= n) return;
-    const T s = group_row<G, T>(rp, ci, av, row, lane, [&](int32_t j) { return dinv[j] * b[j]; });
+    T s;
+    if (XPRE) s = group_row<G, T>(rp, ci, av, row, lane, [&](int32_t j) { return x[j]; });
+    else s = group_row<G, T>(rp, ci, av, row, lane, [&](int32_t j) { return dinv[j] * b[j]; });
     if (lane == 0) {
-        x[row] = dinv[row] * b[row];
+        if (!XPRE) x[row] = dinv[row] * b[row];
         r[row] = b[row] - s;
     }
 }
 
-// y = M x (restriction with R = P^T) or y += M x (prolongation)
-template <int G, typename T, bool ADD>
+// y = M x (restriction with R = P^T) or y += M x (prolongation); with XN
+// (restriction) also xn = dn y, the next level's pre-smoothed x
+template <int G, typename T, bool ADD, bool XN = false>
 __global__ __launch_bounds__(BS) void vc_spmv_kernel(int64_t n, const int32_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, const T* __restrict__ mv,
                                                      const T* __restrict__ x, T* __restrict__ y,
+                                                     const T* __restrict__ dn, T* __restrict__ xn,
                                                      const int* __restrict__ done) {
     if (done && *done) return;
     const int64_t row = (xcd_chunk(blockIdx.x, gridDim.x) * (int64_t)BS + threadIdx.x) / G;
@@ -258,6 +263,7 @@ __global__ __launch_bounds__(BS) void vc_spmv_kernel(int64_t n, const int32_t* _
     if (lane == 0) {
         if (ADD) y[row] += s;
         else y[row] = s;
+        if (XN) xn[row] = dn[row] * s;
     }
 }
 
@@ -397,8 +403,10 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
     T* bc = pickw<T>(nx.b, nx.b32);
     T* zc = pickw<T>(nx.z, nx.z32);
     const int gA = group_of(lv.A), gR = group_of(lv.R), gP = group_of(lv.P);
-#define PRE(G, ...) hipLaunchKernelGGL((vc_pre_kernel<G, T>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
+#define PRE(G, ...) hipLaunchKernelGGL((vc_pre_kernel<G, T, false>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
+#define PREX(G, ...) hipLaunchKernelGGL((vc_pre_kernel<G, T, true>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
 #define RES(G, ...) hipLaunchKernelGGL((vc_spmv_kernel<G, T, false>), dim3(gblk(lv.R.nrows, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
+#define RESX(G, ...) hipLaunchKernelGGL((vc_spmv_kernel<G, T, false, true>), dim3(gblk(lv.R.nrows, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
 #define PRO(G, ...) hipLaunchKernelGGL((vc_spmv_kernel<G, T, true>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
 #define POST(G, ...) hipLaunchKernelGGL((vc_post_kernel<G, T>), dim3(gblk(n, G)), dim3(BS), 0, c->stream, __VA_ARGS__)
     if (l == 0 && !c->unstructured) {
@@ -415,13 +423,27 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
             default: S0PRE(6); break;
         }
 #undef S0PRE
+    } else if (l > 0) {
+        // x = dinv b was written with b by the restriction from level l - 1
+        HD_GROUP_DISPATCH(gA, PREX, n, lv.A.rp, lv.A.ci, av, dinv, b, x, r, done)
     } else {
         HD_GROUP_DISPATCH(gA, PRE, n, lv.A.rp, lv.A.ci, av, dinv, b, x, r, done)
     }
-    HD_GROUP_DISPATCH(gR, RES, lv.R.nrows, lv.R.rp, lv.R.ci, pick<T>(lv.R.v, lv.R.v32), (const T*)r, bc, done)
+    // restriction; above the coarsest level it also writes the next level's
+    // x = dinv b (the pre-smoother's first half)
+    if (l + 2 < L) {
+        const T* dn = pick<T>(nx.dinv, nx.dinv32);
+        T* xn = pickw<T>(nx.x, nx.x32);
+        HD_GROUP_DISPATCH(gR, RESX, lv.R.nrows, lv.R.rp, lv.R.ci, pick<T>(lv.R.v, lv.R.v32), (const T*)r, bc, dn, xn,
+                          done)
+    } else {
+        HD_GROUP_DISPATCH(gR, RES, lv.R.nrows, lv.R.rp, lv.R.ci, pick<T>(lv.R.v, lv.R.v32), (const T*)r, bc,
+                          (const T*)nullptr, (T*)nullptr, done)
+    }
     int rc = cycle<T>(c, l + 1, bc, zc, nullptr, 0, done);
     if (rc) return rc;
-    HD_GROUP_DISPATCH(gP, PRO, n, lv.P.rp, lv.P.ci, pick<T>(lv.P.v, lv.P.v32), (const T*)zc, x, done)
+    HD_GROUP_DISPATCH(gP, PRO, n, lv.P.rp, lv.P.ci, pick<T>(lv.P.v, lv.P.v32), (const T*)zc, x, (const T*)nullptr,
+                      (T*)nullptr, done)
     if (l == 0 && !c->unstructured) {
         const T* sd = pick<T>(c->d_sdiag, c->d_sdiag32);
         const T* wl = pick<T>(c->d_wlo, c->d_wlo32);
@@ -458,7 +480,9 @@ int cycle(hd_ctx* c, int l, const T* b, T* z, double* part, int part_kind, const
         }
     }
 #undef PRE
+#undef PREX
 #undef RES
+#undef RESX
 #undef PRO
 #undef POST
     return HD_OK;

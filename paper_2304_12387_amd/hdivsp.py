@@ -36,7 +36,7 @@ EXPORTED = [
     'hd_batch_set_launch', 'hd_batch_build_precond', 'hd_batch_minres_solve', 'hd_constant_flux',
     'hd_set_local_solver', 'hd_set_gamma_field', 'hd_gmres_solve', 'hd_apply_tri_precond',
     'hd_apply_tri_precond_noalloc', 'hd_setup_mesh_unstructured', 'hd_set_essential_dofs', 'hd_get_dof_map',
-    'hd_host_unstructured_map',
+    'hd_host_unstructured_map', 'hd_apply_block_op_interleaved',
 ]
 
 
@@ -100,6 +100,7 @@ def load():
         'hd_get_dof_map': (I, [P, P]),
         'hd_sizes': (I, [P, pI64, pI64]),
         'hd_apply_block_op': (I, [P, I, I, P, P]),
+        'hd_apply_block_op_interleaved': (I, [P, I, I, P, P]),
         'hd_apply_mass_inverse': (I, [P, I, I, P, P]),
         'hd_set_local_solver': (I, [P, I]),
         'hd_set_gamma_field': (I, [P, P]),
@@ -258,6 +259,13 @@ class Context:
         self._dev(x, nrhs * (nu + nq), prec, 'x')
         self._dev(y, nrhs * (nu + nq), prec, 'y')
         return self._check(self.lib.hd_apply_block_op(self.h, prec, nrhs, _ptr(x), _ptr(y)))
+
+    def apply_block_op_interleaved(self, x, y, nrhs, prec=HD_F64):
+        """y = A x for nrhs right-hand sides interleaved ([dof][nrhs])."""
+        nu, nq = self.sizes()
+        self._dev(x, nrhs * (nu + nq), prec, 'x')
+        self._dev(y, nrhs * (nu + nq), prec, 'y')
+        return self._check(self.lib.hd_apply_block_op_interleaved(self.h, prec, nrhs, _ptr(x), _ptr(y)))
 
     def set_gamma_field(self, gamma_vertices):
         """Darcy: gamma as the trilinear field of these vertex values (host
