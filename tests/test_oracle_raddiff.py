@@ -1,0 +1,96 @@
+"""Pins of the radiation-diffusion driver oracle (Section 4.3; oracle.raddiff):
+
+* the three-stage SDIRK method is third-order accurate: on a spatially
+  uniform state (D F = 0, F = 0) the energies converge at rate 3 as dt halves,
+  against scipy's Radau integration of the same exchange ODE;
+* with F . n = 0 on the boundary and no sources the total energy
+  sum_j m_j (rho e_j + E_j) is conserved (the exchange terms cancel and the
+  divergence of F integrates to zero);
+* radiative equilibrium (E = a T^4, uniform) is a steady state on a box mesh
+  (where the constants are in the L2 space);
+* the sub-cell volumes of a unit cube element sum to 1;
+* the dof-wise Newton solve leaves zero residuals."""
+import numpy as np
+import pytest
+
+from oracle import raddiff
+from paper_2304_12387_amd import inputs
+
+
+def test_sdirk_third_order_on_the_uniform_exchange():
+    rd = raddiff.RadDiff(1, 1, 1, 1, inputs.box_vertices(1, 1, 1), rho=1.0, cv=1.0, c=1.0, a=1.0, sigma=1.0)
+    nq, nu = rd.mesh.n_q, rd.mesh.n_u
+    assert abs(rd.vol[0] - 1.0) <= 1e-14
+    e0, E0, tend = 1.5, 0.2, 0.6
+    eref, Eref = raddiff.uniform_exchange_reference(e0, E0, tend)
+    errs = []
+    for nsteps in (20, 40, 80):
+        e, E, F = np.full(nq, e0), np.full(nq, E0), np.zeros(nu)
+        for _ in range(nsteps):
+            e, E, F, _ = rd.step(e, E, F, tend / nsteps)
+        assert np.abs(F).max() <= 1e-12
+        errs.append(max(abs(e[0] - eref), abs(E[0] - Eref)))
+    rates = [np.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    print('errors', errs, 'rates', rates)
+    assert all(2.7 <= r <= 3.4 for r in rates), rates
+
+
+def _hot_spot(rd, seed=0):
+    X = raddiff_dof_centres(rd)
+    r2 = ((X - 0.5) ** 2).sum(axis=1)
+    e = (1.0 + 0.5 * np.exp(-r2 / 0.05)) * rd.vol
+    E = (0.3 + 0.2 * np.exp(-r2 / 0.08)) * rd.vol
+    return e, E
+
+
+def raddiff_dof_centres(rd):
+    """Physical centres of the L2 dofs' sub-volumes (for initial data)."""
+    from oracle.basis import gauss_lobatto_points
+    from oracle.element import trilinear
+    p = rd.mesh.p
+    xi = gauss_lobatto_points(p)
+    mid = 0.5 * (xi[:-1] + xi[1:])
+    c, b, a = np.meshgrid(mid, mid, mid, indexing='ij')
+    Xr = np.stack([a.ravel(), b.ravel(), c.ravel()], axis=1)
+    x, _ = trilinear(rd.mesh.element_vertices(), Xr)
+    return x.reshape(-1, 3)
+
+
+def test_total_energy_is_conserved():
+    V = inputs.jittered_vertices(3, 3, 3, 0.1, 5)
+    rd = raddiff.RadDiff(3, 3, 3, 2, V, rho=2.0, cv=1.5, c=3.0, a=0.7, sigma=2.0)
+    e, E = _hot_spot(rd)
+    F = np.zeros(rd.mesh.n_u)
+    W0 = rd.energy(e, E)
+    for _ in range(2):
+        e, E, F, outers = rd.step(e, E, F, 0.05)
+        assert max(outers) <= 20
+    assert np.abs(F).max() > 1e-6          # the flux is not trivial
+    assert abs(rd.energy(e, E) - W0) <= 1e-10 * abs(W0)
+
+
+def test_equilibrium_is_steady():
+    # a box mesh: with det J constant the constant fields are in the space
+    rd = raddiff.RadDiff(2, 2, 2, 2, inputs.box_vertices(2, 2, 2, 1.0, 0.7, 1.3), rho=1.0, cv=2.0, c=1.0, a=0.5,
+                         sigma=3.0)
+    T = 1.3
+    e = rd.rho * rd.cv * T * rd.vol
+    E = rd.a * T ** 4 * rd.vol
+    F = np.zeros(rd.mesh.n_u)
+    e1, E1, F1, _ = rd.step(e, E, F, 0.1)
+    assert np.abs(e1 - e).max() <= 1e-11 * e.max() and np.abs(E1 - E).max() <= 1e-11 * E.max()
+    assert np.abs(F1).max() <= 1e-12
+
+
+def test_newton_leaves_zero_residuals():
+    rd = raddiff.RadDiff(1, 1, 1, 2, inputs.box_vertices(1, 1, 1), rho=1.0, cv=1.0, c=2.0, a=1.0, sigma=1.5)
+    rng = np.random.default_rng(3)
+    n = rd.mesh.n_q
+    eh, Eh, dF = rng.uniform(0.5, 2, n), rng.uniform(0.1, 1, n), rng.uniform(-0.3, 0.3, n)
+    gdt = 0.05
+    e, E, its = rd.newton(eh, Eh, dF, gdt)
+    B = rd.emission(e)
+    R1 = (e - eh) / gdt + rd.c * rd.sigma * (B - E)
+    R2 = (E - Eh) / gdt + dF - rd.c * rd.sigma * (B - E)
+    assert np.abs(R1).max() <= 1e-9 * (np.abs(e).max() / gdt) and np.abs(R2).max() <= 1e-9 * (np.abs(E).max() / gdt)
+    assert its < 20
