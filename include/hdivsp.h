@@ -486,6 +486,91 @@ int hd_get_amg_prolongator(hd_ctx* ctx, int level, int64_t* nrows, int64_t* ncol
  * clears the accumulators). */
 int hd_apply_timing(hd_ctx* ctx, int reset, double* avg_ms, int64_t* count);
 
+/* ---- grey nonlinear radiation diffusion (Section 4.3) ------------------- */
+
+/* (D F)_j for an RT vector F: the signed sum of the fluxes through the six
+ * faces of sub-cell j (D = W^{-1} B, the +-1 incidence of the interpolation-
+ * histopolation basis, Section 2.1, Algorithm 1), i.e. the q-part of the block
+ * operator applied to [F; 0].  F: FP64 device array of n_u values; q: FP64
+ * device array of n_q values; caller-owned.  Asynchronous on the context's
+ * stream.  HD_ERR_STATE before a mesh, HD_ERR_ARG for NULL pointers. */
+int hd_apply_divergence(hd_ctx* ctx, const double* F, double* q);
+
+/* |K_j| for every L2 dof: the physical volume of its sub-cell (the mapped
+ * Gauss-Lobatto sub-cell of Section 2.1), det J integrated by 2 x 2 x 2
+ * Gauss-Legendre points per sub-cell (exact for the trilinear map).  An L2
+ * dof of the transformed space is the integral of the function over its
+ * sub-cell, so a density f is represented by f |K_j|.  vol: FP64 device
+ * array of n_q values, caller-owned.  Asynchronous.  HD_ERR_STATE before a
+ * mesh. */
+int hd_subcell_volumes(hd_ctx* ctx, double* vol);
+
+/* Parameters of the radiation-diffusion time step (Section 4.3, eqs. rad-diff-e,
+ * rad-diff-E, rad-diff-F with Q = S = 0 and constant coefficients). */
+typedef struct hd_rd_params {
+    double rho, cv, c, a, sigma;  /* density, specific heat, speed of light,
+                                     radiation constant, opacity; all > 0 */
+    double dt;                    /* time step > 0 */
+    double tol_outer;             /* stop of a stage's outer iteration:
+                                     ||R_e|| / (||e - e^|| / (g dt) + c sigma ||E||)
+                                     with R_e the material-energy residual after
+                                     the Darcy solve; default 1e-10 */
+    int max_outer;                /* default 20 */
+    double newton_tol;            /* per-dof Newton: both updates below
+                                     newton_tol times the iterate; default 1e-12 */
+    int newton_max_it;            /* default 50 */
+    double lin_tol;               /* each Darcy MINRES: |eta| <= lin_tol |eta_0|
+                                     from the previous solution as initial guess;
+                                     default 1e-8 */
+    int lin_max_it;               /* default 10000 */
+    int lin_mode;                 /* HD_MODE_* of the Darcy solves; default
+                                     HD_MODE_PLAIN64 */
+} hd_rd_params;
+
+typedef struct hd_rd_info {
+    int status;                   /* 0, or HD_NOT_CONVERGED when a stage's
+                                     outer iteration or a Darcy solve hit its limit */
+    int outer[3];                 /* outer iterations of each stage */
+    int newton_max_it;            /* largest Newton count of any dof in the step */
+    int linear_solves;            /* Darcy solves in the step */
+    int linear_iterations;        /* MINRES iterations summed over them */
+    double e_residual[3];         /* the last outer residual of each stage */
+    double time_s;                /* wall time of the step */
+    double linear_time_s;         /* of which in the Darcy solves (MINRES) */
+} hd_rd_info;
+
+/* Fill *p with the defaults above (rho = cv = c = a = sigma = dt = 1). */
+int hd_rd_default_params(hd_rd_params* p);
+
+/* Prepare the context for hd_rd_step on its mesh (structured, or
+ * unstructured): the coefficients of the Darcy system of a stage
+ * (HD_DARCY, c_mass = 3 sigma / c, gamma = kappa = 1 / (g dt) + c sigma with
+ * g the SDIRK diagonal, every boundary RT dof essential: F . n = 0), the
+ * preconditioner (precond may be NULL for the defaults of hd_build_precond),
+ * the sub-cell volumes and the work space (14 n_q + 2 (n_u + n_q) doubles).
+ * Replaces any coefficients and preconditioner the context held.  Errors:
+ * HD_ERR_STATE before a mesh, HD_ERR_ARG for a parameter out of range, and
+ * those of hd_setup_coeffs and hd_build_precond. */
+int hd_rd_setup(hd_ctx* ctx, const hd_rd_params* params, const hd_precond_params* precond);
+
+/* One step of length dt of the three-stage L-stable SDIRK method of
+ * Alexander (1977, Section 4.3), stiffly accurate, each stage solved by the
+ * outer iteration of Section 4.3: (1) F lagged, the 2 x 2 nonlinear system
+ * of every L2 dof for (e_j, E_j) by Newton's method from the stage's
+ * e^, E^; (2) e fixed, the Darcy system kappa E + D F = E^ / (g dt) +
+ * c sigma a T^4 |K|, M_{3 sigma / c} F - B^T E = 0 in the transformed form
+ * with unknowns (F, -W E), by block-preconditioned MINRES from the previous
+ * solution; repeated until tol_outer.  e_j, E_j are energy amounts per
+ * sub-cell (the integrals of rho e and E over K_j), T_j = e_j / (rho C_v |K_j|).
+ * e, E: FP64 device arrays of n_q values; F: FP64 device array of n_u values
+ * (zero on the boundary); all caller-owned, updated in place to t + dt.
+ * Synchronises the stream.  info may be NULL.  Returns 0, HD_NOT_CONVERGED
+ * (state still updated), HD_ERR_NONFINITE when a Newton solve fails to reach
+ * a positive finite energy or a residual is not finite (state not
+ * updated), HD_ERR_STATE before hd_rd_setup, HD_ERR_ARG for NULL or
+ * aliased pointers. */
+int hd_rd_step(hd_ctx* ctx, double* e, double* E, double* F, hd_rd_info* info);
+
 /* ---- host-only entry (no device needed) -------------------------------- */
 
 /* Build the aggregation AMG hierarchy of a host CSR matrix with the

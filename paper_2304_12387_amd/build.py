@@ -18,7 +18,7 @@ BUILD = os.path.join(os.path.dirname(HERE), '_build')
 LIB = os.path.join(HERE, 'libhdivsp.so')
 
 SOURCES = ['tables.cpp', 'amg_host.cpp', 'unstructured.cpp', 'amg_gpu.hip', 'setup.hip', 'apply.hip', 'precond.hip', 'minres.hip', 'gmres.hip',
-           'learned.hip',
+           'learned.hip', 'raddiff.hip',
            'capi.hip']
 ARCH = 'gfx950'
 FLAGS = ['-O3', '-std=c++17', '-fPIC', f'--offload-arch={ARCH}', '-munsafe-fp-atomics',

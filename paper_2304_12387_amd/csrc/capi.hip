@@ -229,6 +229,7 @@ int hd_destroy(hd_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->solve_cache) c->solve_cache_free(c->solve_cache);
     batch_free(c);
+    rd_free(c);
     free_prec(c);
     free_coeffs(c);
     free_mesh(c);
@@ -259,6 +260,7 @@ int hd_setup_mesh(hd_ctx* c, int nx, int ny, int nz, int p, const double* vertic
     if (rc) return rc;
     // everything built on the previous mesh goes (coefficients included: a
     // failed call below must not leave an apply-able state behind)
+    rd_free(c);
     free_prec(c);
     free_coeffs(c);
     free_mesh(c);
@@ -339,6 +341,7 @@ int hd_setup_coeffs(hd_ctx* c, int problem, const double* c_mass, const double* 
             kap[e] = c_22[e];
         }
     }
+    rd_free(c);
     free_prec(c);
     free_coeffs(c);
     c->problem = problem;
@@ -366,6 +369,7 @@ int hd_setup_mesh_unstructured(hd_ctx* c, int64_t nv, const double* vertices, in
     if (ne > (int64_t)INT32_MAX / 8) return set_err(c, HD_ERR_ARG, "too many elements");
     int rc = use_device(c);
     if (rc) return rc;
+    rd_free(c);
     free_prec(c);
     free_coeffs(c);
     free_mesh(c);
@@ -744,6 +748,63 @@ int hd_minres_solve(hd_ctx* c, const hd_solve_params* params, int nrhs, const do
     rc = minres_solve(c, prm, nrhs, b, x, info);
     if (rc == HD_NOT_CONVERGED) c->err = "MINRES did not reach the tolerance";
     return rc;
+}
+
+int hd_apply_divergence(hd_ctx* c, const double* F, double* q) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_mesh) return set_err(c, HD_ERR_STATE, "a mesh first");
+    if (!F || !q) return set_err(c, HD_ERR_ARG, "null pointer");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_divergence(c, F, q);
+}
+
+int hd_subcell_volumes(hd_ctx* c, double* vol) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_mesh) return set_err(c, HD_ERR_STATE, "a mesh first");
+    if (!vol) return set_err(c, HD_ERR_ARG, "null pointer");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return launch_subcell_volumes(c, vol);
+}
+
+int hd_rd_default_params(hd_rd_params* p) {
+    if (!p) return HD_ERR_ARG;
+    p->rho = p->cv = p->c = p->a = p->sigma = p->dt = 1.0;
+    p->tol_outer = 1e-10;
+    p->max_outer = 20;
+    p->newton_tol = 1e-12;
+    p->newton_max_it = 50;
+    p->lin_tol = 1e-8;
+    p->lin_max_it = 10000;
+    p->lin_mode = HD_MODE_PLAIN64;
+    return HD_OK;
+}
+
+int hd_rd_setup(hd_ctx* c, const hd_rd_params* prm, const hd_precond_params* pp) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->have_mesh) return set_err(c, HD_ERR_STATE, "a mesh first");
+    if (!prm) return set_err(c, HD_ERR_ARG, "null parameters");
+    const double pos[] = {prm->rho, prm->cv, prm->c, prm->a, prm->sigma, prm->dt, prm->tol_outer, prm->newton_tol,
+                          prm->lin_tol};
+    for (double v : pos)
+        if (!(v > 0) || !std::isfinite(v)) return set_err(c, HD_ERR_ARG, "parameters must be positive and finite");
+    if (prm->max_outer < 1 || prm->newton_max_it < 1 || prm->lin_max_it < 1 || prm->lin_mode < HD_MODE_PLAIN64 ||
+        prm->lin_mode > HD_MODE_PREC32)
+        return set_err(c, HD_ERR_ARG, "bad iteration limits or mode");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return rd_setup(c, *prm, pp);
+}
+
+int hd_rd_step(hd_ctx* c, double* e, double* E, double* F, hd_rd_info* info) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->rd || !c->have_prec) return set_err(c, HD_ERR_STATE, "hd_rd_setup first");
+    if (!e || !E || !F || e == E || (void*)e == (void*)F || (void*)E == (void*)F)
+        return set_err(c, HD_ERR_ARG, "e, E, F must be distinct device pointers");
+    int rc = use_device(c);
+    if (rc) return rc;
+    return rd_step(c, e, E, F, info);
 }
 
 int hd_learned_targets(hd_ctx* c, int p, int64_t n, const double* vertices, int max_steps, double* theta,

@@ -145,6 +145,8 @@ struct BatchState {
     bool have_prec = false;
 };
 
+struct RadDiffState;
+
 }  // namespace hd
 
 struct hd_ctx {
@@ -244,6 +246,9 @@ struct hd_ctx {
 
     // batch of independent instances (hd_setup_batch)
     hd::BatchState* batch = nullptr;
+
+    // radiation-diffusion time stepping (hd_rd_setup): work space and parameters
+    hd::RadDiffState* rd = nullptr;
 
     // scratch
     double* d_partial = nullptr;     // per-block partial sums (>= ne and >= reduce grid)
@@ -349,6 +354,13 @@ void batch_free(hd_ctx* c);
 // minres.hip
 // nrhs right-hand sides stored one after the other; info: nrhs entries
 int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* b, double* x, hd_solve_info* info);
+
+// raddiff.hip: the radiation-diffusion time step and its helpers
+int launch_divergence(hd_ctx* c, const double* F, double* q);
+int launch_subcell_volumes(hd_ctx* c, double* vol);
+int rd_setup(hd_ctx* c, const hd_rd_params& prm, const hd_precond_params* pp);
+int rd_step(hd_ctx* c, double* e, double* E, double* F, hd_rd_info* info);
+void rd_free(hd_ctx* c);
 
 // reductions (setup.hip)
 int reduce_sum_partials(hd_ctx* c, const double* partial, int64_t n, double* out_dev);

@@ -36,7 +36,8 @@ EXPORTED = [
     'hd_batch_set_launch', 'hd_batch_build_precond', 'hd_batch_minres_solve', 'hd_constant_flux',
     'hd_set_local_solver', 'hd_set_gamma_field', 'hd_gmres_solve', 'hd_apply_tri_precond',
     'hd_apply_tri_precond_noalloc', 'hd_setup_mesh_unstructured', 'hd_set_essential_dofs', 'hd_get_dof_map',
-    'hd_host_unstructured_map', 'hd_apply_block_op_interleaved',
+    'hd_host_unstructured_map', 'hd_apply_block_op_interleaved', 'hd_apply_divergence', 'hd_subcell_volumes',
+    'hd_rd_default_params', 'hd_rd_setup', 'hd_rd_step',
 ]
 
 
@@ -69,6 +70,24 @@ class SolveInfo(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RdParams(ctypes.Structure):
+    _fields_ = [('rho', ctypes.c_double), ('cv', ctypes.c_double), ('c', ctypes.c_double), ('a', ctypes.c_double),
+                ('sigma', ctypes.c_double), ('dt', ctypes.c_double), ('tol_outer', ctypes.c_double),
+                ('max_outer', ctypes.c_int), ('newton_tol', ctypes.c_double), ('newton_max_it', ctypes.c_int),
+                ('lin_tol', ctypes.c_double), ('lin_max_it', ctypes.c_int), ('lin_mode', ctypes.c_int)]
+
+
+class RdInfo(ctypes.Structure):
+    _fields_ = [('status', ctypes.c_int), ('outer', ctypes.c_int * 3), ('newton_max_it', ctypes.c_int),
+                ('linear_solves', ctypes.c_int), ('linear_iterations', ctypes.c_int),
+                ('e_residual', ctypes.c_double * 3), ('time_s', ctypes.c_double), ('linear_time_s', ctypes.c_double)]
+
+    def as_dict(self):
+        return {'status': self.status, 'outer': list(self.outer), 'newton_max_it': self.newton_max_it,
+                'linear_solves': self.linear_solves, 'linear_iterations': self.linear_iterations,
+                'e_residual': list(self.e_residual), 'time_s': self.time_s, 'linear_time_s': self.linear_time_s}
 
 
 _lib = None
@@ -143,6 +162,11 @@ def load():
         'hd_batch_set_launch': (I, [P, I, I, I]),
         'hd_batch_build_precond': (I, [P, ctypes.POINTER(PrecondParams)]),
         'hd_batch_minres_solve': (I, [P, ctypes.POINTER(SolveParams), P, P, ctypes.POINTER(SolveInfo)]),
+        'hd_apply_divergence': (I, [P, P, P]),
+        'hd_subcell_volumes': (I, [P, P]),
+        'hd_rd_default_params': (I, [ctypes.POINTER(RdParams)]),
+        'hd_rd_setup': (I, [P, ctypes.POINTER(RdParams), ctypes.POINTER(PrecondParams)]),
+        'hd_rd_step': (I, [P, P, P, P, ctypes.POINTER(RdInfo)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -159,6 +183,17 @@ def _ptr(a):
     if hasattr(a, 'data_ptr'):
         return ctypes.c_void_p(a.data_ptr())
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def rd_params(**kw):
+    """hd_rd_params with the library's defaults, overridden by keyword."""
+    p = RdParams()
+    load().hd_rd_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise ValueError(f'unknown radiation-diffusion parameter {k}')
+        setattr(p, k, v)
+    return p
 
 
 def precond_params(tau=1.0, theta=0.25, max_coarse=1024, max_levels=25, omega=2.0 / 3.0, learned=0):
@@ -539,6 +574,37 @@ class Context:
         self._check(self.lib.hd_get_amg_prolongator(self.h, level, ctypes.byref(nr), ctypes.byref(nc),
                                                     ctypes.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v)))
         return (nr.value, nc.value), rp, ci, v
+
+    # ---- radiation diffusion (Section 4.3) -----------------------------------
+    def apply_divergence(self, F, q):
+        """q = D F (n_u -> n_q, FP64 device tensors)."""
+        nu, nq = self.sizes()
+        self._dev(F, nu, HD_F64, 'F')
+        self._dev(q, nq, HD_F64, 'q')
+        return self._check(self.lib.hd_apply_divergence(self.h, _ptr(F), _ptr(q)))
+
+    def subcell_volumes(self):
+        """|K_j| of every L2 dof (FP64 device tensor of n_q)."""
+        _, nq = self.sizes()
+        out = self.torch.empty(nq, dtype=self.torch.float64, device=self.device)
+        self._check(self.lib.hd_subcell_volumes(self.h, _ptr(out)))
+        return out
+
+    def rd_setup(self, params, precond=None):
+        pp = ctypes.byref(precond) if precond is not None else None
+        return self._check(self.lib.hd_rd_setup(self.h, ctypes.byref(params), pp), allow=(HD_FALLBACK_USED,))
+
+    def rd_step(self, e, E, F):
+        """One SDIRK3 step in place; returns the step's RdInfo as a dict
+        (HD_NOT_CONVERGED is reported in it, not raised)."""
+        nu, nq = self.sizes()
+        self._dev(e, nq, HD_F64, 'e')
+        self._dev(E, nq, HD_F64, 'E')
+        self._dev(F, nu, HD_F64, 'F')
+        info = RdInfo()
+        self._check(self.lib.hd_rd_step(self.h, _ptr(e), _ptr(E), _ptr(F), ctypes.byref(info)),
+                    allow=(HD_NOT_CONVERGED,))
+        return info.as_dict()
 
     def apply_timing(self, reset=False):
         ms, cnt = ctypes.c_double(), ctypes.c_int64()

@@ -124,6 +124,21 @@ def darcy_layered(nx=60, ny=220, nz=85, p=2, seed=3):
                 c_mass=k, c_22=None, ess_sides=SIDES_ALL, tol=1e-8, cell=(hx, hy, hz))
 
 
+def raddiff_hotspot(n, seed=9, jitter=0.1, centre=(0.5, 0.5, 0.5), width=0.1, amp=1.0, rad_frac=0.5):
+    """Grey radiation-diffusion test state on the jittered unit cube n^3:
+    the mesh vertices, and per element the material temperature of a
+    Gaussian hot spot T_e = 1 + amp exp(-|x_e - centre|^2 / width^2) at the
+    element's vertex centroid x_e, and the radiation temperature rad_frac T_e
+    (radiation out of equilibrium with the material).  The energies per
+    sub-cell follow as e_j = rho C_v T_e |K_j| and E_j = a T_r^4 |K_j|."""
+    V = jittered_vertices(n, n, n, jitter, seed)
+    G = V.reshape(n + 1, n + 1, n + 1, 3)
+    xc = sum(G[dz:dz + n, dy:dy + n, dx:dx + n] for dz in (0, 1) for dy in (0, 1) for dx in (0, 1)) / 8.0
+    r2 = ((xc - np.asarray(centre)) ** 2).sum(axis=-1).reshape(-1)
+    T = 1.0 + amp * np.exp(-r2 / width ** 2)
+    return dict(vertices=V, T_mat=T, T_rad=rad_frac * T)
+
+
 def graddiv_rhs(n_u, n_q, seed=22):
     """b_u ~ U[-1, 1] on the RT dofs, b_q = 0."""
     return np.concatenate([uniform_vector(n_u, seed), np.zeros(n_q)])
