@@ -767,15 +767,22 @@ def run_raddiff(args, torch, hdivsp, inputs):
     e = Tm * vol
     E = Tr ** 4 * vol
     del Tm, Tr
+    e_init, E_init = e.clone(), E.clone()
     F = torch.zeros(nu, dtype=torch.float64, device=dev)
     energy0 = float(e.sum() + E.sum())
-    infos = []
-    for k in range(args.warmup + args.steps):
-        info = ctx.rd_step(e, E, F)
-        print(f"raddiff step {k}: {info['time_s']:.3f} s, outer {info['outer']}, "
-              f"{info['linear_iterations']} MINRES it in {info['linear_solves']} solves", file=sys.stderr, flush=True)
-        if k >= args.warmup:
-            infos.append(info)
+
+    def run_steps(tag):
+        infos = []
+        for k in range(args.warmup + args.steps):
+            info = ctx.rd_step(e, E, F)
+            print(f"raddiff {tag} step {k}: {info['time_s']:.3f} s, outer {info['outer']}, "
+                  f"{info['linear_iterations']} MINRES it in {info['linear_solves']} solves", file=sys.stderr,
+                  flush=True)
+            if k >= args.warmup:
+                infos.append(info)
+        return infos
+
+    infos = run_steps('PLAIN64')
     energy = float(e.sum() + E.sum())
     t_step = [i['time_s'] for i in infos]
     value = float(np.median(t_step))
@@ -792,6 +799,18 @@ def run_raddiff(args, torch, hdivsp, inputs):
     out["linear_solver_share"] = round(sum(i['linear_time_s'] for i in infos) / max(sum(t_step), 1e-30), 3)
     out["relative_energy_change"] = (energy - energy0) / energy0
     out["setup_s"] = round(t1 - t0, 3)
+    # the same steps with the Schur-block V-cycle in FP32 inside the FP64 MINRES
+    prm.lin_mode = hdivsp.HD_MODE_PREC32
+    ctx.rd_setup(prm)
+    e.copy_(e_init)
+    E.copy_(E_init)
+    F.zero_()
+    i32 = run_steps('PREC32')
+    nsolve32 = sum(i['linear_solves'] for i in i32)
+    out["prec32"] = {"time_per_step_s": round(float(np.median([i['time_s'] for i in i32])), 4),
+                     "minres_iterations_per_solve": round(sum(i['linear_iterations'] for i in i32) / max(nsolve32, 1), 1),
+                     "outer_per_stage": round(sum(sum(i['outer']) for i in i32) / (3 * len(i32)), 2),
+                     "relative_energy_change": (float(e.sum() + E.sum()) - energy0) / energy0}
     ctx.close()
     return out
 

@@ -47,7 +47,7 @@ struct RadDiffState {
     double* b = nullptr;       // [n_u + n_q] Darcy right-hand side
     double* sol = nullptr;     // [n_u + n_q] Darcy solution (F, q~), the warm start
     double* part = nullptr;    // [3][RD_BLOCKS] residual partial sums, then 3 totals
-    int* flags = nullptr;      // [0] largest Newton count, [1] Newton failure
+    int* flags = nullptr;      // [0] largest Newton count, [1] Newton failure, then RD_BLOCKS per-workgroup counts
 };
 
 namespace {
@@ -184,17 +184,20 @@ __device__ __forceinline__ double emission(double e, double vol, const Phys& ph)
 //   (e - e^) / (g dt) + c sigma (B(e) - E) = 0,
 //   (E - E^) / (g dt) + (D F)_j - c sigma (B(e) - E) = 0,
 // from (e^, E^), until both updates are below tol relative to the iterate.
-// Only e is kept (E comes from the Darcy solve).
+// Only e is kept (E comes from the Darcy solve).  Grid-stride over RD_BLOCKS
+// workgroups; each stores the largest iteration count it saw in nit[block]
+// (no atomics on one address), a failed dof sets flags[1].
 __global__ void newton_kernel(int64_t n, const double* __restrict__ eh, const double* __restrict__ Eh,
                               const double* __restrict__ df, const double* __restrict__ vol, Phys ph, double tol,
-                              int max_it, double* __restrict__ e_out, int* __restrict__ flags) {
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int its = 0;
-    if (j < n) {
+                              int max_it, double* __restrict__ e_out, int* __restrict__ nit, int* __restrict__ flags) {
+    int mx = 0;
+    bool bad = false;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         const double e0 = eh[j], E0 = Eh[j], d = df[j], v = vol[j];
         const double inv = 1.0 / ph.gdt, cs = ph.c_sigma;
         double e = e0, E = E0;
         bool conv = false;
+        int its = 0;
         while (its < max_it) {
             const double B = emission(e, v, ph);
             const double dB = 4.0 * B / e;
@@ -213,12 +216,27 @@ __global__ void newton_kernel(int64_t n, const double* __restrict__ eh, const do
             }
         }
         e_out[j] = e;
-        if (!conv || !(e > 0.0) || !isfinite(e)) atomicOr(flags + 1, 1);
+        mx = max(mx, its);
+        if (!conv || !(e > 0.0) || !isfinite(e)) bad = true;
     }
-    // the largest count of the wavefront, one atomic per wavefront
-    int m = its;
+    if (bad) atomicOr(flags + 1, 1);
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+    __shared__ int red[RD_T / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int w = 0; w < RD_T / 64; ++w) m = max(m, red[w]);
+        nit[blockIdx.x] = m;
+    }
+}
+
+// flags[0] = max(flags[0], max of the RD_BLOCKS per-workgroup Newton counts)
+__global__ void newton_finish_kernel(const int* __restrict__ nit, int* __restrict__ flags) {
+    int m = 0;
+    for (int b = threadIdx.x; b < RD_BLOCKS; b += 64) m = max(m, nit[b]);
     for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
-    if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(flags, m);
+    if (threadIdx.x == 0) flags[0] = max(flags[0], m);
 }
 
 // b = [0; E^ / (g dt) + c sigma B(e)]
@@ -327,7 +345,7 @@ int rd_setup(hd_ctx* c, const hd_rd_params& prm, const hd_precond_params* pp) {
     s->prm = prm;
     const int64_t n = 14 * nq + 2 * (nu + nq) + 4 * RD_BLOCKS;
     s->ws = dalloc<double>(n);
-    s->flags = dalloc<int>(4);
+    s->flags = dalloc<int>(4 + RD_BLOCKS);
     if (!s->ws || !s->flags) {
         dfree(s->ws);
         dfree(s->flags);
@@ -407,8 +425,10 @@ int rd_step(hd_ctx* c, double* e, double* E, double* F, hd_rd_info* info) {
         for (; k < P.max_outer;) {
             int rc = launch_divergence(c, s.sol, s.df);
             if (rc) return rc;
-            hipLaunchKernelGGL(newton_kernel, dim3(nblk(nq)), dim3(RD_T), 0, c->stream, nq, s.he[i], s.hE[i], s.df,
-                               s.vol, ph, P.newton_tol, P.newton_max_it, s.xe[i], s.flags);
+            hipLaunchKernelGGL(newton_kernel, dim3(RD_BLOCKS), dim3(RD_T), 0, c->stream, nq, s.he[i], s.hE[i], s.df,
+                               s.vol, ph, P.newton_tol, P.newton_max_it, s.xe[i], s.flags + 4, s.flags);
+            hipLaunchKernelGGL(newton_finish_kernel, dim3(1), dim3(64), 0, c->stream, (const int*)(s.flags + 4),
+                               s.flags);
             hipLaunchKernelGGL(darcy_rhs_kernel, dim3(nblk(nu + nq)), dim3(RD_T), 0, c->stream, nu, nq, s.xe[i],
                                s.hE[i], s.vol, ph, s.b);
             HD_HIP(c, hipGetLastError());
