@@ -565,10 +565,12 @@ int hd_rd_setup(hd_ctx* ctx, const hd_rd_params* params, const hd_precond_params
  * e, E: FP64 device arrays of n_q values; F: FP64 device array of n_u values
  * (zero on the boundary); all caller-owned, updated in place to t + dt.
  * Synchronises the stream.  info may be NULL.  Returns 0, HD_NOT_CONVERGED
- * (state still updated), HD_ERR_NONFINITE when a Newton solve fails to reach
- * a positive finite energy or a residual is not finite (state not
- * updated), HD_ERR_STATE before hd_rd_setup, HD_ERR_ARG for NULL or
- * aliased pointers. */
+ * when a stage's outer iteration or a Darcy solve reached its limit (state
+ * still updated), HD_ERR_NONFINITE when the Newton iteration of some dof
+ * does not meet newton_tol within newton_max_it or ends at a non-positive
+ * or non-finite energy, or a residual is not finite (state not updated),
+ * HD_ERR_STATE before hd_rd_setup, HD_ERR_ARG for NULL or aliased
+ * pointers. */
 int hd_rd_step(hd_ctx* ctx, double* e, double* E, double* F, hd_rd_info* info);
 
 /* ---- host-only entry (no device needed) -------------------------------- */

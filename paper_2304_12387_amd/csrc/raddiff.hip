@@ -461,17 +461,19 @@ int rd_step(hd_ctx* c, double* e, double* E, double* F, hd_rd_info* info) {
     }
     int fl[2];
     HD_HIP(c, hipMemcpyAsync(fl, s.flags, sizeof(fl), hipMemcpyDeviceToHost, c->stream));
+    HD_HIP(c, hipStreamSynchronize(c->stream));
+    inf.newton_max_it = fl[0];
+    if (fl[1]) {
+        // the caller's state stays as it was
+        if (info) *info = inf;
+        return set_err(c, HD_ERR_NONFINITE, "Newton did not converge to a positive energy in some dof");
+    }
     // the new state is the last stage (stiffly accurate)
     hipLaunchKernelGGL(copy_kernel, dim3(nblk(nq)), dim3(RD_T), 0, c->stream, s.xe[2], e, nq);
     hipLaunchKernelGGL(copy_kernel, dim3(nblk(nq)), dim3(RD_T), 0, c->stream, s.xE[2], E, nq);
     hipLaunchKernelGGL(copy_kernel, dim3(nblk(nu)), dim3(RD_T), 0, c->stream, s.sol, F, nu);
     HD_HIP(c, hipGetLastError());
     HD_HIP(c, hipStreamSynchronize(c->stream));
-    inf.newton_max_it = fl[0];
-    if (fl[1]) {
-        if (info) *info = inf;
-        return set_err(c, HD_ERR_NONFINITE, "Newton did not converge to a positive energy in some dof");
-    }
     inf.time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     inf.status = status;
     if (info) *info = inf;

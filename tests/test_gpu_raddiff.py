@@ -204,6 +204,17 @@ def test_errors():
     ctx.rd_setup(_params(hdivsp))
     rc = ctx.lib.hd_rd_step(ctx.h, hdivsp._ptr(x), hdivsp._ptr(x), hdivsp._ptr(F), None)
     assert rc == hdivsp.HD_ERR_ARG
+    # a Newton iteration held to one step below an unreachable tolerance
+    # fails in every dof: an error, and the caller's state is left as it was
+    ctx.rd_setup(_params(hdivsp, newton_max_it=1, newton_tol=1e-300))
+    vol = ctx.subcell_volumes()
+    e0 = (1.0 + vol / vol.max()) * vol
+    E0 = 0.3 * vol
+    ge, gE, gF = e0.clone(), E0.clone(), F.clone()
+    with pytest.raises(hdivsp.HdError) as ei:
+        ctx.rd_step(ge, gE, gF)
+    assert ei.value.code == hdivsp.HD_ERR_NONFINITE
+    assert torch.equal(ge, e0) and torch.equal(gE, E0) and torch.equal(gF, F)
     # a new mesh drops the time-stepping state
     ctx.setup_mesh(2, 2, 2, 1, inputs.box_vertices(2, 2, 2))
     nu, nq = ctx.sizes()
