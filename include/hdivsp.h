@@ -197,7 +197,8 @@ int hd_setup_mesh_unstructured(hd_ctx* ctx, int64_t nv, const double* vertices, 
  * boundary face is essential. */
 int hd_set_essential_dofs(hd_ctx* ctx, const uint8_t* mask);
 
-/* The element-to-dof map of an unstructured mesh: host array [ne][3 p^2 (p+1)]
+/* The element-to-dof map of an unstructured mesh (Section 3.2, Algorithm 1:
+ * the index arrays and orientation signs D is built from): host array [ne][3 p^2 (p+1)]
  * (local RT dofs component-major, each component's tensor index with its
  * first index fastest), entry g where the element's local dof equals global
  * dof g and ~g (bitwise complement, negative) where it equals -g.
@@ -340,7 +341,8 @@ int hd_minres_solve(hd_ctx* ctx, const hd_solve_params* params, int nrhs,
 int hd_gmres_solve(hd_ctx* ctx, double tol, int max_it, int restart, const double* b, double* x,
                    hd_solve_info* info);
 
-/* z = P^{-1} r for the block-triangular preconditioner of hd_gmres_solve:
+/* z = P^{-1} r for the block-triangular preconditioner of hd_gmres_solve
+ * (Section 2.2, the remark on block-triangular preconditioners):
  * z_q = -S^{-1} r_q (one V-cycle), z_u = (tau M~)^{-1} (r_u - D^T z_q) on free
  * RT dofs and z_u = r_u on essential ones.  FP64 device pointers of length
  * n_u + n_q, r != z.  HD_ERR_STATE before hd_build_precond. */
@@ -381,13 +383,15 @@ typedef struct hd_instance_desc {
     uint32_t ess_sides;
 } hd_instance_desc;
 
-/* Set up ninst instances of one problem type (host arrays are copied).
+/* Set up ninst instances of one problem type (host arrays are copied); each
+ * instance is the system of hd_setup_mesh / hd_setup_coeffs (Section 3).
  * Replaces a previous batch of the context; independent of hd_setup_mesh. */
 int hd_setup_batch(hd_ctx* ctx, int problem, int ninst, const hd_instance_desc* inst);
 /* offsets [ninst + 1]: start of each instance's block and the total length;
  * n_u [ninst]: its RT dof count (either may be NULL). */
 int hd_batch_sizes(hd_ctx* ctx, int64_t* offsets, int64_t* n_u);
-/* y = A x for every instance (device pointers of the total length, x != y). */
+/* y = A x for every instance (eq. transformed-saddle-point per instance;
+ * device pointers of the total length, x != y). */
 int hd_batch_apply(hd_ctx* ctx, int prec, const void* x, void* y);
 /* Autotuner: times the batched apply over the launch variants (mode 0: one
  * persistent launch for all degrees; 1: one persistent launch per degree;
@@ -398,9 +402,10 @@ int hd_batch_tune(hd_ctx* ctx, int prec, int* mode, int* grid, int* tile_groups,
 /* Set the launch configuration explicitly (mode 0, 1 or 2, grid >= 1
  * workgroups, tile_groups >= 1; mode 2 uses neither). */
 int hd_batch_set_launch(hd_ctx* ctx, int mode, int grid, int tile_groups);
-/* Each instance's diagonal, S~ and AMG (learned must be 0). */
+/* Each instance's diagonal, S~ and AMG (Section 2.3, eq. approx-schur;
+ * learned must be 0). */
 int hd_batch_build_precond(hd_ctx* ctx, const hd_precond_params* params);
-/* One MINRES recurrence per instance, in any HD_MODE_*.  HD_MODE_MIXED
+/* One MINRES recurrence per instance (Section 2.2), in any HD_MODE_*.  HD_MODE_MIXED
  * refines every instance on its own FP64 residual around one batched FP32
  * MINRES per refinement step (instances already converged get a zero
  * right-hand side); info: host array of ninst entries (may be NULL). */
@@ -464,14 +469,18 @@ int hd_set_diag_scalings(hd_ctx* ctx, const double* theta);
 
 /* ---- inspection (parity checks) ---------------------------------------- */
 
-/* Copy diag(M) (n_u) and diag(W) (unweighted, n_q) into device buffers. */
+/* Copy diag(M) (n_u; M~ of Section 2.3, 1 on essential dofs) and diag(W)
+ * (unweighted, n_q; the diagonal behind C~ of eq. approx-schur) into device
+ * buffers. */
 int hd_get_diagonals(hd_ctx* ctx, double* m_diag, double* w_diag);
 
-/* S~ in CSR: query nnz with rowptr == NULL, then pass host buffers of n_q+1,
+/* S~ (eq. approx-schur-entries) in CSR: query nnz with rowptr == NULL, then pass host buffers of n_q+1,
  * nnz, nnz entries. */
 int hd_get_schur(hd_ctx* ctx, int64_t* nnz, int32_t* rowptr, int32_t* col, double* val);
 
-/* Number of AMG levels and the size/nnz of level `level` (A), and, when the
+/* The AMG hierarchy of S~ (Section 3.2, Schur complement preconditioning; a
+ * smoothed-aggregation hierarchy in place of the paper's BoomerAMG).
+ * Number of AMG levels and the size/nnz of level `level` (A), and, when the
  * buffers are non-NULL, its CSR arrays (host).  For level < nlevels-1 the
  * prolongator P (rows of level, cols of level+1) is returned by
  * hd_get_amg_prolongator. */
@@ -481,7 +490,8 @@ int hd_get_amg_level(hd_ctx* ctx, int level, int64_t* n, int64_t* nnz,
 int hd_get_amg_prolongator(hd_ctx* ctx, int level, int64_t* nrows, int64_t* ncols, int64_t* nnz,
                            int32_t* rowptr, int32_t* col, double* val);
 
-/* Average device duration (ms) of the block-apply kernel over the calls since
+/* Measurement helper (no passage of the method): average device duration
+ * (ms) of the block-apply kernel over the calls since
  * the last reset, measured with events on the context stream (reset = 1
  * clears the accumulators). */
 int hd_apply_timing(hd_ctx* ctx, int reset, double* avg_ms, int64_t* count);
@@ -575,8 +585,9 @@ int hd_rd_step(hd_ctx* ctx, double* e, double* E, double* F, hd_rd_info* info);
 
 /* ---- host-only entry (no device needed) -------------------------------- */
 
-/* Build the aggregation AMG hierarchy of a host CSR matrix with the
- * library's host code and return level sizes; the hierarchy is kept in a
+/* Build the aggregation AMG hierarchy (the set-up of Section 3.2's Schur
+ * complement preconditioner, as the device builds it) of a host CSR matrix
+ * with the library's host code and return level sizes; the hierarchy is kept in a
  * host handle for hd_host_amg_level / hd_host_amg_free.  For checks on
  * machines without a GPU. */
 typedef struct hd_host_amg hd_host_amg;
