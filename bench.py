@@ -730,6 +730,26 @@ def run_batch32_solve(args, torch, hdivsp, inputs):
                      "status": [f['status'] for f in infos]}
         print(f"batch32 {name}: {res[name]['time_to_1e-8_s']} s", file=sys.stderr, flush=True)
     te = time.perf_counter()
+    # the same instances solved one after the other (PLAIN64, each in its own
+    # context; one untimed solve first)
+    solo_t, solo_it = 0.0, []
+    pm = hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_PLAIN64, stop_true=1)
+    for i, d in enumerate(inst):
+        s = hdivsp.Context(0, stream)
+        s.setup_mesh(d['nx'], d['ny'], d['nz'], d['p'], d['vertices'])
+        s.setup_coeffs(0, d['c_mass'], d['c_22'], d['ess_sides'])
+        s.build_precond(hdivsp.precond_params())
+        bi = b[int(off[i]):int(off[i + 1])].contiguous()
+        xi = torch.zeros_like(bi)
+        for rep in range(2):
+            xi.zero_()
+            torch.cuda.synchronize()
+            info = s.minres_solve(bi, xi, pm)
+        solo_t += info['time_s']
+        solo_it.append(info['iterations'])
+        s.close()
+    res["solo_plain_sum"] = {"time_to_1e-8_s": round(solo_t, 4), "iterations": solo_it}
+    print(f"batch32 solo sum: {round(solo_t, 4)} s", file=sys.stderr, flush=True)
     out = base_line("time-to-1e-8 (s) of one batched MINRES over 32 grad-div instances (PLAIN64)",
                     res['plain']['time_to_1e-8_s'], "s", args, round((te - ts) * 1e3, 3),
                     {"workload": "batch_32_graddiv_instances_n8-40_p1-6", "total_dofs": N,
