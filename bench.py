@@ -356,6 +356,18 @@ def run_batch32(args, torch, hdivsp, inputs):
         y = torch.empty_like(x)
         ms = time_applies(torch, stream, lambda: ctx.batch_apply(x, y, prec=prec), max(args.steps, 3))
         res[name] = {"gdofs": round(N / (ms * 1e-3) / 1e9, 3), "ms_per_apply": round(ms, 4), "tuned": tuned}
+        # the best persistent work-queue launch (modes 0 and 1) beside the tuned one
+        best = None
+        for mode in (0, 1):
+            for grid in (1024, 2048, 4096):
+                for tg in (1, 2):
+                    ctx.batch_set_launch(mode, grid, tg)
+                    msp = time_applies(torch, stream, lambda: ctx.batch_apply(x, y, prec=prec), 3)
+                    if best is None or msp < best[0]:
+                        best = (msp, mode, grid, tg)
+        res[name]["best_persistent"] = {"gdofs": round(N / (best[0] * 1e-3) / 1e9, 3), "mode": best[1],
+                                        "grid": best[2], "tile_groups": best[3]}
+        ctx.batch_set_launch(tuned['mode'], tuned['grid'], tuned['tile_groups'])
         del x, y
     te = time.perf_counter()
     out = base_line("GDOF/s of the batched block apply (32 instances, autotuned launch)",
