@@ -107,7 +107,11 @@ typedef struct hd_solve_params {
     int max_it;          /* max MINRES iterations (inner, per refinement); default 10000 */
     int mode;            /* HD_MODE_* */
     int use_x0;          /* 1: x holds the initial guess; 0: start from zero */
-    double inner_tol;    /* HD_MODE_MIXED: inner FP32 tolerance; default 1e-5 */
+    double inner_tol;    /* HD_MODE_MIXED: inner FP32 tolerance; default 1e-5.
+                            Each refinement's inner MINRES stops at
+                            max(inner_tol, 0.1 tol / rho) relative to its start,
+                            rho the current true relative residual, so that the
+                            last refinement does not solve past the target */
     int max_outer;       /* HD_MODE_MIXED: max refinement steps; default 20 */
     int check_every;     /* iterations between host polls of the flag; default 8 */
     int stop_true;       /* HD_MODE_PLAIN64, HD_MODE_PREC32: 0 stops when |eta| <= tol |eta_0| (the

@@ -183,6 +183,9 @@ __global__ void k_start(MinresState* st, const double* __restrict__ pu, int64_t 
     st[blockIdx.x] = s;
 }
 
+// the stop tolerance of one recurrence (set after k_start)
+__global__ void k_set_tol(MinresState* st, double tol) { st->tol = tol; }
+
 // v_old <- q - cv1 v - cv2 v_old  (= v_{j+1});  z_u = mdinv * v_{j+1,u}
 // (blockIdx.y = right-hand side)
 template <typename T>
@@ -486,7 +489,8 @@ struct PeriodGraph {
 
 template <typename T, typename B, typename PT = T>
 int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, int maxit, int check_every,
-                std::vector<hd_solve_info>& out, double true_tol = 0.0, bool use_graph = false) {
+                std::vector<hd_solve_info>& out, double true_tol = 0.0, bool use_graph = false,
+                const double* tols = nullptr) {
     const int prec = std::is_same<T, double>::value ? HD_F64 : HD_F32;
     const int64_t N = wk.N, nu = c->n_u;
     const int nr = wk.nrhs;
@@ -517,6 +521,9 @@ int minres_core(hd_ctx* c, Work& wk, const B* b, T* x, bool use_x0, double tol, 
     }
     hipLaunchKernelGGL(k_start, dim3(nr), dim3(1024), 0, c->stream, wk.st, wk.pu, (int64_t)red_grid(nu),
                        (int64_t)RED_BLOCKS, wk.pq, nqp, wk.nq_part, tol);
+    // per right-hand side tolerances (the refinement's inner solves)
+    if (tols)
+        for (int r = 0; r < nr; ++r) hipLaunchKernelGGL(k_set_tol, dim3(1), dim3(1), 0, c->stream, wk.st + r, tols[r]);
     HD_HIP(c, hipGetLastError());
     const int* stop = &wk.st->stop;
     int launched = 0, retargets = 0;
@@ -686,7 +693,8 @@ int batch_true_residual(hd_ctx* c, BatchWork& W, const double* b, const double* 
 // the |eta| stop, require the true FP64 residual as in the single solve.
 template <typename T, typename Bv, typename PT>
 int batch_minres_core(hd_ctx* c, BatchWork& W, const Bv* b, T* x, bool use_x0, double tol, int maxit,
-                      int check_every, double true_tol, std::vector<hd_solve_info>& out, bool use_graph) {
+                      int check_every, double true_tol, std::vector<hd_solve_info>& out, bool use_graph,
+                      const double* tols = nullptr) {
     constexpr bool F64 = std::is_same<T, double>::value;
     const int prec = F64 ? HD_F64 : HD_F32;
     const BatchState& B = *c->batch;
@@ -711,7 +719,7 @@ int batch_minres_core(hd_ctx* c, BatchWork& W, const Bv* b, T* x, bool use_x0, d
             return rc;
         hipLaunchKernelGGL(k_start, dim3(1), dim3(1024), 0, c->stream, W.st + i, W.pu + (int64_t)i * RED_BLOCKS,
                            (int64_t)red_grid(s->n_u), (int64_t)RED_BLOCKS, W.pq + W.pq_off[i],
-                           schur_parts<T, PT>(s), W.nq_part[i], tol);
+                           schur_parts<T, PT>(s), W.nq_part[i], tols ? tols[i] : tol);
     }
     HD_HIP(c, hipGetLastError());
     int launched = 0, retargets = 0;
@@ -921,11 +929,18 @@ int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* 
                 }
             }
             if (all || outer >= prm.max_outer) break;
+            // each inner solve reduces its residual by inner_tol, but no
+            // further than the target needs (with a factor 10 of margin for
+            // the preconditioned norm it stops on)
+            std::vector<double> itol(nrhs, prm.inner_tol);
+            for (int k = 0; k < nrhs; ++k)
+                if (status[k] == HD_NOT_CONVERGED)
+                    itol[k] = std::max(prm.inner_tol, 0.1 * prm.tol / rel_of(w64.nrm_host, k));
             HD_HIP(c, hipMemcpyAsync(w64.nrm, w64.nrm_host, 2 * nrhs * sizeof(double), hipMemcpyHostToDevice,
                                      c->stream));
             hipLaunchKernelGGL(k_to32, dim3(nblk(w64.N), nrhs), dim3(BS), 0, c->stream, w64.N, r, w64.nrm, r32);
             rc = minres_core<float, float>(c, w32, r32, d32, false, prm.inner_tol, prm.max_it, check, inner, 0.0,
-                                           prm.use_graph != 0);
+                                           prm.use_graph != 0, itol.data());
             if (rc) break;
             ++outer;
             bool brk = false;
@@ -1047,6 +1062,10 @@ int batch_mixed(hd_ctx* c, BatchWork& W, const hd_solve_params& prm, const doubl
             }
         }
         if (all || outer >= prm.max_outer) break;
+        // per-instance inner tolerances, as in the single solve
+        std::vector<double> itol(ni, prm.inner_tol);
+        for (int i = 0; i < ni; ++i)
+            if (status[i] == HD_NOT_CONVERGED) itol[i] = std::max(prm.inner_tol, 0.1 * prm.tol / rel_of(W.nrm_host, i));
         HD_HIP(c, hipMemcpyAsync(W.nrm, W.nrm_host, 2 * ni * sizeof(double), hipMemcpyHostToDevice, c->stream));
         for (int i = 0; i < ni; ++i) {
             const int64_t o = B.off[i], N = B.off[i + 1] - B.off[i];
@@ -1054,7 +1073,7 @@ int batch_mixed(hd_ctx* c, BatchWork& W, const hd_solve_params& prm, const doubl
                                (const double*)W.nrm + 2 * i, r32.p + o);
         }
         if ((rc = batch_minres_core<float, float, float>(c, W32, r32.p, d32.p, false, prm.inner_tol, prm.max_it,
-                                                          check, 0.0, inner, prm.use_graph != 0)))
+                                                          check, 0.0, inner, prm.use_graph != 0, itol.data())))
             return rc;
         ++outer;
         bool brk = false;
