@@ -10,7 +10,7 @@ every Schur preconditioner application).
     B = diag(tau M~, S^)    M~ = diag(M)    S~ = C~ + D M~^{-1} D^T
     S^{-1} = one V-cycle of an aggregation AMG on S~.
 
-The paper uses BoomerAMG for S^{-1}; this build replaces it by a smoothed
+The paper uses BoomerAMG for S^{-1}; here it is replaced by a smoothed
 aggregation V(1,1)-cycle whose every choice is fixed here (and reproduced by
 the GPU library), so that the two can be compared number by number:
 
