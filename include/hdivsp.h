@@ -538,7 +538,10 @@ typedef struct hd_rd_params {
                                      default 1e-8 */
     int lin_max_it;               /* default 10000 */
     int lin_mode;                 /* HD_MODE_* of the Darcy solves; default
-                                     HD_MODE_PLAIN64 */
+                                     HD_MODE_PLAIN64.  With HD_MODE_MIXED a
+                                     solve stops when its true FP64 residual
+                                     has fallen by lin_tol from that of its
+                                     initial guess */
 } hd_rd_params;
 
 typedef struct hd_rd_info {
@@ -561,7 +564,7 @@ int hd_rd_default_params(hd_rd_params* p);
  * (HD_DARCY, c_mass = 3 sigma / c, gamma = kappa = 1 / (g dt) + c sigma with
  * g the SDIRK diagonal, every boundary RT dof essential: F . n = 0), the
  * preconditioner (precond may be NULL for the defaults of hd_build_precond),
- * the sub-cell volumes and the work space (14 n_q + 2 (n_u + n_q) doubles).
+ * the sub-cell volumes and the work space (14 n_q + 3 (n_u + n_q) doubles).
  * Replaces any coefficients and preconditioner the context held.  Errors:
  * HD_ERR_STATE before a mesh, HD_ERR_ARG for a parameter out of range, and
  * those of hd_setup_coeffs and hd_build_precond. */

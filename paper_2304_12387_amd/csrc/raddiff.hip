@@ -46,6 +46,7 @@ struct RadDiffState {
     double* df = nullptr;      // [n_q] D F
     double* b = nullptr;       // [n_u + n_q] Darcy right-hand side
     double* sol = nullptr;     // [n_u + n_q] Darcy solution (F, q~), the warm start
+    double* q = nullptr;       // [n_u + n_q] A sol (the warm start's residual, HD_MODE_MIXED)
     double* part = nullptr;    // [3][RD_BLOCKS] residual partial sums, then 3 totals
     int* flags = nullptr;      // [0] largest Newton count, [1] Newton failure, then RD_BLOCKS per-workgroup counts
 };
@@ -287,6 +288,32 @@ __global__ void resid_kernel(int64_t n, const double* __restrict__ e, const doub
     }
 }
 
+// Per-workgroup partial sums of ||b - q||^2 and ||b||^2 (slots 0 and 1 of
+// the residual layout; slot 2 zeroed)
+__global__ void res0_kernel(int64_t n, const double* __restrict__ b, const double* __restrict__ q,
+                            double* __restrict__ part) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const double d = b[j] - q[j];
+        s0 += d * d;
+        s1 += b[j] * b[j];
+    }
+    __shared__ double red[2][RD_T / 64];
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = s0;
+        red[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double t = 0.0;
+        for (int w = 0; w < RD_T / 64; ++w) t += red[threadIdx.x][w];
+        part[threadIdx.x * RD_BLOCKS + blockIdx.x] = t;
+    }
+    if (threadIdx.x == 2) part[2 * RD_BLOCKS + blockIdx.x] = 0.0;
+}
+
 // the three totals, each over the RD_BLOCKS partials in a fixed order
 __global__ void resid_finish_kernel(double* __restrict__ part) {
     const int k = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -343,7 +370,7 @@ int rd_setup(hd_ctx* c, const hd_rd_params& prm, const hd_precond_params* pp) {
     RadDiffState* s = new (std::nothrow) RadDiffState;
     if (!s) return set_err(c, HD_ERR_OOM, "radiation-diffusion state");
     s->prm = prm;
-    const int64_t n = 14 * nq + 2 * (nu + nq) + 4 * RD_BLOCKS;
+    const int64_t n = 14 * nq + 3 * (nu + nq) + 4 * RD_BLOCKS;
     s->ws = dalloc<double>(n);
     s->flags = dalloc<int>(4 + RD_BLOCKS);
     if (!s->ws || !s->flags) {
@@ -370,6 +397,8 @@ int rd_setup(hd_ctx* c, const hd_rd_params& prm, const hd_precond_params* pp) {
     s->b = p;
     p += nu + nq;
     s->sol = p;
+    p += nu + nq;
+    s->q = p;
     p += nu + nq;
     s->part = p;
     c->rd = s;
@@ -432,6 +461,20 @@ int rd_step(hd_ctx* c, double* e, double* E, double* F, hd_rd_info* info) {
             hipLaunchKernelGGL(darcy_rhs_kernel, dim3(nblk(nu + nq)), dim3(RD_T), 0, c->stream, nu, nq, s.xe[i],
                                s.hE[i], s.vol, ph, s.b);
             HD_HIP(c, hipGetLastError());
+            if (P.lin_mode == HD_MODE_MIXED) {
+                // the mixed solve stops on the true residual relative to
+                // ||b||: ask for lin_tol times the warm start's own
+                if ((rc = launch_apply(c, HD_F64, 1, s.sol, s.q, nullptr, 0, nullptr, 0, ESS_IDENTITY, nullptr, 0)))
+                    return rc;
+                hipLaunchKernelGGL(res0_kernel, dim3(RD_BLOCKS), dim3(RD_T), 0, c->stream, nu + nq, s.b, s.q, s.part);
+                hipLaunchKernelGGL(resid_finish_kernel, dim3(1), dim3(256), 0, c->stream, s.part);
+                HD_HIP(c, hipGetLastError());
+                double h0[2];
+                HD_HIP(c, hipMemcpyAsync(h0, s.part + 3 * RD_BLOCKS, sizeof(h0), hipMemcpyDeviceToHost, c->stream));
+                HD_HIP(c, hipStreamSynchronize(c->stream));
+                const double rel0 = h0[1] > 0.0 ? std::sqrt(h0[0] / h0[1]) : 0.0;
+                lp.tol = std::max(P.lin_tol * rel0, 1e-13);   // above the FP64 round-off of r
+            }
             hd_solve_info si;
             rc = minres_solve(c, lp, 1, s.b, s.sol, &si);
             if (rc < 0) return rc;

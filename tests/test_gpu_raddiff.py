@@ -83,14 +83,19 @@ def test_divergence_unstructured(p):
     ctx.close()
 
 
-STEP_CASES = [(2, 1, 1.0, 1.0, 0.02), (3, 2, 1.0, 1.0, 0.01), (2, 3, 1.0, 10.0, 0.005), (2, 4, 2.0, 3.0, 0.01)]
+STEP_CASES = [(2, 1, 1.0, 1.0, 0.02, 0), (3, 2, 1.0, 1.0, 0.01, 0), (2, 3, 1.0, 10.0, 0.005, 0),
+              (2, 4, 2.0, 3.0, 0.01, 0), (3, 2, 1.0, 2.0, 0.01, 2), (3, 3, 1.0, 2.0, 0.01, 1)]
 
 
-@pytest.mark.parametrize("case", STEP_CASES, ids=['n%d_p%d_c%g_s%g' % c[:4] for c in STEP_CASES])
+@pytest.mark.parametrize("case", STEP_CASES, ids=['n%d_p%d_c%g_s%g' % c[:4] + ['', '_mixed', '_prec32'][c[5]]
+                                                 for c in STEP_CASES])
 def test_step_matches_oracle(case):
+    """lin_mode 2 = HD_MODE_PREC32 (the FP32 Schur V-cycle inside the FP64
+    MINRES) and 1 = HD_MODE_MIXED (FP64 refinement around FP32 MINRES) reach
+    the same states as the FP64 solves."""
     torch = torch_cuda()
     from paper_2304_12387_amd import hdivsp
-    n, p, c, sigma, dt = case
+    n, p, c, sigma, dt, mode = case
     print('case rd step', case, flush=True)
     V = inputs.jittered_vertices(n, n, n, 0.15, 3)
     rd = raddiff.RadDiff(n, n, n, p, V, rho=1.3, cv=0.8, c=c, a=0.7, sigma=sigma)
@@ -98,7 +103,7 @@ def test_step_matches_oracle(case):
     F = np.zeros(rd.mesh.n_u)
     ctx = hdivsp.Context(0)
     ctx.setup_mesh(n, n, n, p, V)
-    ctx.rd_setup(_params(hdivsp, rho=1.3, cv=0.8, c=c, a=0.7, sigma=sigma, dt=dt))
+    ctx.rd_setup(_params(hdivsp, rho=1.3, cv=0.8, c=c, a=0.7, sigma=sigma, dt=dt, lin_mode=mode))
     ge, gE, gF = to_dev(e), to_dev(E), to_dev(F)
     for step in range(2):
         e, E, F, outers = rd.step(e, E, F, dt, tol_outer=1e-12)
