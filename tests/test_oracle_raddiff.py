@@ -8,7 +8,9 @@
   divergence of F integrates to zero);
 * radiative equilibrium (E = a T^4, uniform) is a steady state on a box mesh
   (where the constants are in the L2 space);
-* the sub-cell volumes of a unit cube element sum to 1;
+* the sub-cell volumes of every element add up to its volume (a 3-point
+  Gauss rule over the whole element, exact for the trilinear map), and on a
+  parallelepiped each is |det J| times its Gauss-Lobatto sub-intervals;
 * the dof-wise Newton solve leaves zero residuals."""
 import numpy as np
 import pytest
@@ -94,3 +96,54 @@ def test_newton_leaves_zero_residuals():
     R2 = (E - Eh) / gdt + dF - rd.c * rd.sigma * (B - E)
     assert np.abs(R1).max() <= 1e-9 * (np.abs(e).max() / gdt) and np.abs(R2).max() <= 1e-9 * (np.abs(E).max() / gdt)
     assert its < 20
+
+
+def _hex_volume_gauss3(X):
+    """Volume of a trilinear hexahedron (vertices X[v], v = dx + 2 dy + 4 dz)
+    by 3 x 3 x 3 Gauss-Legendre points over the whole reference cube: det J
+    has degree 2 in each variable, so this rule is exact.  Written here from
+    the trilinear map, independently of the oracle's sub-cell rule."""
+    g = np.array([0.5 - 0.5 * np.sqrt(0.6), 0.5, 0.5 + 0.5 * np.sqrt(0.6)])
+    w = np.array([5.0, 8.0, 5.0]) / 18.0
+    vol = 0.0
+    for i in range(3):
+        for j in range(3):
+            for k in range(3):
+                xi = (g[i], g[j], g[k])
+                J = np.zeros((3, 3))
+                for v in range(8):
+                    b = ((v & 1), (v >> 1) & 1, (v >> 2) & 1)
+                    f = [xi[d] if b[d] else 1.0 - xi[d] for d in range(3)]
+                    s = [1.0 if b[d] else -1.0 for d in range(3)]
+                    J[:, 0] += X[v] * s[0] * f[1] * f[2]
+                    J[:, 1] += X[v] * f[0] * s[1] * f[2]
+                    J[:, 2] += X[v] * f[0] * f[1] * s[2]
+                vol += w[i] * w[j] * w[k] * np.linalg.det(J)
+    return vol
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_subcell_volumes_partition_each_element(p):
+    """The sub-cell volumes of every element add up to its volume (exact
+    rule above), on a distorted mesh; on an affine (parallelepiped) element
+    each sub-cell volume is |det J| times the product of its Gauss-Lobatto
+    sub-intervals."""
+    n = 2
+    V = inputs.jittered_vertices(n, n, n, 0.2, 17)
+    rd = raddiff.RadDiff(n, n, n, p, V)
+    G = V.reshape(n + 1, n + 1, n + 1, 3)
+    vol = rd.vol.reshape(n ** 3, p ** 3)
+    for e in range(n ** 3):
+        ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+        X = np.array([G[ez + (v >> 2), ey + ((v >> 1) & 1), ex + (v & 1)] for v in range(8)])
+        assert abs(vol[e].sum() - _hex_volume_gauss3(X)) <= 1e-13 * abs(vol[e].sum())
+        assert np.all(vol[e] > 0)
+    # a single sheared parallelepiped: x -> A x + c
+    A = np.array([[1.2, 0.3, 0.1], [0.0, 0.8, 0.25], [0.1, 0.0, 1.5]])
+    ref = np.array([[(v & 1), (v >> 1) & 1, (v >> 2) & 1] for v in range(8)], dtype=float)
+    Vp = (ref @ A.T + np.array([0.3, -0.2, 1.0])).reshape(2, 2, 2, 3)
+    rp = raddiff.RadDiff(1, 1, 1, p, Vp)
+    from oracle.basis import gauss_lobatto_points
+    h = np.diff(gauss_lobatto_points(p))
+    expect = abs(np.linalg.det(A)) * np.einsum('c,b,a->cba', h, h, h).reshape(-1)
+    assert np.abs(rp.vol - expect).max() <= 1e-14 * expect.max()
