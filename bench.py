@@ -548,6 +548,18 @@ def run_batch_solve8(args, torch, hdivsp, inputs):
                      "worst_true_rel_res": max(f['true_rel_res'] for f in runs[-1]),
                      "status": [f['status'] for f in runs[-1]]}
     te = time.perf_counter()
+    # the same PLAIN64 solve with every instance's V-cycle launched on its own
+    ctx.batch_set_vcycle(0)
+    tso = []
+    for rep in range(args.warmup + args.steps):
+        x.zero_()
+        torch.cuda.synchronize()
+        infos = ctx.batch_minres_solve(b, x, modes[0][1])
+        if rep >= args.warmup:
+            tso.append(infos[0]['time_s'])
+    ctx.batch_set_vcycle(1)
+    res["plain_own_vcycles"] = {"time_to_1e-8_s": round(float(np.median(tso)), 4),
+                                "iterations": [f['iterations'] for f in infos]}
     ctx.close()
     solo_t, solo_it = 0.0, []
     pm = hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_PLAIN64, stop_true=1)
@@ -742,6 +754,13 @@ def run_batch32_solve(args, torch, hdivsp, inputs):
                      "status": [f['status'] for f in infos]}
         print(f"batch32 {name}: {res[name]['time_to_1e-8_s']} s", file=sys.stderr, flush=True)
     te = time.perf_counter()
+    ctx.batch_set_vcycle(0)
+    x.zero_()
+    torch.cuda.synchronize()
+    infos = ctx.batch_minres_solve(b, x, hdivsp.solve_params(tol=1e-8, mode=hdivsp.HD_MODE_PLAIN64, stop_true=1))
+    ctx.batch_set_vcycle(1)
+    res["plain_own_vcycles"] = {"time_to_1e-8_s": round(infos[0]['time_s'], 4)}
+    print(f"batch32 plain, own V-cycles: {res['plain_own_vcycles']['time_to_1e-8_s']} s", file=sys.stderr, flush=True)
     # the same instances solved one after the other (PLAIN64, each in its own
     # context; one untimed solve first)
     solo_t, solo_it = 0.0, []

@@ -407,8 +407,16 @@ int hd_batch_tune(hd_ctx* ctx, int prec, int* mode, int* grid, int* tile_groups,
  * workgroups, tile_groups >= 1; mode 2 uses neither). */
 int hd_batch_set_launch(hd_ctx* ctx, int mode, int grid, int tile_groups);
 /* Each instance's diagonal, S~ and AMG (Section 2.3, eq. approx-schur;
- * learned must be 0). */
+ * learned must be 0).  The batched MINRES runs the levels >= 1 of the
+ * V-cycles (Section 3: one scalar AMG V-cycle per iteration and instance) of
+ * all instances whose hierarchy has at least two levels and a non-singular
+ * S~ in shared launches, one per operation and level, with the same results
+ * as the instances' own cycles; the other instances keep their own. */
 int hd_batch_build_precond(hd_ctx* ctx, const hd_precond_params* params);
+/* shared = 1 (the default): the shared V-cycle launches above where they
+ * apply; 0: every instance's V-cycle launched on its own.  HD_ERR_STATE
+ * before hd_setup_batch, HD_ERR_ARG for another value. */
+int hd_batch_set_vcycle(hd_ctx* ctx, int shared);
 /* One MINRES recurrence per instance (Section 2.2), in any HD_MODE_*.  HD_MODE_MIXED
  * refines every instance on its own FP64 residual around one batched FP32
  * MINRES per refinement step (instances already converged get a zero

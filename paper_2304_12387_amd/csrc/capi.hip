@@ -155,6 +155,7 @@ hd_precond_params default_precond();
 
 void hd::batch_free(hd_ctx* c) {
     if (!c->batch) return;
+    batch_union_free(c);
     BatchState* B = c->batch;
     for (hd_ctx* s : B->inst) hd_destroy(s);
     dfree(B->d_inst64);
@@ -1067,7 +1068,17 @@ int hd_batch_build_precond(hd_ctx* c, const hd_precond_params* params) {
         const int rc = hd_build_precond(B.inst[i], params);
         if (rc) return set_err(c, rc, "instance " + std::to_string(i) + ": " + B.inst[i]->err);
     }
+    const int rc = batch_union_build(c);
+    if (rc) return rc;
     B.have_prec = true;
+    return HD_OK;
+}
+
+int hd_batch_set_vcycle(hd_ctx* c, int shared) {
+    if (!c) return HD_ERR_ARG;
+    if (!c->batch) return set_err(c, HD_ERR_STATE, "hd_setup_batch first");
+    if (shared != 0 && shared != 1) return set_err(c, HD_ERR_ARG, "shared must be 0 or 1");
+    c->batch->vcycle_shared = shared;
     return HD_OK;
 }
 

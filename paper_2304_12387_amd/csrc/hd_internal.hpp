@@ -126,6 +126,32 @@ struct BatchTile {
     unsigned grp0, ngrp;
 };
 
+// One (instance, operation) of a level in the batch's shared V-cycle
+// launches: the operation's CSR matrix, its vectors and its first workgroup.
+template <typename T>
+struct UDesc {
+    const int32_t* rp;
+    const int32_t* ci;
+    const T* mv;
+    const T* dinv;       // post: this level's; restriction: the next level's (with out2)
+    const double* cinv;  // coarse solve: the dense inverse
+    const T* in;         // the vector the matrix multiplies (coarse: b)
+    const T* b;          // pre- and post-smoothing: the level's right-hand side
+    T* out;
+    T* out2;             // restriction: the next level's x = dinv b, or null
+    int64_t n;           // rows
+    int g;               // lanes per row
+    int inst;
+    unsigned blk0;       // first workgroup of this descriptor
+};
+template <typename T>
+struct UnionLaunch {
+    int op = 0;
+    int nd = 0;
+    unsigned nblocks = 0;
+    UDesc<T>* d = nullptr;
+};
+
 struct BatchState {
     std::vector<hd_ctx*> inst;                // one context per instance (shares device and stream)
     std::vector<int64_t> off;                 // ninst + 1 offsets of the concatenated vector
@@ -143,6 +169,13 @@ struct BatchState {
     int grid = 0;                             // persistent grid (workgroups)
     int tile_groups = 1;                      // element groups per tile
     bool have_prec = false;
+    // V-cycle levels >= 1 of all instances in shared launches (built with
+    // the preconditioners when every instance qualifies)
+    std::vector<UnionLaunch<double>> un64;
+    std::vector<UnionLaunch<float>> un32;
+    std::vector<char> in_union;               // per instance: takes part in them
+    bool union_ok = false;
+    int vcycle_shared = 1;                    // 0: each instance's own V-cycle launches
 };
 
 struct RadDiffState;
@@ -354,6 +387,13 @@ void batch_free(hd_ctx* c);
 // minres.hip
 // nrhs right-hand sides stored one after the other; info: nrhs entries
 int minres_solve(hd_ctx* c, const hd_solve_params& prm, int nrhs, const double* b, double* x, hd_solve_info* info);
+
+// precond.hip: the batch's shared V-cycle launches
+int batch_union_build(hd_ctx* c);
+void batch_union_free(hd_ctx* c);
+template <typename T>
+int batch_union_cycle(hd_ctx* c, const T* const* vq, T* const* zq, double* const* part, const int* stop,
+                      int stop_stride);
 
 // raddiff.hip: the radiation-diffusion time step and its helpers
 int launch_divergence(hd_ctx* c, const double* F, double* q);

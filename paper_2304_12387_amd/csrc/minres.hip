@@ -654,7 +654,13 @@ struct BatchWork {
     MinresState* st_host = nullptr;
     double* nrm_host = nullptr;
     Work schur32;   // FP32 Schur buffers (sized for the largest instance)
+    // FP32 V-cycle input and output of every instance (the shared V-cycle
+    // launches with an FP64 recurrence), at q32_off
+    float *t32all = nullptr, *z32all = nullptr;
+    std::vector<int64_t> q32_off;
     ~BatchWork() {
+        dfree(t32all);
+        dfree(z32all);
         for (void* p : {v, vo, z, zn, w, wo, q}) dfree(p);
         for (double* p : {pu, pr, pq, nrm}) dfree(p);
         dfree(st);
@@ -729,6 +735,9 @@ int batch_minres_core(hd_ctx* c, BatchWork& W, const Bv* b, T* x, bool use_x0, d
         int rc2;
         if ((rc2 = launch_batch_apply(c, prec, z, q, &W.st->inv_gamma, ST_STRIDE_D, &W.st->stop, ST_STRIDE_I, true)))
             return rc2;
+        // levels >= 1 of every instance's V-cycle in shared launches (same
+        // results as the instances' own cycles); otherwise one cycle each
+        const bool shared = B.union_ok && B.vcycle_shared && (std::is_same<T, PT>::value || W.t32all);
         for (int i = 0; i < ni; ++i) {
             hd_ctx* s = B.inst[i];
             const int64_t o = B.off[i], N = s->n_u + s->n_q, np = apply_partial_count(s);
@@ -739,9 +748,53 @@ int batch_minres_core(hd_ctx* c, BatchWork& W, const Bv* b, T* x, bool use_x0, d
             hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, s->n_u,
                                (const T*)q + o, (const T*)v + o, vo + o, mdinv, zn + o,
                                (const MinresState*)(W.st + i), W.pu + (int64_t)i * RED_BLOCKS);
-            if ((rc2 = schur_step<T, PT>(s, W.schur32, vo + o + s->n_u, zn + o + s->n_u, W.pq + W.pq_off[i],
-                                        stop_i)))
-                return rc2;
+            if (!shared || !B.in_union[i]) {
+                if ((rc2 = schur_step<T, PT>(s, W.schur32, vo + o + s->n_u, zn + o + s->n_u, W.pq + W.pq_off[i],
+                                             stop_i)))
+                    return rc2;
+            } else if constexpr (!std::is_same<T, PT>::value) {
+                // the FP32 cycle's input (as schur_step does, per instance)
+                hipLaunchKernelGGL(k_down, dim3(nblk(s->n_q)), dim3(BS), 0, c->stream, s->n_q,
+                                   (const double*)(vo + o + s->n_u), W.t32all + W.q32_off[i], stop_i);
+            }
+        }
+        if (shared) {
+            if constexpr (std::is_same<T, PT>::value) {
+                std::vector<const T*> vq(ni);
+                std::vector<T*> zq(ni);
+                std::vector<double*> pp(ni);
+                for (int i = 0; i < ni; ++i) {
+                    const int64_t o = B.off[i] + B.inst[i]->n_u;
+                    vq[i] = vo + o;
+                    zq[i] = zn + o;
+                    pp[i] = W.pq + W.pq_off[i];
+                }
+                if ((rc2 = batch_union_cycle<T>(c, vq.data(), zq.data(), pp.data(), &W.st->stop, ST_STRIDE_I)))
+                    return rc2;
+            } else {
+                std::vector<const float*> vq(ni);
+                std::vector<float*> zq(ni);
+                std::vector<double*> pp(ni, nullptr);
+                for (int i = 0; i < ni; ++i) {
+                    vq[i] = W.t32all + W.q32_off[i];
+                    zq[i] = W.z32all + W.q32_off[i];
+                }
+                if ((rc2 = batch_union_cycle<float>(c, vq.data(), zq.data(), pp.data(), &W.st->stop, ST_STRIDE_I)))
+                    return rc2;
+                // back to FP64 with the partial sums of <z_q, v_q> (as schur_step)
+                for (int i = 0; i < ni; ++i) {
+                    if (!B.in_union[i]) continue;
+                    hd_ctx* s = B.inst[i];
+                    const int64_t o = B.off[i] + s->n_u;
+                    hipLaunchKernelGGL(k_up_dot, dim3(red_grid(s->n_q)), dim3(BS), 0, c->stream, s->n_q,
+                                       (const float*)(W.z32all + W.q32_off[i]), (const double*)(vo + o),
+                                       (double*)(zn + o), W.pq + W.pq_off[i], &W.st[i].stop);
+                }
+            }
+        }
+        for (int i = 0; i < ni; ++i) {
+            hd_ctx* s = B.inst[i];
+            const int64_t o = B.off[i], N = s->n_u + s->n_q;
             hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, W.st + i,
                                (const double*)(W.pu + (int64_t)i * RED_BLOCKS), (int64_t)red_grid(N),
                                (int64_t)RED_BLOCKS, (const double*)(W.pq + W.pq_off[i]),
@@ -1015,6 +1068,16 @@ int alloc_batch_work(hd_ctx* c, BatchWork& W, size_t es, bool schur32) {
         W.schur32.z32 = dalloc<float>(nq_max);
         W.schur32.p32 = dalloc<double>(npm);
         if (!W.schur32.t32 || !W.schur32.z32 || !W.schur32.p32) return set_err(c, HD_ERR_OOM, "FP32 Schur buffers");
+        if (B.union_ok) {
+            int64_t tot = 0;
+            for (int i = 0; i < ni; ++i) {
+                W.q32_off.push_back(tot);
+                tot += B.inst[i]->n_q;
+            }
+            W.t32all = dalloc<float>(tot);
+            W.z32all = dalloc<float>(tot);
+            if (!W.t32all || !W.z32all) return set_err(c, HD_ERR_OOM, "FP32 Schur buffers");
+        }
     }
     return HD_OK;
 }

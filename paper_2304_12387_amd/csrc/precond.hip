@@ -539,6 +539,134 @@ int schur_apply(hd_ctx* c, const T* b, T* z, double* part, const int* done) {
     return HD_OK;
 }
 
+// ---- batches: levels >= 1 of every instance's V-cycle in shared launches --
+// One descriptor per (instance, operation) of a level; a workgroup finds its
+// descriptor from the first-block offsets and runs the same row computation,
+// with the same lanes per row, as the single-instance kernels, so the results
+// are those of the instances' own V-cycles bit for bit.
+enum { U_PRE = 0, U_RES = 1, U_PRO = 2, U_POST = 3, U_COARSE = 4 };
+
+template <int G, int OP, typename T>
+__device__ __forceinline__ void ubody(const UDesc<T>& D, unsigned lb) {
+    if constexpr (OP == U_COARSE) {
+        // x = Cinv b, one wavefront per row (as vc_coarse_kernel)
+        const int64_t row = lb * (int64_t)(BS / 64) + threadIdx.x / 64;
+        const int lane = threadIdx.x % 64;
+        if (row >= D.n) return;
+        double acc = 0.0;
+        for (int64_t k = lane; k < D.n; k += 64) acc += D.cinv[row * D.n + k] * (double)D.in[k];
+        acc = wave_sum(acc);
+        if (lane == 0) D.out[row] = (T)acc;
+    } else {
+        const int64_t row = (lb * (int64_t)BS + threadIdx.x) / G;
+        const int lane = threadIdx.x % G;
+        if (row >= D.n) return;
+        const T* in = D.in;
+        const T acc = group_row<G, T>(D.rp, D.ci, D.mv, row, lane, [&](int32_t j) { return in[j]; });
+        if (lane != 0) return;
+        if constexpr (OP == U_PRE) {
+            D.out[row] = D.b[row] - acc;
+        } else if constexpr (OP == U_RES) {
+            D.out[row] = acc;
+            if (D.out2) D.out2[row] = D.dinv[row] * acc;
+        } else if constexpr (OP == U_PRO) {
+            D.out[row] += acc;
+        } else {
+            D.out[row] = in[row] + D.dinv[row] * (D.b[row] - acc);
+        }
+    }
+}
+
+template <int OP, typename T>
+__global__ __launch_bounds__(BS) void uvc_kernel(const UDesc<T>* __restrict__ d, int nd, const int* __restrict__ stop,
+                                                 int stop_stride) {
+    __shared__ int di;
+    if (threadIdx.x == 0) {
+        int k = 0;
+        while (k + 1 < nd && d[k + 1].blk0 <= blockIdx.x) ++k;
+        di = k;
+    }
+    __syncthreads();
+    const UDesc<T> D = d[di];
+    if (stop && stop[(int64_t)D.inst * stop_stride]) return;
+    const unsigned lb = blockIdx.x - D.blk0;
+    switch (D.g) {
+        case 1: ubody<1, OP, T>(D, lb); break;
+        case 2: ubody<2, OP, T>(D, lb); break;
+        case 4: ubody<4, OP, T>(D, lb); break;
+        case 8: ubody<8, OP, T>(D, lb); break;
+        case 16: ubody<16, OP, T>(D, lb); break;
+        case 32: ubody<32, OP, T>(D, lb); break;
+        default: ubody<64, OP, T>(D, lb); break;
+    }
+}
+
+// level 0 of one instance's cycle (matrix-free on structured meshes):
+// x = dinv b, r = b - S~ x
+template <typename T>
+void s0_pre_launch(hd_ctx* c, const T* b, const int* done) {
+    DevLevel& lv = c->lev[0];
+    const int64_t n = lv.A.nrows;
+    const T* sd = pick<T>(c->d_sdiag, c->d_sdiag32);
+    const T* wl = pick<T>(c->d_wlo, c->d_wlo32);
+    const T* dinv = pick<T>(lv.dinv, lv.dinv32);
+    T* x = pickw<T>(lv.x, lv.x32);
+    T* r = pickw<T>(lv.r, lv.r32);
+    const Geo g = geo_of(c);
+#define S0PRE_U(PP) hipLaunchKernelGGL((s0_pre_kernel<PP, T>), dim3(nblk(n)), dim3(BS), 0, c->stream, g, n, sd, wl, dinv, b, x, r, done)
+    switch (c->p) {
+        case 1: S0PRE_U(1); break;
+        case 2: S0PRE_U(2); break;
+        case 3: S0PRE_U(3); break;
+        case 4: S0PRE_U(4); break;
+        case 5: S0PRE_U(5); break;
+        default: S0PRE_U(6); break;
+    }
+#undef S0PRE_U
+}
+
+// z = x + dinv (b - S~ x) at level 0 with the partial sums of z * b (the
+// solver's count, folded as in the single-instance cycle)
+template <typename T>
+void s0_post_launch(hd_ctx* c, const T* b, T* z, double* part, const int* done) {
+    DevLevel& lv = c->lev[0];
+    const int64_t n = lv.A.nrows;
+    const T* sd = pick<T>(c->d_sdiag, c->d_sdiag32);
+    const T* wl = pick<T>(c->d_wlo, c->d_wlo32);
+    const T* dinv = pick<T>(lv.dinv, lv.dinv32);
+    const T* x = pickw<T>(lv.x, lv.x32);
+    const Geo g = geo_of(c);
+    const bool fold = part && (int64_t)nblk(n) > (int64_t)red_grid(n);
+    double* bp = fold ? c->d_s0part : part;
+#define S0POST_U(PP) hipLaunchKernelGGL((s0_post_kernel<PP, T>), dim3(nblk(n)), dim3(BS), 0, c->stream, g, n, sd, wl, dinv, b, x, z, bp, 2, done)
+    switch (c->p) {
+        case 1: S0POST_U(1); break;
+        case 2: S0POST_U(2); break;
+        case 3: S0POST_U(3); break;
+        case 4: S0POST_U(4); break;
+        case 5: S0POST_U(5); break;
+        default: S0POST_U(6); break;
+    }
+#undef S0POST_U
+    if (fold) {
+        const int64_t nin = nblk(n), nout = red_grid(n), q = (nin + nout - 1) / nout;
+        hipLaunchKernelGGL(fold_partials_kernel, dim3((unsigned)((nout + BS - 1) / BS)), dim3(BS), 0, c->stream, nin,
+                           q, nout, (const double*)c->d_s0part, part, done);
+    }
+}
+
+template <typename T>
+void launch_union(hd_ctx* c, const UnionLaunch<T>& u, const int* stop, int stop_stride) {
+    if (u.nd == 0 || u.nblocks == 0) return;
+    switch (u.op) {
+        case U_PRE: hipLaunchKernelGGL((uvc_kernel<U_PRE, T>), dim3(u.nblocks), dim3(BS), 0, c->stream, u.d, u.nd, stop, stop_stride); break;
+        case U_RES: hipLaunchKernelGGL((uvc_kernel<U_RES, T>), dim3(u.nblocks), dim3(BS), 0, c->stream, u.d, u.nd, stop, stop_stride); break;
+        case U_PRO: hipLaunchKernelGGL((uvc_kernel<U_PRO, T>), dim3(u.nblocks), dim3(BS), 0, c->stream, u.d, u.nd, stop, stop_stride); break;
+        case U_POST: hipLaunchKernelGGL((uvc_kernel<U_POST, T>), dim3(u.nblocks), dim3(BS), 0, c->stream, u.d, u.nd, stop, stop_stride); break;
+        default: hipLaunchKernelGGL((uvc_kernel<U_COARSE, T>), dim3(u.nblocks), dim3(BS), 0, c->stream, u.d, u.nd, stop, stop_stride); break;
+    }
+}
+
 }  // namespace
 
 int launch_diag_prec(hd_ctx* c, int prec, const void* r, void* z, double* part) {
@@ -562,6 +690,163 @@ int launch_schur_prec(hd_ctx* c, int prec, const void* b, void* z, double* part,
 }
 
 int64_t schur_partial_count(const hd_ctx* c) { return red_grid(c->n_q); }
+
+namespace {
+
+// The shared launches of one precision for the instances' levels >= 1
+// (their order is the cycle's: restrictions and pre-smoothing down, the
+// coarse solves, prolongations and post-smoothing up).
+template <typename T>
+int build_union_t(hd_ctx* c, std::vector<UnionLaunch<T>>& out) {
+    BatchState& B = *c->batch;
+    const int ni = (int)B.inst.size();
+    int lmax = 0;
+    for (int i = 0; i < ni; ++i)
+        if (B.in_union[i]) lmax = std::max(lmax, (int)B.inst[i]->lev.size());
+    auto make = [&](int op, auto&& pickdesc) -> int {
+        std::vector<UDesc<T>> ds;
+        unsigned blk = 0;
+        for (int i = 0; i < ni; ++i) {
+            UDesc<T> d = {};
+            if (!B.in_union[i] || !pickdesc(i, d)) continue;
+            d.inst = i;
+            d.blk0 = blk;
+            const int64_t nb = op == U_COARSE ? (d.n + 3) / 4 : (int64_t)gblk(d.n, d.g);
+            if (nb <= 0) continue;
+            blk += (unsigned)nb;
+            ds.push_back(d);
+        }
+        UnionLaunch<T> u;
+        u.op = op;
+        u.nd = (int)ds.size();
+        u.nblocks = blk;
+        if (u.nd) {
+            u.d = dalloc<UDesc<T>>(ds.size());
+            if (!u.d) return set_err(c, HD_ERR_OOM, "batched V-cycle tables");
+            HD_HIP(c, hipMemcpy(u.d, ds.data(), ds.size() * sizeof(UDesc<T>), hipMemcpyHostToDevice));
+        }
+        out.push_back(u);
+        return HD_OK;
+    };
+    int rc;
+    for (int l = 0; l + 1 < lmax; ++l) {
+        if (l >= 1 && (rc = make(U_PRE, [&](int i, UDesc<T>& d) {
+                hd_ctx* s = B.inst[i];
+                if ((int)s->lev.size() <= l + 1) return false;
+                DevLevel& lv = s->lev[l];
+                d.rp = lv.A.rp; d.ci = lv.A.ci; d.mv = pick<T>(lv.A.v, lv.A.v32);
+                d.in = pickw<T>(lv.x, lv.x32); d.b = pickw<T>(lv.b, lv.b32); d.out = pickw<T>(lv.r, lv.r32);
+                d.n = lv.A.nrows; d.g = group_of(lv.A);
+                return true;
+            })))
+            return rc;
+        if ((rc = make(U_RES, [&](int i, UDesc<T>& d) {
+                hd_ctx* s = B.inst[i];
+                const int L = (int)s->lev.size();
+                if (L <= l + 1) return false;
+                DevLevel& lv = s->lev[l];
+                DevLevel& nx = s->lev[l + 1];
+                d.rp = lv.R.rp; d.ci = lv.R.ci; d.mv = pick<T>(lv.R.v, lv.R.v32);
+                d.in = pickw<T>(lv.r, lv.r32); d.out = pickw<T>(nx.b, nx.b32);
+                if (l + 2 < L) {
+                    d.out2 = pickw<T>(nx.x, nx.x32);
+                    d.dinv = pick<T>(nx.dinv, nx.dinv32);
+                }
+                d.n = lv.R.nrows; d.g = group_of(lv.R);
+                return true;
+            })))
+            return rc;
+    }
+    if ((rc = make(U_COARSE, [&](int i, UDesc<T>& d) {
+            hd_ctx* s = B.inst[i];
+            DevLevel& lv = s->lev.back();
+            d.cinv = s->d_cinv;
+            d.in = pickw<T>(lv.b, lv.b32); d.out = pickw<T>(lv.z, lv.z32);
+            d.n = lv.A.nrows;
+            return true;
+        })))
+        return rc;
+    for (int l = lmax - 2; l >= 0; --l) {
+        if ((rc = make(U_PRO, [&](int i, UDesc<T>& d) {
+                hd_ctx* s = B.inst[i];
+                if ((int)s->lev.size() <= l + 1) return false;
+                DevLevel& lv = s->lev[l];
+                DevLevel& nx = s->lev[l + 1];
+                d.rp = lv.P.rp; d.ci = lv.P.ci; d.mv = pick<T>(lv.P.v, lv.P.v32);
+                d.in = pickw<T>(nx.z, nx.z32); d.out = pickw<T>(lv.x, lv.x32);
+                d.n = lv.P.nrows; d.g = group_of(lv.P);
+                return true;
+            })))
+            return rc;
+        if (l >= 1 && (rc = make(U_POST, [&](int i, UDesc<T>& d) {
+                hd_ctx* s = B.inst[i];
+                if ((int)s->lev.size() <= l + 1) return false;
+                DevLevel& lv = s->lev[l];
+                d.rp = lv.A.rp; d.ci = lv.A.ci; d.mv = pick<T>(lv.A.v, lv.A.v32);
+                d.dinv = pick<T>(lv.dinv, lv.dinv32);
+                d.in = pickw<T>(lv.x, lv.x32); d.b = pickw<T>(lv.b, lv.b32); d.out = pickw<T>(lv.z, lv.z32);
+                d.n = lv.A.nrows; d.g = group_of(lv.A);
+                return true;
+            })))
+            return rc;
+    }
+    return HD_OK;
+}
+
+}  // namespace
+
+int batch_union_build(hd_ctx* c) {
+    BatchState& B = *c->batch;
+    batch_union_free(c);
+    // instances with a structured, non-singular hierarchy of at least two
+    // levels take part; the others keep their own V-cycle launches
+    B.in_union.assign(B.inst.size(), 0);
+    bool any = false;
+    for (size_t i = 0; i < B.inst.size(); ++i) {
+        hd_ctx* s = B.inst[i];
+        B.in_union[i] = !s->unstructured && !s->singular && s->lev.size() >= 2;
+        any = any || B.in_union[i];
+    }
+    if (!any) return HD_OK;
+    int rc = build_union_t<double>(c, B.un64);
+    if (!rc) rc = build_union_t<float>(c, B.un32);
+    if (rc) {
+        batch_union_free(c);
+        return rc;
+    }
+    B.union_ok = true;
+    return HD_OK;
+}
+
+void batch_union_free(hd_ctx* c) {
+    BatchState& B = *c->batch;
+    for (auto& u : B.un64) dfree(u.d);
+    for (auto& u : B.un32) dfree(u.d);
+    B.un64.clear();
+    B.un32.clear();
+    B.in_union.clear();
+    B.union_ok = false;
+}
+
+template <typename T>
+int batch_union_cycle(hd_ctx* c, const T* const* vq, T* const* zq, double* const* part, const int* stop,
+                      int stop_stride) {
+    BatchState& B = *c->batch;
+    const int ni = (int)B.inst.size();
+    const std::vector<UnionLaunch<T>>* U;
+    if constexpr (std::is_same<T, double>::value) U = &B.un64;
+    else U = &B.un32;
+    for (int i = 0; i < ni; ++i)
+        if (B.in_union[i]) s0_pre_launch<T>(B.inst[i], vq[i], stop + (int64_t)i * stop_stride);
+    for (const auto& u : *U) launch_union<T>(c, u, stop, stop_stride);
+    for (int i = 0; i < ni; ++i)
+        if (B.in_union[i]) s0_post_launch<T>(B.inst[i], vq[i], zq[i], part[i], stop + (int64_t)i * stop_stride);
+    HD_HIP(c, hipGetLastError());
+    return HD_OK;
+}
+
+template int batch_union_cycle<double>(hd_ctx*, const double* const*, double* const*, double* const*, const int*, int);
+template int batch_union_cycle<float>(hd_ctx*, const float* const*, float* const*, double* const*, const int*, int);
 
 int launch_precond(hd_ctx* c, int prec, const void* r, void* z, double* dot_partial_u, double* dot_partial_q,
                    const int* done) {

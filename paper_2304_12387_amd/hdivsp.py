@@ -37,7 +37,7 @@ EXPORTED = [
     'hd_set_local_solver', 'hd_set_gamma_field', 'hd_gmres_solve', 'hd_apply_tri_precond',
     'hd_apply_tri_precond_noalloc', 'hd_setup_mesh_unstructured', 'hd_set_essential_dofs', 'hd_get_dof_map',
     'hd_host_unstructured_map', 'hd_apply_block_op_interleaved', 'hd_apply_divergence', 'hd_subcell_volumes',
-    'hd_rd_default_params', 'hd_rd_setup', 'hd_rd_step',
+    'hd_rd_default_params', 'hd_rd_setup', 'hd_rd_step', 'hd_batch_set_vcycle',
 ]
 
 
@@ -160,6 +160,7 @@ def load():
         'hd_batch_apply': (I, [P, I, P, P]),
         'hd_batch_tune': (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(D)]),
         'hd_batch_set_launch': (I, [P, I, I, I]),
+        'hd_batch_set_vcycle': (I, [P, I]),
         'hd_batch_build_precond': (I, [P, ctypes.POINTER(PrecondParams)]),
         'hd_batch_minres_solve': (I, [P, ctypes.POINTER(SolveParams), P, P, ctypes.POINTER(SolveInfo)]),
         'hd_apply_divergence': (I, [P, P, P]),
@@ -386,6 +387,11 @@ class Context:
 
     def batch_set_launch(self, mode, grid, tile_groups):
         return self._check(self.lib.hd_batch_set_launch(self.h, mode, grid, tile_groups))
+
+    def batch_set_vcycle(self, shared):
+        """1: the instances' V-cycle levels >= 1 in shared launches; 0: each
+        instance's own launches."""
+        return self._check(self.lib.hd_batch_set_vcycle(self.h, int(shared)))
 
     def batch_build_precond(self, params=None):
         pp = ctypes.byref(params) if params is not None else None
