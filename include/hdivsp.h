@@ -414,8 +414,10 @@ int hd_batch_set_launch(hd_ctx* ctx, int mode, int grid, int tile_groups);
  * as the instances' own cycles; the other instances keep their own. */
 int hd_batch_build_precond(hd_ctx* ctx, const hd_precond_params* params);
 /* shared = 1 (the default): the shared V-cycle launches above where they
- * apply; 0: every instance's V-cycle launched on its own.  HD_ERR_STATE
- * before hd_setup_batch, HD_ERR_ARG for another value. */
+ * apply, and the recurrence's vector updates and scalar steps of all
+ * instances in one launch each (same results); 0: every instance's V-cycle
+ * and recurrence kernels launched on their own.  HD_ERR_STATE before
+ * hd_setup_batch, HD_ERR_ARG for another value. */
 int hd_batch_set_vcycle(hd_ctx* ctx, int shared);
 /* One MINRES recurrence per instance (Section 2.2), in any HD_MODE_*.  HD_MODE_MIXED
  * refines every instance on its own FP64 residual around one batched FP32

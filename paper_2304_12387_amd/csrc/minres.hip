@@ -86,10 +86,8 @@ __global__ void k_sum_stage(const double* __restrict__ part, int64_t n, int64_t 
 }
 
 // one block per right-hand side r: delta = sum of its apply partials
-__global__ void k_delta(MinresState* st, const double* __restrict__ part, int64_t n, int64_t stride) {
-    MinresState* S = st + blockIdx.x;
+__device__ void delta_body(MinresState* S, const double* __restrict__ p, int64_t n) {
     if (S->stop) return;
-    const double* p = part + blockIdx.x * stride;
     double acc = 0.0;
     for (int64_t k = threadIdx.x; k < n; k += blockDim.x) acc += p[k];
     const double d = block_sum(acc);
@@ -100,15 +98,16 @@ __global__ void k_delta(MinresState* st, const double* __restrict__ part, int64_
     }
 }
 
-__global__ void k_givens(MinresState* st, const double* __restrict__ pu, int64_t nu, int64_t su,
-                         const double* __restrict__ pq, int64_t nq, int64_t sq, int maxit) {
-    MinresState* S = st + blockIdx.x;
+__global__ void k_delta(MinresState* st, const double* __restrict__ part, int64_t n, int64_t stride) {
+    delta_body(st + blockIdx.x, part + blockIdx.x * stride, n);
+}
+
+__device__ void givens_body(MinresState* S, const double* __restrict__ a, int64_t nu, const double* __restrict__ b,
+                            int64_t nq, int maxit) {
     if (S->stop) {
         if (threadIdx.x == 0) S->skipped = 1;
         return;
     }
-    const double* a = pu + blockIdx.x * su;
-    const double* b = pq + blockIdx.x * sq;
     double acc = 0.0;
     for (int64_t k = threadIdx.x; k < nu; k += blockDim.x) acc += a[k];
     double acc2 = 0.0;
@@ -154,6 +153,11 @@ __global__ void k_givens(MinresState* st, const double* __restrict__ pu, int64_t
     }
 }
 
+__global__ void k_givens(MinresState* st, const double* __restrict__ pu, int64_t nu, int64_t su,
+                         const double* __restrict__ pq, int64_t nq, int64_t sq, int maxit) {
+    givens_body(st + blockIdx.x, pu + blockIdx.x * su, nu, pq + blockIdx.x * sq, nq, maxit);
+}
+
 __global__ void k_start(MinresState* st, const double* __restrict__ pu, int64_t nu, int64_t su,
                         const double* __restrict__ pq, int64_t nq, int64_t sq, double tol) {
     const double* a = pu + blockIdx.x * su;
@@ -189,21 +193,19 @@ __global__ void k_set_tol(MinresState* st, double tol) { st->tol = tol; }
 // v_old <- q - cv1 v - cv2 v_old  (= v_{j+1});  z_u = mdinv * v_{j+1,u}
 // (blockIdx.y = right-hand side)
 template <typename T>
-__global__ void k_vupd(int64_t N, int64_t nu, const T* __restrict__ q, const T* __restrict__ v, T* __restrict__ vo,
-                       const T* __restrict__ mdinv, T* __restrict__ z, const MinresState* __restrict__ st,
-                       double* __restrict__ part) {
-    const int r = blockIdx.y;
-    if (st[r].stop) return;
+__device__ __forceinline__ void vupd_body(int64_t N, int64_t nu, const T* __restrict__ q, const T* __restrict__ v,
+                                          T* __restrict__ vo, const T* __restrict__ mdinv, T* __restrict__ z,
+                                          const MinresState& st, double* __restrict__ part, unsigned lb, unsigned nb) {
+    if (st.stop) return;
     __shared__ double s[BS];
-    const T cv1 = (T)st[r].cv1, cv2 = (T)st[r].cv2;
-    const int64_t o = (int64_t)r * N;
+    const T cv1 = (T)st.cv1, cv2 = (T)st.cv2;
     double contrib = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
-        const T vn = q[o + i] - cv1 * v[o + i] - cv2 * vo[o + i];
-        vo[o + i] = vn;
+    for (int64_t i = lb * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)nb * BS) {
+        const T vn = q[i] - cv1 * v[i] - cv2 * vo[i];
+        vo[i] = vn;
         if (i < nu) {
             const T zi = mdinv[i] * vn;
-            z[o + i] = zi;
+            z[i] = zi;
             contrib += (double)zi * (double)vn;
         }
     }
@@ -213,7 +215,33 @@ __global__ void k_vupd(int64_t N, int64_t nu, const T* __restrict__ q, const T* 
         if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[(int64_t)r * RED_BLOCKS + blockIdx.x] = s[0];
+    if (threadIdx.x == 0) part[lb] = s[0];
+}
+
+// v_old <- q - cv1 v - cv2 v_old  (= v_{j+1});  z_u = mdinv * v_{j+1,u}
+// (blockIdx.y = right-hand side)
+template <typename T>
+__global__ void k_vupd(int64_t N, int64_t nu, const T* __restrict__ q, const T* __restrict__ v, T* __restrict__ vo,
+                       const T* __restrict__ mdinv, T* __restrict__ z, const MinresState* __restrict__ st,
+                       double* __restrict__ part) {
+    const int r = blockIdx.y;
+    const int64_t o = (int64_t)r * N;
+    vupd_body<T>(N, nu, q + o, v + o, vo + o, mdinv, z + o, st[r], part + (int64_t)r * RED_BLOCKS, blockIdx.x,
+                 gridDim.x);
+}
+
+// w_old <- (z zscale - a3 w_old - a2 w) a1inv  (= w_{j+1});  x += xcoef w_{j+1}
+template <typename T, typename X>
+__device__ __forceinline__ void wupd_body(int64_t N, const T* __restrict__ z, T* __restrict__ wo,
+                                          const T* __restrict__ w, X* __restrict__ x, const MinresState& st,
+                                          unsigned lb) {
+    if (st.skipped) return;
+    const int64_t k = lb * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const T zs = (T)st.zscale, a3 = (T)st.a3, a2 = (T)st.a2, a1i = (T)st.a1inv;
+    const T wn = (z[k] * zs - a3 * wo[k] - a2 * w[k]) * a1i;
+    wo[k] = wn;
+    x[k] += (X)st.xcoef * (X)wn;
 }
 
 // w_old <- (z zscale - a3 w_old - a2 w) a1inv  (= w_{j+1});  x += xcoef w_{j+1}
@@ -221,14 +249,61 @@ template <typename T, typename X>
 __global__ void k_wupd(int64_t N, const T* __restrict__ z, T* __restrict__ wo, const T* __restrict__ w,
                        X* __restrict__ x, const MinresState* __restrict__ st) {
     const int r = blockIdx.y;
-    if (st[r].skipped) return;
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int64_t k = (int64_t)r * N + i;
-    const T zs = (T)st[r].zscale, a3 = (T)st[r].a3, a2 = (T)st[r].a2, a1i = (T)st[r].a1inv;
-    const T wn = (z[k] * zs - a3 * wo[k] - a2 * w[k]) * a1i;
-    wo[k] = wn;
-    x[k] += (X)st[r].xcoef * (X)wn;
+    const int64_t o = (int64_t)r * N;
+    wupd_body<T, X>(N, z + o, wo + o, w + o, x + o, st[r], blockIdx.x);
+}
+
+// ---- the recurrence kernels of a batch in shared launches ----------------
+// One descriptor per instance; the bodies are those of the kernels above, so
+// every instance computes what its own launches compute, bit for bit.
+struct BVec {
+    int64_t o, N, nu;          // offset in the concatenated vectors, length, RT part
+    const void* mdinv;         // 1 / (tau diag M) of the working precision
+    const double* apart;       // the apply's partial sums of <A v, v>
+    int64_t napart;
+    const double* pq;          // the V-cycle's partial sums of <z_q, v_q>
+    int64_t npq;
+    unsigned blk_v, nb_v;      // first block and blocks of the vector update (red_grid(N))
+    unsigned blk_w;            // first block of the direction update (nblk(N))
+};
+
+__device__ __forceinline__ int bvec_find(const BVec* __restrict__ t, int ni, bool w) {
+    __shared__ int fi;
+    if (threadIdx.x == 0) {
+        int k = 0;
+        while (k + 1 < ni && (w ? t[k + 1].blk_w : t[k + 1].blk_v) <= blockIdx.x) ++k;
+        fi = k;
+    }
+    __syncthreads();
+    return fi;
+}
+
+__global__ void kb_delta(MinresState* st, const BVec* __restrict__ t) {
+    const BVec& d = t[blockIdx.x];
+    delta_body(st + blockIdx.x, d.apart, d.napart);
+}
+
+template <typename T>
+__global__ void kb_vupd(const BVec* __restrict__ t, int ni, const T* __restrict__ q, const T* __restrict__ v,
+                        T* __restrict__ vo, T* __restrict__ z, const MinresState* __restrict__ st,
+                        double* __restrict__ pu) {
+    const int i = bvec_find(t, ni, false);
+    const BVec d = t[i];
+    vupd_body<T>(d.N, d.nu, q + d.o, v + d.o, vo + d.o, (const T*)d.mdinv, z + d.o, st[i],
+                 pu + (int64_t)i * RED_BLOCKS, blockIdx.x - d.blk_v, d.nb_v);
+}
+
+__global__ void kb_givens(MinresState* st, const double* __restrict__ pu, const BVec* __restrict__ t, int maxit) {
+    const BVec& d = t[blockIdx.x];
+    givens_body(st + blockIdx.x, pu + (int64_t)blockIdx.x * RED_BLOCKS, d.nb_v, d.pq, d.npq, maxit);
+}
+
+template <typename T>
+__global__ void kb_wupd(const BVec* __restrict__ t, int ni, const T* __restrict__ z, T* __restrict__ wo,
+                        const T* __restrict__ w, T* __restrict__ x, const MinresState* __restrict__ st) {
+    const int i = bvec_find(t, ni, true);
+    const BVec d = t[i];
+    wupd_body<T, T>(d.N, z + d.o, wo + d.o, w + d.o, x + d.o, st[i], blockIdx.x - d.blk_w);
 }
 
 // v = b - q (or b when q == nullptr), v_old = w = w_old = 0 (all RHS)
@@ -658,9 +733,12 @@ struct BatchWork {
     // launches with an FP64 recurrence), at q32_off
     float *t32all = nullptr, *z32all = nullptr;
     std::vector<int64_t> q32_off;
+    BVec* bvec = nullptr;      // the shared recurrence kernels' descriptors
+    int bvec_n = 0;
     ~BatchWork() {
         dfree(t32all);
         dfree(z32all);
+        dfree(bvec);
         for (void* p : {v, vo, z, zn, w, wo, q}) dfree(p);
         for (double* p : {pu, pr, pq, nrm}) dfree(p);
         dfree(st);
@@ -728,6 +806,38 @@ int batch_minres_core(hd_ctx* c, BatchWork& W, const Bv* b, T* x, bool use_x0, d
                            schur_parts<T, PT>(s), W.nq_part[i], tols ? tols[i] : tol);
     }
     HD_HIP(c, hipGetLastError());
+    // the recurrence kernels of all instances in shared launches
+    const bool vshared = B.vcycle_shared != 0;
+    BVec* d_bvec = nullptr;
+    unsigned nbv = 0, nbw = 0;
+    if (vshared) {
+        std::vector<BVec> tb(ni);
+        for (int i = 0; i < ni; ++i) {
+            hd_ctx* s = B.inst[i];
+            BVec& d = tb[i];
+            d.o = B.off[i];
+            d.N = s->n_u + s->n_q;
+            d.nu = s->n_u;
+            d.mdinv = F64 ? (const void*)s->d_mdinv : (const void*)s->d_mdinv32;
+            d.apart = c->batch->d_part + c->batch->part_off[i];
+            d.napart = apply_partial_count(s);
+            d.pq = W.pq + W.pq_off[i];
+            d.npq = schur_parts<T, PT>(s);
+            d.blk_v = nbv;
+            d.nb_v = red_grid(d.N);
+            d.blk_w = nbw;
+            nbv += d.nb_v;
+            nbw += nblk(d.N);
+        }
+        if (!W.bvec || W.bvec_n < ni) {
+            dfree(W.bvec);
+            W.bvec = dalloc<BVec>(ni);
+            W.bvec_n = W.bvec ? ni : 0;
+            if (!W.bvec) return set_err(c, HD_ERR_OOM, "batched MINRES tables");
+        }
+        d_bvec = W.bvec;
+        HD_HIP(c, hipMemcpyAsync(d_bvec, tb.data(), sizeof(BVec) * ni, hipMemcpyHostToDevice, c->stream));
+    }
     int launched = 0, retargets = 0;
     // one MINRES iteration for every instance (kernels only; those of a
     // stopped instance return at once on its stop flag)
@@ -738,16 +848,23 @@ int batch_minres_core(hd_ctx* c, BatchWork& W, const Bv* b, T* x, bool use_x0, d
         // levels >= 1 of every instance's V-cycle in shared launches (same
         // results as the instances' own cycles); otherwise one cycle each
         const bool shared = B.union_ok && B.vcycle_shared && (std::is_same<T, PT>::value || W.t32all);
+        if (vshared) {
+            hipLaunchKernelGGL(kb_delta, dim3(ni), dim3(1024), 0, c->stream, W.st, (const BVec*)d_bvec);
+            hipLaunchKernelGGL(kb_vupd<T>, dim3(nbv), dim3(BS), 0, c->stream, (const BVec*)d_bvec, ni, (const T*)q,
+                               (const T*)v, vo, zn, (const MinresState*)W.st, W.pu);
+        }
         for (int i = 0; i < ni; ++i) {
             hd_ctx* s = B.inst[i];
             const int64_t o = B.off[i], N = s->n_u + s->n_q, np = apply_partial_count(s);
             const int* stop_i = &W.st[i].stop;
             const T* mdinv = F64 ? (const T*)s->d_mdinv : (const T*)s->d_mdinv32;
-            hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), 0, c->stream, W.st + i,
-                               (const double*)(c->batch->d_part + c->batch->part_off[i]), np, np);
-            hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, s->n_u,
-                               (const T*)q + o, (const T*)v + o, vo + o, mdinv, zn + o,
-                               (const MinresState*)(W.st + i), W.pu + (int64_t)i * RED_BLOCKS);
+            if (!vshared) {
+                hipLaunchKernelGGL(k_delta, dim3(1), dim3(1024), 0, c->stream, W.st + i,
+                                   (const double*)(c->batch->d_part + c->batch->part_off[i]), np, np);
+                hipLaunchKernelGGL(k_vupd<T>, dim3(red_grid(N), 1), dim3(BS), 0, c->stream, N, s->n_u,
+                                   (const T*)q + o, (const T*)v + o, vo + o, mdinv, zn + o,
+                                   (const MinresState*)(W.st + i), W.pu + (int64_t)i * RED_BLOCKS);
+            }
             if (!shared || !B.in_union[i]) {
                 if ((rc2 = schur_step<T, PT>(s, W.schur32, vo + o + s->n_u, zn + o + s->n_u, W.pq + W.pq_off[i],
                                              stop_i)))
@@ -792,15 +909,22 @@ int batch_minres_core(hd_ctx* c, BatchWork& W, const Bv* b, T* x, bool use_x0, d
                 }
             }
         }
-        for (int i = 0; i < ni; ++i) {
-            hd_ctx* s = B.inst[i];
-            const int64_t o = B.off[i], N = s->n_u + s->n_q;
-            hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, W.st + i,
-                               (const double*)(W.pu + (int64_t)i * RED_BLOCKS), (int64_t)red_grid(N),
-                               (int64_t)RED_BLOCKS, (const double*)(W.pq + W.pq_off[i]),
-                               schur_parts<T, PT>(s), W.nq_part[i], maxit);
-            hipLaunchKernelGGL((k_wupd<T, T>), dim3(nblk(N), 1), dim3(BS), 0, c->stream, N, (const T*)z + o,
-                               wo + o, (const T*)w + o, x + o, (const MinresState*)(W.st + i));
+        if (vshared) {
+            hipLaunchKernelGGL(kb_givens, dim3(ni), dim3(1024), 0, c->stream, W.st, (const double*)W.pu,
+                               (const BVec*)d_bvec, maxit);
+            hipLaunchKernelGGL(kb_wupd<T>, dim3(nbw), dim3(BS), 0, c->stream, (const BVec*)d_bvec, ni, (const T*)z,
+                               wo, (const T*)w, x, (const MinresState*)W.st);
+        } else {
+            for (int i = 0; i < ni; ++i) {
+                hd_ctx* s = B.inst[i];
+                const int64_t o = B.off[i], N = s->n_u + s->n_q;
+                hipLaunchKernelGGL(k_givens, dim3(1), dim3(1024), 0, c->stream, W.st + i,
+                                   (const double*)(W.pu + (int64_t)i * RED_BLOCKS), (int64_t)red_grid(N),
+                                   (int64_t)RED_BLOCKS, (const double*)(W.pq + W.pq_off[i]),
+                                   schur_parts<T, PT>(s), W.nq_part[i], maxit);
+                hipLaunchKernelGGL((k_wupd<T, T>), dim3(nblk(N), 1), dim3(BS), 0, c->stream, N, (const T*)z + o,
+                                   wo + o, (const T*)w + o, x + o, (const MinresState*)(W.st + i));
+            }
         }
         std::swap(v, vo);
         std::swap(z, zn);
