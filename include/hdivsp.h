@@ -231,6 +231,15 @@ int hd_set_gamma_field(hd_ctx* ctx, const double* gamma_vertices);
  * hd_setup_mesh. */
 int hd_sizes(const hd_ctx* ctx, int64_t* n_u, int64_t* n_q);
 
+/* Whether hd_setup_mesh found every element to be a parallelepiped (the
+ * trilinear map of Section 3 affine: the twist vectors of each vertex cube
+ * below 1e-14 of its edges), written to *affine as 1 or 0.  Then J, and
+ * J^T J / det J, are the same at all quadrature points of an element, and
+ * hd_apply_block_op forms them once per element (same operator; unstructured
+ * meshes and a gamma field always take the general path).  HD_ERR_ARG for a
+ * NULL pointer, HD_ERR_STATE before hd_setup_mesh. */
+int hd_mesh_affine(const hd_ctx* ctx, int* affine);
+
 /* y = A x (eq. transformed-saddle-point, Section 3).  x != y, device
  * pointers of length nrhs*(n_u+n_q).  Essential convention as above.
  * Matrix-free: M by sum factorisation at the quadrature points, D and D^T

@@ -366,12 +366,55 @@ __device__ __forceinline__ void quad_to_rt(ElemLDS<P, T>& L, tkp<P, T> tk, int t
 // for the three components, and gw = w / det J (1 without a (2,2) block).
 // The factors come from the trilinear map of the element vertices in L.vx:
 // dx/dxi and dx/deta are linear in zeta and dx/dzeta is constant along the
-// column.
-template <int P, typename T, bool HAS_C>
+// column.  AFF: every element of the mesh is a parallelepiped (the map is
+// affine), so J is the same at every point and J^T J / det J is formed once
+// per lane; the points differ only in their weights.
+template <int P, typename T, bool HAS_C, bool AFF = false>
 __device__ __forceinline__ void quad_factors(ElemLDS<P, T>& L, tkp<P, T> tb, int t, T cM, T (&U0)[Slot<P>::QC][P + 1],
                                              T (&U1)[Slot<P>::QC][P + 1], T (&U2)[Slot<P>::QC][P + 1],
                                              T (&gw)[Slot<P>::QC][P + 1]) {
     constexpr int Q = P + 1, W = Slot<P>::W, QC = Slot<P>::QC;
+    if constexpr (AFF) {
+        // columns of J: the edges from vertex 0 to vertices 1 (dx), 2 (dy), 4 (dz)
+        const T* X = L.vx;
+        T J0[3], J1[3], C[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            J0[r] = X[3 + r] - X[r];
+            J1[r] = X[6 + r] - X[r];
+            C[r] = X[12 + r] - X[r];
+        }
+        const T det = J0[0] * (J1[1] * C[2] - J1[2] * C[1]) - J0[1] * (J1[0] * C[2] - J1[2] * C[0]) +
+                      J0[2] * (J1[0] * C[1] - J1[1] * C[0]);
+        const T id = T(1) / det;
+        const T h = cM * id;
+        const T g00 = h * (J0[0] * J0[0] + J0[1] * J0[1] + J0[2] * J0[2]);
+        const T g01 = h * (J0[0] * J1[0] + J0[1] * J1[1] + J0[2] * J1[2]);
+        const T g02 = h * (J0[0] * C[0] + J0[1] * C[1] + J0[2] * C[2]);
+        const T g11 = h * (J1[0] * J1[0] + J1[1] * J1[1] + J1[2] * J1[2]);
+        const T g12 = h * (J1[0] * C[0] + J1[1] * C[1] + J1[2] * C[2]);
+        const T g22 = h * (C[0] * C[0] + C[1] * C[1] + C[2] * C[2]);
+#pragma unroll
+        for (int cc = 0; cc < QC; ++cc) {
+            const int col = t + cc * W;
+            if (col < Q * Q) {
+                const T wab = tb->wq[col % Q] * tb->wq[col / Q];
+#pragma unroll
+                for (int c = 0; c < Q; ++c) {
+                    const T w = wab * tb->wq[c];
+                    const T a0 = U0[cc][c], a1 = U1[cc][c], a2 = U2[cc][c];
+                    U0[cc][c] = w * (g00 * a0 + g01 * a1 + g02 * a2);
+                    U1[cc][c] = w * (g01 * a0 + g11 * a1 + g12 * a2);
+                    U2[cc][c] = w * (g02 * a0 + g12 * a1 + g22 * a2);
+                    gw[cc][c] = HAS_C ? w * id : T(1);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < Q; ++c) gw[cc][c] = T(1);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int cc = 0; cc < QC; ++cc) {
         const int col = t + cc * W;
@@ -602,7 +645,7 @@ struct RhsArgs {
 // M u by sum factorisation, the local CG for -kappa W^{-1} q~, scatter.
 // x and y point at one right-hand side's vector; the return value is the
 // group's <A x, x> contribution summed over the wavefront (all lanes).
-template <int P, typename T, bool HAS_C = true, bool VARG = false>
+template <int P, typename T, bool HAS_C = true, bool VARG = false, bool AFF = false>
 __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, const double* __restrict__ vert,
                                               tkp<P, T> tb,
                                               const T* __restrict__ cm, const T* __restrict__ kap, uint32_t ess,
@@ -655,7 +698,7 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     rt_to_quad<P, T, 1>(L, tb, t, U1);
     rt_to_quad<P, T, 2>(L, tb, t, U2);
     T gw[QC][Q];
-    quad_factors<P, T, HAS_C>(L, tb, t, cM, U0, U1, U2, gw);
+    quad_factors<P, T, HAS_C, AFF>(L, tb, t, cM, U0, U1, U2, gw);
     double dot = 0.0;
     {
         // the first colour's values on this lane's lines, loaded before the
@@ -736,7 +779,7 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     return slot_sum<double, 64>(dot);
 }
 
-template <int P, typename T, bool HAS_C, bool VARG = false>
+template <int P, typename T, bool HAS_C, bool VARG = false, bool AFF = false>
 __global__ __launch_bounds__(64) void block_apply_kernel(
     Geo g, const double* __restrict__ vert, tkp<P, T> tb, const T* __restrict__ cm, const T* __restrict__ kap,
     uint32_t ess, int ess_mode, int64_t ne, int64_t n_u, const T* __restrict__ xall, T* __restrict__ yall, RhsArgs ra,
@@ -760,7 +803,7 @@ __global__ __launch_bounds__(64) void block_apply_kernel(
     if (ra.done && ra.done[(int64_t)r * ra.done_stride]) return;   // uniform over the block
     __shared__ ElemLDS<P, T> sm[Slot<P>::EPW];
     const T s_in = ra.scale ? (T)ra.scale[(int64_t)r * ra.scale_stride] : T(1);
-    const double dot = apply_group<P, T, HAS_C, VARG>(sm, g, vert, tb, cm, kap, ess, ess_mode, n_u, xall + r * ra.ldv,
+    const double dot = apply_group<P, T, HAS_C, VARG, AFF>(sm, g, vert, tb, cm, kap, ess, ess_mode, n_u, xall + r * ra.ldv,
                                                 yall + r * ra.ldv, s_in, cgp, with_c, colour, grp, nb, winv,
                                                       gvert);
     if (ra.partial && grp < nb && threadIdx.x == 0) ra.partial[r * ra.part_stride + part_offset + grp] = dot;
@@ -1549,11 +1592,19 @@ void launch_apply_p(hd_ctx* c, const T* x, T* y, const RhsArgs& ra, int ess_mode
             hipLaunchKernelGGL((block_apply_kernel<P, T, true, true>), dim3(grid), dim3(64), 0, c->stream, g,
                                c->d_vert, tb, cm, kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 1,
                                colour, (int64_t)colour * nb, nb, winv, (const double*)c->d_gv);
+        else if (!c->kappa_zero && c->affine)
+            hipLaunchKernelGGL((block_apply_kernel<P, T, true, false, true>), dim3(grid), dim3(64), 0, c->stream, g,
+                               c->d_vert, tb, cm, kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 1,
+                               colour, (int64_t)colour * nb, nb, winv, (const double*)nullptr);
         else if (!c->kappa_zero)
             hipLaunchKernelGGL((block_apply_kernel<P, T, true>), dim3(grid), dim3(64), 0, c->stream, g, c->d_vert, tb,
                                cm,
                                kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 1, colour,
                                (int64_t)colour * nb, nb, winv, (const double*)nullptr);
+        else if (c->affine)
+            hipLaunchKernelGGL((block_apply_kernel<P, T, false, false, true>), dim3(grid), dim3(64), 0, c->stream, g,
+                               c->d_vert, tb, cm, kap, c->ess, ess_mode, c->ne, c->n_u, x, y, ra, cg_params<T>(), 0,
+                               colour, (int64_t)colour * nb, nb, (const T*)nullptr, (const double*)nullptr);
         else
             hipLaunchKernelGGL((block_apply_kernel<P, T, false>), dim3(grid), dim3(64), 0, c->stream, g, c->d_vert, tb,
                                cm,

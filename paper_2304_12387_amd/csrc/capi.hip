@@ -1,4 +1,5 @@
 // extern "C" entry points of libhdivsp (declared in include/hdivsp.h).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -72,6 +73,7 @@ void free_mesh(hd_ctx* c) {
     c->d_vert = nullptr;
     c->d_theta = nullptr;
     c->theta_set = false;
+    c->affine = false;
     c->have_mesh = false;
 }
 
@@ -194,6 +196,36 @@ __global__ void tune_pattern_kernel(T* __restrict__ x, int64_t n) {
 }  // namespace
 }  // namespace hd
 
+namespace {
+
+// Whether every element of the structured mesh is a parallelepiped: the
+// bilinear and trilinear terms of its trilinear map (the twist vectors of
+// its vertex cube) vanish to 1e-14 of its longest edge from vertex 0.
+bool mesh_is_affine(int nx, int ny, int nz, const double* V) {
+    auto X = [&](int64_t i, int64_t j, int64_t k, int r) {
+        return V[3 * (i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * k)) + r];
+    };
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                double scale = 0.0, twist = 0.0;
+                for (int r = 0; r < 3; ++r) {
+                    const double x000 = X(i, j, k, r), x100 = X(i + 1, j, k, r), x010 = X(i, j + 1, k, r),
+                                 x001 = X(i, j, k + 1, r), x110 = X(i + 1, j + 1, k, r),
+                                 x101 = X(i + 1, j, k + 1, r), x011 = X(i, j + 1, k + 1, r),
+                                 x111 = X(i + 1, j + 1, k + 1, r);
+                    scale = std::max({scale, std::fabs(x100 - x000), std::fabs(x010 - x000), std::fabs(x001 - x000)});
+                    twist = std::max({twist, std::fabs(x110 - x100 - x010 + x000),
+                                      std::fabs(x101 - x100 - x001 + x000), std::fabs(x011 - x010 - x001 + x000),
+                                      std::fabs(x111 - x110 - x101 - x011 + x100 + x010 + x001 - x000)});
+                }
+                if (!(twist <= 1e-14 * scale)) return false;
+            }
+    return true;
+}
+
+}  // namespace
+
 extern "C" {
 
 int hd_create(hd_ctx** out, int device, void* stream) {
@@ -312,6 +344,7 @@ int hd_setup_mesh(hd_ctx* c, int nx, int ny, int nz, int p, const double* vertic
     }
     rc = launch_ensure_partial(c, c->ne);
     if (rc) return rc;
+    c->affine = mesh_is_affine(nx, ny, nz, vertices);
     c->have_mesh = true;
     c->have_coeffs = false;
     return HD_OK;
@@ -536,6 +569,13 @@ int hd_sizes(const hd_ctx* c, int64_t* n_u, int64_t* n_q) {
     if (!c || !c->have_mesh) return HD_ERR_STATE;
     if (n_u) *n_u = c->n_u;
     if (n_q) *n_q = c->n_q;
+    return HD_OK;
+}
+
+int hd_mesh_affine(const hd_ctx* c, int* affine) {
+    if (!c || !affine) return HD_ERR_ARG;
+    if (!c->have_mesh) return HD_ERR_STATE;
+    *affine = c->affine ? 1 : 0;
     return HD_OK;
 }
 

@@ -200,6 +200,8 @@ struct hd_ctx {
     hd::Tables<double> tab64_host;
     hd::Tables<float> tab32_host;
     double* d_vert = nullptr;   // [(nx+1)(ny+1)(nz+1)][3], kept for the learned features
+    bool affine = false;        // every element a parallelepiped (structured meshes): the apply
+                                // forms J^T J / det J once per element
 
     // unstructured hexahedral mesh (hd_setup_mesh_unstructured); nx = ne,
     // ny = nz = 1 then, and the structured index arithmetic is not used

@@ -25,7 +25,7 @@ HD_SIDE_ALL = 63
 HD_LOCAL_AUTO, HD_LOCAL_CG, HD_LOCAL_EXPLICIT = 0, 1, 2
 
 EXPORTED = [
-    'hd_create', 'hd_destroy', 'hd_last_error', 'hd_setup_mesh', 'hd_setup_coeffs', 'hd_sizes',
+    'hd_create', 'hd_destroy', 'hd_last_error', 'hd_setup_mesh', 'hd_setup_coeffs', 'hd_sizes', 'hd_mesh_affine',
     'hd_apply_block_op', 'hd_apply_mass_inverse', 'hd_apply_l2_mass_inverse', 'hd_lift_essential',
     'hd_build_precond', 'hd_apply_precond', 'hd_minres_solve', 'hd_get_diagonals', 'hd_get_schur',
     'hd_get_amg_nlevels', 'hd_get_amg_level', 'hd_get_amg_prolongator', 'hd_apply_timing',
@@ -118,6 +118,7 @@ def load():
         'hd_set_essential_dofs': (I, [P, P]),
         'hd_get_dof_map': (I, [P, P]),
         'hd_sizes': (I, [P, pI64, pI64]),
+        'hd_mesh_affine': (I, [P, ctypes.POINTER(ctypes.c_int)]),
         'hd_apply_block_op': (I, [P, I, I, P, P]),
         'hd_apply_block_op_interleaved': (I, [P, I, I, P, P]),
         'hd_apply_mass_inverse': (I, [P, I, I, P, P]),
@@ -277,6 +278,12 @@ class Context:
         nu, nq = ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.hd_sizes(self.h, ctypes.byref(nu), ctypes.byref(nq)))
         return nu.value, nq.value
+
+    def mesh_affine(self):
+        """True when every element of the structured mesh is a parallelepiped."""
+        a = ctypes.c_int()
+        self._check(self.lib.hd_mesh_affine(self.h, ctypes.byref(a)))
+        return bool(a.value)
 
     def _dev(self, a, n, prec, name):
         """Refuse a buffer the kernels would read or write out of bounds."""
