@@ -50,14 +50,19 @@ struct CGParams {
 // passes of W; in particular the (p+1)^2 quadrature columns are held QC per
 // lane (column t + W c on lane t).  The vectors of the local CG live in the
 // p^2 x-pencils, so W >= p^2.  W is the smallest power of two >= (p+1)^2, so
-// that one pass covers every stage (4 at p = 1, 16 at p = 2 and 3, 32 at
-// p = 4, 64 at p = 5 and 6); at p = 4, 16-lane slots with two passes (four
-// elements per wavefront) measured 7% slower: they need twice the LDS and
-// registers per wavefront, which halves the wavefronts per SIMD.
+// that one pass covers every stage (4 at p = 1, 16 at p = 3, 32 at p = 4, 64
+// at p = 5 and 6), except at p = 2: 8-lane slots, eight elements per
+// wavefront, the ninth quadrature column in a second pass.  There the
+// 16-lane slot leaves 7 of its lanes idle in the column stages and most of
+// them in the line stages, and the 8-lane one measured 10-18% faster in FP64
+// and 10-34% in FP32 (jittered and box grids, with and without the (2,2)
+// block).  At p = 4, 16-lane slots with two passes (four elements per
+// wavefront) measured 7% slower: they need twice the LDS and registers per
+// wavefront, which halves the wavefronts per SIMD.
 template <int P>
 struct Slot {
     static constexpr int Q = P + 1;
-    static constexpr int W = Q * Q <= 4 ? 4 : (Q * Q <= 16 ? 16 : (Q * Q <= 32 ? 32 : 64));
+    static constexpr int W = P == 2 ? 8 : (Q * Q <= 4 ? 4 : (Q * Q <= 16 ? 16 : (Q * Q <= 32 ? 32 : 64)));
     static constexpr int EPW = 64 / W;
     static constexpr int QC = (Q * Q + W - 1) / W;
     static_assert(P * P <= W && 64 % W == 0, "slot width");
@@ -482,26 +487,36 @@ __device__ __forceinline__ void quad_factors(ElemLDS<P, T>& L, tkp<P, T> tb, int
 // Global position of the x-line (., j, k) of RT component C in element
 // (ex, ey, ez): index of its first dof, whether the whole line lies on an
 // element face normal to y or z (C = 1, 2), and its domain-boundary side.
+// Index arithmetic of the structured element kernels: 32-bit at p <= 3 (a
+// context holds fewer than 2^31 unknowns, checked when the mesh is set up),
+// where the per-element index work is a visible share of the kernel (layered
+// Darcy grid, p = 2: 14% less time per apply); 64-bit at p >= 4, where the
+// 32-bit form measured 3-7% slower (a different register allocation).
+template <int P>
+using Idx = typename std::conditional<(P <= 3), uint32_t, int64_t>::type;
+
+template <typename I>
 struct RtLine {
-    int64_t base;      // global index of local i = 0
+    I base;            // global index of local i = 0
     int tan_face;      // C = 1 (j in {0,P}) or C = 2 (k in {0,P}): the line lies on an element face
     int tan_bnd;       // ... and that face is on the domain boundary: side 0 / 1, else -1
 };
 
 template <int P, int C>
-__device__ __forceinline__ RtLine rt_line(const Geo& g, int ex, int ey, int ez, int j, int k) {
-    const int64_t d0 = (int64_t)g.nx * P + (C == 0), d1 = (int64_t)g.ny * P + (C == 1);
-    const int64_t gj = (int64_t)ey * P + j, gk = (int64_t)ez * P + k;
-    RtLine r;
-    r.base = g.off[C] + (int64_t)ex * P + d0 * (gj + d1 * gk);
+__device__ __forceinline__ RtLine<Idx<P>> rt_line(const Geo& g, int ex, int ey, int ez, int j, int k) {
+    using I = Idx<P>;
+    const I d0 = (I)g.nx * P + (C == 0), d1 = (I)g.ny * P + (C == 1);
+    const I gj = (I)ey * P + j, gk = (I)ez * P + k;
+    RtLine<I> r;
+    r.base = (I)g.off[C] + (I)ex * P + d0 * (gj + d1 * gk);
     r.tan_face = 0;
     r.tan_bnd = -1;
     if (C == 1) {
         r.tan_face = j == 0 || j == P;
-        r.tan_bnd = gj == 0 ? 0 : (gj == (int64_t)g.ny * P ? 1 : -1);
+        r.tan_bnd = gj == 0 ? 0 : (gj == (I)g.ny * P ? 1 : -1);
     } else if (C == 2) {
         r.tan_face = k == 0 || k == P;
-        r.tan_bnd = gk == 0 ? 0 : (gk == (int64_t)g.nz * P ? 1 : -1);
+        r.tan_bnd = gk == 0 ? 0 : (gk == (I)g.nz * P ? 1 : -1);
     }
     return r;
 }
@@ -509,7 +524,7 @@ __device__ __forceinline__ RtLine rt_line(const Geo& g, int ex, int ey, int ez, 
 // Classify dof i of an x-line of component C: on an element face, and on
 // which domain-boundary side (-1: interior).
 template <int P, int C>
-__device__ __forceinline__ void rt_line_dof(const Geo& g, int ex, const RtLine& r, int i, int& onf, int& bs) {
+__device__ __forceinline__ void rt_line_dof(const Geo& g, int ex, const RtLine<Idx<P>>& r, int i, int& onf, int& bs) {
     if (C == 0) {
         onf = i == 0 || i == P;
         const int gi = ex * P + i;
@@ -529,7 +544,7 @@ __device__ __forceinline__ void gather_rt(ElemLDS<P, T>& L, const Geo& g, int ex
     constexpr int W = Slot<P>::W;
     for (int tt = t; tt < N1 * N2; tt += W) {
         const int j = tt % N1, k = tt / N1;
-        const RtLine r = rt_line<P, C>(g, ex, ey, ez, j, k);
+        const auto r = rt_line<P, C>(g, ex, ey, ez, j, k);
         T v[N0];
 #pragma unroll
         for (int i = 0; i < N0; ++i) v[i] = x[r.base + i];
@@ -553,7 +568,7 @@ __device__ __forceinline__ void prefetch_line(const Geo& g, int ex, int ey, int 
                                               T (&old)[P + 1]) {
     constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
     if (t < N1 * N2) {
-        const RtLine r = rt_line<P, C>(g, ex, ey, ez, t % N1, t / N1);
+        const auto r = rt_line<P, C>(g, ex, ey, ez, t % N1, t / N1);
         if (C == 0) {
             // only the two end dofs of an x-line lie on element faces
             old[0] = y[r.base];
@@ -586,7 +601,7 @@ __device__ __forceinline__ double finish_rt(ElemLDS<P, T>& L, tkp<P, T> tk, cons
         pencil_mul<T, Q, N0, N0, true>(in, yv, C == 0 ? &tfence<P, T>(tk)->L[0][0] : &tfence<P, T>(tk)->H[0][0]);
     }
     const int j = t % N1, k = t / N1;
-    const RtLine r = rt_line<P, C>(g, ex, ey, ez, j, k);
+    const auto r = rt_line<P, C>(g, ex, ey, ez, j, k);
     unsigned ess_mask = 0, add_mask = 0;
 #pragma unroll
     for (int i = 0; i < N0; ++i) {
@@ -659,15 +674,17 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
     const int lane = threadIdx.x;
     const int slot = lane / W, t = lane % W;
     // elements of one colour ((ex + ey + ez) mod 2 == colour), half-row by half-row
-    const int hx = (g.nx + 1) / 2;
-    const int64_t idx = (int64_t)grp * S::EPW + slot;
-    const int64_t row = idx / hx;
+    using I = Idx<P>;
+    const I hx = (I)((g.nx + 1) / 2);
+    const I idx = (I)grp * S::EPW + slot;
+    const I row = idx / hx;
     const int m = (int)(idx % hx);
-    const int ey0 = (int)(row % g.ny), ez0 = (int)(row / g.ny);
+    const int ey0 = (int)(row % (I)g.ny), ez0 = (int)(row / (I)g.ny);
     const int ex0 = 2 * m + ((colour + ey0 + ez0) & 1);
-    const bool valid = grp < nb && row < (int64_t)g.ny * g.nz && ex0 < g.nx;
+    const bool valid = grp < nb && row < (I)g.ny * (I)g.nz && ex0 < g.nx;
     const int ex = valid ? ex0 : 0, ey = valid ? ey0 : 0, ez = valid ? ez0 : 0;
-    const int64_t ee = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);   // clamped for address arithmetic
+    const I ee = ex + (I)g.nx * (ey + (I)g.ny * ez);   // clamped for address arithmetic
+    const I qoff = (I)n_u + ee * NL;                   // first L2 dof of the element
     ElemLDS<P, T>& L = sm[slot];
     const T cM = cm[ee];
     const T kE = kap[ee];
@@ -688,7 +705,7 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
         gather_rt<P, T, 0>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
         gather_rt<P, T, 1>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
         gather_rt<P, T, 2>(L, g, ex, ey, ez, t, ess, ess_mode, s_in, x);
-        for (int l = t; l < NL; l += W) L.sq[l] = s_in * x[n_u + ee * NL + l];
+        for (int l = t; l < NL; l += W) L.sq[l] = s_in * x[qoff + l];
     }
     __syncthreads();
     // M u: the three components to the quadrature points
@@ -772,7 +789,7 @@ __device__ __forceinline__ double apply_group(ElemLDS<P, T>* sm, const Geo& g, c
             v += L.su[NC + a + P * ((b + 1) + (P + 1) * c)] - L.su[NC + a + P * (b + (P + 1) * c)];
             v += L.su[2 * NC + a + P * (b + P * (c + 1))] - L.su[2 * NC + a + P * (b + P * c)];
             if (cg) v -= L.A1[l];
-            y[n_u + ee * NL + l] = v;
+            y[qoff + l] = v;
             dot += (double)v * (double)L.sq[l];
         }
     }
@@ -1069,13 +1086,13 @@ __global__ __launch_bounds__(IL_T) void block_apply_il_kernel(
             constexpr int N0 = C == 0 ? P + 1 : P, N1 = C == 1 ? P + 1 : P, N2 = C == 2 ? P + 1 : P;
             for (int tt = ps; tt < N1 * N2; tt += PS) {
                 const int j = tt % N1, k = tt / N1;
-                const RtLine rl = rt_line<P, C>(g, ex, ey, ez, j, k);
+                const auto rl = rt_line<P, C>(g, ex, ey, ez, j, k);
 #pragma unroll
                 for (int i = 0; i < N0; ++i) {
                     int onf, bs;
                     rt_line_dof<P, C>(g, ex, rl, i, onf, bs);
                     const bool is_ess = bs >= 0 && ((ess >> (2 * C + bs)) & 1u);
-                    const T v = x[(rl.base + i) * ldr + rx];
+                    const T v = x[((int64_t)rl.base + i) * ldr + rx];
                     L.su[(C * NC + N0 * tt + i) * NR + r] = is_ess ? T(0) : v;
                 }
             }
@@ -1181,12 +1198,12 @@ __global__ __launch_bounds__(IL_T) void block_apply_il_kernel(
 #pragma unroll
                 for (int q = 0; q < Q; ++q) in[q] = L.A1[(GQ::base(tt) + q) * NR + r];
                 pencil_mul<T, Q, N0, N0, true>(in, yv, B0);
-                const RtLine rl = rt_line<P, C>(g, ex, ey, ez, j, k);
+                const auto rl = rt_line<P, C>(g, ex, ey, ez, j, k);
 #pragma unroll
                 for (int i = 0; i < N0; ++i) {
                     int onf, bs;
                     rt_line_dof<P, C>(g, ex, rl, i, onf, bs);
-                    const int64_t gi = (rl.base + i) * ldr + rx;
+                    const int64_t gi = ((int64_t)rl.base + i) * ldr + rx;
                     if (!live) continue;
                     if (bs >= 0 && ((ess >> (2 * C + bs)) & 1u)) {
                         y[gi] = x[gi];   // identity row
