@@ -342,7 +342,7 @@ def run_default(args, torch, hdivsp, inputs):
     traffic = measured_traffic() if (args.n, args.p) == (32, 4) else None
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                       "kernel": f"block_apply_kernel<{args.p},double,true,false>",
+                       "kernel": f"block_apply_kernel<{args.p},double,true,false,false>",
                        "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(launch_ms, 5),
                        "launches_per_apply": 2}
     out["apply_f32_gdofs"] = round(N / (f32_ms * 1e-3) / 1e9, 3)
