@@ -25,7 +25,8 @@ factors from the element vertices, so its measured HBM traffic
 Other workloads (`--workload`, one JSON line each, no CPU baseline):
   darcy_layered  60 x 220 x 85 cells, p = 2, layered log-normal permeability,
                  flux boundary condition: FP64 MINRES with the FP64 and with
-                 the FP32 Schur V-cycle, time to a true residual of 1e-8.
+                 the FP32 Schur V-cycle, and the mixed-precision solve, time
+                 to a true residual of 1e-8.
   batch32        32 independent grad-div instances (n^3, n in 8..40, p in
                  1..6): batched apply in the autotuned launch mode (persistent
                  work queue, or each instance's own launch), FP64 and FP32.
@@ -380,7 +381,8 @@ def run_darcy_layered(args, torch, hdivsp, inputs):
     ctx.lift_essential(ctx.constant_flux((1.0, 0.0, 0.0)), b)
     res = {}
     ts = time.perf_counter()
-    for name, mode in (('plain_f64', hdivsp.HD_MODE_PLAIN64), ('prec32', hdivsp.HD_MODE_PREC32)):
+    for name, mode in (('plain_f64', hdivsp.HD_MODE_PLAIN64), ('prec32', hdivsp.HD_MODE_PREC32),
+                       ('mixed', hdivsp.HD_MODE_MIXED)):
         times = []
         for _ in range(args.warmup + args.steps):
             x = torch.zeros_like(b)
@@ -388,13 +390,15 @@ def run_darcy_layered(args, torch, hdivsp, inputs):
             times.append(info['time_s'])
         res[name] = {"time_to_1e-8_s": round(float(np.median(times[args.warmup:])), 4),
                      "iterations": info['iterations'], "true_rel_res": info['true_rel_res']}
+        if mode == hdivsp.HD_MODE_MIXED:
+            res[name]["outer"] = info.get('outer')
     te = time.perf_counter()
     x = torch.from_numpy(inputs.uniform_vector(nu + nq, 32)).to(dev)
     y = torch.empty_like(x)
     ms = time_applies(torch, stream, lambda: ctx.apply_block_op(x, y), NAPPLY)
     out = base_line("MINRES time-to-1e-8 (s) of layered Darcy, FP32 Schur V-cycle in FP64 MINRES",
                     res['prec32']['time_to_1e-8_s'], "s", args,
-                    round((te - ts) * 1e3 / (2 * (args.warmup + args.steps)), 3),
+                    round((te - ts) * 1e3 / (3 * (args.warmup + args.steps)), 3),
                     {"workload": "darcy_layered_60x220x85_p2", "n_u": nu, "n_q": nq,
                      "bc": "u.n = (1,0,0).n on the whole boundary"}, higher=False)
     out["minres"] = res
