@@ -21,7 +21,7 @@
 // factorisation.
 //
 // Launch: one 64-lane wavefront per workgroup, holding 64 / W elements (W
-// lanes per element, W >= (p+1)^2).  Each lane owns register pencils; LDS
+// lanes per element, see Slot).  Each lane owns register pencils; LDS
 // only re-orients pencils between contraction directions.  RT dofs are
 // shared only by the two elements across a face, and face neighbours always
 // differ in the parity of ex + ey + ez, so the operator runs as two launches
