@@ -200,7 +200,34 @@ __device__ __forceinline__ void vupd_body(int64_t N, int64_t nu, const T* __rest
     __shared__ double s[BS];
     const T cv1 = (T)st.cv1, cv2 = (T)st.cv2;
     double contrib = 0.0;
-    for (int64_t i = lb * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)nb * BS) {
+    const int64_t stride = (int64_t)nb * BS;
+    int64_t i = lb * (int64_t)blockDim.x + threadIdx.x;
+    // four strides at a time, all loads first (more bytes in flight per
+    // thread, which the 4-byte FP32 loads need); the same per-thread order of
+    // the elements and of the partial sum as one at a time
+    constexpr int U = 4;
+    for (; i + (U - 1) * stride < N; i += U * stride) {
+        T qv[U], vv[U], ov[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = i + u * stride;
+            qv[u] = q[k];
+            vv[u] = v[k];
+            ov[u] = vo[k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = i + u * stride;
+            const T vn = qv[u] - cv1 * vv[u] - cv2 * ov[u];
+            vo[k] = vn;
+            if (k < nu) {
+                const T zi = mdinv[k] * vn;
+                z[k] = zi;
+                contrib += (double)zi * (double)vn;
+            }
+        }
+    }
+    for (; i < N; i += stride) {
         const T vn = q[i] - cv1 * v[i] - cv2 * vo[i];
         vo[i] = vn;
         if (i < nu) {
