@@ -75,6 +75,7 @@ def test_full_size_layered_60x220x85_p2():
     ctx = gpu_context(cfg)
     nu, nq = ctx.sizes()
     assert (nu, nq) == (m.n_u, m.n_q) and nu + nq == 36052000
+    assert ctx.mesh_affine()   # box cells: the apply takes the parallelepiped path
     x = inputs.uniform_vector(nu + nq, 32)
     xd = to_dev(x)
     yd = torch.empty_like(xd)
