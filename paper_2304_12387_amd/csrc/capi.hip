@@ -968,8 +968,13 @@ int hd_setup_batch(hd_ctx* c, int problem, int ninst, const hd_instance_desc* d)
         else if ((rc = hd_setup_mesh(s, d[i].nx, d[i].ny, d[i].nz, d[i].p, d[i].vertices)) ||
                  (rc = hd_setup_coeffs(s, problem, d[i].c_mass, d[i].c_22, d[i].ess_sides)))
             rc = set_err(c, rc, "instance " + std::to_string(i) + ": " + s->err);
-        else
+        else {
+            // the work-queue launches form the factors point by point; the
+            // instance's own launches do the same, so that every launch mode
+            // gives the same result bit for bit
+            s->affine = false;
             B->off.push_back(B->off.back() + s->n_u + s->n_q);
+        }
     }
     if (!rc) {
         B->total = B->off.back();

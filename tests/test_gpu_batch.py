@@ -70,6 +70,36 @@ def test_batch_tuner_keeps_results():
     ctx.close()
 
 
+def test_batch_launch_modes_agree_on_box_instances():
+    """Instances on box grids (every element a parallelepiped): the
+    persistent work-queue launch and each instance's own launch give the same
+    result bit for bit (the instances' own launches keep the point-by-point
+    factors of the work queue), and match the oracle."""
+    torch = torch_cuda()
+    from paper_2304_12387_amd import hdivsp
+    I = inputs.batch_instances(n_inst=3, seed=41, nmin=2, nmax=4, pmin=1, pmax=3)
+    for d in I[:2]:
+        d['vertices'] = inputs.box_vertices(d['nx'], d['ny'], d['nz'])
+    ctx = hdivsp.Context(0)
+    ctx.setup_batch(0, I)
+    off = ctx.batch_offsets
+    x = np.random.default_rng(5).uniform(-1, 1, int(off[-1]))
+    xd = to_dev(x)
+    ys = []
+    for launch in (0, 2):
+        ctx.batch_set_launch(launch, 2048, 1)
+        y = torch.full_like(xd, np.nan)
+        ctx.batch_apply(xd, y)
+        torch.cuda.synchronize()
+        ys.append(y)
+    assert torch.equal(ys[0], ys[1])
+    y = ys[0].cpu().numpy()
+    for i, d in enumerate(I):
+        seg = slice(off[i], off[i + 1])
+        assert rel(y[seg], oracle_problem(d).apply(x[seg])) <= 1e-12, i
+    ctx.close()
+
+
 @pytest.mark.parametrize("mode", ['plain', 'prec32'])
 def test_batch_minres_matches_solo_solves(mode):
     torch = torch_cuda()
