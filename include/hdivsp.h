@@ -236,8 +236,8 @@ int hd_sizes(const hd_ctx* ctx, int64_t* n_u, int64_t* n_q);
  * below 1e-14 of its edges), written to *affine as 1 or 0.  Then J, and
  * J^T J / det J, are the same at all quadrature points of an element, and
  * hd_apply_block_op forms them once per element (same operator; unstructured
- * meshes and a gamma field always take the general path).  HD_ERR_ARG for a
- * NULL pointer, HD_ERR_STATE before hd_setup_mesh. */
+ * meshes, a gamma field and the instances of a batch always take the general
+ * path).  HD_ERR_ARG for a NULL pointer, HD_ERR_STATE before hd_setup_mesh. */
 int hd_mesh_affine(const hd_ctx* ctx, int* affine);
 
 /* y = A x (eq. transformed-saddle-point, Section 3).  x != y, device
